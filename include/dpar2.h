@@ -1,0 +1,183 @@
+/*
+ * libdpar2 -- DPar2 (fast PARAFAC2 of irregular dense tensors) on one AMD
+ * Instinct MI355X (gfx950).  C ABI.
+ *
+ * Method: Jang & Kang, "DPar2: Fast and Scalable PARAFAC2 Decomposition for
+ * Irregular Dense Tensors" (arXiv 2203.12798).
+ *   - dpar2_compress   : the two-stage randomized-SVD compression of Sec. III-B
+ *                        (Alg. 1 applied to every slice, Eq. 4; M = ||_k C_k B_k;
+ *                        Alg. 1 applied to M, Eq. 5; F^(k) blocks, Eqs. 6-7).
+ *   - dpar2_als_step   : the repeat loop of Alg. 3 (Eq. 8 Q-step, implicit Y_k of
+ *                        Sec. III-D, Lemmas 1-3 for G^(1), G^(2), G^(3),
+ *                        pseudoinverse updates of H, V, W, S_k = diag(W(k,:)),
+ *                        the compressed error of Sec. III-E and its stop rule).
+ *   - dpar2_fitness    : fitness of Sec. IV-A against the original slices, from
+ *                        the compressed factors (no second pass over the slab).
+ *   - dpar2_output_U   : U_k = A_k Z_k P_k^T H (last lines of Alg. 3).
+ *   - dpar2_decompose  : all of the above, Alg. 3 end to end.
+ *
+ * Conventions (all calls):
+ *   - Pointers are DEVICE pointers unless marked (host).  The caller owns every
+ *     buffer; the library never allocates or frees device memory.  All
+ *     intermediate data lives in one caller-provided workspace whose size comes
+ *     from dpar2_workspace_size(); compress, als_step, fitness and output_U of
+ *     one decomposition must be given the same workspace.
+ *   - Work is enqueued on the caller's stream `stream` and is asynchronous;
+ *     results are valid after the stream is synchronised.  Calls on different
+ *     streams need different workspaces.  The only host<->device copies the
+ *     library makes are the small schedule upload in dpar2_compress and the
+ *     report read in dpar2_report_read.
+ *   - Matrices are row-major.  Factor matrices are float64: H (R x R),
+ *     V (J x R), W (K x R); S_k = diag(W(k,:)).
+ *   - Irregular tensor {X_k}: slab of N = sum_k I_k rows, each of J float32
+ *     values, row-major; slice k is rows row_offsets[k] .. row_offsets[k+1]-1.
+ *   - Errors: every call returns a dpar2_status.  Shape and argument errors are
+ *     detected on the host before anything is enqueued.  HIP errors map to
+ *     DPAR2_EHIP with the HIP message available from dpar2_last_error()
+ *     (thread-local).  No call aborts or throws across the ABI.
+ */
+#ifndef LIBDPAR2_DPAR2_H
+#define LIBDPAR2_DPAR2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* dpar2_stream_t;   /* = hipStream_t; NULL = default stream */
+
+typedef enum {
+  DPAR2_OK = 0,
+  DPAR2_EINVAL = -1,     /* NULL pointer, bad option value, malformed row_offsets   */
+  DPAR2_ESHAPE = -2,     /* rank / sketch width incompatible with K, J or some I_k  */
+  DPAR2_ENUMERIC = -3,   /* non-finite input or a Gram matrix that is not positive  */
+  DPAR2_EHIP = -5,       /* a HIP runtime call failed (see dpar2_last_error)        */
+  DPAR2_EWORKSPACE = -6  /* workspace NULL, misaligned (256 B) or too small         */
+} dpar2_status;
+
+typedef enum {
+  DPAR2_F32 = 0          /* slab of float32 values */
+} dpar2_dtype;
+
+/* Warning bits reported in dpar2_report.warn_bits (device-side, never fatal). */
+#define DPAR2_WARN_JACOBI_CAP   0x1u  /* a Jacobi eigen/SVD solve hit its sweep cap   */
+#define DPAR2_WARN_RANK_DEFICIENT 0x2u /* a T_k had a (near) zero singular value      */
+#define DPAR2_WARN_NOT_PD       0x4u  /* a per-slice Gram matrix was not positive     */
+
+/* Irregular dense tensor {X_k}, k = 0..K-1, X_k in R^{I_k x J} (Sec. II-A). */
+typedef struct {
+  int64_t K;                        /* number of slices, >= 1                           */
+  int64_t J;                        /* number of columns, >= 1                          */
+  const int64_t* row_offsets;       /* device, K+1 entries: [0] = 0, non-decreasing      */
+  const int64_t* row_offsets_host;  /* (host) the same K+1 values (validation, schedule) */
+  const void* slab;                 /* device, N x J row-major, N = row_offsets[K]       */
+  int32_t dtype;                    /* dpar2_dtype                                       */
+} dpar2_tensor;
+
+/* Parameters of Alg. 1 / Alg. 3. */
+typedef struct {
+  int32_t rank;        /* R: target rank of both stages and of PARAFAC2            */
+  int32_t sketch;      /* L = R + s: columns of Omega_1 (first stage), R <= L <= 32,
+                          L <= J and L <= every I_k                                 */
+  int32_t sketch2;     /* L2: columns of Omega_2 (second stage), R <= L2 <= 32,
+                          L2 <= J and L2 <= K R                                     */
+  int32_t max_iter;    /* iterations of the repeat loop of Alg. 3, >= 0             */
+  double tol;          /* stop when e_{t-1} - e_t < tol * e_{t-1}; tol < 0: never   */
+  uint32_t flags;      /* reserved, must be 0                                       */
+} dpar2_opts;
+
+/* Factor matrices (device, float64, row-major). */
+typedef struct {
+  double* H;           /* R x R */
+  double* V;           /* J x R */
+  double* W;           /* K x R, row k = diagonal of S_k */
+} dpar2_factors;
+
+/* Device views of the compressed representation held in the workspace after
+ * dpar2_compress (Sec. III-B; the preprocessed data of Sec. III-G).  All
+ * float64, row-major.  Valid until the workspace is reused. */
+typedef struct {
+  const double* Mt;      /* (K R) x J: row kR + r is column r of C_k B_k (M^T)      */
+  const double* D;       /* J x R                                                    */
+  const double* E;       /* R, diagonal of E                                         */
+  const double* F;       /* (K R) x R; F^(k) = rows kR .. kR+R-1                     */
+  const double* Phi;     /* K x L x R: A_k = (X_k Omega_1) Phi_k                     */
+  const double* sigma;   /* K x R: first-stage singular values (diagonal of B_k)    */
+  const double* xnorm2;  /* K: ||X_k||_F^2                                           */
+} dpar2_compressed;
+
+/* Host-side summary of a decomposition (filled by dpar2_report_read). */
+typedef struct {
+  int32_t iters;           /* iterations executed by the repeat loop          */
+  int32_t converged;       /* 1 if the stop rule fired before max_iter        */
+  double err_last;         /* e of the last iteration (Sec. III-E)             */
+  double fit_compressed;   /* 1 - e / sum_k ||X_k||^2                          */
+  double fit_true;         /* fitness of Sec. IV-A (after dpar2_fitness)       */
+  double xnorm2;           /* sum_k ||X_k||_F^2                                */
+  uint32_t warn_bits;      /* DPAR2_WARN_* bits                                */
+} dpar2_report;
+
+/* Bytes of device workspace needed for a decomposition of X with options o
+ * (host only, pure; 0 on invalid arguments). */
+size_t dpar2_workspace_size(const dpar2_tensor* X, const dpar2_opts* o);
+
+/* Sec. III-B, two-stage compression (Alg. 3, first loop and the two lines
+ * after it).  omega1: device float32 J x L (Gaussian test matrix shared by all
+ * slices); omega2: device float32 (K R) x L2 (second stage).  Leaves A_k (as a
+ * recipe), M, D, E, F and sum ||X_k||^2 in the workspace.  The slab is read
+ * once.  Resets the iteration state and report held in the workspace. */
+dpar2_status dpar2_compress(const dpar2_tensor* X, const dpar2_opts* o,
+                            const float* omega1, const float* omega2,
+                            void* ws, size_t ws_bytes, dpar2_stream_t stream);
+
+/* Alg. 3, repeat loop: runs up to n_steps further iterations starting from the
+ * factors in f (updated in place), stopping early by the rule of opts.tol
+ * (checked on the device; later iterations become no-ops).  Requires a prior
+ * dpar2_compress on the same workspace.  err_trace: device, n_steps doubles or
+ * NULL; receives e_t for each executed iteration (untouched after a stop). */
+dpar2_status dpar2_als_step(const dpar2_tensor* X, const dpar2_opts* o, dpar2_factors* f,
+                            int32_t n_steps, double* err_trace,
+                            void* ws, size_t ws_bytes, dpar2_stream_t stream);
+
+/* Sec. IV-A fitness 1 - sum_k ||X_k - U_k S_k V^T||^2 / sum_k ||X_k||^2 with
+ * U_k = A_k Z_k P_k^T H from the last Q-step, computed from the compressed
+ * factors via A_k^T X_k = (C_k B_k)^T.  fit: device, 1 double. */
+dpar2_status dpar2_fitness(const dpar2_tensor* X, const dpar2_opts* o, const dpar2_factors* f,
+                           double* fit, void* ws, size_t ws_bytes, dpar2_stream_t stream);
+
+/* Alg. 3 output U_k = A_k Z_k P_k^T H for all k: U device float64 N x R
+ * (row i of slice k at row row_offsets[k] + i).  Reads the slab once more. */
+dpar2_status dpar2_output_U(const dpar2_tensor* X, const dpar2_opts* o, const dpar2_factors* f,
+                            double* U, void* ws, size_t ws_bytes, dpar2_stream_t stream);
+
+/* Alg. 3 end to end: compress, iterate from the factors in `f` (in/out),
+ * then the fitness (written into the workspace report) and, if U != NULL,
+ * U_k.  Enqueue only; read the report with dpar2_report_read. */
+dpar2_status dpar2_decompose(const dpar2_tensor* X, const dpar2_opts* o,
+                             const float* omega1, const float* omega2,
+                             dpar2_factors* f, double* U,
+                             void* ws, size_t ws_bytes, dpar2_stream_t stream);
+
+/* Fills *out (host struct) with device pointers into the workspace (host-only
+ * pointer arithmetic; nothing is enqueued). */
+dpar2_status dpar2_compressed_view(const dpar2_tensor* X, const dpar2_opts* o, const void* ws,
+                                   size_t ws_bytes, dpar2_compressed* out);
+
+/* Synchronises `stream` and copies the report held in the workspace to *rep
+ * (host). */
+dpar2_status dpar2_report_read(const dpar2_tensor* X, const dpar2_opts* o, const void* ws,
+                               dpar2_report* rep, dpar2_stream_t stream);
+
+/* Static description of a status code. */
+const char* dpar2_status_string(int32_t status);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* dpar2_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBDPAR2_DPAR2_H */

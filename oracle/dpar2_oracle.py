@@ -30,6 +30,10 @@ Readings where the paper is silent (each also listed in the design notes):
   * QR is Householder with diag(R) > 0 (the Q of any QR algorithm after that
     sign rule);
   * truncated SVD = full SVD of the small matrix, keep the leading R triplets;
+    each singular pair is signed so that the largest-magnitude entry of its
+    right singular vector is positive (the paper fixes no sign; the sign of a
+    column of M = ||_k C_k B_k changes the second-stage sketch M Omega_2, so
+    both implementations must agree on it);
   * "normalize H / V" = scale each column to unit 2-norm (norms < 1e-300 are
     left alone); the following least-squares update absorbs the scale;
   * pseudoinverse = Moore-Penrose with cutoff R * eps * sigma_max;
@@ -93,7 +97,12 @@ def randomized_svd(A: np.ndarray, R: int, omega: np.ndarray, q: int = 0):
     Q, _ = qr_pos(Y)
     B = Q.T @ A
     Ut, s, Vt = np.linalg.svd(B, full_matrices=False)
-    return Q @ Ut[:, :R], s[:R], Vt[:R].T
+    U, V = Q @ Ut[:, :R], Vt[:R].T
+    # sign gauge: the largest-magnitude entry of each right singular vector is
+    # positive (first such entry on ties); U changes sign with it
+    sg = np.sign(V[np.argmax(np.abs(V), axis=0), np.arange(R)])
+    sg[sg == 0] = 1.0
+    return U * sg[None, :], s[:R], V * sg[None, :]
 
 
 # ---------------------------------------------------------------------------

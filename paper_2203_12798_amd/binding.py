@@ -1,0 +1,285 @@
+"""ctypes binding of libdpar2 (include/dpar2.h).  Argument marshalling only:
+every step of the method runs in the library's HIP kernels.  PyTorch supplies
+device memory and the stream; nothing here computes on the host or falls back
+to another implementation -- a missing library is an error."""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdpar2.so")
+
+DPAR2_OK = 0
+DPAR2_EINVAL = -1
+DPAR2_ESHAPE = -2
+DPAR2_ENUMERIC = -3
+DPAR2_EHIP = -5
+DPAR2_EWORKSPACE = -6
+DPAR2_F32 = 0
+
+WARN_JACOBI_CAP = 0x1
+WARN_RANK_DEFICIENT = 0x2
+WARN_NOT_PD = 0x4
+
+
+class Dpar2Error(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"libdpar2 status {status}: {message}")
+        self.status = status
+
+
+class c_tensor(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int64), ("J", ctypes.c_int64),
+                ("row_offsets", ctypes.c_void_p), ("row_offsets_host", ctypes.c_void_p),
+                ("slab", ctypes.c_void_p), ("dtype", ctypes.c_int32)]
+
+
+class c_opts(ctypes.Structure):
+    _fields_ = [("rank", ctypes.c_int32), ("sketch", ctypes.c_int32), ("sketch2", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("flags", ctypes.c_uint32)]
+
+
+class c_factors(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_void_p), ("V", ctypes.c_void_p), ("W", ctypes.c_void_p)]
+
+
+class c_compressed(ctypes.Structure):
+    _fields_ = [("Mt", ctypes.c_void_p), ("D", ctypes.c_void_p), ("E", ctypes.c_void_p),
+                ("F", ctypes.c_void_p), ("Phi", ctypes.c_void_p), ("sigma", ctypes.c_void_p),
+                ("xnorm2", ctypes.c_void_p)]
+
+
+class c_report(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("err_last", ctypes.c_double),
+                ("fit_compressed", ctypes.c_double), ("fit_true", ctypes.c_double),
+                ("xnorm2", ctypes.c_double), ("warn_bits", ctypes.c_uint32)]
+
+
+EXPORTS = ["dpar2_workspace_size", "dpar2_compress", "dpar2_als_step", "dpar2_fitness",
+           "dpar2_output_U", "dpar2_decompose", "dpar2_compressed_view", "dpar2_report_read",
+           "dpar2_status_string", "dpar2_last_error"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libdpar2.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} not found: build it with paper_2203_12798_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    lib.dpar2_workspace_size.restype = ctypes.c_size_t
+    lib.dpar2_workspace_size.argtypes = [P(c_tensor), P(c_opts)]
+    lib.dpar2_compress.restype = ctypes.c_int32
+    lib.dpar2_compress.argtypes = [P(c_tensor), P(c_opts), vp, vp, vp, ctypes.c_size_t, vp]
+    lib.dpar2_als_step.restype = ctypes.c_int32
+    lib.dpar2_als_step.argtypes = [P(c_tensor), P(c_opts), P(c_factors), ctypes.c_int32, vp, vp,
+                                   ctypes.c_size_t, vp]
+    lib.dpar2_fitness.restype = ctypes.c_int32
+    lib.dpar2_fitness.argtypes = [P(c_tensor), P(c_opts), P(c_factors), vp, vp, ctypes.c_size_t, vp]
+    lib.dpar2_output_U.restype = ctypes.c_int32
+    lib.dpar2_output_U.argtypes = [P(c_tensor), P(c_opts), P(c_factors), vp, vp, ctypes.c_size_t, vp]
+    lib.dpar2_decompose.restype = ctypes.c_int32
+    lib.dpar2_decompose.argtypes = [P(c_tensor), P(c_opts), vp, vp, P(c_factors), vp, vp,
+                                    ctypes.c_size_t, vp]
+    lib.dpar2_compressed_view.restype = ctypes.c_int32
+    lib.dpar2_compressed_view.argtypes = [P(c_tensor), P(c_opts), vp, ctypes.c_size_t, P(c_compressed)]
+    lib.dpar2_report_read.restype = ctypes.c_int32
+    lib.dpar2_report_read.argtypes = [P(c_tensor), P(c_opts), vp, P(c_report), vp]
+    lib.dpar2_status_string.restype = ctypes.c_char_p
+    lib.dpar2_status_string.argtypes = [ctypes.c_int32]
+    lib.dpar2_last_error.restype = ctypes.c_char_p
+    lib.dpar2_last_error.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _check(st: int):
+    if st != DPAR2_OK:
+        msg = load().dpar2_last_error().decode(errors="replace")
+        raise Dpar2Error(st, msg)
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    return int(t.data_ptr())
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        import torch
+        return int(torch.cuda.current_stream().cuda_stream)
+    return int(stream)
+
+
+@dataclasses.dataclass
+class Options:
+    rank: int
+    sketch: int
+    sketch2: int
+    max_iter: int
+    tol: float = -1.0
+
+    def c(self) -> c_opts:
+        return c_opts(self.rank, self.sketch, self.sketch2, self.max_iter, float(self.tol), 0)
+
+
+class Tensor:
+    """An irregular tensor resident on the GPU: float32 slab (N x J,
+    row-major) and int64 row offsets (device copy + host copy)."""
+
+    def __init__(self, slab, offsets_dev, offsets_host: np.ndarray):
+        import torch
+        assert slab.is_cuda and slab.dtype == torch.float32 and slab.is_contiguous() and slab.dim() == 2
+        assert offsets_dev.is_cuda and offsets_dev.dtype == torch.int64 and offsets_dev.is_contiguous()
+        self.slab = slab
+        self.offsets_dev = offsets_dev
+        self.offsets_host = np.ascontiguousarray(offsets_host, dtype=np.int64)
+        self.K = int(self.offsets_host.shape[0] - 1)
+        self.J = int(slab.shape[1])
+
+    @classmethod
+    def from_numpy(cls, slab: np.ndarray, offsets: np.ndarray, device="cuda:0"):
+        import torch
+        s = torch.from_numpy(np.ascontiguousarray(slab, dtype=np.float32)).to(device)
+        o = torch.from_numpy(np.ascontiguousarray(offsets, dtype=np.int64)).to(device)
+        return cls(s, o, offsets)
+
+    def c(self) -> c_tensor:
+        return c_tensor(self.K, self.J, _ptr(self.offsets_dev),
+                        self.offsets_host.ctypes.data_as(ctypes.c_void_p).value,
+                        _ptr(self.slab), DPAR2_F32)
+
+
+class Factors:
+    """H (R x R), V (J x R), W (K x R) float64 device tensors, row-major."""
+
+    def __init__(self, H, V, W):
+        import torch
+        for t in (H, V, W):
+            assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+        self.H, self.V, self.W = H, V, W
+
+    @classmethod
+    def from_numpy(cls, H, V, W, device="cuda:0"):
+        import torch
+        f = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(device)
+        return cls(f(H), f(V), f(W))
+
+    def c(self) -> c_factors:
+        return c_factors(_ptr(self.H), _ptr(self.V), _ptr(self.W))
+
+    def numpy(self):
+        return self.H.cpu().numpy(), self.V.cpu().numpy(), self.W.cpu().numpy()
+
+
+def workspace_size(X: Tensor, o: Options) -> int:
+    """Bytes of workspace for (X, o); raises on invalid arguments."""
+    lib = load()
+    tc, oc = X.c(), o.c()
+    n = lib.dpar2_workspace_size(ctypes.byref(tc), ctypes.byref(oc))
+    if n == 0:
+        raise Dpar2Error(DPAR2_EINVAL, last_error())
+    return int(n)
+
+
+def alloc_workspace(X: Tensor, o: Options, device="cuda:0"):
+    import torch
+    n = workspace_size(X, o)
+    return torch.empty(n + 256, dtype=torch.uint8, device=device)
+
+
+def _ws(ws):
+    p = int(ws.data_ptr())
+    off = (-p) % 256
+    return p + off, int(ws.numel()) - off
+
+
+def compress(X: Tensor, o: Options, omega1, omega2, ws, stream=None):
+    lib = load()
+    p, n = _ws(ws)
+    _check(lib.dpar2_compress(ctypes.byref(X.c()), ctypes.byref(o.c()), _ptr(omega1), _ptr(omega2),
+                              p, n, _stream(stream)))
+
+
+def als_step(X: Tensor, o: Options, f: Factors, n_steps: int, ws, err_trace=None, stream=None):
+    lib = load()
+    p, n = _ws(ws)
+    fc = f.c()
+    _check(lib.dpar2_als_step(ctypes.byref(X.c()), ctypes.byref(o.c()), ctypes.byref(fc), int(n_steps),
+                              _ptr(err_trace), p, n, _stream(stream)))
+
+
+def fitness(X: Tensor, o: Options, f: Factors, ws, fit=None, stream=None):
+    lib = load()
+    p, n = _ws(ws)
+    fc = f.c()
+    _check(lib.dpar2_fitness(ctypes.byref(X.c()), ctypes.byref(o.c()), ctypes.byref(fc), _ptr(fit),
+                             p, n, _stream(stream)))
+
+
+def output_U(X: Tensor, o: Options, f: Factors, U, ws, stream=None):
+    lib = load()
+    p, n = _ws(ws)
+    fc = f.c()
+    _check(lib.dpar2_output_U(ctypes.byref(X.c()), ctypes.byref(o.c()), ctypes.byref(fc), _ptr(U),
+                              p, n, _stream(stream)))
+
+
+def decompose(X: Tensor, o: Options, omega1, omega2, f: Factors, ws, U=None, stream=None):
+    lib = load()
+    p, n = _ws(ws)
+    fc = f.c()
+    _check(lib.dpar2_decompose(ctypes.byref(X.c()), ctypes.byref(o.c()), _ptr(omega1), _ptr(omega2),
+                               ctypes.byref(fc), _ptr(U), p, n, _stream(stream)))
+
+
+def compressed_view(X: Tensor, o: Options, ws) -> dict:
+    """Copies of the compressed representation (numpy float64): Mt ((KR) x J),
+    D (J x R), E (R), F ((KR) x R), Phi (K x L x R), sigma (K x R), xnorm2 (K)."""
+    import torch
+    lib = load()
+    p, n = _ws(ws)
+    c = c_compressed()
+    _check(lib.dpar2_compressed_view(ctypes.byref(X.c()), ctypes.byref(o.c()), p, n, ctypes.byref(c)))
+    torch.cuda.synchronize()
+    K, J, R, L = X.K, X.J, o.rank, o.sketch
+    shapes = {"Mt": (K * R, J), "D": (J, R), "E": (R,), "F": (K * R, R), "Phi": (K, L, R),
+              "sigma": (K, R), "xnorm2": (K,)}
+    out = {}
+    base = int(ws.data_ptr())
+    for name, shp in shapes.items():
+        addr = getattr(c, name)
+        nel = int(np.prod(shp))
+        off = (addr - base) // 8
+        assert (addr - base) % 8 == 0
+        out[name] = ws[off * 8:(off + nel) * 8].view(torch.float64).cpu().numpy().reshape(shp).copy()
+    return out
+
+
+def report_read(X: Tensor, o: Options, ws, stream=None) -> dict:
+    lib = load()
+    p, _ = _ws(ws)
+    r = c_report()
+    _check(lib.dpar2_report_read(ctypes.byref(X.c()), ctypes.byref(o.c()), p, ctypes.byref(r),
+                                 _stream(stream)))
+    return {"iters": r.iters, "converged": bool(r.converged), "err_last": r.err_last,
+            "fit_compressed": r.fit_compressed, "fit_true": r.fit_true, "xnorm2": r.xnorm2,
+            "warn_bits": r.warn_bits}
+
+
+def last_error() -> str:
+    return load().dpar2_last_error().decode(errors="replace")
+
+
+def status_string(st: int) -> str:
+    return load().dpar2_status_string(int(st)).decode()

@@ -1,0 +1,84 @@
+// Host-side interfaces between the C ABI (api.hip) and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace dpar2 {
+
+// One unit of first-stage work: rows [row0, row1) of slice `slice`.  Items are
+// listed longest first (the GPU form of Alg. 4: the dispatcher hands the next
+// item to the first free compute unit, which is the least-loaded one).
+struct Item {
+  int64_t row0;
+  int64_t row1;
+  int32_t slice;
+  int32_t pad;
+};
+
+constexpr int SKETCH_TM = 64;          // rows per tile of the slab pass
+constexpr int MAX_CHUNK_ROWS = 16384;  // longest item (rows)
+constexpr int STAGE2_CHUNK = 1024;     // rows of M^T per second-stage block
+constexpr int ALS_THREADS = 256;
+
+// Byte offsets of every buffer inside the caller's workspace.
+struct Layout {
+  int64_t K, J, N, n_items;
+  int R, L, L2, max_iter;
+  int64_t n2;             // second-stage row chunks of M^T
+  int nblkA, nblkB, nblkC, nblkF;
+  size_t ctl, items, slice_ptr, slice_list;
+  size_t partG, partP, partS;
+  size_t xnorm2, Mt, Phi, sig1;
+  size_t Y2p, Y2, B2t, S2p, U2;
+  size_t D, E, F, FtFp;
+  size_t Psi, Pw, Mk, small, partA, partB, partC, fitp, trace, om1;
+  size_t total;
+};
+
+// indices of R x R blocks inside Layout::small
+enum SmallSlot {
+  SM_BM = 0,     // E D^T V (current V)
+  SM_GAM,        // Hadamard Gram (scratch)
+  SM_HTH,        // H^T H
+  SM_VTV,        // V^T V
+  SM_WTW,        // W^T W
+  SM_G3INV,      // (V^T V * H^T H)^dagger
+  SM_HV,         // H^T H * V^T V
+  SM_DTD,        // D^T D
+  SM_FTF,        // F^T F
+  SM_SCR0, SM_SCR1, SM_SCR2,
+  SM_COUNT
+};
+
+// --- launchers (each returns the hipGetLastError() of its launches) ---------
+hipError_t launch_sketch(const float* slab, int J, int L, const float* omega1,
+                         const Item* items, int64_t n_items,
+                         double* partG, double* partP, double* partS, hipStream_t s);
+hipError_t launch_output_U(const float* slab, int J, int L, int R, const float* omega1,
+                           const Item* items, int64_t n_items, const double* theta,
+                           double* U, hipStream_t s);
+hipError_t launch_slice_finish(int64_t K, int J, int L, int R, const int32_t* slice_ptr,
+                               const int32_t* slice_list, const double* partG,
+                               const double* partP, const double* partS, double* xnorm2,
+                               double* Mt, double* Phi, double* sig1, Ctl* ctl, hipStream_t s);
+hipError_t launch_stage2(const Layout& lay, char* ws, const float* omega2, hipStream_t s);
+hipError_t launch_als_begin(const Layout& lay, char* ws, const double* W, hipStream_t s);
+hipError_t launch_als_iteration(const Layout& lay, char* ws, double* H, double* V, double* W,
+                                double* err_trace, double tol, hipStream_t s);
+hipError_t launch_als_finalize(const Layout& lay, char* ws, double* err_trace, double tol,
+                               hipStream_t s);
+hipError_t launch_fitness(const Layout& lay, char* ws, const double* H, const double* V,
+                          const double* W, double* fit, hipStream_t s);
+hipError_t launch_theta(const Layout& lay, char* ws, const double* H, double* theta,
+                        hipStream_t s);
+
+hipError_t launch_pw_identity(const Layout& lay, char* ws, hipStream_t s);
+int als_blocks(int64_t K, int R);
+
+bool sketch_supported(int J, int L);
+
+}  // namespace dpar2

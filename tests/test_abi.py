@@ -1,0 +1,95 @@
+"""The C ABI loads, exports every symbol the header declares, and rejects bad
+arguments on the host before touching the GPU.  CPU only."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dpar2.h")
+
+
+def _lib():
+    from paper_2203_12798_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("libdpar2.so not built (run __graft_entry__.build())")
+    return binding, binding.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dpar2_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ["dpar2_compress", "dpar2_als_step", "dpar2_decompose", "dpar2_workspace_size",
+              "dpar2_fitness", "dpar2_output_U", "dpar2_report_read", "dpar2_compressed_view"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    binding, lib = _lib()
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+    assert set(binding.EXPORTS) == set(declared_functions())
+
+
+def _tensor(binding, offsets, J=8):
+    off = np.asarray(offsets, dtype=np.int64)
+    t = binding.c_tensor(len(off) - 1, J, 0x1000, off.ctypes.data_as(ctypes.c_void_p).value, 0x2000, 0)
+    return t, off
+
+
+def _status(lib, binding, t, o, ws=0x10000, nbytes=1 << 40):
+    return lib.dpar2_compress(ctypes.byref(t), ctypes.byref(o), 0x3000, 0x4000, ws, nbytes, None)
+
+
+@pytest.mark.parametrize("offsets,opts,status", [
+    ([0, 10, 5], (2, 3, 3, 5), -1),        # decreasing offsets
+    ([1, 10, 20], (2, 3, 3, 5), -1),       # offsets[0] != 0
+    ([0, 10, 12], (2, 3, 3, 5), -2),       # slice shorter than L
+    ([0, 10, 20], (2, 9, 3, 5), -2),       # L > J
+    ([0, 10, 20], (4, 3, 4, 5), -2),       # L < R
+    ([0, 10, 20], (2, 3, 5, 5), -2),       # L2 > K R
+    ([0, 10, 20], (0, 3, 3, 5), -2),       # R = 0
+    ([0, 10, 20], (2, 3, 3, -1), -1),      # max_iter < 0
+])
+def test_invalid_arguments_are_rejected_on_host(offsets, opts, status):
+    binding, lib = _lib()
+    t, _keep = _tensor(binding, offsets)
+    o = binding.c_opts(opts[0], opts[1], opts[2], opts[3], -1.0, 0)
+    assert _status(lib, binding, t, o) == status
+    assert lib.dpar2_last_error().decode()
+    assert lib.dpar2_workspace_size(ctypes.byref(t), ctypes.byref(o)) == 0
+
+
+def test_workspace_checks():
+    binding, lib = _lib()
+    t, _keep = _tensor(binding, [0, 10, 25, 40])
+    o = binding.c_opts(2, 3, 3, 5, -1.0, 0)
+    need = lib.dpar2_workspace_size(ctypes.byref(t), ctypes.byref(o))
+    assert need > 0
+    assert _status(lib, binding, t, o, ws=0, nbytes=need) == -6          # NULL
+    assert _status(lib, binding, t, o, ws=0x10010, nbytes=need) == -6    # misaligned
+    assert _status(lib, binding, t, o, ws=0x10000, nbytes=need - 1) == -6  # too small
+    assert b"too small" in lib.dpar2_last_error()
+
+
+def test_null_pointers_rejected():
+    binding, lib = _lib()
+    off = np.array([0, 10, 20], dtype=np.int64)
+    t = binding.c_tensor(2, 8, 0, off.ctypes.data_as(ctypes.c_void_p).value, 0x2000, 0)
+    o = binding.c_opts(2, 3, 3, 5, -1.0, 0)
+    assert _status(lib, binding, t, o) == -1
+    t2, _k = _tensor(binding, [0, 10, 20])
+    assert lib.dpar2_compress(ctypes.byref(t2), ctypes.byref(o), None, 0x4000, 0x10000, 1 << 40, None) == -1
+
+
+def test_status_strings():
+    _, lib = _lib()
+    for st in (0, -1, -2, -3, -5, -6, 7):
+        assert lib.dpar2_status_string(st)
