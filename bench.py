@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""End-to-end DPar2 benchmark on one MI355X.
+
+Workload: a US-Stock-shaped irregular tensor (K = 4000 slices, J = 88
+features, lognormal history lengths I_k in [200, 8000] with median 1500,
+rank-10 PARAFAC2 entries with feature scales over 1e-2..1e3 and 5% noise;
+N ~ 7.66M rows, 2.70 GB float32), R = 10, oversampling 10 (L = 20), 32
+iterations.  One step = one whole decomposition from the same initial
+factors: two-stage compression (one read of the slab), 32 compressed ALS
+iterations and the fitness against the original slices, all on the device
+with the slab already resident in HBM.
+
+Prints one JSON line: slices/s, ms per decomposition, the roofline of the
+slab-pass kernel (timed with HIP events recorded around it on its launch
+stream), and the FP64 oracle timed on a bounded sample of the same workload
+on the host cores (with the fitness of both on that sample)."""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-sample", type=int, default=2000,
+                    help="slices of the workload the CPU oracle runs on (0 = skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain 1 GiB device copy (counter calibration)")
+    return ap.parse_args()
+
+
+def traffic_record(kernel_src):
+    """HBM bytes per slab-pass launch from the committed counter summary, if
+    it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(slices would shard across GPUs; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2203_12798_amd as d
+    from paper_2203_12798_amd import binding
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    print("[bench] generating workload", file=sys.stderr, flush=True)
+    t = time.perf_counter()
+    X = synth.stock_like()
+    gen_s = time.perf_counter() - t
+    K, J = X.K, X.J
+    R, L, L2, iters = 10, 20, 20, 32
+    om1, om2 = synth.omegas(J, L, K * R)
+    H0, V0, W0 = synth.init_factors(J, K, R)
+    print(f"[bench] K={K} J={J} N={X.N} slab={X.slab.nbytes / 1e9:.2f} GB (gen {gen_s:.1f}s)",
+          file=sys.stderr, flush=True)
+
+    T = d.Tensor.from_numpy(X.slab, X.offsets)
+    o = d.Options(rank=R, sketch=L, sketch2=L2, max_iter=iters)
+    ws = d.alloc_workspace(T, o)
+    o1 = torch.from_numpy(om1).cuda()
+    o2 = torch.from_numpy(om2).cuda()
+    init = [torch.from_numpy(a).cuda() for a in (H0, V0, W0)]
+    f = d.Factors.from_numpy(H0, V0, W0)
+
+    def step():
+        f.H.copy_(init[0])
+        f.V.copy_(init[1])
+        f.W.copy_(init[2])
+        d.decompose(T, o, o1, o2, f, ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    binding.profile_enable(True)
+    binding.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    launches, sketch_ms_total = binding.profile_read()
+    binding.profile_enable(False)
+    rep = d.report_read(T, o, ws)
+    print(f"[bench] timed {args.steps} steps", file=sys.stderr, flush=True)
+
+    if args.calib_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    ms_per_step = (t1 - t0) * 1e3 / max(args.steps, 1)
+    sec = ms_per_step / 1e3
+    # slab-pass roofline: one read of the slab plus the per-item FP64 partials
+    n_items = int(sum(max(1, -(-int(r) // 16384)) for r in X.rows))
+    alg_bytes = X.N * J * 4 + n_items * (L * L + L * J + 1) * 8
+    alg_flops = 2.0 * X.N * J * L * 2 + 2.0 * X.N * L * L
+    sk_ms = sketch_ms_total / max(launches, 1)
+    achieved = alg_bytes / (sk_ms / 1e3) / 1e9
+    src = os.path.join(ROOT, "paper_2203_12798_amd", "csrc", "k_sketch.hip")
+    tr = traffic_record(src)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if tr is None else tr["bytes_per_launch"],
+                "kernel": "k_sketch (slab pass: FP32 MFMA sketch + FP64 MFMA Gram/projection)",
+                "kernel_ms": round(sk_ms, 4), "algorithmic_bytes": int(alg_bytes),
+                "timed_launches": launches}
+    sketch_tf = alg_flops / (sk_ms / 1e3) / 1e12
+    out = {
+        "metric": "end-to-end DPar2 s & slices/s at R=10; sketch-GEMM % peak; fitness vs FP64",
+        "value": round(K / sec, 1), "unit": "slices/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "seconds": round(sec, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "us-stock-shaped irregular tensor K=4000 J=88 I_k lognormal[200,8000] "
+                               "median 1500, rank-10 PARAFAC2 + 5% noise; R=10 L=20 L2=20 32 iterations",
+                   "K": K, "J": J, "N": int(X.N), "rank": R, "sketch": L, "iterations": iters},
+        "roofline": roofline,
+        "sketch_gemm": {"achieved_tflops": round(sketch_tf, 2),
+                        "frac_of_fp32_mfma_peak": round(sketch_tf / FP32_MFMA_PEAK_TFLOPS, 4),
+                        "note": "useful flops 4NJL+2NL^2; sketch in FP32, Gram and projection in FP64"},
+        "fitness": {"gpu": rep["fit_true"], "iters": rep["iters"], "warn_bits": rep["warn_bits"]},
+    }
+
+    if not args.no_cpu_baseline and args.cpu_sample > 0:
+        from threadpoolctl import threadpool_limits
+
+        from oracle import dpar2_oracle as O
+        Ks = min(args.cpu_sample, K)
+        off = X.offsets[:Ks + 1]
+        slab = X.slab[:off[-1]]
+        oms1, oms2 = synth.omegas(J, L, Ks * R)
+        Hs, Vs, Ws = synth.init_factors(J, Ks, R)
+        cores = len(os.sched_getaffinity(0))
+        print(f"[bench] oracle on {Ks} slices, {cores} threads", file=sys.stderr, flush=True)
+        with threadpool_limits(limits=1, user_api="blas"):
+            tc = time.perf_counter()
+            ref = O.dpar2(slab, off, R, oms1, oms2, Hs, Vs, Ws, iters, threads=cores)
+            cpu_s = time.perf_counter() - tc
+        Ts = d.Tensor.from_numpy(slab, off)
+        wss = d.alloc_workspace(Ts, o)
+        fs = d.Factors.from_numpy(Hs, Vs, Ws)
+        d.decompose(Ts, o, torch.from_numpy(oms1).cuda(), torch.from_numpy(oms2).cuda(), fs, wss)
+        reps = d.report_read(Ts, o, wss)
+        out["cpu_baseline"] = {"value": round(Ks / cpu_s, 2), "unit": "slices/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": f"first {Ks} of the {K} slices (same generator, own Omega and "
+                                         f"init of that size), full DPar2: compression + {iters} "
+                                         f"iterations + fitness, {cpu_s:.1f} s"}
+        out["fitness"].update({"sample_gpu": reps["fit_true"], "sample_oracle": ref.fit,
+                               "sample_abs_diff": abs(reps["fit_true"] - ref.fit)})
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

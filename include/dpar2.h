@@ -52,7 +52,7 @@ typedef enum {
   DPAR2_OK = 0,
   DPAR2_EINVAL = -1,     /* NULL pointer, bad option value, malformed row_offsets   */
   DPAR2_ESHAPE = -2,     /* rank / sketch width incompatible with K, J or some I_k  */
-  DPAR2_ENUMERIC = -3,   /* non-finite input or a Gram matrix that is not positive  */
+  DPAR2_ENUMERIC = -3,   /* reserved for numerical failures                         */
   DPAR2_EHIP = -5,       /* a HIP runtime call failed (see dpar2_last_error)        */
   DPAR2_EWORKSPACE = -6  /* workspace NULL, misaligned (256 B) or too small         */
 } dpar2_status;
@@ -64,7 +64,6 @@ typedef enum {
 /* Warning bits reported in dpar2_report.warn_bits (device-side, never fatal). */
 #define DPAR2_WARN_JACOBI_CAP   0x1u  /* a Jacobi eigen/SVD solve hit its sweep cap   */
 #define DPAR2_WARN_RANK_DEFICIENT 0x2u /* a T_k had a (near) zero singular value      */
-#define DPAR2_WARN_NOT_PD       0x4u  /* a per-slice Gram matrix was not positive     */
 
 /* Irregular dense tensor {X_k}, k = 0..K-1, X_k in R^{I_k x J} (Sec. II-A). */
 typedef struct {
@@ -169,6 +168,14 @@ dpar2_status dpar2_compressed_view(const dpar2_tensor* X, const dpar2_opts* o, c
  * (host). */
 dpar2_status dpar2_report_read(const dpar2_tensor* X, const dpar2_opts* o, const void* ws,
                                dpar2_report* rep, dpar2_stream_t stream);
+
+/* Kernel timing for measurement.  While enabled, every dpar2_compress records
+ * a pair of HIP events around its slab pass (the first-stage kernel that reads
+ * the slab) on the launch stream.  dpar2_profile_read waits for the recorded
+ * events, returns the number of timed launches and their summed duration in
+ * milliseconds (host pointers), and clears the record.  Process-wide. */
+dpar2_status dpar2_profile_enable(int32_t on);
+dpar2_status dpar2_profile_read(int32_t* launches, double* total_ms);
 
 /* Static description of a status code. */
 const char* dpar2_status_string(int32_t status);

@@ -23,7 +23,6 @@ DPAR2_F32 = 0
 
 WARN_JACOBI_CAP = 0x1
 WARN_RANK_DEFICIENT = 0x2
-WARN_NOT_PD = 0x4
 
 
 class Dpar2Error(RuntimeError):
@@ -61,7 +60,7 @@ class c_report(ctypes.Structure):
 
 EXPORTS = ["dpar2_workspace_size", "dpar2_compress", "dpar2_als_step", "dpar2_fitness",
            "dpar2_output_U", "dpar2_decompose", "dpar2_compressed_view", "dpar2_report_read",
-           "dpar2_status_string", "dpar2_last_error"]
+           "dpar2_profile_enable", "dpar2_profile_read", "dpar2_status_string", "dpar2_last_error"]
 
 _lib = None
 
@@ -94,6 +93,10 @@ def load(path: str = LIB_PATH):
     lib.dpar2_compressed_view.argtypes = [P(c_tensor), P(c_opts), vp, ctypes.c_size_t, P(c_compressed)]
     lib.dpar2_report_read.restype = ctypes.c_int32
     lib.dpar2_report_read.argtypes = [P(c_tensor), P(c_opts), vp, P(c_report), vp]
+    lib.dpar2_profile_enable.restype = ctypes.c_int32
+    lib.dpar2_profile_enable.argtypes = [ctypes.c_int32]
+    lib.dpar2_profile_read.restype = ctypes.c_int32
+    lib.dpar2_profile_read.argtypes = [P(ctypes.c_int32), P(ctypes.c_double)]
     lib.dpar2_status_string.restype = ctypes.c_char_p
     lib.dpar2_status_string.argtypes = [ctypes.c_int32]
     lib.dpar2_last_error.restype = ctypes.c_char_p
@@ -275,6 +278,18 @@ def report_read(X: Tensor, o: Options, ws, stream=None) -> dict:
     return {"iters": r.iters, "converged": bool(r.converged), "err_last": r.err_last,
             "fit_compressed": r.fit_compressed, "fit_true": r.fit_true, "xnorm2": r.xnorm2,
             "warn_bits": r.warn_bits}
+
+
+def profile_enable(on: bool = True):
+    _check(load().dpar2_profile_enable(1 if on else 0))
+
+
+def profile_read():
+    """(launches, total_ms) of the slab-pass kernel since the last read."""
+    n = ctypes.c_int32()
+    ms = ctypes.c_double()
+    _check(load().dpar2_profile_read(ctypes.byref(n), ctypes.byref(ms)))
+    return int(n.value), float(ms.value)
 
 
 def last_error() -> str:

@@ -185,6 +185,15 @@ struct Staging {
 std::mutex g_stage_mu;
 std::unordered_map<const void*, Staging> g_stage;
 
+// Slab-pass timing (dpar2_profile_*).
+struct Profile {
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+  size_t used = 0;
+};
+std::mutex g_prof_mu;
+Profile g_prof;
+
 __global__ void k_ctl_reset(Ctl* ctl) {
   Ctl z;
   std::memset(&z, 0, sizeof(z));
@@ -260,9 +269,26 @@ dpar2_status dpar2_compress(const dpar2_tensor* X, const dpar2_opts* o, const fl
   double* partG = reinterpret_cast<double*>(w + y.partG);
   double* partP = reinterpret_cast<double*>(w + y.partP);
   double* partS = reinterpret_cast<double*>(w + y.partS);
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (g_prof.on) {
+      if (g_prof.used == g_prof.pool.size()) {
+        hipEvent_t a0, a1;
+        if ((e = hipEventCreate(&a0)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+        if ((e = hipEventCreate(&a1)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+        g_prof.pool.emplace_back(a0, a1);
+      }
+      ev0 = g_prof.pool[g_prof.used].first;
+      ev1 = g_prof.pool[g_prof.used].second;
+      g_prof.used++;
+    }
+  }
+  if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
   e = launch_sketch(static_cast<const float*>(X->slab), (int)X->J, y.L, omega1, items, y.n_items, partG,
                     partP, partS, s);
   if (e != hipSuccess) return hip_fail(e, "slab pass");
+  if (ev1 && (e = hipEventRecord(ev1, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
   e = launch_slice_finish(y.K, (int)y.J, y.L, y.R, reinterpret_cast<const int32_t*>(w + y.slice_ptr),
                           reinterpret_cast<const int32_t*>(w + y.slice_list), partG, partP, partS,
                           reinterpret_cast<double*>(w + y.xnorm2), reinterpret_cast<double*>(w + y.Mt),
@@ -382,6 +408,30 @@ dpar2_status dpar2_compressed_view(const dpar2_tensor* X, const dpar2_opts* o, c
   out->Phi = reinterpret_cast<const double*>(w + y.Phi);
   out->sigma = reinterpret_cast<const double*>(w + y.sig1);
   out->xnorm2 = reinterpret_cast<const double*>(w + y.xnorm2);
+  return DPAR2_OK;
+}
+
+dpar2_status dpar2_profile_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof.on = on != 0;
+  return DPAR2_OK;
+}
+
+dpar2_status dpar2_profile_read(int32_t* launches, double* total_ms) {
+  if (!launches || !total_ms) return fail(DPAR2_EINVAL, "launches and total_ms must be non-NULL");
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  double tot = 0.0;
+  for (size_t i = 0; i < g_prof.used; ++i) {
+    hipError_t e = hipEventSynchronize(g_prof.pool[i].second);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, g_prof.pool[i].first, g_prof.pool[i].second);
+    if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    tot += ms;
+  }
+  *launches = (int32_t)g_prof.used;
+  *total_ms = tot;
+  g_prof.used = 0;
   return DPAR2_OK;
 }
 

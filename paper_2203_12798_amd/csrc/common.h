@@ -175,38 +175,24 @@ __device__ inline void block_sort_desc(const double* A, int ld, int n, int* perm
   __syncthreads();
 }
 
-// Cholesky G = R^T R (R upper triangular, written over the upper triangle of
-// G; the strict lower triangle is zeroed).  Non-positive pivots are replaced
-// by a tiny positive value and reported (returns 1).
-__device__ inline int block_cholesky_upper(double* G, int ld, int n, double* scratch) {
-  const int tid = threadIdx.x;
-  int bad = 0;
-  double tr = 0.0;
-  for (int i = 0; i < n; ++i) tr += fabs(G[i * ld + i]);
-  for (int j = 0; j < n; ++j) {
-    if (tid == 0) {
-      double d = G[j * ld + j];
-      for (int p = 0; p < j; ++p) d -= G[p * ld + j] * G[p * ld + j];
-      double floor_v = 1e-30 * (tr > 0 ? tr : 1.0);
-      scratch[0] = (d > floor_v) ? 0.0 : 1.0;
-      G[j * ld + j] = sqrt(d > floor_v ? d : floor_v);
-    }
-    __syncthreads();
-    if (scratch[0] != 0.0) bad = 1;
-    const double rjj = G[j * ld + j];
-    for (int i = j + 1 + tid; i < n; i += blockDim.x) {
-      double v = G[j * ld + i];
-      for (int p = 0; p < j; ++p) v -= G[p * ld + j] * G[p * ld + i];
-      G[j * ld + i] = v / rjj;
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < n * n; e += blockDim.x) {
-    const int i = e / n, c = e % n;
-    if (c < i) G[i * ld + c] = 0.0;
+// Whitening of a symmetric positive semidefinite n x n Gram matrix G = Y^T Y
+// (LDS; destroyed): G = V diag(lambda) V^T and Wh = V diag(lambda^{-1/2}) over
+// eigenvalues above 64 eps lambda_max (zero columns for the others), so that
+// Y Wh is an orthonormal basis of the numerical range of Y (an eigen-based
+// CholeskyQR that stays defined when Y is rank deficient).  V: LDS scratch.
+// Returns 1 if the Jacobi sweep cap was reached.
+__device__ inline int block_whiten(double* G, int ld, int n, double* Wh, double* V, double* cs) {
+  const int capped = block_sym_evd(G, ld, V, n, cs);
+  double lmax = 0.0;
+  for (int i = 0; i < n; ++i) lmax = fmax(lmax, G[i * ld + i]);
+  const double cut = 64.0 * 2.220446049250313e-16 * lmax;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int a = e / n, b = e % n;
+    const double lam = G[b * ld + b];
+    Wh[a * ld + b] = (lam > cut && lam > 0.0) ? V[a * ld + b] / sqrt(lam) : 0.0;
   }
   __syncthreads();
-  return bad;
+  return capped;
 }
 
 // Moore-Penrose pseudoinverse of a symmetric positive semidefinite n x n

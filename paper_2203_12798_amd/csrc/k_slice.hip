@@ -1,10 +1,12 @@
 // Per-slice completion of the first-stage randomized SVD (Alg. 1 lines 3-6 for
 // every X_k, Eq. 4), from the FP64 partial sums of the slab pass:
-//   Rc      = chol(Y_k^T Y_k)                      (Y_k = Q_k Rc, Alg. 1 line 3)
-//   B_k     = Rc^{-T} P_k,  P_k = Y_k^T X_k        (= Q_k^T X_k, line 4)
-//   B_k B_k^T = Rc^{-T} (P_k P_k^T) Rc^{-1} = U~ Lambda U~^T   (line 5)
-//   sigma   = sqrt(lambda[:R]),  C_k B_k = B_k^T U~_R = P_k^T Phi_k,
-//   Phi_k   = Rc^{-1} U~_R     (so A_k = Y_k Phi_k = Q_k U~_R, line 6)
+//   Y_k^T Y_k = V Lambda V^T,  Wh = V Lambda^{-1/2}  (Q_k = Y_k Wh, line 3;
+//               directions with negligible lambda are dropped, so a rank-
+//               deficient sketch still yields an orthonormal basis)
+//   B_k     = Q_k^T X_k = Wh^T P_k,  P_k = Y_k^T X_k           (line 4)
+//   B_k B_k^T = Wh^T (P_k P_k^T) Wh = U~ Lambda~ U~^T          (line 5)
+//   sigma   = sqrt(lambda~[:R]),  C_k B_k = B_k^T U~_R = P_k^T Phi_k,
+//   Phi_k   = Wh U~_R          (so A_k = Y_k Phi_k = Q_k U~_R, line 6)
 // Output: block k of M = ||_k C_k B_k, stored as rows kR..kR+R-1 of M^T
 // (R x J), the A_k recipe Phi_k (L x R), sigma_k and ||X_k||^2.
 // Sign gauge: each column of C_k B_k is signed so that its largest-magnitude
@@ -78,27 +80,21 @@ __global__ __launch_bounds__(256) void k_slice_finish(
   }
   __syncthreads();
 
-  // Rc = chol(G) (upper), stored in G
-  const int notpd = block_cholesky_upper(G, LD, L, cs);
-
-  // T = Rc^{-T} S'  (forward substitution, one column per thread)
-  if (tid < L) {
-    const int c = tid;
-    for (int i = 0; i < L; ++i) {
-      double v = S[i * LD + c];
-      for (int p = 0; p < i; ++p) v -= G[p * LD + i] * T[p * LD + c];
-      T[i * LD + c] = v / G[i * LD + i];
-    }
+  // Wh (in T): Y Wh is an orthonormal basis Q of span(Y) (Alg. 1 line 3)
+  const int capped0 = block_whiten(G, LD, L, T, U, cs);
+  // B B^T = Wh^T (P P^T) Wh with B = Q^T X = Wh^T P (Alg. 1 line 4)
+  for (int e = tid; e < L * L; e += 256) {
+    const int a = e / L, b = e % L;
+    double v = 0.0;
+    for (int i = 0; i < L; ++i) v += S[a * LD + i] * T[i * LD + b];
+    G[a * LD + b] = v;
   }
   __syncthreads();
-  // S = T Rc^{-1}  (solve S Rc = T row by row)
-  if (tid < L) {
-    const int a = tid;
-    for (int j = 0; j < L; ++j) {
-      double v = T[a * LD + j];
-      for (int p = 0; p < j; ++p) v -= S[a * LD + p] * G[p * LD + j];
-      S[a * LD + j] = v / G[j * LD + j];
-    }
+  for (int e = tid; e < L * L; e += 256) {
+    const int a = e / L, b = e % L;
+    double v = 0.0;
+    for (int i = 0; i < L; ++i) v += T[i * LD + a] * G[i * LD + b];
+    S[a * LD + b] = v;
   }
   __syncthreads();
   for (int e = tid; e < L * L; e += 256) {
@@ -111,19 +107,20 @@ __global__ __launch_bounds__(256) void k_slice_finish(
   }
   __syncthreads();
 
-  const int capped = block_sym_evd(S, LD, U, L, cs);
+  // B B^T = U~ Lambda U~^T (Alg. 1 line 5)
+  const int capped = block_sym_evd(S, LD, U, L, cs) | capped0;
   block_sort_desc(S, LD, L, perm);
 
-  // Phi = Rc^{-1} U~_R (back substitution, one column per thread)
+  // Phi = Wh U~_R (in G), sigma = sqrt(lambda_R)
+  for (int e = tid; e < L * R; e += 256) {
+    const int l = e / R, r = e % R;
+    double v = 0.0;
+    for (int i = 0; i < L; ++i) v += T[l * LD + i] * U[i * LD + perm[r]];
+    G[l * LD + r] = v;
+  }
   if (tid < R) {
-    const int r = tid, src = perm[r];
-    for (int i = L - 1; i >= 0; --i) {
-      double v = U[i * LD + src];
-      for (int p = i + 1; p < L; ++p) v -= G[i * LD + p] * T[p * LD + r];
-      T[i * LD + r] = v / G[i * LD + i];
-    }
-    const double lam = S[src * LD + src];
-    sig1[(size_t)k * R + r] = sqrt(lam > 0.0 ? lam : 0.0);
+    const double lam = S[perm[tid] * LD + perm[tid]];
+    sig1[(size_t)k * R + tid] = sqrt(lam > 0.0 ? lam : 0.0);
   }
   __syncthreads();
 
@@ -135,7 +132,7 @@ __global__ __launch_bounds__(256) void k_slice_finish(
     for (int l = 0; l < L; ++l) {
       double p = 0.0;
       for (int ii = i0; ii < i1; ++ii) p += partP[(size_t)slice_list[ii] * L * J + (size_t)l * J + j];
-      m += T[l * LD + r] * p;
+      m += G[l * LD + r] * p;
     }
     Mk[(size_t)r * J + j] = m;
   }
@@ -157,11 +154,10 @@ __global__ __launch_bounds__(256) void k_slice_finish(
   }
   for (int e = tid; e < L * R; e += 256) {
     const int l = e / R, r = e % R;
-    Phi[(size_t)k * L * R + e] = (colmax[r] < 0.0) ? -T[l * LD + r] : T[l * LD + r];
+    Phi[(size_t)k * L * R + e] = (colmax[r] < 0.0) ? -G[l * LD + r] : G[l * LD + r];
   }
   if (tid == 0) {
     unsigned bits = 0;
-    if (notpd) bits |= 0x4u;
     if (capped) bits |= 0x1u;
     if (bits) atomicOr(&ctl->warn, bits);
   }

@@ -1,7 +1,7 @@
 // Second-stage compression (Sec. III-B, Eq. 5): randomized SVD (Alg. 1) of
 // M = ||_k C_k B_k (J x KR), held transposed as M^T (KR x J, FP64):
 //   Y2 = M Omega_2                      (J x L2)
-//   Y2 = Q2 R  (CholeskyQR2, FP64)      (Alg. 1 line 3)
+//   Q2 = orthonormal basis of span(Y2)  (Alg. 1 line 3; FP64)
 //   B2 = Q2^T M                         (L2 x KR, stored as B2^T)
 //   B2 B2^T = U2 Lambda U2^T            (Alg. 1 line 5)
 //   D = Q2 U2_R,  E = sqrt(Lambda_R),  F = B2^T U2_R E^{-1}   (KR x R)
@@ -59,13 +59,15 @@ __global__ void k_s2_y_reduce(int64_t n2, int J, int L2, const double* __restric
   Y2[e] = s;
 }
 
-// CholeskyQR2 of Y2 (J x L2, row-major) in place: Y2 <- Q2.
+// Orthonormal basis of span(Y2) in place (Y2 <- Q2), by two whitening passes
+// (eigen-based CholeskyQR2: the second pass restores orthogonality to FP64
+// rounding; dropped directions become zero columns).
 __global__ __launch_bounds__(256) void k_s2_cqr2(int J, int L2, double* __restrict__ Y, Ctl* ctl) {
   constexpr int LD = 33;
-  __shared__ double G[32 * LD], cs[40];
+  __shared__ double G[32 * LD], Wh[32 * LD], V[32 * LD], cs[40];
   const int tid = threadIdx.x;
   const int npairs = L2 * (L2 + 1) / 2;
-  int bad = 0;
+  int capped = 0;
   for (int pass = 0; pass < 2; ++pass) {
     for (int pi = tid; pi < npairs; pi += 256) {
       int a = 0, rem = pi;
@@ -77,21 +79,19 @@ __global__ __launch_bounds__(256) void k_s2_cqr2(int J, int L2, double* __restri
       G[b * LD + a] = s;
     }
     __syncthreads();
-    bad |= block_cholesky_upper(G, LD, L2, cs);
-    // row j: y <- y R^{-1}
+    capped |= block_whiten(G, LD, L2, Wh, V, cs);
     for (int j = tid; j < J; j += 256) {
       double y[32];
       for (int l = 0; l < L2; ++l) y[l] = Y[(size_t)j * L2 + l];
-      for (int l = 0; l < L2; ++l) {
-        double v = y[l];
-        for (int p = 0; p < l; ++p) v -= y[p] * G[p * LD + l];
-        y[l] = v / G[l * LD + l];
+      for (int b = 0; b < L2; ++b) {
+        double v = 0.0;
+        for (int a = 0; a < L2; ++a) v += y[a] * Wh[a * LD + b];
+        Y[(size_t)j * L2 + b] = v;
       }
-      for (int l = 0; l < L2; ++l) Y[(size_t)j * L2 + l] = y[l];
     }
     __syncthreads();
   }
-  if (tid == 0 && bad) atomicOr(&ctl->warn, 0x4u);
+  if (tid == 0 && capped) atomicOr(&ctl->warn, 0x1u);
 }
 
 // B2^T rows of one chunk: B2t[row][l] = sum_j Mt[row][j] Q2[j][l], plus the

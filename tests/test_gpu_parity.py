@@ -2,7 +2,7 @@
 seeded inputs.  Tolerances: factors within 1e-5 relative (up to the sign and
 scale gauges of PARAFAC2), fitness within 1e-4 absolute (tested tighter
 where the arithmetic allows), and the compressed intermediates within the
-FP32 rounding of the slab."""
+FP32 rounding of the sketch."""
 import numpy as np
 import pytest
 
@@ -45,7 +45,10 @@ def _run_gpu(X, R, L, L2, iters, om1, om2, H0, V0, W0, tol=-1.0, want_U=False, t
                 U=None if U is None else U.cpu().numpy())
 
 
-def _check_compression(X, R, g, ref, tol_m=1e-8):
+def _check_compression(X, R, g, ref, tol_m=1e-6):
+    """The sketch Y = X Omega_1 is rounded to FP32 once (by design), which
+    perturbs span(Y) by ~eps32 * sigma_1 / sigma_r relative to the FP64
+    oracle's; products after that are FP64.  Bound: 1e-6 relative."""
     c = ref.comp
     K, J = X.K, X.J
     np.testing.assert_allclose(g["comp"]["xnorm2"], c.xnorm2, rtol=1e-12)
@@ -56,6 +59,16 @@ def _check_compression(X, R, g, ref, tol_m=1e-8):
     s = match_columns(g["comp"]["D"], c.D)
     assert rel(g["comp"]["D"] * s, c.D) < tol_m
     assert rel(g["comp"]["F"] * s, c.F) < tol_m
+
+
+def _check_errors(g, ref):
+    """Per-iteration error e_t of Sec. III-E.  The GPU evaluates it in closed
+    form, e0 - 2 sum W.G3 + sum W (H^T H * V^T V) W^T, whose cancellation
+    leaves an absolute rounding error of a few eps64 * e0; the oracle forms
+    the R x J residuals explicitly."""
+    e_ref = np.asarray(ref.state.errors)
+    e0 = float(np.sum(ref.comp.E ** 2))
+    np.testing.assert_allclose(g["err"], e_ref, rtol=1e-6, atol=1e-12 * e0)
 
 
 def _check_factors(g, ref, tol=1e-5):
@@ -80,7 +93,7 @@ def test_small_parity_end_to_end():
     g = _run_gpu(X, R, L, L, iters, om1, om2, H0, V0, W0, want_U=True)
     _check_compression(X, R, g, ref)
     assert g["rep"]["iters"] == iters
-    np.testing.assert_allclose(g["err"], ref.state.errors, rtol=1e-6)
+    _check_errors(g, ref)
     _check_factors(g, ref)
     assert abs(g["rep"]["fit_true"] - ref.fit) < 1e-7
     Ug = g["U"]
@@ -98,8 +111,8 @@ def test_stock_like_scaled_down():
     H0, V0, W0 = synth.init_factors(X.J, X.K, R)
     ref = O.dpar2(X.slab, X.offsets, R, om1, om2, H0, V0, W0, iters)
     g = _run_gpu(X, R, L, L, iters, om1, om2, H0, V0, W0)
-    _check_compression(X, R, g, ref, tol_m=1e-7)
-    np.testing.assert_allclose(g["err"], ref.state.errors, rtol=1e-6)
+    _check_compression(X, R, g, ref)
+    _check_errors(g, ref)
     _check_factors(g, ref)
     assert abs(g["rep"]["fit_true"] - ref.fit) < 1e-6
 
@@ -126,8 +139,8 @@ def test_ragged_edge_cases(case):
     H0, V0, W0 = synth.init_factors(X.J, X.K, R)
     ref = O.dpar2(X.slab, X.offsets, R, om1, om2, H0, V0, W0, iters)
     g = _run_gpu(X, R, L, L2, iters, om1, om2, H0, V0, W0, want_U=True)
-    _check_compression(X, R, g, ref, tol_m=1e-7)
-    np.testing.assert_allclose(g["err"], ref.state.errors, rtol=1e-6)
+    _check_compression(X, R, g, ref)
+    _check_errors(g, ref)
     _check_factors(g, ref)
     assert abs(g["rep"]["fit_true"] - ref.fit) < 1e-6
     assert rel(g["U"], np.concatenate(ref.U, axis=0)) < 1e-5
@@ -135,7 +148,7 @@ def test_ragged_edge_cases(case):
 
 def test_tolerance_stop_matches_oracle():
     X = synth.small_parity(seed=5)
-    R, L, iters, tol = 5, 15, 200, 1e-4
+    R, L, iters, tol = 5, 15, 200, 5e-3
     om1, om2 = synth.omegas(X.J, L, X.K * R)
     H0, V0, W0 = synth.init_factors(X.J, X.K, R)
     ref = O.dpar2(X.slab, X.offsets, R, om1, om2, H0, V0, W0, iters, tol=tol)
@@ -143,7 +156,7 @@ def test_tolerance_stop_matches_oracle():
     assert ref.state.iters < iters
     assert g["rep"]["iters"] == ref.state.iters
     assert g["rep"]["converged"]
-    np.testing.assert_allclose(g["err"], ref.state.errors, rtol=1e-6)
+    _check_errors(g, ref)
 
 
 def test_resume_is_bitwise_and_deterministic():
@@ -187,4 +200,4 @@ def test_exact_low_rank_reaches_fit_one():
     W0 = X.W * (1 + 0.01 * rng.standard_normal(X.W.shape))
     om1, om2 = synth.omegas(X.J, L, X.K * R)
     g = _run_gpu(X, R, L, L, iters, om1, om2, H0, V0, W0, trace=False)
-    assert 1.0 - g["rep"]["fit_true"] < 1e-10
+    assert 1.0 - g["rep"]["fit_true"] < 1e-10, g["rep"]
