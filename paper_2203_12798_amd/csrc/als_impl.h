@@ -1,0 +1,719 @@
+// Compressed PARAFAC2-ALS iteration (Alg. 3 repeat loop, Secs. III-C..III-E),
+// templated on the rank R so that every R x R loop is unrolled and the
+// column exchanges of the Jacobi rounds are issued back to back.
+//
+// One iteration = six launches:
+//   A     per slice: T_k = F^(k) Bm S_k H^T with Bm = E D^T V (Eq. 8);
+//         one-sided Jacobi SVD T_k = Z_k Sigma_k P_k^T (FP64, warm-started
+//         from the previous P_k); Psi_k = Z_k P_k^T; M_k = P_k Z_k^T F^(k) =
+//         Psi_k^T F^(k) (the factor of Y_k, Sec. III-D); block partial of
+//         G1 = sum_k M_k Bm S_k (Lemma 1)
+//   Aepi  H = G1 (W^T W * V^T V)^dagger, unit columns; H^T H
+//   B     block partial of N = sum_k M_k^T H S_k (Lemma 2: G2 = D E N)
+//   Bepi  V = D E N (W^T W * H^T H)^dagger with unit columns, kept as
+//         V = D VC (VC is R x R; V^T V = VC^T D^T D VC, D^T V = D^T D VC):
+//         the loop never touches a J-long array; Bm = E D^T V;
+//         (V^T V * H^T H)^dagger
+//   C     G3(k,r) = H(:,r)^T M_k Bm(:,r) (Lemma 3); W(k,:) = G3(k,:)
+//         (V^T V * H^T H)^dagger, S_k = diag(W(k,:)); block partials of
+//         W^T W and of e = e0 - 2 sum W.G3 + sum_k W(k,:)(H^T H*V^T V)W(k,:)^T
+//   Cepi  W^T W, e_t of Sec. III-E, stop rule
+// Every kernel returns at once after the stop rule fired.  Per-slice work
+// gives each slice a group of RM lanes, lane j owning column j of the R x R
+// matrices (rows in registers).  Epilogues sum the block partials in a fixed
+// order (bitwise reproducible).
+#pragma once
+
+#include "internal.h"
+
+namespace dpar2 {
+
+constexpr int EPI_THREADS = 1024;
+constexpr double EPS64 = 2.220446049250313e-16;
+// Jacobi pairs are rotated while |a.b| > JACOBI_TOL sqrt(|a|^2 |b|^2): above
+// the rounding floor of an R-term dot product, so converged columns stop.
+constexpr double JACOBI_TOL = 1e-13;
+constexpr int JACOBI_SWEEPS = 30;
+
+struct AlsArgs {
+  int K, J;
+  const double *F, *D, *E;
+  double *H, *V, *W;
+  double *Pw, *Psi, *Mk;
+  double *small, *partA, *partB, *partC, *partBegin;
+  double* trace;
+  double tol;
+  Ctl* ctl;
+};
+
+__host__ __device__ constexpr int pow2ceil(int x) {
+  int p = 1;
+  while (p < x) p *= 2;
+  return p;
+}
+
+template <int R>
+struct RC {
+  static constexpr int N = R + (R & 1);                           // Jacobi players
+  static constexpr int RM = pow2ceil(N) < 2 ? 2 : pow2ceil(N);    // lanes per slice
+  static constexpr int TPB = (R > 16) ? 128 : 256;                // per-slice block
+  static constexpr int GPB = TPB / RM;                            // slices per block
+  static constexpr int RR = R * R;
+};
+
+// One-sided Jacobi (Hestenes) on the R columns held by a group of RM lanes:
+// lane j holds column j of T in t[] and of the accumulated right rotation in
+// v[].  Round-robin pairing; both lanes of a pair compute the same rotation
+// from the same sums.  All lanes of the wave must call it.  Returns sweeps.
+template <int R>
+__device__ inline int group_jacobi(double (&t)[R], double (&v)[R], int j, int gbase) {
+  constexpr int N = RC<R>::N;
+  int sweep;
+  for (sweep = 0; sweep < JACOBI_SWEEPS; ++sweep) {
+    int rotated = 0;
+    for (int r = 0; r < N - 1; ++r) {
+      const int pc = (j < N) ? rr_partner(j, r, N) : j;
+      const int src = gbase + pc;
+      double tp[R], vp[R];
+#pragma unroll
+      for (int i = 0; i < R; ++i) tp[i] = __shfl(t[i], src, 64);
+#pragma unroll
+      for (int i = 0; i < R; ++i) vp[i] = __shfl(v[i], src, 64);
+      double aa = 0.0, bb = 0.0, ab = 0.0;
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        aa = fma(t[i], t[i], aa);
+        bb = fma(tp[i], tp[i], bb);
+        ab = fma(t[i], tp[i], ab);
+      }
+      const bool low = j < pc;
+      const double alpha = low ? aa : bb, beta = low ? bb : aa;
+      if (j < N && pc != j && ab != 0.0 && fabs(ab) > JACOBI_TOL * sqrt(alpha * beta)) {
+        double c, s;
+        jacobi_cs(alpha, beta, ab, &c, &s);
+        rotated = 1;
+        const double sa = low ? -s : s;   // low: c a - s b ; high: s a + c b = c b + s a
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          t[i] = fma(c, t[i], sa * tp[i]);
+          v[i] = fma(c, v[i], sa * vp[i]);
+        }
+      }
+    }
+    if (!__any(rotated)) break;
+  }
+  return sweep;
+}
+
+// Inverse of a symmetric positive definite R x R matrix G (LDS, leading
+// dimension 33) by Gauss-Jordan elimination without pivoting on [G | I], one
+// lane per column (2R <= 64 lanes of wave 0).  Returns false (wave-uniform)
+// when a pivot falls below 1e-13 max_i G_ii, i.e. when G is singular to
+// working accuracy; the caller then takes the eigen-based pseudoinverse.
+template <int R>
+__device__ inline bool wave_spd_inverse(const double* G, double* Ginv) {
+  const int c = threadIdx.x;   // lane of wave 0
+  double col[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+    col[i] = (c < R) ? G[i * 33 + c] : ((c - R == i) ? 1.0 : 0.0);
+  double dmax = 0.0;
+#pragma unroll
+  for (int i = 0; i < R; ++i) dmax = fmax(dmax, G[i * 33 + i]);
+  bool ok = dmax > 0.0;
+#pragma unroll
+  for (int p = 0; p < R; ++p) {
+    double colp[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) colp[i] = __shfl(col[i], p, 64);
+    const double piv = colp[p];
+    ok = ok && (piv > 1e-13 * dmax);
+    const double f = col[p] / piv;
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+      if (i != p) col[i] = fma(-colp[i], f, col[i]);
+    col[p] = f;
+  }
+  if (c >= R && c < 2 * R)
+#pragma unroll
+    for (int i = 0; i < R; ++i) Ginv[i * 33 + (c - R)] = col[i];
+  return ok;
+}
+
+// Moore-Penrose pseudoinverse of a symmetric positive semidefinite R x R
+// matrix G (LDS, ld 33): one-sided Jacobi G P = T (columns t_j = lambda_j
+// p_j), G^dagger = sum_j p_j t_j^T / lambda_j^2 over lambda_j > R eps
+// lambda_max.  Wave 0 runs the Jacobi; sT, sV: LDS 32 x 33; sg: 32 doubles.
+template <int R>
+__device__ inline int jacobi_pinv(const double* G, double* Ginv, double* sT, double* sV, double* sg) {
+  constexpr int RM = RC<R>::RM;
+  int capped = 0;
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x, j = lane % RM, gbase = lane & ~(RM - 1);
+    double t[R], v[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      t[i] = (j < R) ? G[i * 33 + j] : 0.0;
+      v[i] = (i == j) ? 1.0 : 0.0;
+    }
+    capped = group_jacobi<R>(t, v, j, gbase) == JACOBI_SWEEPS;
+    double s2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) s2 = fma(t[i], t[i], s2);
+    if (lane < RM && j < R) {
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        sT[i * 33 + j] = t[i];
+        sV[i * 33 + j] = v[i];
+      }
+      sg[j] = sqrt(s2);
+    }
+  }
+  __syncthreads();
+  double smax = 0.0;
+  for (int i = 0; i < R; ++i) smax = fmax(smax, sg[i]);
+  const double cut = (double)R * EPS64 * smax;
+  for (int e = threadIdx.x; e < R * R; e += blockDim.x) {
+    const int a = e / R, b = e % R;
+    double s = 0.0;
+    for (int i = 0; i < R; ++i) {
+      const double l = sg[i];
+      if (l > cut) s += sV[a * 33 + i] * sT[b * 33 + i] / (l * l);
+    }
+    Ginv[a * 33 + b] = s;
+  }
+  __syncthreads();
+  return capped;
+}
+
+// Pseudoinverse of an SPD/PSD R x R LDS matrix: Gauss-Jordan when G is
+// nonsingular to working accuracy (then G^dagger = G^{-1}), else Jacobi.
+// Block-cooperative; returns 1 if a Jacobi fallback hit its sweep cap.
+template <int R>
+__device__ inline int block_pinv(const double* G, double* Ginv, double* sT, double* sV, double* sg,
+                                 int* sflag) {
+  if (threadIdx.x < 64) {
+    const bool ok = wave_spd_inverse<R>(G, Ginv);
+    if (threadIdx.x == 0) *sflag = ok ? 1 : 0;
+  }
+  __syncthreads();
+  if (*sflag) return 0;
+  return jacobi_pinv<R>(G, Ginv, sT, sV, sg);
+}
+
+// out[e] = sum_b part[b * stride + e] for e < width, summed in a fixed order
+// by teams of T lanes (T a power of two, team inside one wave).
+__device__ inline void team_sum(const double* __restrict__ part, int nb, int stride, int width, double* out) {
+  int T = 1;
+  while (T < 64 && 2 * T * width <= (int)blockDim.x) T *= 2;
+  const int team = threadIdx.x / T, sub = threadIdx.x % T;
+  const int nteam = blockDim.x / T;
+  for (int e = team; e < width; e += nteam) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int b = sub;
+    for (; b + 3 * T < nb; b += 4 * T) {
+      s0 += part[(size_t)b * stride + e];
+      s1 += part[(size_t)(b + T) * stride + e];
+      s2 += part[(size_t)(b + 2 * T) * stride + e];
+      s3 += part[(size_t)(b + 3 * T) * stride + e];
+    }
+    for (; b < nb; b += T) s0 += part[(size_t)b * stride + e];
+    double s = (s0 + s1) + (s2 + s3);
+    for (int o = T / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (sub == 0) out[e] = s;
+  }
+  __syncthreads();
+}
+
+// Group-column accumulators acc[] (lane j: column j) summed over the groups
+// of the block into an R x R partial at `out` (global).
+template <int R>
+__device__ inline void block_partial_out(const double (&acc)[R], double* sred, double* out) {
+  constexpr int RM = RC<R>::RM, GPB = RC<R>::GPB, TPB = RC<R>::TPB;
+  const int g = threadIdx.x / RM, j = threadIdx.x % RM;
+  __syncthreads();
+  if (j < R)
+#pragma unroll
+    for (int a = 0; a < R; ++a) sred[g * R * R + a * R + j] = acc[a];
+  __syncthreads();
+  for (int e = threadIdx.x; e < R * R; e += TPB) {
+    double s = 0.0;
+    for (int gg = 0; gg < GPB; ++gg) s += sred[gg * R * R + e];
+    out[e] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// A: Q-step (Eq. 8), implicit Y_k, Lemma 1 partial
+// ---------------------------------------------------------------------------
+template <int R>
+__global__ __launch_bounds__(RC<R>::TPB) void k_als_A(AlsArgs a) {
+  Ctl* ctl = a.ctl;
+  if (ctl->done) return;
+  constexpr int RM = RC<R>::RM, GPB = RC<R>::GPB, TPB = RC<R>::TPB, RR = R * R;
+  __shared__ double sH[RR], sB[RR];
+  __shared__ double sF[GPB * RR], sZ[GPB * RR], sP[GPB * RR];
+  const int K = a.K;
+  const int tid = threadIdx.x, g = tid / RM, j = tid % RM;
+  const int lane = tid & 63, gbase = lane & ~(RM - 1);
+  const double* Bm = a.small + SM_BM * RR;
+  for (int e = tid; e < RR; e += TPB) {
+    sH[e] = a.H[e];
+    sB[e] = Bm[e];
+  }
+  double* F_ = sF + g * RR;
+  double* Z_ = sZ + g * RR;
+  double* P_ = sP + g * RR;
+  double acc[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) acc[i] = 0.0;
+  unsigned warn = 0;
+  for (int64_t base = (int64_t)blockIdx.x * GPB; base < K; base += (int64_t)gridDim.x * GPB) {
+    const int64_t k = base + g;
+    const bool live = (k < K) && (j < R);
+    __syncthreads();
+    if (k < K)
+      for (int e = j; e < RR; e += RM) F_[e] = a.F[(size_t)k * RR + e];
+    __syncthreads();
+    double t[R], v[R], wk[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      wk[i] = (k < K) ? a.W[(size_t)k * R + i] : 0.0;
+      v[i] = live ? a.Pw[(size_t)k * RR + i * R + j] : 0.0;
+    }
+    // t = F^(k) Bm diag(W_k) H^T p_j  (column j of T_k P_k)
+    {
+      double u[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) s = fma(sH[i * R + q], v[i], s);
+        u[q] = s * wk[q];
+      }
+      double x[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) s = fma(sB[q * R + i], u[i], s);
+        x[q] = s;
+      }
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) s = fma(F_[q * R + i], x[i], s);
+        t[q] = live ? s : 0.0;
+      }
+    }
+    if (group_jacobi<R>(t, v, j, gbase) == JACOBI_SWEEPS) warn |= 0x1u;
+    double sig = 0.0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) sig = fma(t[i], t[i], sig);
+    sig = sqrt(sig);
+    double smax = sig;
+    for (int o = 1; o < RM; o <<= 1) smax = fmax(smax, __shfl_xor(smax, o, 64));
+    if (live && !(sig > 1e-14 * smax)) warn |= 0x2u;
+    const double inv = (sig > 0.0) ? 1.0 / sig : 0.0;
+    if (live) {
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        Z_[i * R + j] = t[i] * inv;
+        P_[i * R + j] = v[i];
+        a.Pw[(size_t)k * RR + i * R + j] = v[i];
+      }
+    }
+    __syncthreads();
+    // Psi column j: Psi[q][j] = sum_c Z[q][c] P[j][c]
+    double psi[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      double s = 0.0;
+      if (j < R)
+#pragma unroll
+        for (int c = 0; c < R; ++c) s = fma(Z_[q * R + c], P_[j * R + c], s);
+      psi[q] = s;
+    }
+    __syncthreads();
+    if (live) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        P_[q * R + j] = psi[q];
+        a.Psi[(size_t)k * RR + q * R + j] = psi[q];
+      }
+    }
+    __syncthreads();
+    // M_k column j = Psi^T F^(k)(:, j)
+    if (live) {
+      double mcol[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) s = fma(P_[i * R + q], F_[i * R + j], s);
+        mcol[q] = s;
+      }
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        Z_[q * R + j] = mcol[q];
+        a.Mk[(size_t)k * RR + q * R + j] = mcol[q];
+      }
+    }
+    __syncthreads();
+    // G1 partial, column j: W(k,j) * M_k Bm(:, j)
+    if (live) {
+      double wj = 0.0;
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+        if (i == j) wj = wk[i];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) s = fma(Z_[q * R + i], sB[i * R + j], s);
+        acc[q] = fma(wj, s, acc[q]);
+      }
+    }
+  }
+  for (int o = 1; o < 64; o <<= 1) warn |= __shfl_xor((int)warn, o, 64);
+  if (lane == 0 && warn) atomicOr(&ctl->warn, warn);
+  block_partial_out<R>(acc, sZ, a.partA + (size_t)blockIdx.x * RR);
+}
+
+// H = G1 (W^T W * V^T V)^dagger, unit columns; H^T H.
+template <int R>
+__global__ __launch_bounds__(EPI_THREADS) void k_als_A_epi(AlsArgs a, int nblk) {
+  Ctl* ctl = a.ctl;
+  if (ctl->done) return;
+  constexpr int LD = 33, RR = R * R;
+  __shared__ double G1[32 * LD], Gm[32 * LD], Gi[32 * LD], sT[32 * LD], sV[32 * LD], sg[32], tmp[RR];
+  __shared__ int sflag;
+  const int tid = threadIdx.x;
+  team_sum(a.partA, nblk, RR, RR, tmp);
+  const double* WtW = a.small + SM_WTW * RR;
+  const double* VtV = a.small + SM_VTV * RR;
+  for (int e = tid; e < RR; e += EPI_THREADS) {
+    G1[(e / R) * LD + e % R] = tmp[e];
+    Gm[(e / R) * LD + e % R] = WtW[e] * VtV[e];
+  }
+  __syncthreads();
+  const int capped = block_pinv<R>(Gm, Gi, sT, sV, sg, &sflag);
+  for (int e = tid; e < RR; e += EPI_THREADS) {      // raw H = G1 Gi
+    const int q = e / R, c = e % R;
+    double s = 0.0;
+    for (int i = 0; i < R; ++i) s = fma(G1[q * LD + i], Gi[i * LD + c], s);
+    sT[q * LD + c] = s;
+  }
+  __syncthreads();
+  if (tid < R) {
+    double s = 0.0;
+    for (int q = 0; q < R; ++q) s = fma(sT[q * LD + tid], sT[q * LD + tid], s);
+    s = sqrt(s);
+    sg[tid] = (s < 1e-300) ? 1.0 : s;
+  }
+  __syncthreads();
+  for (int e = tid; e < RR; e += EPI_THREADS) {
+    const int q = e / R, c = e % R;
+    const double h = sT[q * LD + c] / sg[c];
+    a.H[e] = h;
+    G1[q * LD + c] = h;
+  }
+  __syncthreads();
+  double* HtH = a.small + SM_HTH * RR;
+  for (int e = tid; e < RR; e += EPI_THREADS) {
+    const int q = e / R, c = e % R;
+    double s = 0.0;
+    for (int i = 0; i < R; ++i) s = fma(G1[i * LD + q], G1[i * LD + c], s);
+    HtH[e] = s;
+  }
+  if (tid == 0 && capped) atomicOr(&ctl->warn, 0x1u);
+}
+
+// ---------------------------------------------------------------------------
+// B: Lemma 2 partials
+// ---------------------------------------------------------------------------
+template <int R>
+__global__ __launch_bounds__(RC<R>::TPB) void k_als_B(AlsArgs a) {
+  Ctl* ctl = a.ctl;
+  if (ctl->done) return;
+  constexpr int RM = RC<R>::RM, GPB = RC<R>::GPB, TPB = RC<R>::TPB, RR = R * R;
+  __shared__ double sH[RR];
+  __shared__ double sM[GPB * RR];
+  const int K = a.K;
+  const int tid = threadIdx.x, g = tid / RM, j = tid % RM;
+  for (int e = tid; e < RR; e += TPB) sH[e] = a.H[e];
+  double* M_ = sM + g * RR;
+  double acc[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) acc[q] = 0.0;
+  for (int64_t base = (int64_t)blockIdx.x * GPB; base < K; base += (int64_t)gridDim.x * GPB) {
+    const int64_t k = base + g;
+    __syncthreads();
+    if (k < K)
+      for (int e = j; e < RR; e += RM) M_[e] = a.Mk[(size_t)k * RR + e];
+    __syncthreads();
+    if (k < K && j < R) {
+      const double wj = a.W[(size_t)k * R + j];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) s = fma(M_[i * R + q], sH[i * R + j], s);
+        acc[q] = fma(wj, s, acc[q]);
+      }
+    }
+  }
+  block_partial_out<R>(acc, sM, a.partB + (size_t)blockIdx.x * RR);
+}
+
+// V = D E N (W^T W * H^T H)^dagger with unit columns, held as V = D VC;
+// V^T V, Bm = E D^T V, H^T H * V^T V, (V^T V * H^T H)^dagger.
+template <int R>
+__global__ __launch_bounds__(EPI_THREADS) void k_als_B_epi(AlsArgs a, int nblk) {
+  Ctl* ctl = a.ctl;
+  if (ctl->done) return;
+  constexpr int LD = 33, RR = R * R;
+  __shared__ double N[32 * LD], Gm[32 * LD], Gi[32 * LD], sT[32 * LD], sV[32 * LD], sg[32], tmp[RR];
+  __shared__ int sflag;
+  const int tid = threadIdx.x;
+  double* small = a.small;
+  team_sum(a.partB, nblk, RR, RR, tmp);
+  const double* WtW = small + SM_WTW * RR;
+  const double* HtH = small + SM_HTH * RR;
+  const double* DtD = small + SM_DTD * RR;
+  for (int e = tid; e < RR; e += EPI_THREADS) {
+    N[(e / R) * LD + e % R] = tmp[e];
+    Gm[(e / R) * LD + e % R] = WtW[e] * HtH[e];
+  }
+  __syncthreads();
+  int capped = block_pinv<R>(Gm, Gi, sT, sV, sg, &sflag);
+  // VC = diag(E) N Gi  (V = D VC before normalisation)
+  for (int e = tid; e < RR; e += EPI_THREADS) {
+    const int q = e / R, c = e % R;
+    double s = 0.0;
+    for (int i = 0; i < R; ++i) s = fma(N[q * LD + i], Gi[i * LD + c], s);
+    Gm[q * LD + c] = a.E[q] * s;
+  }
+  __syncthreads();
+  for (int e = tid; e < RR; e += EPI_THREADS) {            // sT <- (D^T D) VC
+    const int q = e / R, c = e % R;
+    double s = 0.0;
+    for (int i = 0; i < R; ++i) s = fma(DtD[q * R + i], Gm[i * LD + c], s);
+    sT[q * LD + c] = s;
+  }
+  __syncthreads();
+  if (tid < R) {                                            // column norms of V
+    double s = 0.0;
+    for (int i = 0; i < R; ++i) s = fma(Gm[i * LD + tid], sT[i * LD + tid], s);
+    s = sqrt(s > 0.0 ? s : 0.0);
+    sg[tid] = (s < 1e-300) ? 1.0 : s;
+  }
+  __syncthreads();
+  for (int e = tid; e < RR; e += EPI_THREADS) {
+    const int q = e / R, c = e % R;
+    Gm[q * LD + c] /= sg[c];
+    sT[q * LD + c] /= sg[c];
+  }
+  __syncthreads();
+  double* VtV = small + SM_VTV * RR;
+  double* Bm = small + SM_BM * RR;
+  double* HV = small + SM_HV * RR;
+  double* VC = small + SM_VC * RR;
+  for (int e = tid; e < RR; e += EPI_THREADS) {
+    const int q = e / R, c = e % R;
+    double s = 0.0;
+    for (int i = 0; i < R; ++i) s = fma(Gm[i * LD + q], sT[i * LD + c], s);   // VC^T (D^T D) VC
+    VtV[e] = s;
+    Bm[e] = a.E[q] * sT[q * LD + c];                                           // E D^T V
+    HV[e] = s * HtH[e];
+    VC[e] = Gm[q * LD + c];
+    N[q * LD + c] = s * HtH[e];
+  }
+  __syncthreads();
+  capped |= block_pinv<R>(N, Gi, sT, sV, sg, &sflag);
+  for (int e = tid; e < RR; e += EPI_THREADS) small[SM_G3INV * RR + e] = Gi[(e / R) * LD + e % R];
+  if (tid == 0) {
+    ctl->vc_valid = 1;
+    if (capped) atomicOr(&ctl->warn, 0x1u);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// C: Lemma 3, W rows, error partials
+// ---------------------------------------------------------------------------
+template <int R>
+__global__ __launch_bounds__(RC<R>::TPB) void k_als_C(AlsArgs a) {
+  Ctl* ctl = a.ctl;
+  if (ctl->done) return;
+  constexpr int RM = RC<R>::RM, GPB = RC<R>::GPB, TPB = RC<R>::TPB, RR = R * R;
+  __shared__ double sH[RR], sB[RR], sGi[RR], sHV[RR];
+  __shared__ double sM[GPB * RR];
+  __shared__ double sRed[TPB * 2];
+  const int K = a.K;
+  const int tid = threadIdx.x, g = tid / RM, j = tid % RM;
+  const int lane = tid & 63, gbase = lane & ~(RM - 1);
+  for (int e = tid; e < RR; e += TPB) {
+    sH[e] = a.H[e];
+    sB[e] = a.small[SM_BM * RR + e];
+    sGi[e] = a.small[SM_G3INV * RR + e];
+    sHV[e] = a.small[SM_HV * RR + e];
+  }
+  double* M_ = sM + g * RR;
+  double wtw[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) wtw[q] = 0.0;
+  double ewg = 0.0, equad = 0.0;
+  for (int64_t base = (int64_t)blockIdx.x * GPB; base < K; base += (int64_t)gridDim.x * GPB) {
+    const int64_t k = base + g;
+    const bool live = (k < K) && (j < R);
+    __syncthreads();
+    if (k < K)
+      for (int e = j; e < RR; e += RM) M_[e] = a.Mk[(size_t)k * RR + e];
+    __syncthreads();
+    double g3 = 0.0;
+    if (live) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) s = fma(M_[q * R + i], sB[i * R + j], s);
+        g3 = fma(sH[q * R + j], s, g3);
+      }
+    }
+    double gs[R];
+#pragma unroll
+    for (int s = 0; s < R; ++s) gs[s] = __shfl(g3, gbase + s, 64);
+    double wnew = 0.0;
+    if (live) {
+#pragma unroll
+      for (int s = 0; s < R; ++s) wnew = fma(gs[s], sGi[s * R + j], wnew);
+      a.W[(size_t)k * R + j] = wnew;
+      ewg = fma(wnew, g3, ewg);
+    }
+    double ws[R];
+#pragma unroll
+    for (int s = 0; s < R; ++s) ws[s] = __shfl(wnew, gbase + s, 64);
+    if (live) {
+      double q2 = 0.0;
+#pragma unroll
+      for (int s = 0; s < R; ++s) {
+        q2 = fma(sHV[j * R + s], ws[s], q2);
+        wtw[s] = fma(ws[s], wnew, wtw[s]);
+      }
+      equad = fma(wnew, q2, equad);
+    }
+  }
+  __syncthreads();
+  if (j < R)
+#pragma unroll
+    for (int q = 0; q < R; ++q) sM[g * RR + q * R + j] = wtw[q];
+  sRed[tid * 2] = ewg;
+  sRed[tid * 2 + 1] = equad;
+  __syncthreads();
+  double* out = a.partC + (size_t)blockIdx.x * (RR + 2);
+  for (int e = tid; e < RR; e += TPB) {
+    double s = 0.0;
+    for (int gg = 0; gg < GPB; ++gg) s += sM[gg * RR + e];
+    out[e] = s;
+  }
+  if (tid < 2) {
+    double s = 0.0;
+    for (int i = 0; i < TPB; ++i) s += sRed[i * 2 + tid];
+    out[RR + tid] = s;
+  }
+}
+
+// W^T W, e_t = e0 - 2 sum W.G3 + sum W (H^T H * V^T V) W^T, stop rule.
+template <int R>
+__global__ __launch_bounds__(EPI_THREADS) void k_als_C_epi(AlsArgs a, int nblk) {
+  Ctl* ctl = a.ctl;
+  if (ctl->done) return;
+  constexpr int RR = R * R;
+  __shared__ double tmp[RR + 2];
+  team_sum(a.partC, nblk, RR + 2, RR + 2, tmp);
+  for (int e = threadIdx.x; e < RR; e += EPI_THREADS) a.small[SM_WTW * RR + e] = tmp[e];
+  if (threadIdx.x == 0) {
+    const double e = ctl->e0 - 2.0 * tmp[RR] + tmp[RR + 1];
+    if (a.trace) a.trace[ctl->iters - ctl->base] = e;
+    ctl->iters += 1;
+    if (a.tol >= 0.0 && ctl->iters >= 2 && ctl->e_prev - e < a.tol * ctl->e_prev) ctl->done = 1;
+    ctl->e_prev = e;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Begin of a call: W^T W, V^T V and E D^T V of the factors given
+// ---------------------------------------------------------------------------
+template <int R>
+__global__ __launch_bounds__(RC<R>::TPB) void k_als_begin(AlsArgs a) {
+  constexpr int RM = RC<R>::RM, GPB = RC<R>::GPB, RR = R * R;
+  __shared__ double sM[GPB * RR];
+  const int K = a.K, J = a.J;
+  const int tid = threadIdx.x, g = tid / RM, j = tid % RM;
+  const int lane = tid & 63, gbase = lane & ~(RM - 1);
+  double acc0[R], acc1[R], acc2[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) acc0[q] = acc1[q] = acc2[q] = 0.0;
+  const int64_t rows = (K > J) ? K : J;
+  for (int64_t base = (int64_t)blockIdx.x * GPB; base < rows; base += (int64_t)gridDim.x * GPB) {
+    const int64_t k = base + g;
+    const double w = (k < K && j < R) ? a.W[(size_t)k * R + j] : 0.0;
+    const double v = (k < J && j < R) ? a.V[(size_t)k * R + j] : 0.0;
+    const double d = (k < J && j < R) ? a.D[(size_t)k * R + j] : 0.0;
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+      const double ws = __shfl(w, gbase + s, 64);
+      const double vs = __shfl(v, gbase + s, 64);
+      const double ds = __shfl(d, gbase + s, 64);
+      acc0[s] = fma(ws, w, acc0[s]);   // (W^T W)[s][j]
+      acc1[s] = fma(vs, v, acc1[s]);   // (V^T V)[s][j]
+      acc2[s] = fma(ds, v, acc2[s]);   // (D^T V)[s][j]
+    }
+  }
+  double* out = a.partBegin + (size_t)blockIdx.x * 3 * RR;
+  block_partial_out<R>(acc0, sM, out);
+  block_partial_out<R>(acc1, sM, out + RR);
+  block_partial_out<R>(acc2, sM, out + 2 * RR);
+}
+
+template <int R>
+__global__ __launch_bounds__(EPI_THREADS) void k_als_begin_epi(AlsArgs a, int nblk) {
+  Ctl* ctl = a.ctl;
+  constexpr int RR = R * R;
+  __shared__ double tmp[3 * RR];
+  team_sum(a.partBegin, nblk, 3 * RR, 3 * RR, tmp);
+  for (int e = threadIdx.x; e < RR; e += EPI_THREADS) {
+    a.small[SM_WTW * RR + e] = tmp[e];
+    a.small[SM_VTV * RR + e] = tmp[RR + e];
+    a.small[SM_BM * RR + e] = a.E[e / R] * tmp[2 * RR + e];
+  }
+  if (threadIdx.x == 0) {
+    ctl->base = ctl->iters;
+    ctl->vc_valid = 0;
+  }
+}
+
+// Launches of one rank's kernels: phase 0 = begin (+epi), 1 = one iteration.
+template <int R>
+hipError_t als_launch(int phase, const AlsArgs& a, hipStream_t s) {
+  constexpr int TPB = RC<R>::TPB, GPB = RC<R>::GPB;
+  int64_t nb = ((int64_t)(phase == 0 ? ((a.K > a.J) ? a.K : a.J) : a.K) + GPB - 1) / GPB;
+  if (nb > RED_MAXBLK) nb = RED_MAXBLK;
+  if (nb < 1) nb = 1;
+  const int n = (int)nb;
+  if (phase == 0) {
+    hipLaunchKernelGGL(k_als_begin<R>, dim3(n), dim3(TPB), 0, s, a);
+    hipLaunchKernelGGL(k_als_begin_epi<R>, dim3(1), dim3(EPI_THREADS), 0, s, a, n);
+  } else {
+    hipLaunchKernelGGL(k_als_A<R>, dim3(n), dim3(TPB), 0, s, a);
+    hipLaunchKernelGGL(k_als_A_epi<R>, dim3(1), dim3(EPI_THREADS), 0, s, a, n);
+    hipLaunchKernelGGL(k_als_B<R>, dim3(n), dim3(TPB), 0, s, a);
+    hipLaunchKernelGGL(k_als_B_epi<R>, dim3(1), dim3(EPI_THREADS), 0, s, a, n);
+    hipLaunchKernelGGL(k_als_C<R>, dim3(n), dim3(TPB), 0, s, a);
+    hipLaunchKernelGGL(k_als_C_epi<R>, dim3(1), dim3(EPI_THREADS), 0, s, a, n);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace dpar2

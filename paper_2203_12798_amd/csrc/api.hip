@@ -120,7 +120,7 @@ Layout make_layout(const dpar2_tensor* X, const dpar2_opts* o) {
   y.n_items = count_items(X->row_offsets_host, X->K);
   const int64_t K = y.K, J = y.J, R = y.R, L = y.L, L2 = y.L2, KR = K * R, RR = R * R;
   y.n2 = (KR + STAGE2_CHUNK - 1) / STAGE2_CHUNK;
-  y.nblkA = y.nblkB = y.nblkC = als_blocks(K, (int)R);
+  y.nblkA = y.nblkB = y.nblkC = als_blocks(K > J ? K : J, (int)R);
   y.nblkF = (int)std::min<int64_t>(K, 1024);
   const int64_t nbf = (KR + 255) / 256;
   size_t p = 0;
@@ -156,6 +156,8 @@ Layout make_layout(const dpar2_tensor* X, const dpar2_opts* o) {
   y.partA = take(sizeof(double) * (size_t)(y.nblkA * RR));
   y.partB = take(sizeof(double) * (size_t)(y.nblkB * RR));
   y.partC = take(sizeof(double) * (size_t)(y.nblkC * (RR + 2)));
+  y.partBegin = take(sizeof(double) * (size_t)(y.nblkC * 3 * RR));
+
   y.fitp = take(sizeof(double) * (size_t)(2 * y.nblkF));
   y.trace = take(sizeof(double) * (size_t)(K * L * R));   // Theta for the U output
   y.om1 = take(sizeof(float) * (size_t)(J * L));           // copy of Omega_1 for the U pass
@@ -312,13 +314,13 @@ dpar2_status dpar2_als_step(const dpar2_tensor* X, const dpar2_opts* o, dpar2_fa
   if ((st = check_ws(y, ws, ws_bytes)) != DPAR2_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
-  hipError_t e = launch_als_begin(y, w, f->W, s);
+  hipError_t e = launch_als_begin(y, w, f->H, f->V, f->W, s);
   if (e != hipSuccess) return hip_fail(e, "iteration begin");
   for (int32_t t = 0; t < n_steps; ++t) {
     e = launch_als_iteration(y, w, f->H, f->V, f->W, err_trace, o->tol, s);
     if (e != hipSuccess) return hip_fail(e, "iteration");
   }
-  e = launch_als_finalize(y, w, err_trace, o->tol, s);
+  e = launch_als_end(y, w, f->V, s);
   if (e != hipSuccess) return hip_fail(e, "iteration end");
   return DPAR2_OK;
 }

@@ -31,16 +31,15 @@ __device__ __forceinline__ int f64_row(int lane, int v) { return (lane >> 4) + 4
 // ---------------------------------------------------------------------------
 struct Ctl {
   int32_t iters;        // iterations whose error is recorded
-  int32_t pending;      // phase-C partials of an unrecorded iteration exist
   int32_t done;         // stop rule fired: later iterations are no-ops
   int32_t base;         // value of `iters` when the current als_step call began
   uint32_t warn;        // DPAR2_WARN_* bits
+  int32_t vc_valid;     // V is held as D VC (V not yet written back)
   int32_t pad0;
   double e_prev;        // last recorded error
   double e0;            // sum_k ||F^(k) E D^T||_F^2 (constant part of e)
   double xnorm2;        // sum_k ||X_k||_F^2
   double fit_true;
-  double pad1[2];
 };
 
 // ---------------------------------------------------------------------------
@@ -83,8 +82,11 @@ __device__ __forceinline__ void jacobi_cs(double app, double aqq, double apq, do
 // ---------------------------------------------------------------------------
 
 // Symmetric eigen-decomposition by cyclic Jacobi with parallel (round-robin)
-// ordering.  On return A's diagonal holds the eigenvalues, V (n x n) the
-// eigenvectors as columns.  cs: LDS scratch of >= 2*16+2 doubles.
+// ordering.  A pair is rotated while |a_pq| > 1e-14 sqrt(|a_pp a_qq|) (a
+// relative threshold above the rounding floor, which keeps the small
+// eigenvalues of a Gram matrix relatively accurate); the sweeps stop after
+// one without rotations.  On return A's diagonal holds the eigenvalues, V
+// (n x n) the eigenvectors as columns.  cs: LDS scratch of >= 2*16+2 doubles.
 // Returns 1 if the sweep cap was reached.
 __device__ inline int block_sym_evd(double* A, int ld, double* V, int n, double* cs) {
   const int tid = threadIdx.x;
@@ -95,21 +97,11 @@ __device__ inline int block_sym_evd(double* A, int ld, double* V, int n, double*
   const int ne = n + (n & 1);        // players (one dummy when n is odd)
   const int npair = ne / 2;
   const int max_sweeps = 40;
-  int sweep = 0;
   int capped = 1;
   double* flag = cs + 2 * 16;
-  for (sweep = 0; sweep < max_sweeps; ++sweep) {
-    // convergence: off-diagonal mass relative to the diagonal
-    if (tid == 0) {
-      double off = 0.0, dia = 0.0;
-      for (int i = 0; i < n; ++i) {
-        dia += A[i * ld + i] * A[i * ld + i];
-        for (int j = i + 1; j < n; ++j) off += A[i * ld + j] * A[i * ld + j];
-      }
-      flag[0] = (off <= 1e-32 * dia || off == 0.0) ? 1.0 : 0.0;
-    }
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    if (tid == 0) flag[0] = 0.0;
     __syncthreads();
-    if (flag[0] != 0.0) { capped = 0; break; }
     for (int r = 0; r < ne - 1; ++r) {
       if (tid < npair) {
         int p, q;
@@ -118,7 +110,10 @@ __device__ inline int block_sym_evd(double* A, int ld, double* V, int n, double*
         if (q < n) {
           const double apq = A[p * ld + q];
           const double app = A[p * ld + p], aqq = A[q * ld + q];
-          if (apq != 0.0 && fabs(apq) > 1e-300) jacobi_cs(app, aqq, apq, &c, &s);
+          if (apq != 0.0 && fabs(apq) > 1e-14 * sqrt(fabs(app * aqq))) {
+            jacobi_cs(app, aqq, apq, &c, &s);
+            flag[0] = 1.0;
+          }
         }
         cs[2 * tid] = c;
         cs[2 * tid + 1] = s;
@@ -129,7 +124,7 @@ __device__ inline int block_sym_evd(double* A, int ld, double* V, int n, double*
         const int i = e / n, m = e % n;
         int p, q;
         rr_pair(i, r, ne, &p, &q);
-        if (q < n) {
+        if (q < n && cs[2 * i + 1] != 0.0) {
           const double c = cs[2 * i], s = cs[2 * i + 1];
           const double ap = A[p * ld + m], aq = A[q * ld + m];
           A[p * ld + m] = c * ap - s * aq;
@@ -142,7 +137,7 @@ __device__ inline int block_sym_evd(double* A, int ld, double* V, int n, double*
         const int i = e / n, m = e % n;
         int p, q;
         rr_pair(i, r, ne, &p, &q);
-        if (q < n) {
+        if (q < n && cs[2 * i + 1] != 0.0) {
           const double c = cs[2 * i], s = cs[2 * i + 1];
           const double ap = A[m * ld + p], aq = A[m * ld + q];
           A[m * ld + p] = c * ap - s * aq;
@@ -154,6 +149,11 @@ __device__ inline int block_sym_evd(double* A, int ld, double* V, int n, double*
       }
       __syncthreads();
     }
+    if (flag[0] == 0.0) {
+      capped = 0;
+      break;
+    }
+    __syncthreads();
   }
   __syncthreads();
   return capped;

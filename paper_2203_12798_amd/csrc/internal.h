@@ -35,7 +35,7 @@ struct Layout {
   size_t xnorm2, Mt, Phi, sig1;
   size_t Y2p, Y2, B2t, S2p, U2;
   size_t D, E, F, FtFp;
-  size_t Psi, Pw, Mk, small, partA, partB, partC, fitp, trace, om1;
+  size_t Psi, Pw, Mk, small, partA, partB, partC, partBegin, fitp, trace, om1;
   size_t total;
 };
 
@@ -50,9 +50,11 @@ enum SmallSlot {
   SM_HV,         // H^T H * V^T V
   SM_DTD,        // D^T D
   SM_FTF,        // F^T F
-  SM_SCR0, SM_SCR1, SM_SCR2,
+  SM_VC,         // V = D VC after a V update (R x R coordinates of V)
   SM_COUNT
 };
+
+constexpr int RED_MAXBLK = 1024;         // grid size cap of the per-slice kernels
 
 // --- launchers (each returns the hipGetLastError() of its launches) ---------
 hipError_t launch_sketch(const float* slab, int J, int L, const float* omega1,
@@ -66,17 +68,16 @@ hipError_t launch_slice_finish(int64_t K, int J, int L, int R, const int32_t* sl
                                const double* partP, const double* partS, double* xnorm2,
                                double* Mt, double* Phi, double* sig1, Ctl* ctl, hipStream_t s);
 hipError_t launch_stage2(const Layout& lay, char* ws, const float* omega2, hipStream_t s);
-hipError_t launch_als_begin(const Layout& lay, char* ws, const double* W, hipStream_t s);
+hipError_t launch_als_begin(const Layout& lay, char* ws, double* H, double* V, double* W, hipStream_t s);
 hipError_t launch_als_iteration(const Layout& lay, char* ws, double* H, double* V, double* W,
                                 double* err_trace, double tol, hipStream_t s);
-hipError_t launch_als_finalize(const Layout& lay, char* ws, double* err_trace, double tol,
-                               hipStream_t s);
 hipError_t launch_fitness(const Layout& lay, char* ws, const double* H, const double* V,
                           const double* W, double* fit, hipStream_t s);
 hipError_t launch_theta(const Layout& lay, char* ws, const double* H, double* theta,
                         hipStream_t s);
 
 hipError_t launch_pw_identity(const Layout& lay, char* ws, hipStream_t s);
+hipError_t launch_als_end(const Layout& lay, char* ws, double* V, hipStream_t s);
 int als_blocks(int64_t K, int R);
 
 bool sketch_supported(int J, int L);

@@ -1,0 +1,20 @@
+// Rank instantiations 25..32 of the compressed ALS kernels (als_impl.h).
+#include "als_impl.h"
+
+namespace dpar2 {
+
+hipError_t als_dispatch_4(int R, int phase, const AlsArgs& a, hipStream_t s) {
+  switch (R) {
+    case 25: return als_launch<25>(phase, a, s);
+    case 26: return als_launch<26>(phase, a, s);
+    case 27: return als_launch<27>(phase, a, s);
+    case 28: return als_launch<28>(phase, a, s);
+    case 29: return als_launch<29>(phase, a, s);
+    case 30: return als_launch<30>(phase, a, s);
+    case 31: return als_launch<31>(phase, a, s);
+    case 32: return als_launch<32>(phase, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace dpar2
