@@ -2,11 +2,11 @@
 //
 // One pass over the slab computes, for every work item (a row range of one
 // slice), the pieces of the randomized SVD that need the slab:
-//   Y   = X Omega_1                (sketch, Alg. 1 line 2; FP32 matrix cores)
+//   Y   = X Omega_1                (sketch step of Alg. 1; FP32 matrix cores)
 //   G   = Y^T Y                    (Gram of the sketch; FP64 matrix cores)
 //   P   = Y^T X                    (projection; FP64 matrix cores)
 //   ss  = ||X||_F^2                (for the fitness of Sec. IV-A)
-// With Y = Q Rc (Rc upper, Rc^T Rc = G) the matrix B = Q^T X of Alg. 1 line 4
+// With Y = Q Rc (Rc upper, Rc^T Rc = G) the matrix B = Q^T X of Alg. 1's projection step
 // is Rc^{-T} P, so the slab is read exactly once.  Y is rounded to FP32 once
 // and that same Y enters both G and P, whose products and sums are exact /
 // FP64: the orthogonal projection onto span(Y) is then exact up to FP64
@@ -212,13 +212,15 @@ __global__ __launch_bounds__(256) void k_sketch(
 // Y^T Y and Y^T X are formed on the int8 matrix cores: per 64-row tile, every
 // column of Y and of X is scaled by a power of two so that its largest entry
 // is below 2^22 and written as three balanced base-256 digits
-// (q = d0 2^16 + d1 2^8 + d2, |d| <= 128); the digit products are summed
-// exactly in int32 (one 16x16x64 instruction per digit pair covers the whole
-// tile), combined exactly in FP64 and rescaled.  The only rounding is the 22-
-// bit fixed-point representation of each column within its tile (relative
-// 2^-23 of the column maximum); the tile sums then accumulate in FP64.  This
-// is as accurate as forming the products in FP32 and summing them in FP64,
-// at int8 matrix-core speed.
+// (q = d0 2^16 + d1 2^8 + d2, |d| <= 128); all nine digit products are
+// summed exactly in int32 (one 16x16x64 instruction per digit pair covers the
+// whole tile), combined exactly in FP64 and rescaled.  The only rounding is
+// the 22-bit fixed-point representation of each column within its tile (at
+// most 2^-22 of the column maximum); the tile sums then accumulate in FP64.
+// The Gram is therefore the exact Gram of the represented Y, consistent with
+// the projection: the whitening that follows amplifies any inconsistency
+// between the two by the condition number of Y^T Y, so no digit product may
+// be dropped.
 // ---------------------------------------------------------------------------
 typedef int v4i __attribute__((ext_vector_type(4)));
 
@@ -236,10 +238,10 @@ __device__ __forceinline__ int col_exp(float m) {
 // three balanced base-256 digits of round(x * 2^(22 - e)), |x| < 2^e
 __device__ __forceinline__ void digits3(float x, int e, int& d0, int& d1, int& d2) {
   const int q = (int)rint(ldexp((double)x, 22 - e));
-  d2 = (q << 24) >> 24;
-  const int q1 = (q - d2) >> 8;
-  d1 = (q1 << 24) >> 24;
-  d0 = (q1 - d1) >> 8;
+  d2 = (int)(int8_t)(q & 0xff);
+  const int q1 = (q - d2) / 256;
+  d1 = (int)(int8_t)(q1 & 0xff);
+  d0 = (q1 - d1) / 256;
 }
 
 __device__ __forceinline__ uint32_t pack4(int a, int b, int c, int d) {
@@ -443,11 +445,12 @@ __global__ __launch_bounds__(256) void k_sketch_q(const float* __restrict__ slab
         S2 = mfma_i8(A[2], B[0], S2);
         v4i S3 = mfma_i8(A[1], B[2], z);
         S3 = mfma_i8(A[2], B[1], S3);
+        const v4i S4 = mfma_i8(A[2], B[2], z);
         const int ecol = eb[cb + lr];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const double val = (double)S0[v] * 4294967296.0 + (double)S1[v] * 16777216.0 +
-                             (double)S2[v] * 65536.0 + (double)S3[v] * 256.0;
+                             (double)S2[v] * 65536.0 + (double)S3[v] * 256.0 + (double)S4[v];
           const int erow = sYe[ca + f32_row(lane, v)];
           pacc[qi][v] += ldexp(val, erow + ecol - 44);
         }

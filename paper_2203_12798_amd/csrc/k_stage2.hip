@@ -1,9 +1,9 @@
 // Second-stage compression (Sec. III-B, Eq. 5): randomized SVD (Alg. 1) of
 // M = ||_k C_k B_k (J x KR), held transposed as M^T (KR x J, FP64):
 //   Y2 = M Omega_2                      (J x L2)
-//   Q2 = orthonormal basis of span(Y2)  (Alg. 1 line 3; FP64)
+//   Q2 = orthonormal basis of span(Y2)  (QR step of Alg. 1; FP64)
 //   B2 = Q2^T M                         (L2 x KR, stored as B2^T)
-//   B2 B2^T = U2 Lambda U2^T            (Alg. 1 line 5)
+//   B2 B2^T = U2 Lambda U2^T            (small SVD of Alg. 1)
 //   D = Q2 U2_R,  E = sqrt(Lambda_R),  F = B2^T U2_R E^{-1}   (KR x R)
 // and the constant part e0 = sum_k ||F^(k) E D^T||_F^2 of the iteration error.
 #include "internal.h"

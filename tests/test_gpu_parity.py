@@ -46,9 +46,13 @@ def _run_gpu(X, R, L, L2, iters, om1, om2, H0, V0, W0, tol=-1.0, want_U=False, t
 
 
 def _check_compression(X, R, g, ref, tol_m=1e-6):
-    """The sketch Y = X Omega_1 is rounded to FP32 once (by design), which
-    perturbs span(Y) by ~eps32 * sigma_1 / sigma_r relative to the FP64
-    oracle's; products after that are FP64.  Bound: 1e-6 relative."""
+    """The slab pass rounds the sketch Y = X Omega_1 to FP32 once and then
+    represents Y and X in 22-bit fixed point per column of each 64-row tile
+    (error at most 2^-22 of that column's maximum); the Gram, the projection
+    and everything after them are exact or FP64.  A CPU emulation of exactly
+    this arithmetic differs from the FP64 oracle by at most 4.6e-7 (sigma, on
+    the minimal-rows case) and 5.3e-7 (stock-shaped, K=120).  Bound: 1e-6
+    relative."""
     c = ref.comp
     K, J = X.K, X.J
     np.testing.assert_allclose(g["comp"]["xnorm2"], c.xnorm2, rtol=1e-12)
