@@ -6,8 +6,9 @@
 //     Cholesky factor G = R^T R; when a pivot falls below 1e-9 max_i G_ii the
 //     eigen form Wh = V Lambda^{-1/2} over the eigenvalues above
 //     64 eps lambda_max is used instead (defined also for a rank-deficient Y)
-//   B B^T = Wh^T (P P^T) Wh with B = Q^T X = Wh^T P (projection)
-//   B B^T = U~ Lambda~ U~^T (one-sided Jacobi; small SVD), sigma = sqrt(lambda~)
+//   S = B B^T = Wh^T (P P^T) Wh with B = Q^T X = Wh^T P (projection)
+//   S = C^T C (Cholesky), one-sided Jacobi on C^T: C^T V = U~ Sigma gives the
+//     eigenvectors U~ of S and the singular values Sigma of B (small SVD)
 //   Phi = Wh U~_R (A_k = Y Phi = Q U~_R), C_k B_k = B^T U~_R = P^T Phi
 // Each column of C_k B_k is signed so that its largest-magnitude entry is
 // positive (first one on ties); Phi's column follows.
@@ -32,25 +33,31 @@ struct SC {
 };
 
 // One-sided Jacobi (Hestenes) on L columns split over H lanes each: lane
-// (h, c) holds rows h LH .. of column c of T in t[] and of the accumulated
-// rotation in v[].  Round-robin pairing; both lanes of a pair, and all H lanes
-// of a column, compute the same rotation from the same sums (the butterfly
-// sums are symmetric, hence identical on every lane).  All 64 lanes must call
-// it.  Returns the number of sweeps.
-template <int L>
+// (h, c) holds rows h LH .. of column c of T in t[] and, if WITHV, of the
+// accumulated rotation in v[].  Round-robin pairing; both lanes of a pair, and
+// all H lanes of a column, compute the same rotation from the same sums (the
+// butterfly sums are symmetric, hence identical on every lane).  A pair is
+// rotated while |a.b| > JACOBI_TOL |a| |b|; the sweeps stop after one without
+// rotations, or after one whose largest |a.b| / (|a| |b|) was below 1e-7
+// (convergence is quadratic, so the next sweep would not rotate).  All 64
+// lanes must call it.  Returns the number of sweeps.
+template <int L, bool WITHV>
 __device__ inline int split_jacobi(double (&t)[SC<L>::LH], double (&v)[SC<L>::LH], int c, int h) {
   constexpr int N = SC<L>::N, RM = SC<L>::RM, LH = SC<L>::LH;
   int sweep;
   for (sweep = 0; sweep < JACOBI_SWEEPS; ++sweep) {
     int rotated = 0;
+    double worst = 0.0;
     for (int r = 0; r < N - 1; ++r) {
       const int pc = (c < N) ? rr_partner(c, r, N) : c;
       const int src = h * RM + pc;
       double tp[LH], vp[LH];
 #pragma unroll
       for (int i = 0; i < LH; ++i) tp[i] = __shfl(t[i], src, 64);
+      if constexpr (WITHV) {
 #pragma unroll
-      for (int i = 0; i < LH; ++i) vp[i] = __shfl(v[i], src, 64);
+        for (int i = 0; i < LH; ++i) vp[i] = __shfl(v[i], src, 64);
+      }
       double aa = 0.0, bb = 0.0, ab = 0.0;
 #pragma unroll
       for (int i = 0; i < LH; ++i) {
@@ -66,19 +73,26 @@ __device__ inline int split_jacobi(double (&t)[SC<L>::LH], double (&v)[SC<L>::LH
       }
       const bool low = c < pc;
       const double alpha = low ? aa : bb, beta = low ? bb : aa;
-      if (c < N && pc != c && ab != 0.0 && fabs(ab) > JACOBI_TOL * sqrt(alpha * beta)) {
+      const double nrm = sqrt(alpha * beta);
+      if (c < N && pc != c && ab != 0.0 && fabs(ab) > JACOBI_TOL * nrm) {
+        worst = fmax(worst, fabs(ab) / nrm);
         double cs, sn;
         jacobi_cs(alpha, beta, ab, &cs, &sn);
         rotated = 1;
         const double sa = low ? -sn : sn;
 #pragma unroll
-        for (int i = 0; i < LH; ++i) {
-          t[i] = fma(cs, t[i], sa * tp[i]);
-          v[i] = fma(cs, v[i], sa * vp[i]);
+        for (int i = 0; i < LH; ++i) t[i] = fma(cs, t[i], sa * tp[i]);
+        if constexpr (WITHV) {
+#pragma unroll
+          for (int i = 0; i < LH; ++i) v[i] = fma(cs, v[i], sa * vp[i]);
         }
       }
     }
     if (!__any(rotated)) break;
+    if (!__any(worst > 1e-7)) {
+      ++sweep;
+      break;
+    }
   }
   return sweep;
 }
@@ -89,6 +103,44 @@ __device__ __forceinline__ double col_sum(double x) {
 #pragma unroll
   for (int o = SC<L>::RM; o < 64; o <<= 1) x += __shfl_xor(x, o, 64);
   return x;
+}
+
+// Upper Cholesky factor of a symmetric positive semidefinite L x L matrix
+// held by columns (lane c < L: a[i] = A[i][c]), right-looking; lane p
+// publishes its column through LDS `row` at step p.  A pivot <= tau gives a
+// zero row of the factor.  On return lane c < L holds C[i][c] in a[i]
+// (a[i] = 0 below the diagonal) and rinv[p] = 1 / C[p][p] (0 for a zero
+// pivot).  Returns the number of zero pivots (the same on every lane).  All
+// 64 lanes must call it.
+template <int L>
+__device__ inline int lane_cholesky(double (&a)[L], double* row, double* rinv, double tau) {
+  const int c = threadIdx.x;
+  int zeros = 0;
+#pragma unroll
+  for (int p = 0; p < L; ++p) {
+    if (c == p) {
+#pragma unroll
+      for (int i = p; i < L; ++i) row[i] = a[i];
+    }
+    __syncthreads();
+    const double d = row[p];
+    const double ri = (d > tau) ? 1.0 / sqrt(d) : 0.0;
+    zeros += (d > tau) ? 0 : 1;
+    if (c >= p && c < L) {
+      const double rpc = a[p] * ri;   // C[p][c]
+      if (c > p) {
+#pragma unroll
+        for (int i = p + 1; i < L; ++i) a[i] = fma(-(row[i] * ri), rpc, a[i]);
+      }
+      a[p] = rpc;
+    }
+    if (c == 0) rinv[p] = ri;
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < L; ++i)
+    if (i > c) a[i] = 0.0;
+  return zeros;
 }
 
 template <int L>
@@ -104,9 +156,10 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
   __shared__ double Ss[L * LD];    // S' = P P^T; then Phi
   __shared__ double Ws[L * LD];    // whitening Wh
   __shared__ double Xs[L * LD];    // S' Wh; then sorted eigenvectors U~
-  __shared__ double Pc[L * CW];    // chunk of P
-  __shared__ double Mc[L * CW];    // chunk of C_k B_k (rows r < R)
-  __shared__ double sgn[L];
+  constexpr int CP = CW + 1;        // padded chunk row (conflict-free column reads)
+  __shared__ double Pc[L * CP];    // chunk of P
+  __shared__ double Mc[L * CP];    // chunk of C_k B_k (rows r < R)
+  __shared__ double sgn[L], row[L], rinv[L];
 
   const int lane = threadIdx.x, c = lane % RM, h = lane / RM;
   const int k = blockIdx.x;
@@ -118,13 +171,25 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
   double t[LH], v[LH];
 #pragma unroll
   for (int ii = 0; ii < LH; ++ii) {
+    t[ii] = 0.0;
+    v[ii] = (h * LH + ii == c) ? 1.0 : 0.0;
+  }
+  // loads are unconditional (clamped index, value masked) so that they are
+  // issued back to back instead of one branch and wait each
+  for (int q = i0; q < i1; ++q) {
+    const double* g = partG + (size_t)slice_list[q] * LL;
+#pragma unroll
+    for (int ii = 0; ii < LH; ++ii) {
+      const int a = h * LH + ii;
+      const bool ok = cv && a < L;
+      const double x = g[ok ? a * L + c : 0];
+      t[ii] += ok ? x : 0.0;
+    }
+  }
+#pragma unroll
+  for (int ii = 0; ii < LH; ++ii) {
     const int a = h * LH + ii;
-    double s = 0.0;
-    if (cv && a < L)
-      for (int q = i0; q < i1; ++q) s += partG[(size_t)slice_list[q] * LL + a * L + c];
-    t[ii] = s;
-    v[ii] = (a == c) ? 1.0 : 0.0;
-    if (cv && a < L) Gs[a * LD + c] = s;
+    if (cv && a < L) Gs[a * LD + c] = t[ii];
   }
   if (lane == 0) {
     double s = 0.0;
@@ -136,22 +201,38 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
   double sp[LH];
 #pragma unroll
   for (int ii = 0; ii < LH; ++ii) sp[ii] = 0.0;
-  for (int jc = 0; jc < J; jc += CW) {
-    for (int e = lane; e < L * CW; e += 64) {
-      const int a = e / CW, jj = e % CW;
-      double p = 0.0;
-      if (jc + jj < J)
-        for (int q = i0; q < i1; ++q) p += partP[(size_t)slice_list[q] * L * J + (size_t)a * J + jc + jj];
-      Pc[e] = p;
+  // chunk jc of P into Pc; the loads of one item are issued together
+  auto load_chunk = [&](int jc) {
+    constexpr int NE = (L * CW + 63) / 64;
+    double pv[NE];
+#pragma unroll
+    for (int u = 0; u < NE; ++u) pv[u] = 0.0;
+    for (int q = i0; q < i1; ++q) {
+      const double* base = partP + (size_t)slice_list[q] * L * J + jc;
+#pragma unroll
+      for (int u = 0; u < NE; ++u) {
+        const int e = lane + 64 * u, a = e / CW, jj = e % CW;
+        const bool ok = e < L * CW && jc + jj < J;
+        const double x = base[ok ? (size_t)a * J + jj : 0];
+        pv[u] += ok ? x : 0.0;
+      }
     }
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int e = lane + 64 * u;
+      if (e < L * CW) Pc[(e / CW) * CP + e % CW] = pv[u];
+    }
+  };
+  for (int jc = 0; jc < J; jc += CW) {
+    load_chunk(jc);
     __syncthreads();
     if (cv) {
       for (int jj = 0; jj < CW; ++jj) {
-        const double pc = Pc[c * CW + jj];
+        const double pc = Pc[c * CP + jj];
 #pragma unroll
         for (int ii = 0; ii < LH; ++ii) {
           const int a = h * LH + ii;
-          if (a < L) sp[ii] = fma(Pc[a * CW + jj], pc, sp[ii]);
+          if (a < L) sp[ii] = fma(Pc[a * CP + jj], pc, sp[ii]);
         }
       }
     }
@@ -164,30 +245,21 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
   }
   __syncthreads();
 
-  // Whitening.  Cholesky G = R^T R in Gs (upper triangle, row p = row p of R)
+  // Whitening: G = R^T R (lane_cholesky), Wh = R^{-1}
   double dmax = 0.0;
   for (int a = 0; a < L; ++a) dmax = fmax(dmax, Gs[a * LD + a]);
-  const double tau = 1e-9 * dmax;
-  bool chol = dmax > 0.0;
-  for (int p = 0; p < L && chol; ++p) {
-    const double d = Gs[p * LD + p];
-    __syncthreads();
-    if (!(d > tau)) {
-      chol = false;   // every lane read the same d
-      break;
-    }
-    const double rp = sqrt(d);
-    if (lane >= p && lane < L) Gs[p * LD + lane] = (lane == p) ? rp : Gs[p * LD + lane] / rp;
-    __syncthreads();
-    const int m = L - p - 1;
-    for (int e = lane; e < m * m; e += 64) {
-      const int i = p + 1 + e / m, j = p + 1 + e % m;
-      if (j >= i) Gs[i * LD + j] -= Gs[p * LD + i] * Gs[p * LD + j];
-    }
-    __syncthreads();
-  }
+  double col[L];
+#pragma unroll
+  for (int i = 0; i < L; ++i) col[i] = (lane < L) ? Gs[i * LD + lane] : 0.0;
+  __syncthreads();
+  const bool chol = dmax > 0.0 && lane_cholesky<L>(col, row, rinv, 1e-9 * dmax) == 0;
   if (chol) {
-    // Wh = R^{-1}: lane c < L solves R x = e_c by back substitution
+    if (lane < L) {
+#pragma unroll
+      for (int i = 0; i < L; ++i) Gs[i * LD + lane] = col[i];
+    }
+    __syncthreads();
+    // lane c < L solves R x = e_c by back substitution
     if (lane < L) {
       double x[L];
 #pragma unroll
@@ -195,14 +267,14 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
         double s = (i == lane) ? 1.0 : 0.0;
 #pragma unroll
         for (int j = i + 1; j < L; ++j) s = fma(-Gs[i * LD + j], x[j], s);
-        x[i] = (i > lane) ? 0.0 : s / Gs[i * LD + i];
+        x[i] = (i > lane) ? 0.0 : s * rinv[i];
       }
 #pragma unroll
       for (int i = 0; i < L; ++i) Ws[i * LD + lane] = x[i];
     }
   } else {
     // eigen form: G = V Lambda V^T, Wh column c = v_c / sqrt(lambda_c) or 0
-    if (split_jacobi<L>(t, v, c, h) == JACOBI_SWEEPS) warn |= 0x1u;
+    if (split_jacobi<L, true>(t, v, c, h) == JACOBI_SWEEPS) warn |= 0x1u;
     double lam = 0.0;
 #pragma unroll
     for (int ii = 0; ii < LH; ++ii) lam = fma(t[ii], t[ii], lam);
@@ -230,24 +302,54 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
     }
   }
   __syncthreads();
+  // column c of S = Wh^T (S' Wh), Cholesky S = C^T C (semidefinite)
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    double s = 0.0;
+    if (lane < L)
+#pragma unroll
+      for (int b = 0; b < L; ++b) s = fma(Ws[b * LD + i], Xs[b * LD + lane], s);
+    col[i] = s;
+  }
+  double smax = 0.0;
+#pragma unroll
+  for (int i = 0; i < L; ++i)
+    if (i == lane) smax = col[i];
+  for (int o = 1; o < 64; o <<= 1) smax = fmax(smax, __shfl_xor(smax, o, 64));
+  lane_cholesky<L>(col, row, rinv, 1e-13 * smax);
+  // rows of C become the Jacobi columns (A = C^T, A A^T = S): lane (h, c)
+  // takes entries h LH .. of row c
+  if (lane < L) {
+#pragma unroll
+    for (int i = 0; i < L; ++i) Gs[i * LD + lane] = col[i];
+  }
+  __syncthreads();
 #pragma unroll
   for (int ii = 0; ii < LH; ++ii) {
-    const int a = h * LH + ii;
-    double s = 0.0;
-    if (cv && a < L)
-#pragma unroll
-      for (int b = 0; b < L; ++b) s = fma(Ws[b * LD + a], Xs[b * LD + c], s);
-    t[ii] = s;
-    v[ii] = (a == c) ? 1.0 : 0.0;
+    const int b = h * LH + ii;
+    t[ii] = (cv && b < L) ? Gs[c * LD + b] : 0.0;
   }
   __syncthreads();
 
-  // B B^T = U~ Lambda~ U~^T
-  if (split_jacobi<L>(t, v, c, h) == JACOBI_SWEEPS) warn |= 0x1u;
+  // One-sided Jacobi on A = C^T: A V = U~ Sigma, U~ the eigenvectors of
+  // S = B B^T and Sigma the singular values of B; the left vectors are the
+  // normalised converged columns, so no rotation is accumulated.  (The
+  // triangular factor makes this converge in about half the sweeps needed on
+  // S itself.)
+  if (split_jacobi<L, false>(t, v, c, h) == JACOBI_SWEEPS) warn |= 0x1u;
   double mu = 0.0;
 #pragma unroll
   for (int ii = 0; ii < LH; ++ii) mu = fma(t[ii], t[ii], mu);
-  mu = sqrt(col_sum<L>(mu));   // eigenvalue of the PSD matrix B B^T
+  mu = sqrt(col_sum<L>(mu));   // singular value of B
+  {
+    // directions at the rounding level of the largest carry no information
+    // (their normalised columns would be noise): zero them
+    double mmax = cv ? mu : 0.0;
+    for (int o = 1; o < 64; o <<= 1) mmax = fmax(mmax, __shfl_xor(mmax, o, 64));
+    const double inv = (mu > 64.0 * EPS64 * mmax && mu > 0.0) ? 1.0 / mu : 0.0;
+#pragma unroll
+    for (int ii = 0; ii < LH; ++ii) v[ii] = t[ii] * inv;
+  }
   // rank by decreasing eigenvalue (ties: lower index first)
   int rank = 0;
   for (int c2 = 0; c2 < L; ++c2) {
@@ -260,7 +362,7 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
       const int a = h * LH + ii;
       if (a < L) Xs[a * LD + rank] = v[ii];
     }
-    if (h == 0 && rank < R) sig1[(size_t)k * R + rank] = sqrt(mu > 0.0 ? mu : 0.0);
+    if (h == 0 && rank < R) sig1[(size_t)k * R + rank] = mu;
   }
   __syncthreads();
   // Phi = Wh U~_R (into Ss)
@@ -278,27 +380,21 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
   double* Mk = Mt + (size_t)k * R * J;
   for (int pass = 0; pass < 2; ++pass) {
     for (int jc = 0; jc < J; jc += CW) {
-      for (int e = lane; e < L * CW; e += 64) {
-        const int a = e / CW, jj = e % CW;
-        double p = 0.0;
-        if (jc + jj < J)
-          for (int q = i0; q < i1; ++q) p += partP[(size_t)slice_list[q] * L * J + (size_t)a * J + jc + jj];
-        Pc[e] = p;
-      }
+      load_chunk(jc);
       __syncthreads();
       for (int e = lane; e < R * CW; e += 64) {
         const int r = e / CW, jj = e % CW;
         double m = 0.0;
 #pragma unroll
-        for (int a = 0; a < L; ++a) m = fma(Ss[a * LD + r], Pc[a * CW + jj], m);
-        if (pass == 0) Mc[e] = m;
+        for (int a = 0; a < L; ++a) m = fma(Ss[a * LD + r], Pc[a * CP + jj], m);
+        if (pass == 0) Mc[r * CP + jj] = m;
         else if (jc + jj < J) Mk[(size_t)r * J + jc + jj] = sgn[r] * m;
       }
       __syncthreads();
       if (pass == 0 && lane < R) {
         const int nj = (J - jc < CW) ? J - jc : CW;
         for (int jj = 0; jj < nj; ++jj) {
-          const double m = Mc[lane * CW + jj];
+          const double m = Mc[lane * CP + jj];
           if (fabs(m) > bv) {
             bv = fabs(m);
             bs = m;
