@@ -24,16 +24,11 @@
 // order (bitwise reproducible).
 #pragma once
 
-#include "internal.h"
+#include "wave_linalg.h"
 
 namespace dpar2 {
 
 constexpr int EPI_THREADS = 1024;
-constexpr double EPS64 = 2.220446049250313e-16;
-// Jacobi pairs are rotated while |a.b| > JACOBI_TOL sqrt(|a|^2 |b|^2): above
-// the rounding floor of an R-term dot product, so converged columns stop.
-constexpr double JACOBI_TOL = 1e-13;
-constexpr int JACOBI_SWEEPS = 30;
 
 struct AlsArgs {
   int K, J;
@@ -45,12 +40,6 @@ struct AlsArgs {
   double tol;
   Ctl* ctl;
 };
-
-__host__ __device__ constexpr int pow2ceil(int x) {
-  int p = 1;
-  while (p < x) p *= 2;
-  return p;
-}
 
 template <int R>
 struct RC {
@@ -71,6 +60,7 @@ __device__ inline int group_jacobi(double (&t)[R], double (&v)[R], int j, int gb
   int sweep;
   for (sweep = 0; sweep < JACOBI_SWEEPS; ++sweep) {
     int rotated = 0;
+    double worst = 0.0;
     for (int r = 0; r < N - 1; ++r) {
       const int pc = (j < N) ? rr_partner(j, r, N) : j;
       const int src = gbase + pc;
@@ -88,7 +78,9 @@ __device__ inline int group_jacobi(double (&t)[R], double (&v)[R], int j, int gb
       }
       const bool low = j < pc;
       const double alpha = low ? aa : bb, beta = low ? bb : aa;
-      if (j < N && pc != j && ab != 0.0 && fabs(ab) > JACOBI_TOL * sqrt(alpha * beta)) {
+      const double ab2 = ab * ab, ref = alpha * beta;
+      if (j < N && pc != j && ab != 0.0 && ab2 > (JACOBI_TOL * JACOBI_TOL) * ref) {
+        worst = fmax(worst, ab2 / ref);
         double c, s;
         jacobi_cs(alpha, beta, ab, &c, &s);
         rotated = 1;
@@ -101,6 +93,10 @@ __device__ inline int group_jacobi(double (&t)[R], double (&v)[R], int j, int gb
       }
     }
     if (!__any(rotated)) break;
+    if (!__any(worst > 1e-14)) {   // largest |a.b| / (|a| |b|) below 1e-7: quadratic
+      ++sweep;                     // convergence leaves nothing for another sweep
+      break;
+    }
   }
   return sweep;
 }

@@ -1,9 +1,9 @@
 // Second-stage compression (Sec. III-B, Eq. 5): randomized SVD (Alg. 1) of
 // M = ||_k C_k B_k (J x KR), held transposed as M^T (KR x J, FP64):
 //   Y2 = M Omega_2                      (J x L2)
-//   Q2 = orthonormal basis of span(Y2)  (QR step of Alg. 1; FP64)
+//   Q2 = orthonormal basis of span(Y2)  (QR step of Alg. 1; FP64, stage2_impl.h)
 //   B2 = Q2^T M                         (L2 x KR, stored as B2^T)
-//   B2 B2^T = U2 Lambda U2^T            (small SVD of Alg. 1)
+//   B2 B2^T = U2 Lambda U2^T            (small SVD of Alg. 1, stage2_impl.h)
 //   D = Q2 U2_R,  E = sqrt(Lambda_R),  F = B2^T U2_R E^{-1}   (KR x R)
 // and the constant part e0 = sum_k ||F^(k) E D^T||_F^2 of the iteration error.
 #include "internal.h"
@@ -11,7 +11,7 @@
 namespace dpar2 {
 
 // partial Y2^T over a chunk of STAGE2_CHUNK rows of M^T:
-// Y2p[c][l][j] = sum_rows Omega2[row][l] * Mt[row][j]
+// Y2p[c][j][l] = sum_rows Mt[row][j] * Omega2[row][l]
 __global__ __launch_bounds__(256) void k_s2_y(int64_t KR, int J, int L2, const float* __restrict__ om2,
                                               const double* __restrict__ Mt, double* __restrict__ Y2p) {
   __shared__ double sM[64 * 64];
@@ -26,13 +26,28 @@ __global__ __launch_bounds__(256) void k_s2_y(int64_t KR, int J, int L2, const f
   for (int64_t rb = r0; rb < r1; rb += 64) {
     const int nr = (int)((r1 - rb) < 64 ? (r1 - rb) : 64);
     __syncthreads();
-    for (int e = tid; e < 64 * 64; e += 256) {
-      const int rr = e / 64, jj = e % 64;
-      sM[e] = (rr < nr && jb * 64 + jj < J) ? Mt[(size_t)(rb + rr) * J + jb * 64 + jj] : 0.0;
-    }
-    for (int e = tid; e < 64 * 32; e += 256) {
-      const int rr = e / 32, ll = e % 32;
-      sO[e] = (rr < nr && ll < L2) ? om2[(size_t)(rb + rr) * L2 + ll] : 0.f;
+    // staging loads are unrolled with clamped indices so they issue together
+    {
+      double mv[16];
+      float ov[8];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = tid + 256 * u, rr = e / 64, jj = e % 64;
+        const bool ok = rr < nr && jb * 64 + jj < J;
+        const double x = Mt[ok ? (size_t)(rb + rr) * J + jb * 64 + jj : 0];
+        mv[u] = ok ? x : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = tid + 256 * u, rr = e / 32, ll = e % 32;
+        const bool ok = rr < nr && ll < L2;
+        const float x = om2[ok ? (size_t)(rb + rr) * L2 + ll : 0];
+        ov[u] = ok ? x : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) sM[tid + 256 * u] = mv[u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) sO[tid + 256 * u] = ov[u];
     }
     __syncthreads();
     for (int rr = 0; rr < nr; ++rr) {
@@ -44,54 +59,29 @@ __global__ __launch_bounds__(256) void k_s2_y(int64_t KR, int J, int L2, const f
   if (j < J)
     for (int q = 0; q < 8; ++q) {
       const int l = l0 + 4 * q;
-      if (l < L2) Y2p[((size_t)c * L2 + l) * J + j] = acc[q];
+      if (l < L2) Y2p[((size_t)c * J + j) * L2 + l] = acc[q];
     }
 }
 
-// Y2[j][l] = sum_c Y2p[c][l][j]
-__global__ void k_s2_y_reduce(int64_t n2, int J, int L2, const double* __restrict__ Y2p,
-                              double* __restrict__ Y2) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= J * L2) return;
-  const int j = e / L2, l = e % L2;
-  double s = 0.0;
-  for (int64_t c = 0; c < n2; ++c) s += Y2p[((size_t)c * L2 + l) * J + j];
-  Y2[e] = s;
-}
-
-// Orthonormal basis of span(Y2) in place (Y2 <- Q2), by two whitening passes
-// (eigen-based CholeskyQR2: the second pass restores orthogonality to FP64
-// rounding; dropped directions become zero columns).
-__global__ __launch_bounds__(256) void k_s2_cqr2(int J, int L2, double* __restrict__ Y, Ctl* ctl) {
-  constexpr int LD = 33;
-  __shared__ double G[32 * LD], Wh[32 * LD], V[32 * LD], cs[40];
+// out[e * ostride] = sum_q part[q * stride + e] for e < gridDim.x: one block
+// per e, the threads split q (four independent accumulators each) and combine
+// in a fixed order.
+__global__ __launch_bounds__(256) void k_colsum(int64_t nb, int64_t stride, const double* __restrict__ part,
+                                                double* __restrict__ out, int64_t ostride) {
+  __shared__ double red[16];
+  const int64_t e = blockIdx.x;
   const int tid = threadIdx.x;
-  const int npairs = L2 * (L2 + 1) / 2;
-  int capped = 0;
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int pi = tid; pi < npairs; pi += 256) {
-      int a = 0, rem = pi;
-      while (rem >= L2 - a) { rem -= L2 - a; ++a; }
-      const int b = a + rem;
-      double s = 0.0;
-      for (int j = 0; j < J; ++j) s += Y[(size_t)j * L2 + a] * Y[(size_t)j * L2 + b];
-      G[a * LD + b] = s;
-      G[b * LD + a] = s;
-    }
-    __syncthreads();
-    capped |= block_whiten(G, LD, L2, Wh, V, cs);
-    for (int j = tid; j < J; j += 256) {
-      double y[32];
-      for (int l = 0; l < L2; ++l) y[l] = Y[(size_t)j * L2 + l];
-      for (int b = 0; b < L2; ++b) {
-        double v = 0.0;
-        for (int a = 0; a < L2; ++a) v += y[a] * Wh[a * LD + b];
-        Y[(size_t)j * L2 + b] = v;
-      }
-    }
-    __syncthreads();
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int64_t q = tid;
+  for (; q + 768 < nb; q += 1024) {
+    s0 += part[(size_t)q * stride + e];
+    s1 += part[(size_t)(q + 256) * stride + e];
+    s2 += part[(size_t)(q + 512) * stride + e];
+    s3 += part[(size_t)(q + 768) * stride + e];
   }
-  if (tid == 0 && capped) atomicOr(&ctl->warn, 0x1u);
+  for (; q < nb; q += 256) s0 += part[(size_t)q * stride + e];
+  const double t = block_sum((s0 + s1) + (s2 + s3), red);
+  if (tid == 0) out[e * ostride] = t;
 }
 
 // B2^T rows of one chunk: B2t[row][l] = sum_j Mt[row][j] Q2[j][l], plus the
@@ -114,13 +104,29 @@ __global__ __launch_bounds__(256) void k_s2_b(int64_t KR, int J, int L2, const d
     for (int q = 0; q < 8; ++q) acc[q] = 0.0;
     for (int jc = 0; jc < J; jc += 64) {
       __syncthreads();
-      for (int e = tid; e < 64 * 64; e += 256) {
-        const int rr = e / 64, jj = e % 64;
-        sM[rr * 65 + jj] = (rr < nr && jc + jj < J) ? Mt[(size_t)(rb + rr) * J + jc + jj] : 0.0;
-      }
-      for (int e = tid; e < 64 * 32; e += 256) {
-        const int jj = e / 32, ll = e % 32;
-        sQ[e] = (jc + jj < J && ll < L2) ? Q2[(size_t)(jc + jj) * L2 + ll] : 0.0;
+      {
+        double mv[16], qv[8];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int e = tid + 256 * u, rr = e / 64, jj = e % 64;
+          const bool ok = rr < nr && jc + jj < J;
+          const double x = Mt[ok ? (size_t)(rb + rr) * J + jc + jj : 0];
+          mv[u] = ok ? x : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int e = tid + 256 * u, jj = e / 32, ll = e % 32;
+          const bool ok = jc + jj < J && ll < L2;
+          const double x = Q2[ok ? (size_t)(jc + jj) * L2 + ll : 0];
+          qv[u] = ok ? x : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int e = tid + 256 * u;
+          sM[(e / 64) * 65 + e % 64] = mv[u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sQ[tid + 256 * u] = qv[u];
       }
       __syncthreads();
       for (int jj = 0; jj < 64; ++jj) {
@@ -156,58 +162,16 @@ __global__ __launch_bounds__(256) void k_s2_b(int64_t KR, int J, int L2, const d
   }
 }
 
-// EVD of B2 B2^T, then D, E, the L2 x R map U2_R E^{-1}, D^T D, and the
-// total ||X||^2.
-__global__ __launch_bounds__(256) void k_s2_evd(int64_t n2, int64_t K, int J, int L2, int R,
-                                                const double* __restrict__ S2p, const double* __restrict__ Q2,
-                                                const double* __restrict__ xnorm2, double* __restrict__ D,
-                                                double* __restrict__ E, double* __restrict__ U2s,
-                                                double* __restrict__ DtD, Ctl* ctl) {
-  constexpr int LD = 33;
-  __shared__ double S[32 * LD], U[32 * LD], cs[40], red[16], sD[1];
-  __shared__ int perm[32];
-  const int tid = threadIdx.x;
-  const int npairs = L2 * (L2 + 1) / 2;
-  for (int pi = tid; pi < npairs; pi += 256) {
-    int a = 0, rem = pi;
-    while (rem >= L2 - a) { rem -= L2 - a; ++a; }
-    const int b = a + rem;
-    double s = 0.0;
-    for (int64_t c = 0; c < n2; ++c) s += S2p[(size_t)c * npairs + pi];
-    S[a * LD + b] = s;
-    S[b * LD + a] = s;
-  }
-  double xs = 0.0;
-  for (int64_t k = tid; k < K; k += 256) xs += xnorm2[k];
-  xs = block_sum(xs, red);
-  if (tid == 0) ctl->xnorm2 = xs;
-  __syncthreads();
-  const int capped = block_sym_evd(S, LD, U, L2, cs);
-  block_sort_desc(S, LD, L2, perm);
-  if (tid < R) {
-    const double lam = S[perm[tid] * LD + perm[tid]];
-    E[tid] = sqrt(lam > 0.0 ? lam : 0.0);
-  }
-  __syncthreads();
-  for (int e = tid; e < L2 * R; e += 256) {
-    const int l = e / R, r = e % R;
-    const double er = E[r];
-    U2s[e] = er > 0.0 ? U[l * LD + perm[r]] / er : 0.0;
-  }
-  for (int e = tid; e < J * R; e += 256) {
-    const int j = e / R, r = e % R;
-    double s = 0.0;
-    for (int l = 0; l < L2; ++l) s += Q2[(size_t)j * L2 + l] * U[l * LD + perm[r]];
-    D[e] = s;
-  }
-  __syncthreads();
-  for (int e = tid; e < R * R; e += 256) {
-    const int a = e / R, b = e % R;
-    double s = 0.0;
-    for (int j = 0; j < J; ++j) s += D[(size_t)j * R + a] * D[(size_t)j * R + b];
-    DtD[e] = s;
-  }
-  if (tid == 0 && capped) atomicOr(&ctl->warn, 0x1u);
+hipError_t s2_small_dispatch_1(int L2, int which, int J, int R, double* Y2, const double* S2, double* D,
+                               double* E, double* U2s, double* DtD, Ctl* ctl, hipStream_t s);
+hipError_t s2_small_dispatch_2(int L2, int which, int J, int R, double* Y2, const double* S2, double* D,
+                               double* E, double* U2s, double* DtD, Ctl* ctl, hipStream_t s);
+
+// orthonormalisation of Y2 (which = 0) or the small SVD and D, E (which = 1)
+static hipError_t s2_small(int L2, int which, int J, int R, double* Y2, const double* S2, double* D, double* E,
+                           double* U2s, double* DtD, Ctl* ctl, hipStream_t s) {
+  if (L2 <= 16) return s2_small_dispatch_1(L2, which, J, R, Y2, S2, D, E, U2s, DtD, ctl, s);
+  return s2_small_dispatch_2(L2, which, J, R, Y2, S2, D, E, U2s, DtD, ctl, s);
 }
 
 // F = B2^T (U2_R E^{-1}) and per-block partials of F^T F.
@@ -236,22 +200,18 @@ __global__ __launch_bounds__(256) void k_s2_f(int64_t KR, int L2, int R, const d
   }
 }
 
-// F^T F and e0 = sum_{r,s} E_r E_s (F^T F)_{rs} (D^T D)_{rs}.
-__global__ __launch_bounds__(256) void k_s2_final(int nblk, int R, const double* __restrict__ FtFp,
-                                                  const double* __restrict__ E, const double* __restrict__ DtD,
-                                                  double* __restrict__ FtF, Ctl* ctl) {
-  __shared__ double red[16];
-  const int tid = threadIdx.x;
+// e0 = sum_{r,s} E_r E_s (F^T F)_{rs} (D^T D)_{rs} (Sec. III-E constant term)
+__global__ __launch_bounds__(64) void k_s2_final(int R, const double* __restrict__ FtF,
+                                                 const double* __restrict__ E, const double* __restrict__ DtD,
+                                                 Ctl* ctl) {
+  const int lane = threadIdx.x;
   double e0 = 0.0;
-  for (int e = tid; e < R * R; e += 256) {
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += FtFp[(size_t)b * R * R + e];
-    FtF[e] = s;
+  for (int e = lane; e < R * R; e += 64) {
     const int a = e / R, c = e % R;
-    e0 += E[a] * E[c] * s * DtD[e];
+    e0 += E[a] * E[c] * FtF[e] * DtD[e];
   }
-  e0 = block_sum(e0, red);
-  if (tid == 0) ctl->e0 = e0;
+  for (int o = 1; o < 64; o <<= 1) e0 += __shfl_xor(e0, o, 64);
+  if (lane == 0) ctl->e0 = e0;
 }
 
 hipError_t launch_stage2(const Layout& lay, char* ws, const float* omega2, hipStream_t s) {
@@ -273,16 +233,23 @@ hipError_t launch_stage2(const Layout& lay, char* ws, const float* omega2, hipSt
   const int RR = R * R;
   hipLaunchKernelGGL(k_s2_y, dim3((unsigned)lay.n2, (unsigned)((J + 63) / 64)), dim3(256), 0, s, KR, J,
                      L2, omega2, Mt, Y2p);
-  hipLaunchKernelGGL(k_s2_y_reduce, dim3((unsigned)((J * L2 + 255) / 256)), dim3(256), 0, s, lay.n2,
-                     J, L2, Y2p, Y2);
-  hipLaunchKernelGGL(k_s2_cqr2, dim3(1), dim3(256), 0, s, J, L2, Y2, ctl);
+  hipLaunchKernelGGL(k_colsum, dim3((unsigned)(J * L2)), dim3(256), 0, s, lay.n2, (int64_t)J * L2, Y2p, Y2,
+                     (int64_t)1);
+  hipError_t e = s2_small(L2, 0, J, R, Y2, nullptr, D, E, U2s, small + SM_DTD * RR, ctl, s);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_s2_b, dim3((unsigned)lay.n2), dim3(256), 0, s, KR, J, L2, Mt, Y2, B2t, S2p);
-  hipLaunchKernelGGL(k_s2_evd, dim3(1), dim3(256), 0, s, lay.n2, lay.K, J, L2, R, S2p, Y2, xnorm2, D,
-                     E, U2s, small + SM_DTD * RR, ctl);
+  // B2 B2^T (packed pairs) into Y2p, dead by now; sum of ||X_k||^2 into ctl
+  const int npairs = L2 * (L2 + 1) / 2;
+  hipLaunchKernelGGL(k_colsum, dim3((unsigned)npairs), dim3(256), 0, s, lay.n2, (int64_t)npairs, S2p, Y2p,
+                     (int64_t)1);
+  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, s, lay.K, (int64_t)1, xnorm2, &ctl->xnorm2, (int64_t)1);
+  e = s2_small(L2, 1, J, R, Y2, Y2p, D, E, U2s, small + SM_DTD * RR, ctl, s);
+  if (e != hipSuccess) return e;
   const unsigned nbf = (unsigned)((KR + 255) / 256);
   hipLaunchKernelGGL(k_s2_f, dim3(nbf), dim3(256), 0, s, KR, L2, R, B2t, U2s, F, FtFp);
-  hipLaunchKernelGGL(k_s2_final, dim3(1), dim3(256), 0, s, (int)nbf, R, FtFp, E, small + SM_DTD * RR,
-                     small + SM_FTF * RR, ctl);
+  hipLaunchKernelGGL(k_colsum, dim3((unsigned)RR), dim3(256), 0, s, (int64_t)nbf, (int64_t)RR, FtFp,
+                     small + SM_FTF * RR, (int64_t)1);
+  hipLaunchKernelGGL(k_s2_final, dim3(1), dim3(64), 0, s, R, small + SM_FTF * RR, E, small + SM_DTD * RR, ctl);
   return hipGetLastError();
 }
 

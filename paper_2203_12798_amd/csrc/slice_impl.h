@@ -13,135 +13,12 @@
 // Each column of C_k B_k is signed so that its largest-magnitude entry is
 // positive (first one on ties); Phi's column follows.
 //
-// Lane layout for the L x L matrices: column c is split over H = 64 / RM lanes
-// (lane = h RM + c), lane h holding rows h LH .. h LH + LH - 1.  The Jacobi
-// rounds then exchange LH rows per lane instead of L.
+// Lane layout for the L x L matrices: the split layout of wave_linalg.h.
 #pragma once
 
-#include "als_impl.h"
+#include "wave_linalg.h"
 
 namespace dpar2 {
-
-template <int L>
-struct SC {
-  static constexpr int N = L + (L & 1);                          // Jacobi players
-  static constexpr int RM = pow2ceil(N) < 2 ? 2 : pow2ceil(N);   // column groups
-  static constexpr int H = 64 / RM;                              // lanes per column
-  static constexpr int LH = (L + H - 1) / H;                     // rows per lane
-  static constexpr int LD = L + 1;                               // LDS leading dimension
-  static constexpr int CW = 32;                                  // P columns per chunk
-};
-
-// One-sided Jacobi (Hestenes) on L columns split over H lanes each: lane
-// (h, c) holds rows h LH .. of column c of T in t[] and, if WITHV, of the
-// accumulated rotation in v[].  Round-robin pairing; both lanes of a pair, and
-// all H lanes of a column, compute the same rotation from the same sums (the
-// butterfly sums are symmetric, hence identical on every lane).  A pair is
-// rotated while |a.b| > JACOBI_TOL |a| |b|; the sweeps stop after one without
-// rotations, or after one whose largest |a.b| / (|a| |b|) was below 1e-7
-// (convergence is quadratic, so the next sweep would not rotate).  All 64
-// lanes must call it.  Returns the number of sweeps.
-template <int L, bool WITHV>
-__device__ inline int split_jacobi(double (&t)[SC<L>::LH], double (&v)[SC<L>::LH], int c, int h) {
-  constexpr int N = SC<L>::N, RM = SC<L>::RM, LH = SC<L>::LH;
-  int sweep;
-  for (sweep = 0; sweep < JACOBI_SWEEPS; ++sweep) {
-    int rotated = 0;
-    double worst = 0.0;
-    for (int r = 0; r < N - 1; ++r) {
-      const int pc = (c < N) ? rr_partner(c, r, N) : c;
-      const int src = h * RM + pc;
-      double tp[LH], vp[LH];
-#pragma unroll
-      for (int i = 0; i < LH; ++i) tp[i] = __shfl(t[i], src, 64);
-      if constexpr (WITHV) {
-#pragma unroll
-        for (int i = 0; i < LH; ++i) vp[i] = __shfl(v[i], src, 64);
-      }
-      double aa = 0.0, bb = 0.0, ab = 0.0;
-#pragma unroll
-      for (int i = 0; i < LH; ++i) {
-        aa = fma(t[i], t[i], aa);
-        bb = fma(tp[i], tp[i], bb);
-        ab = fma(t[i], tp[i], ab);
-      }
-#pragma unroll
-      for (int o = RM; o < 64; o <<= 1) {
-        aa += __shfl_xor(aa, o, 64);
-        bb += __shfl_xor(bb, o, 64);
-        ab += __shfl_xor(ab, o, 64);
-      }
-      const bool low = c < pc;
-      const double alpha = low ? aa : bb, beta = low ? bb : aa;
-      const double nrm = sqrt(alpha * beta);
-      if (c < N && pc != c && ab != 0.0 && fabs(ab) > JACOBI_TOL * nrm) {
-        worst = fmax(worst, fabs(ab) / nrm);
-        double cs, sn;
-        jacobi_cs(alpha, beta, ab, &cs, &sn);
-        rotated = 1;
-        const double sa = low ? -sn : sn;
-#pragma unroll
-        for (int i = 0; i < LH; ++i) t[i] = fma(cs, t[i], sa * tp[i]);
-        if constexpr (WITHV) {
-#pragma unroll
-          for (int i = 0; i < LH; ++i) v[i] = fma(cs, v[i], sa * vp[i]);
-        }
-      }
-    }
-    if (!__any(rotated)) break;
-    if (!__any(worst > 1e-7)) {
-      ++sweep;
-      break;
-    }
-  }
-  return sweep;
-}
-
-// sum over the H lanes of a column (identical result on each of them)
-template <int L>
-__device__ __forceinline__ double col_sum(double x) {
-#pragma unroll
-  for (int o = SC<L>::RM; o < 64; o <<= 1) x += __shfl_xor(x, o, 64);
-  return x;
-}
-
-// Upper Cholesky factor of a symmetric positive semidefinite L x L matrix
-// held by columns (lane c < L: a[i] = A[i][c]), right-looking; lane p
-// publishes its column through LDS `row` at step p.  A pivot <= tau gives a
-// zero row of the factor.  On return lane c < L holds C[i][c] in a[i]
-// (a[i] = 0 below the diagonal) and rinv[p] = 1 / C[p][p] (0 for a zero
-// pivot).  Returns the number of zero pivots (the same on every lane).  All
-// 64 lanes must call it.
-template <int L>
-__device__ inline int lane_cholesky(double (&a)[L], double* row, double* rinv, double tau) {
-  const int c = threadIdx.x;
-  int zeros = 0;
-#pragma unroll
-  for (int p = 0; p < L; ++p) {
-    if (c == p) {
-#pragma unroll
-      for (int i = p; i < L; ++i) row[i] = a[i];
-    }
-    __syncthreads();
-    const double d = row[p];
-    const double ri = (d > tau) ? 1.0 / sqrt(d) : 0.0;
-    zeros += (d > tau) ? 0 : 1;
-    if (c >= p && c < L) {
-      const double rpc = a[p] * ri;   // C[p][c]
-      if (c > p) {
-#pragma unroll
-        for (int i = p + 1; i < L; ++i) a[i] = fma(-(row[i] * ri), rpc, a[i]);
-      }
-      a[p] = rpc;
-    }
-    if (c == 0) rinv[p] = ri;
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < L; ++i)
-    if (i > c) a[i] = 0.0;
-  return zeros;
-}
 
 template <int L>
 __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int32_t* __restrict__ slice_ptr,

@@ -1,0 +1,245 @@
+// Second-stage small kernels (Sec. III-B, Eq. 5, Alg. 1 applied to M),
+// templated on the sketch width L2 and run by one 64-lane wave:
+//   k_s2_orth  Q2 = orthonormal basis of span(Y2) (QR step), Y2 overwritten:
+//              two whitening passes (CholeskyQR2), each Wh = R^{-1} from the
+//              Cholesky factor of Y2^T Y2, or the eigen form V Lambda^{-1/2}
+//              (directions below 64 eps lambda_max dropped) when a pivot is
+//              below 1e-9 of the largest diagonal (e.g. M of exact low rank)
+//   k_s2_evd   B2 B2^T = U2 Lambda U2^T (small SVD): Cholesky B2 B2^T = C^T C
+//              and one-sided Jacobi on C^T, whose normalised columns are U2;
+//              E = sqrt(Lambda_R), D = Q2 U2_R, U2_R E^{-1} and D^T D
+#pragma once
+
+#include "slice_impl.h"
+
+namespace dpar2 {
+
+template <int L>
+__global__ __launch_bounds__(64) void k_s2_orth(int J, double* __restrict__ Y, Ctl* ctl) {
+  constexpr int RM = SC<L>::RM, LH = SC<L>::LH, LD = SC<L>::LD;
+  constexpr int TJ = 64;                       // rows of Y2 per LDS tile
+  __shared__ double Ys[TJ * LD];
+  __shared__ double Gs[L * LD], Ws[L * LD], row[L], rinv[L];
+  const int lane = threadIdx.x, c = lane % RM, h = lane / RM;
+  const bool cv = c < L;
+  unsigned warn = 0;
+  // rows j0 .. j0 + nj - 1 of Y2 into Ys (TJ * L / 64 = L loads per lane,
+  // issued together)
+  auto stage = [&](int j0, int nj) {
+    double yv[L];
+#pragma unroll
+    for (int u = 0; u < L; ++u) {
+      const int e = lane + 64 * u, jj = e / L;
+      const double x = Y[(jj < nj) ? (size_t)(j0 + jj) * L + e % L : 0];
+      yv[u] = (jj < nj) ? x : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < L; ++u) {
+      const int e = lane + 64 * u;
+      Ys[(e / L) * LD + e % L] = yv[u];
+    }
+  };
+#pragma unroll 1
+  for (int pass = 0; pass < 2; ++pass) {
+    // Gram column c (own rows), Y2 streamed through LDS
+    double t[LH], v[LH];
+#pragma unroll
+    for (int ii = 0; ii < LH; ++ii) {
+      t[ii] = 0.0;
+      v[ii] = (h * LH + ii == c) ? 1.0 : 0.0;
+    }
+    for (int j0 = 0; j0 < J; j0 += TJ) {
+      const int nj = (J - j0 < TJ) ? J - j0 : TJ;
+      stage(j0, nj);
+      __syncthreads();
+      if (cv) {
+        for (int jj = 0; jj < nj; ++jj) {
+          const double yc = Ys[jj * LD + c];
+#pragma unroll
+          for (int ii = 0; ii < LH; ++ii) {
+            const int a = h * LH + ii;
+            if (a < L) t[ii] = fma(Ys[jj * LD + a], yc, t[ii]);
+          }
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int ii = 0; ii < LH; ++ii) {
+      const int a = h * LH + ii;
+      if (cv && a < L) Gs[a * LD + c] = t[ii];
+    }
+    __syncthreads();
+    double dmax = 0.0;
+    for (int a = 0; a < L; ++a) dmax = fmax(dmax, Gs[a * LD + a]);
+    double col[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) col[i] = (lane < L) ? Gs[i * LD + lane] : 0.0;
+    __syncthreads();
+    const bool chol = dmax > 0.0 && lane_cholesky<L>(col, row, rinv, 1e-9 * dmax) == 0;
+    if (chol) {
+      if (lane < L) {
+#pragma unroll
+        for (int i = 0; i < L; ++i) Gs[i * LD + lane] = col[i];
+      }
+      __syncthreads();
+      if (lane < L) {
+        double x[L];
+#pragma unroll
+        for (int i = L - 1; i >= 0; --i) {
+          double s = (i == lane) ? 1.0 : 0.0;
+#pragma unroll
+          for (int j = i + 1; j < L; ++j) s = fma(-Gs[i * LD + j], x[j], s);
+          x[i] = (i > lane) ? 0.0 : s * rinv[i];
+        }
+#pragma unroll
+        for (int i = 0; i < L; ++i) Ws[i * LD + lane] = x[i];
+      }
+    } else {
+      if (split_jacobi<L, true>(t, v, c, h) == JACOBI_SWEEPS) warn |= 0x1u;
+      double lam = 0.0;
+#pragma unroll
+      for (int ii = 0; ii < LH; ++ii) lam = fma(t[ii], t[ii], lam);
+      lam = sqrt(col_sum<L>(lam));
+      double lmax = cv ? lam : 0.0;
+      for (int o = 1; o < 64; o <<= 1) lmax = fmax(lmax, __shfl_xor(lmax, o, 64));
+      const double ws = (lam > 64.0 * EPS64 * lmax && lam > 0.0) ? 1.0 / sqrt(lam) : 0.0;
+#pragma unroll
+      for (int ii = 0; ii < LH; ++ii) {
+        const int a = h * LH + ii;
+        if (cv && a < L) Ws[a * LD + c] = v[ii] * ws;
+      }
+    }
+    __syncthreads();
+    // Y2 <- Y2 Wh: lane (h, c) keeps column c of Wh and produces column c of
+    // the rows h, h + H, ... of each LDS tile
+    {
+      constexpr int H = SC<L>::H;
+      double w[L];
+#pragma unroll
+      for (int a = 0; a < L; ++a) w[a] = cv ? Ws[a * LD + c] : 0.0;
+      for (int j0 = 0; j0 < J; j0 += TJ) {
+        const int nj = (J - j0 < TJ) ? J - j0 : TJ;
+        __syncthreads();
+        stage(j0, nj);
+        __syncthreads();
+        if (cv)
+          for (int jj = h; jj < nj; jj += H) {
+            double s = 0.0;
+#pragma unroll
+            for (int a = 0; a < L; ++a) s = fma(Ys[jj * LD + a], w[a], s);
+            Y[(size_t)(j0 + jj) * L + c] = s;
+          }
+      }
+    }
+    __syncthreads();
+  }
+  for (int o = 1; o < 64; o <<= 1) warn |= __shfl_xor((int)warn, o, 64);
+  if (lane == 0 && warn) atomicOr(&ctl->warn, warn);
+}
+
+template <int L>
+__global__ __launch_bounds__(64) void k_s2_evd(int J, int R, const double* __restrict__ S2,
+                                               const double* __restrict__ Q2, double* __restrict__ D,
+                                               double* __restrict__ E, double* __restrict__ U2s,
+                                               double* __restrict__ DtD, Ctl* ctl) {
+  constexpr int RM = SC<L>::RM, LH = SC<L>::LH, LD = SC<L>::LD;
+  constexpr int NP = L * (L + 1) / 2;
+  __shared__ double Ss[L * LD], Us[L * LD], Es[L], row[L], rinv[L];
+  const int lane = threadIdx.x, c = lane % RM, h = lane / RM;
+  const bool cv = c < L;
+  unsigned warn = 0;
+  // B2 B2^T, packed upper-triangle pairs
+  for (int pi = lane; pi < NP; pi += 64) {
+    int a = 0, rem = pi;
+    while (rem >= L - a) {
+      rem -= L - a;
+      ++a;
+    }
+    const int b = a + rem;
+    const double s = S2[pi];
+    Ss[a * LD + b] = s;
+    Ss[b * LD + a] = s;
+  }
+  __syncthreads();
+  double col[L];
+#pragma unroll
+  for (int i = 0; i < L; ++i) col[i] = (lane < L) ? Ss[i * LD + lane] : 0.0;
+  double smax = 0.0;
+  for (int a = 0; a < L; ++a) smax = fmax(smax, Ss[a * LD + a]);
+  __syncthreads();
+  lane_cholesky<L>(col, row, rinv, 1e-13 * smax);
+  if (lane < L) {
+#pragma unroll
+    for (int i = 0; i < L; ++i) Ss[i * LD + lane] = col[i];
+  }
+  __syncthreads();
+  double t[LH], v[LH];
+#pragma unroll
+  for (int ii = 0; ii < LH; ++ii) {
+    const int b = h * LH + ii;
+    t[ii] = (cv && b < L) ? Ss[c * LD + b] : 0.0;
+  }
+  if (split_jacobi<L, false>(t, v, c, h) == JACOBI_SWEEPS) warn |= 0x1u;
+  double mu = 0.0;
+#pragma unroll
+  for (int ii = 0; ii < LH; ++ii) mu = fma(t[ii], t[ii], mu);
+  mu = sqrt(col_sum<L>(mu));   // singular value of B2
+  double mmax = cv ? mu : 0.0;
+  for (int o = 1; o < 64; o <<= 1) mmax = fmax(mmax, __shfl_xor(mmax, o, 64));
+  const double inv = (mu > 64.0 * EPS64 * mmax && mu > 0.0) ? 1.0 / mu : 0.0;
+  int rank = 0;
+  for (int c2 = 0; c2 < L; ++c2) {
+    const double m2 = __shfl(mu, c2, 64);
+    if (m2 > mu || (m2 == mu && c2 < c)) ++rank;
+  }
+  if (cv) {
+#pragma unroll
+    for (int ii = 0; ii < LH; ++ii) {
+      const int a = h * LH + ii;
+      if (a < L) Us[a * LD + rank] = t[ii] * inv;
+    }
+    if (h == 0) Es[rank] = mu;
+  }
+  __syncthreads();
+  if (lane < R) E[lane] = Es[lane];
+  for (int e = lane; e < L * R; e += 64) {
+    const int l = e / R, r = e % R;
+    U2s[e] = Es[r] > 0.0 ? Us[l * LD + r] / Es[r] : 0.0;
+  }
+  // D = Q2 U2_R (J x R); D^T D from the same values, in a fixed order
+  for (int j = lane; j < J; j += 64) {
+    double q[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) q[l] = Q2[(size_t)j * L + l];
+    for (int r = 0; r < R; ++r) {
+      double s = 0.0;
+#pragma unroll
+      for (int l = 0; l < L; ++l) s = fma(q[l], Us[l * LD + r], s);
+      D[(size_t)j * R + r] = s;
+    }
+  }
+  __syncthreads();
+  for (int e = lane; e < R * R; e += 64) {
+    const int a = e / R, b = e % R;
+    double s = 0.0;
+    for (int j = 0; j < J; ++j) s = fma(D[(size_t)j * R + a], D[(size_t)j * R + b], s);
+    DtD[e] = s;
+  }
+  for (int o = 1; o < 64; o <<= 1) warn |= __shfl_xor((int)warn, o, 64);
+  if (lane == 0 && warn) atomicOr(&ctl->warn, warn);
+}
+
+// which = 0: orthonormalise Y2 in place; which = 1: small SVD of B2 B2^T
+// (packed pairs S2) and D, E, U2_R E^{-1}, D^T D
+template <int L>
+hipError_t s2_small_launch(int which, int J, int R, double* Y2, const double* S2, double* D, double* E,
+                           double* U2s, double* DtD, Ctl* ctl, hipStream_t s) {
+  if (which == 0)
+    hipLaunchKernelGGL(k_s2_orth<L>, dim3(1), dim3(64), 0, s, J, Y2, ctl);
+  else
+    hipLaunchKernelGGL(k_s2_evd<L>, dim3(1), dim3(64), 0, s, J, R, S2, Y2, D, E, U2s, DtD, ctl);
+  return hipGetLastError();
+}
+
+}  // namespace dpar2
