@@ -235,18 +235,38 @@ __device__ __forceinline__ int col_exp(float m) {
   return e;
 }
 
-// three balanced base-256 digits of round(x * 2^(22 - e)), |x| < 2^e
-__device__ __forceinline__ void digits3(float x, int e, int& d0, int& d1, int& d2) {
-  const int q = (int)rint(ldexp((double)x, 22 - e));
-  d2 = (int)(int8_t)(q & 0xff);
-  const int q1 = (q - d2) / 256;
-  d1 = (int)(int8_t)(q1 & 0xff);
-  d0 = (q1 - d1) / 256;
+// round(x 2^(22 - e)) for |x| < 2^e: the scaled value is exact in FP32 and
+// |x 2^(22-e)| < 2^22, so adding 1.5 * 2^23 leaves the nearest integer (ties
+// to even) in the low mantissa bits.
+__device__ __forceinline__ int q22(float x, int e) {
+  const float m = ldexpf(x, 22 - e) + 12582912.0f;
+  return __float_as_int(m) - 0x4B400000;
 }
 
-__device__ __forceinline__ uint32_t pack4(int a, int b, int c, int d) {
-  return (uint32_t)(a & 0xff) | ((uint32_t)(b & 0xff) << 8) | ((uint32_t)(c & 0xff) << 16) |
-         ((uint32_t)(d & 0xff) << 24);
+// byte k of each of w0..w3 packed into one word (w0 in the low byte)
+template <int K>
+__device__ __forceinline__ uint32_t bytes_k(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3) {
+  constexpr uint32_t sel = 0x0c0c0000u | ((4u + K) << 8) | K;
+  const uint32_t lo = __builtin_amdgcn_perm(w1, w0, sel);
+  const uint32_t hi = __builtin_amdgcn_perm(w3, w2, sel);
+  return __builtin_amdgcn_perm(hi, lo, 0x05040100u);
+}
+
+// Balanced base-256 digits of four values |q| <= 2^22, q = d0 2^16 + d1 2^8
+// + d2 with |d| <= 128, packed as the byte planes p0 (d0), p1, p2.  With
+// r = q - d2 (a multiple of 256) and r2 = r - 256 d1 (a multiple of 2^16),
+// d2, d1 and d0 are the signed bytes 0, 1 and 2 of q, r and r2.
+__device__ __forceinline__ void digits4(const int (&q)[4], uint32_t& p0, uint32_t& p1, uint32_t& p2) {
+  uint32_t r[4], r2[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int rv = q[v] - __builtin_amdgcn_sbfe(q[v], 0, 8);
+    r[v] = (uint32_t)rv;
+    r2[v] = (uint32_t)(rv - (__builtin_amdgcn_sbfe(rv, 8, 8) << 8));
+  }
+  p2 = bytes_k<0>((uint32_t)q[0], (uint32_t)q[1], (uint32_t)q[2], (uint32_t)q[3]);
+  p1 = bytes_k<1>(r[0], r[1], r[2], r[3]);
+  p0 = bytes_k<2>(r2[0], r2[1], r2[2], r2[3]);
 }
 
 template <int LT, int JT, bool VEC>
@@ -380,12 +400,13 @@ __global__ __launch_bounds__(256) void k_sketch_q(const float* __restrict__ slab
       const int col = lt * 16 + lr;
       const float m = fmaxf(fmaxf(sYm[col], sYm[LP + col]), fmaxf(sYm[2 * LP + col], sYm[3 * LP + col]));
       const int e = col_exp(m);
-      int d[3][4];
+      int q[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) digits3(acc[lt][v], e, d[0][v], d[1][v], d[2][v]);
+      for (int v = 0; v < 4; ++v) q[v] = q22(acc[lt][v], e);
+      uint32_t p[3];
+      digits4(q, p[0], p[1], p[2]);
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
-        sYq[(a * LP + col) * QW + 4 * w + lk] = pack4(d[a][0], d[a][1], d[a][2], d[a][3]);
+      for (int a = 0; a < 3; ++a) sYq[(a * LP + col) * QW + 4 * w + lk] = p[a];
       if (w == 0 && lk == 0) sYe[col] = e;
     }
     // digits of X
@@ -396,11 +417,10 @@ __global__ __launch_bounds__(256) void k_sketch_q(const float* __restrict__ slab
       uint32_t pk[3][4];
 #pragma unroll
       for (int r4 = 0; r4 < 4; ++r4) {
-        int d[3][4];
+        int qv[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) digits3(sX[(16 * q + 4 * r4 + v) * XS + j], e, d[0][v], d[1][v], d[2][v]);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) pk[a][r4] = pack4(d[a][0], d[a][1], d[a][2], d[a][3]);
+        for (int v = 0; v < 4; ++v) qv[v] = q22(sX[(16 * q + 4 * r4 + v) * XS + j], e);
+        digits4(qv, pk[0][r4], pk[1][r4], pk[2][r4]);
       }
 #pragma unroll
       for (int a = 0; a < 3; ++a)
@@ -449,8 +469,10 @@ __global__ __launch_bounds__(256) void k_sketch_q(const float* __restrict__ slab
         const int ecol = eb[cb + lr];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const double val = (double)S0[v] * 4294967296.0 + (double)S1[v] * 16777216.0 +
-                             (double)S2[v] * 65536.0 + (double)S3[v] * 256.0 + (double)S4[v];
+          // |S0| <= 2^18, |S1| <= 2^20, |S3| <= 2^21, |S4| <= 2^20: the two
+          // pairs combine exactly in int32, the total exactly in FP64 (< 2^52)
+          const int hi = S0[v] * 256 + S1[v], lo = S3[v] * 256 + S4[v];
+          const double val = fma((double)hi, 16777216.0, fma((double)S2[v], 65536.0, (double)lo));
           const int erow = sYe[ca + f32_row(lane, v)];
           pacc[qi][v] += ldexp(val, erow + ecol - 44);
         }
