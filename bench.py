@@ -38,7 +38,46 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic.json from two rocprofv3 --pmc counter_collection.csv "
+                         "files (FETCH_SIZE, WRITE_SIZE) of a --calib-copy run, then exit")
     return ap.parse_args()
+
+
+SLAB_KERNEL = "k_sketch_q"
+CALIB_BYTES = 1 << 30          # the --calib-copy copy reads and writes 1 GiB
+
+
+def write_traffic(fetch_csv, write_csv):
+    """HBM bytes per slab-pass launch from FETCH_SIZE / WRITE_SIZE (KiB per
+    dispatch), each scaled so that the 1 GiB calibration copy reads as 1 GiB."""
+    import csv
+
+    def per_dispatch(path, counter):
+        slab, copy = [], []
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            v = float(r["Counter_Value"]) * 1024.0
+            if SLAB_KERNEL in r["Kernel_Name"]:
+                slab.append(v)
+            elif "copyBuffer" in r["Kernel_Name"]:
+                copy.append(v)
+        return sum(slab) / len(slab), max(copy)
+
+    f_slab, f_copy = per_dispatch(fetch_csv, "FETCH_SIZE")
+    w_slab, w_copy = per_dispatch(write_csv, "WRITE_SIZE")
+    f_scale, w_scale = CALIB_BYTES / f_copy, CALIB_BYTES / w_copy
+    src = os.path.join(ROOT, "paper_2203_12798_amd", "csrc", "k_sketch.hip")
+    rec = {"kernel": SLAB_KERNEL, "source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
+           "fetch_counter_bytes": f_slab, "write_counter_bytes": w_slab,
+           "fetch_scale": f_scale, "write_scale": w_scale,
+           "bytes_per_launch": int(round(f_slab * f_scale + w_slab * w_scale)),
+           "calibration": "1 GiB device copy: FETCH_SIZE and WRITE_SIZE scaled to read as 1 GiB each"}
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
 
 
 def traffic_record(kernel_src):
@@ -57,6 +96,9 @@ def traffic_record(kernel_src):
 
 def main():
     args = parse()
+    if args.write_traffic:
+        write_traffic(*args.write_traffic)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(slices would shard across GPUs; see the design notes)", file=sys.stderr)

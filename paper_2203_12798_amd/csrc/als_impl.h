@@ -36,6 +36,7 @@ struct AlsArgs {
   double *H, *V, *W;
   double *Pw, *Psi, *Mk;
   double *small, *partA, *partB, *partC, *partBegin;
+  double* red;   // column sums of the block partials: A (RR), B (RR), C (RR + 2), begin (3 RR)
   double* trace;
   double tol;
   Ctl* ctl;
@@ -54,7 +55,7 @@ struct RC {
 // lane j holds column j of T in t[] and of the accumulated right rotation in
 // v[].  Round-robin pairing; both lanes of a pair compute the same rotation
 // from the same sums.  All lanes of the wave must call it.  Returns sweeps.
-template <int R>
+template <int R, bool WITHV = true>
 __device__ inline int group_jacobi(double (&t)[R], double (&v)[R], int j, int gbase) {
   constexpr int N = RC<R>::N;
   int sweep;
@@ -67,8 +68,10 @@ __device__ inline int group_jacobi(double (&t)[R], double (&v)[R], int j, int gb
       double tp[R], vp[R];
 #pragma unroll
       for (int i = 0; i < R; ++i) tp[i] = __shfl(t[i], src, 64);
+      if constexpr (WITHV) {
 #pragma unroll
-      for (int i = 0; i < R; ++i) vp[i] = __shfl(v[i], src, 64);
+        for (int i = 0; i < R; ++i) vp[i] = __shfl(v[i], src, 64);
+      }
       double aa = 0.0, bb = 0.0, ab = 0.0;
 #pragma unroll
       for (int i = 0; i < R; ++i) {
@@ -86,9 +89,10 @@ __device__ inline int group_jacobi(double (&t)[R], double (&v)[R], int j, int gb
         rotated = 1;
         const double sa = low ? -s : s;   // low: c a - s b ; high: s a + c b = c b + s a
 #pragma unroll
-        for (int i = 0; i < R; ++i) {
-          t[i] = fma(c, t[i], sa * tp[i]);
-          v[i] = fma(c, v[i], sa * vp[i]);
+        for (int i = 0; i < R; ++i) t[i] = fma(c, t[i], sa * tp[i]);
+        if constexpr (WITHV) {
+#pragma unroll
+          for (int i = 0; i < R; ++i) v[i] = fma(c, v[i], sa * vp[i]);
         }
       }
     }
@@ -198,25 +202,28 @@ __device__ inline int block_pinv(const double* G, double* Ginv, double* sT, doub
 }
 
 // out[e] = sum_b part[b * stride + e] for e < width, summed in a fixed order
-// by teams of T lanes (T a power of two, team inside one wave).
+// by teams of T lanes (T a power of two, team inside one wave, as large as
+// the block allows), eight independent loads in flight per lane.
 __device__ inline void team_sum(const double* __restrict__ part, int nb, int stride, int width, double* out) {
   int T = 1;
   while (T < 64 && 2 * T * width <= (int)blockDim.x) T *= 2;
   const int team = threadIdx.x / T, sub = threadIdx.x % T;
   const int nteam = blockDim.x / T;
   for (int e = team; e < width; e += nteam) {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    double s[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] = 0.0;
     int b = sub;
-    for (; b + 3 * T < nb; b += 4 * T) {
-      s0 += part[(size_t)b * stride + e];
-      s1 += part[(size_t)(b + T) * stride + e];
-      s2 += part[(size_t)(b + 2 * T) * stride + e];
-      s3 += part[(size_t)(b + 3 * T) * stride + e];
+    for (; b + 7 * T < nb; b += 8 * T) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s[u] += part[(size_t)(b + u * T) * stride + e];
     }
-    for (; b < nb; b += T) s0 += part[(size_t)b * stride + e];
-    double s = (s0 + s1) + (s2 + s3);
-    for (int o = T / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if (sub == 0) out[e] = s;
+#pragma unroll
+    for (int u = 0; u < 7; ++u)
+      if (b + u * T < nb) s[u] += part[(size_t)(b + u * T) * stride + e];
+    double x = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+    for (int o = T / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if (sub == 0) out[e] = x;
   }
   __syncthreads();
 }
@@ -248,7 +255,7 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_A(AlsArgs a) {
   if (ctl->done) return;
   constexpr int RM = RC<R>::RM, GPB = RC<R>::GPB, TPB = RC<R>::TPB, RR = R * R;
   __shared__ double sH[RR], sB[RR];
-  __shared__ double sF[GPB * RR], sZ[GPB * RR], sP[GPB * RR];
+  __shared__ double sF[GPB * RR], sZ[GPB * RR], sP[GPB * RR], sT[GPB * RR];
   const int K = a.K;
   const int tid = threadIdx.x, g = tid / RM, j = tid % RM;
   const int lane = tid & 63, gbase = lane & ~(RM - 1);
@@ -260,6 +267,7 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_A(AlsArgs a) {
   double* F_ = sF + g * RR;
   double* Z_ = sZ + g * RR;
   double* P_ = sP + g * RR;
+  double* T_ = sT + g * RR;
   double acc[R];
 #pragma unroll
   for (int i = 0; i < R; ++i) acc[i] = 0.0;
@@ -268,8 +276,20 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_A(AlsArgs a) {
     const int64_t k = base + g;
     const bool live = (k < K) && (j < R);
     __syncthreads();
-    if (k < K)
-      for (int e = j; e < RR; e += RM) F_[e] = a.F[(size_t)k * RR + e];
+    {
+      constexpr int NF = (RR + RM - 1) / RM;   // loads issued together (clamped index)
+      double fv[NF];
+#pragma unroll
+      for (int u = 0; u < NF; ++u) {
+        const int e = j + RM * u;
+        const bool ok = k < K && e < RR;
+        const double x = a.F[ok ? (size_t)k * RR + e : 0];
+        fv[u] = ok ? x : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < NF; ++u)
+        if (j + RM * u < RR) F_[j + RM * u] = fv[u];
+    }
     __syncthreads();
     double t[R], v[R], wk[R];
 #pragma unroll
@@ -277,33 +297,38 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_A(AlsArgs a) {
       wk[i] = (k < K) ? a.W[(size_t)k * R + i] : 0.0;
       v[i] = live ? a.Pw[(size_t)k * RR + i * R + j] : 0.0;
     }
-    // t = F^(k) Bm diag(W_k) H^T p_j  (column j of T_k P_k)
+    // column j of T_k = F^(k) Bm diag(W(k,:)) H^T (Eq. 8)
     {
-      double u[R];
-#pragma unroll
-      for (int q = 0; q < R; ++q) {
-        double s = 0.0;
-#pragma unroll
-        for (int i = 0; i < R; ++i) s = fma(sH[i * R + q], v[i], s);
-        u[q] = s * wk[q];
-      }
       double x[R];
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         double s = 0.0;
 #pragma unroll
-        for (int i = 0; i < R; ++i) s = fma(sB[q * R + i], u[i], s);
+        for (int i = 0; i < R; ++i) s = fma(sB[q * R + i], wk[i] * sH[(live ? j : 0) * R + i], s);
         x[q] = s;
       }
+      if (live)
 #pragma unroll
-      for (int q = 0; q < R; ++q) {
-        double s = 0.0;
+        for (int q = 0; q < R; ++q) {
+          double s = 0.0;
 #pragma unroll
-        for (int i = 0; i < R; ++i) s = fma(F_[q * R + i], x[i], s);
-        t[q] = live ? s : 0.0;
-      }
+          for (int i = 0; i < R; ++i) s = fma(F_[q * R + i], x[i], s);
+          T_[q * R + j] = s;
+        }
     }
-    if (group_jacobi<R>(t, v, j, gbase) == JACOBI_SWEEPS) warn |= 0x1u;
+    __syncthreads();
+    // t = T_k p_j, p_j the warm start (column j of the previous P_k)
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      double s = 0.0;
+      if (live)
+#pragma unroll
+        for (int i = 0; i < R; ++i) s = fma(T_[q * R + i], v[i], s);
+      t[q] = s;
+    }
+    // T_k P V' = Z Sigma (one-sided Jacobi without accumulating V'); then
+    // z_j = t / sigma_j and the new p_j = T_k^T z_j / sigma_j
+    if (group_jacobi<R, false>(t, v, j, gbase) == JACOBI_SWEEPS) warn |= 0x1u;
     double sig = 0.0;
 #pragma unroll
     for (int i = 0; i < R; ++i) sig = fma(t[i], t[i], sig);
@@ -314,8 +339,17 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_A(AlsArgs a) {
     const double inv = (sig > 0.0) ? 1.0 / sig : 0.0;
     if (live) {
 #pragma unroll
+      for (int i = 0; i < R; ++i) t[i] *= inv;
+#pragma unroll
       for (int i = 0; i < R; ++i) {
-        Z_[i * R + j] = t[i] * inv;
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < R; ++q) s = fma(T_[q * R + i], t[q], s);
+        v[i] = s * inv;
+      }
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        Z_[i * R + j] = t[i];
         P_[i * R + j] = v[i];
         a.Pw[(size_t)k * RR + i * R + j] = v[i];
       }
@@ -386,7 +420,8 @@ __global__ __launch_bounds__(EPI_THREADS) void k_als_A_epi(AlsArgs a, int nblk) 
   __shared__ double G1[32 * LD], Gm[32 * LD], Gi[32 * LD], sT[32 * LD], sV[32 * LD], sg[32], tmp[RR];
   __shared__ int sflag;
   const int tid = threadIdx.x;
-  team_sum(a.partA, nblk, RR, RR, tmp);
+  (void)nblk;
+  team_sum(a.red, 1, RR, RR, tmp);
   const double* WtW = a.small + SM_WTW * RR;
   const double* VtV = a.small + SM_VTV * RR;
   for (int e = tid; e < RR; e += EPI_THREADS) {
@@ -474,7 +509,8 @@ __global__ __launch_bounds__(EPI_THREADS) void k_als_B_epi(AlsArgs a, int nblk) 
   __shared__ int sflag;
   const int tid = threadIdx.x;
   double* small = a.small;
-  team_sum(a.partB, nblk, RR, RR, tmp);
+  (void)nblk;
+  team_sum(a.red + RR, 1, RR, RR, tmp);
   const double* WtW = small + SM_WTW * RR;
   const double* HtH = small + SM_HTH * RR;
   const double* DtD = small + SM_DTD * RR;
@@ -627,7 +663,8 @@ __global__ __launch_bounds__(EPI_THREADS) void k_als_C_epi(AlsArgs a, int nblk) 
   if (ctl->done) return;
   constexpr int RR = R * R;
   __shared__ double tmp[RR + 2];
-  team_sum(a.partC, nblk, RR + 2, RR + 2, tmp);
+  (void)nblk;
+  team_sum(a.red + 2 * RR, 1, RR + 2, RR + 2, tmp);
   for (int e = threadIdx.x; e < RR; e += EPI_THREADS) a.small[SM_WTW * RR + e] = tmp[e];
   if (threadIdx.x == 0) {
     const double e = ctl->e0 - 2.0 * tmp[RR] + tmp[RR + 1];
@@ -678,7 +715,8 @@ __global__ __launch_bounds__(EPI_THREADS) void k_als_begin_epi(AlsArgs a, int nb
   Ctl* ctl = a.ctl;
   constexpr int RR = R * R;
   __shared__ double tmp[3 * RR];
-  team_sum(a.partBegin, nblk, 3 * RR, 3 * RR, tmp);
+  (void)nblk;
+  team_sum(a.red + 3 * RR + 2, 1, 3 * RR, 3 * RR, tmp);
   for (int e = threadIdx.x; e < RR; e += EPI_THREADS) {
     a.small[SM_WTW * RR + e] = tmp[e];
     a.small[SM_VTV * RR + e] = tmp[RR + e];
@@ -698,16 +736,24 @@ hipError_t als_launch(int phase, const AlsArgs& a, hipStream_t s) {
   if (nb > RED_MAXBLK) nb = RED_MAXBLK;
   if (nb < 1) nb = 1;
   const int n = (int)nb;
+  // each per-slice kernel writes one partial per block; a many-block column
+  // sum reduces them (one load per thread) before the single-block epilogue
+  constexpr int RR = R * R;
+  hipError_t e;
   if (phase == 0) {
     hipLaunchKernelGGL(k_als_begin<R>, dim3(n), dim3(TPB), 0, s, a);
-    hipLaunchKernelGGL(k_als_begin_epi<R>, dim3(1), dim3(EPI_THREADS), 0, s, a, n);
+    if ((e = launch_colsum(n, 3 * RR, 3 * RR, a.partBegin, a.red + 3 * RR + 2, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_als_begin_epi<R>, dim3(1), dim3(EPI_THREADS), 0, s, a, 1);
   } else {
     hipLaunchKernelGGL(k_als_A<R>, dim3(n), dim3(TPB), 0, s, a);
-    hipLaunchKernelGGL(k_als_A_epi<R>, dim3(1), dim3(EPI_THREADS), 0, s, a, n);
+    if ((e = launch_colsum(n, RR, RR, a.partA, a.red, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_als_A_epi<R>, dim3(1), dim3(EPI_THREADS), 0, s, a, 1);
     hipLaunchKernelGGL(k_als_B<R>, dim3(n), dim3(TPB), 0, s, a);
-    hipLaunchKernelGGL(k_als_B_epi<R>, dim3(1), dim3(EPI_THREADS), 0, s, a, n);
+    if ((e = launch_colsum(n, RR, RR, a.partB, a.red + RR, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_als_B_epi<R>, dim3(1), dim3(EPI_THREADS), 0, s, a, 1);
     hipLaunchKernelGGL(k_als_C<R>, dim3(n), dim3(TPB), 0, s, a);
-    hipLaunchKernelGGL(k_als_C_epi<R>, dim3(1), dim3(EPI_THREADS), 0, s, a, n);
+    if ((e = launch_colsum(n, RR + 2, RR + 2, a.partC, a.red + 2 * RR, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_als_C_epi<R>, dim3(1), dim3(EPI_THREADS), 0, s, a, 1);
   }
   return hipGetLastError();
 }

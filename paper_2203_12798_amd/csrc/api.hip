@@ -157,6 +157,7 @@ Layout make_layout(const dpar2_tensor* X, const dpar2_opts* o) {
   y.partB = take(sizeof(double) * (size_t)(y.nblkB * RR));
   y.partC = take(sizeof(double) * (size_t)(y.nblkC * (RR + 2)));
   y.partBegin = take(sizeof(double) * (size_t)(y.nblkC * 3 * RR));
+  y.red = take(sizeof(double) * (size_t)(6 * RR + 2));
 
   y.fitp = take(sizeof(double) * (size_t)(2 * y.nblkF));
   y.trace = take(sizeof(double) * (size_t)(K * L * R));   // Theta for the U output

@@ -35,7 +35,7 @@ struct Layout {
   size_t xnorm2, Mt, Phi, sig1;
   size_t Y2p, Y2, B2t, S2p, U2;
   size_t D, E, F, FtFp;
-  size_t Psi, Pw, Mk, small, partA, partB, partC, partBegin, fitp, trace, om1;
+  size_t Psi, Pw, Mk, small, partA, partB, partC, partBegin, red, fitp, trace, om1;
   size_t total;
 };
 
@@ -68,6 +68,9 @@ hipError_t launch_slice_finish(int64_t K, int J, int L, int R, const int32_t* sl
                                const double* partP, const double* partS, double* xnorm2,
                                double* Mt, double* Phi, double* sig1, Ctl* ctl, hipStream_t s);
 hipError_t launch_stage2(const Layout& lay, char* ws, const float* omega2, hipStream_t s);
+// out[e] = sum_{b < nb} part[b * stride + e] for e < width, in a fixed order
+hipError_t launch_colsum(int64_t nb, int64_t stride, int64_t width, const double* part, double* out,
+                         hipStream_t s);
 hipError_t launch_als_begin(const Layout& lay, char* ws, double* H, double* V, double* W, hipStream_t s);
 hipError_t launch_als_iteration(const Layout& lay, char* ws, double* H, double* V, double* W,
                                 double* err_trace, double tol, hipStream_t s);

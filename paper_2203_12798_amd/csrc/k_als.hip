@@ -148,6 +148,7 @@ static AlsArgs make_args(const Layout& lay, char* ws, double* H, double* V, doub
   a.partB = reinterpret_cast<double*>(ws + lay.partB);
   a.partC = reinterpret_cast<double*>(ws + lay.partC);
   a.partBegin = reinterpret_cast<double*>(ws + lay.partBegin);
+  a.red = reinterpret_cast<double*>(ws + lay.red);
   a.trace = trace;
   a.tol = tol;
   a.ctl = reinterpret_cast<Ctl*>(ws + lay.ctl);

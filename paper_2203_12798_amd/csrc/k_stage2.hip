@@ -162,6 +162,13 @@ __global__ __launch_bounds__(256) void k_s2_b(int64_t KR, int J, int L2, const d
   }
 }
 
+hipError_t launch_colsum(int64_t nb, int64_t stride, int64_t width, const double* part, double* out,
+                         hipStream_t s) {
+  if (width <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_colsum, dim3((unsigned)width), dim3(256), 0, s, nb, stride, part, out, (int64_t)1);
+  return hipGetLastError();
+}
+
 hipError_t s2_small_dispatch_1(int L2, int which, int J, int R, double* Y2, const double* S2, double* D,
                                double* E, double* U2s, double* DtD, Ctl* ctl, hipStream_t s);
 hipError_t s2_small_dispatch_2(int L2, int which, int J, int R, double* Y2, const double* S2, double* D,
