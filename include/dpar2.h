@@ -29,8 +29,9 @@
  *     report read in dpar2_report_read.
  *   - Matrices are row-major.  Factor matrices are float64: H (R x R),
  *     V (J x R), W (K x R); S_k = diag(W(k,:)).
- *   - Irregular tensor {X_k}: slab of N = sum_k I_k rows, each of J float32
- *     values, row-major; slice k is rows row_offsets[k] .. row_offsets[k+1]-1.
+ *   - Irregular tensor {X_k}: slab of N = sum_k I_k rows, each of J values
+ *     (float32, bfloat16 or fp8 e4m3, see dpar2_dtype), row-major; slice k is
+ *     rows row_offsets[k] .. row_offsets[k+1]-1.
  *   - Errors: every call returns a dpar2_status.  Shape and argument errors are
  *     detected on the host before anything is enqueued.  HIP errors map to
  *     DPAR2_EHIP with the HIP message available from dpar2_last_error()
@@ -58,7 +59,11 @@ typedef enum {
 } dpar2_status;
 
 typedef enum {
-  DPAR2_F32 = 0          /* slab of float32 values */
+  DPAR2_F32 = 0,         /* slab of float32 values                                  */
+  DPAR2_BF16 = 1,        /* slab of bfloat16 bit patterns (uint16); J <= 128         */
+  DPAR2_FP8_E4M3 = 2     /* slab of OCP fp8 e4m3fn bytes; value = decode(byte) *
+                            slice_scale[k] in float32 (powers of two keep it exact);
+                            J <= 128                                                 */
 } dpar2_dtype;
 
 /* Warning bits reported in dpar2_report.warn_bits (device-side, never fatal). */
@@ -73,6 +78,8 @@ typedef struct {
   const int64_t* row_offsets_host;  /* (host) the same K+1 values (validation, schedule) */
   const void* slab;                 /* device, N x J row-major, N = row_offsets[K]       */
   int32_t dtype;                    /* dpar2_dtype                                       */
+  const float* slice_scale;         /* device, K per-slice scales (DPAR2_FP8_E4M3 only,
+                                       else ignored)                                     */
 } dpar2_tensor;
 
 /* Parameters of Alg. 1 / Alg. 3. */
@@ -85,6 +92,10 @@ typedef struct {
   int32_t max_iter;    /* iterations of the repeat loop of Alg. 3, >= 0             */
   double tol;          /* stop when e_{t-1} - e_t < tol * e_{t-1}; tol < 0: never   */
   uint32_t flags;      /* reserved, must be 0                                       */
+  int32_t power_iters; /* q of Alg. 1 for the first stage, 0..4; each step is one more
+                          pass over the slab with a per-slice sketch matrix (the
+                          orthonormal right singular vectors of the previous B_k,
+                          which spans X_k^T Q_k: the stabilised power iteration)   */
 } dpar2_opts;
 
 /* Factor matrices (device, float64, row-major). */
@@ -102,7 +113,8 @@ typedef struct {
   const double* D;       /* J x R                                                    */
   const double* E;       /* R, diagonal of E                                         */
   const double* F;       /* (K R) x R; F^(k) = rows kR .. kR+R-1                     */
-  const double* Phi;     /* K x L x R: A_k = (X_k Omega_1) Phi_k                     */
+  const double* Phi;     /* K x L x R: A_k = (X_k Omega) Phi_k, Omega = Omega_1 (q = 0)
+                            or the slice's power-step sketch matrix                   */
   const double* sigma;   /* K x R: first-stage singular values (diagonal of B_k)    */
   const double* xnorm2;  /* K: ||X_k||_F^2                                           */
 } dpar2_compressed;
@@ -126,7 +138,10 @@ size_t dpar2_workspace_size(const dpar2_tensor* X, const dpar2_opts* o);
  * after it).  omega1: device float32 J x L (Gaussian test matrix shared by all
  * slices); omega2: device float32 (K R) x L2 (second stage).  Leaves A_k (as a
  * recipe), M, D, E, F and sum ||X_k||^2 in the workspace.  The slab is read
- * once.  Resets the iteration state and report held in the workspace. */
+ * 1 + opts.power_iters times.  For bf16 / fp8 slabs the sketch runs on the bf16
+ * matrix cores with Omega rounded to bf16 (round to nearest even); the Gram
+ * and projection are exact for every dtype.  Resets the iteration state and
+ * report held in the workspace. */
 dpar2_status dpar2_compress(const dpar2_tensor* X, const dpar2_opts* o,
                             const float* omega1, const float* omega2,
                             void* ws, size_t ws_bytes, dpar2_stream_t stream);

@@ -20,6 +20,8 @@ DPAR2_ENUMERIC = -3
 DPAR2_EHIP = -5
 DPAR2_EWORKSPACE = -6
 DPAR2_F32 = 0
+DPAR2_BF16 = 1
+DPAR2_FP8_E4M3 = 2
 
 WARN_JACOBI_CAP = 0x1
 WARN_RANK_DEFICIENT = 0x2
@@ -34,12 +36,13 @@ class Dpar2Error(RuntimeError):
 class c_tensor(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int64), ("J", ctypes.c_int64),
                 ("row_offsets", ctypes.c_void_p), ("row_offsets_host", ctypes.c_void_p),
-                ("slab", ctypes.c_void_p), ("dtype", ctypes.c_int32)]
+                ("slab", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("slice_scale", ctypes.c_void_p)]
 
 
 class c_opts(ctypes.Structure):
     _fields_ = [("rank", ctypes.c_int32), ("sketch", ctypes.c_int32), ("sketch2", ctypes.c_int32),
-                ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("flags", ctypes.c_uint32)]
+                ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("flags", ctypes.c_uint32),
+                ("power_iters", ctypes.c_int32)]
 
 
 class c_factors(ctypes.Structure):
@@ -131,36 +134,56 @@ class Options:
     sketch2: int
     max_iter: int
     tol: float = -1.0
+    power_iters: int = 0
 
     def c(self) -> c_opts:
-        return c_opts(self.rank, self.sketch, self.sketch2, self.max_iter, float(self.tol), 0)
+        return c_opts(self.rank, self.sketch, self.sketch2, self.max_iter, float(self.tol), 0,
+                      self.power_iters)
 
 
 class Tensor:
-    """An irregular tensor resident on the GPU: float32 slab (N x J,
-    row-major) and int64 row offsets (device copy + host copy)."""
+    """An irregular tensor resident on the GPU: slab (N x J, row-major) of
+    float32, of bfloat16 bit patterns (uint16 storage, torch.int16) or of fp8
+    e4m3 bytes (torch.uint8) with per-slice float32 scales, and int64 row
+    offsets (device copy + host copy)."""
 
-    def __init__(self, slab, offsets_dev, offsets_host: np.ndarray):
+    def __init__(self, slab, offsets_dev, offsets_host: np.ndarray, dtype: int = DPAR2_F32, scale=None):
         import torch
-        assert slab.is_cuda and slab.dtype == torch.float32 and slab.is_contiguous() and slab.dim() == 2
+        want = {DPAR2_F32: torch.float32, DPAR2_BF16: torch.int16, DPAR2_FP8_E4M3: torch.uint8}[dtype]
+        assert slab.is_cuda and slab.dtype == want and slab.is_contiguous() and slab.dim() == 2
         assert offsets_dev.is_cuda and offsets_dev.dtype == torch.int64 and offsets_dev.is_contiguous()
+        if dtype == DPAR2_FP8_E4M3:
+            assert scale is not None and scale.is_cuda and scale.dtype == torch.float32
         self.slab = slab
+        self.dtype = dtype
+        self.scale = scale
         self.offsets_dev = offsets_dev
         self.offsets_host = np.ascontiguousarray(offsets_host, dtype=np.int64)
         self.K = int(self.offsets_host.shape[0] - 1)
         self.J = int(slab.shape[1])
 
     @classmethod
-    def from_numpy(cls, slab: np.ndarray, offsets: np.ndarray, device="cuda:0"):
+    def from_numpy(cls, slab: np.ndarray, offsets: np.ndarray, device="cuda:0", dtype: int = DPAR2_F32,
+                   scale: np.ndarray | None = None):
+        """slab: float32 values, or for DPAR2_BF16 the uint16 bit patterns,
+        for DPAR2_FP8_E4M3 the uint8 codes (then scale: K float32)."""
         import torch
-        s = torch.from_numpy(np.ascontiguousarray(slab, dtype=np.float32)).to(device)
+        if dtype == DPAR2_F32:
+            s = torch.from_numpy(np.ascontiguousarray(slab, dtype=np.float32)).to(device)
+        elif dtype == DPAR2_BF16:
+            s = torch.from_numpy(np.ascontiguousarray(slab, dtype=np.uint16).view(np.int16)).to(device)
+        else:
+            s = torch.from_numpy(np.ascontiguousarray(slab, dtype=np.uint8)).to(device)
         o = torch.from_numpy(np.ascontiguousarray(offsets, dtype=np.int64)).to(device)
-        return cls(s, o, offsets)
+        sc = None
+        if scale is not None:
+            sc = torch.from_numpy(np.ascontiguousarray(scale, dtype=np.float32)).to(device)
+        return cls(s, o, offsets, dtype, sc)
 
     def c(self) -> c_tensor:
         return c_tensor(self.K, self.J, _ptr(self.offsets_dev),
                         self.offsets_host.ctypes.data_as(ctypes.c_void_p).value,
-                        _ptr(self.slab), DPAR2_F32)
+                        _ptr(self.slab), self.dtype, _ptr(self.scale) if self.scale is not None else None)
 
 
 class Factors:

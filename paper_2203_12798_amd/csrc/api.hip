@@ -85,8 +85,12 @@ dpar2_status validate(const dpar2_tensor* X, const dpar2_opts* o) {
   if (X->J > (int64_t)1 << 30) return fail(DPAR2_EINVAL, "J too large");
   if (!X->row_offsets || !X->row_offsets_host || !X->slab)
     return fail(DPAR2_EINVAL, "row_offsets, row_offsets_host and slab must be non-NULL");
-  if (X->dtype != DPAR2_F32) return fail(DPAR2_EINVAL, "unsupported slab dtype");
+  if (X->dtype != DPAR2_F32 && X->dtype != DPAR2_BF16 && X->dtype != DPAR2_FP8_E4M3)
+    return fail(DPAR2_EINVAL, "unsupported slab dtype");
+  if (X->dtype == DPAR2_FP8_E4M3 && !X->slice_scale)
+    return fail(DPAR2_EINVAL, "fp8 slabs need slice_scale");
   if (o->flags != 0) return fail(DPAR2_EINVAL, "opts.flags must be 0");
+  if (o->power_iters < 0 || o->power_iters > 4) return fail(DPAR2_EINVAL, "power_iters must be in [0, 4]");
   const int R = o->rank, L = o->sketch, L2 = o->sketch2;
   if (R < 1 || R > 32) return fail(DPAR2_ESHAPE, "rank must be in [1, 32]");
   if (L < R || L > 32) return fail(DPAR2_ESHAPE, "sketch width L must satisfy R <= L <= 32");
@@ -96,7 +100,8 @@ dpar2_status validate(const dpar2_tensor* X, const dpar2_opts* o) {
   if (L > J) return fail(DPAR2_ESHAPE, "sketch width L exceeds J");
   if (L2 > J) return fail(DPAR2_ESHAPE, "sketch width L2 exceeds J");
   if ((int64_t)L2 > K * R) return fail(DPAR2_ESHAPE, "sketch width L2 exceeds K*R");
-  if (!sketch_supported((int)J, L)) return fail(DPAR2_ESHAPE, "J > 256 is not supported by the slab pass");
+  if (!sketch_supported((int)J, L, X->dtype))
+    return fail(DPAR2_ESHAPE, "J exceeds the slab pass limit (256 for float32, 128 for bf16 / fp8)");
   const int64_t* off = X->row_offsets_host;
   if (off[0] != 0) return fail(DPAR2_EINVAL, "row_offsets[0] must be 0");
   for (int64_t k = 0; k < K; ++k) {
@@ -162,6 +167,7 @@ Layout make_layout(const dpar2_tensor* X, const dpar2_opts* o) {
   y.fitp = take(sizeof(double) * (size_t)(2 * y.nblkF));
   y.trace = take(sizeof(double) * (size_t)(K * L * R));   // Theta for the U output
   y.om1 = take(sizeof(float) * (size_t)(J * L));           // copy of Omega_1 for the U pass
+  y.omq = take(o->power_iters > 0 ? sizeof(float) * (size_t)(K * J * L) : 0);   // power-step sketches
   y.total = p;
   return y;
 }
@@ -287,17 +293,34 @@ dpar2_status dpar2_compress(const dpar2_tensor* X, const dpar2_opts* o, const fl
       g_prof.used++;
     }
   }
-  if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-  e = launch_sketch(static_cast<const float*>(X->slab), (int)X->J, y.L, omega1, items, y.n_items, partG,
-                    partP, partS, s);
-  if (e != hipSuccess) return hip_fail(e, "slab pass");
-  if (ev1 && (e = hipEventRecord(ev1, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-  e = launch_slice_finish(y.K, (int)y.J, y.L, y.R, reinterpret_cast<const int32_t*>(w + y.slice_ptr),
-                          reinterpret_cast<const int32_t*>(w + y.slice_list), partG, partP, partS,
-                          reinterpret_cast<double*>(w + y.xnorm2), reinterpret_cast<double*>(w + y.Mt),
-                          reinterpret_cast<double*>(w + y.Phi), reinterpret_cast<double*>(w + y.sig1), ctl,
-                          s);
-  if (e != hipSuccess) return hip_fail(e, "slice finish");
+  SlabArgs sa;
+  std::memset(&sa, 0, sizeof(sa));
+  sa.slab = X->slab;
+  sa.scale = X->slice_scale;
+  sa.J = (int)y.J;
+  sa.L = y.L;
+  sa.R = y.R;
+  sa.items = items;
+  sa.partG = partG;
+  sa.partP = partP;
+  sa.partS = partS;
+  float* omq = reinterpret_cast<float*>(w + y.omq);
+  for (int pass = 0; pass <= o->power_iters; ++pass) {
+    // pass 0 sketches with Omega_1; a power step with each slice's own matrix
+    sa.omega = pass == 0 ? omega1 : omq;
+    sa.om_stride = pass == 0 ? 0 : y.J * y.L;
+    if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    e = launch_slab(sa, X->dtype, y.n_items, false, s);
+    if (e != hipSuccess) return hip_fail(e, "slab pass");
+    if (ev1 && (e = hipEventRecord(ev1, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    ev0 = ev1 = nullptr;   // the timing hooks cover the first pass
+    e = launch_slice_finish(y.K, (int)y.J, y.L, y.R, reinterpret_cast<const int32_t*>(w + y.slice_ptr),
+                            reinterpret_cast<const int32_t*>(w + y.slice_list), partG, partP, partS,
+                            reinterpret_cast<double*>(w + y.xnorm2), reinterpret_cast<double*>(w + y.Mt),
+                            reinterpret_cast<double*>(w + y.Phi), reinterpret_cast<double*>(w + y.sig1),
+                            pass < o->power_iters ? omq : nullptr, ctl, s);
+    if (e != hipSuccess) return hip_fail(e, "slice finish");
+  }
   e = launch_stage2(y, w, omega2, s);
   if (e != hipSuccess) return hip_fail(e, "second stage");
   e = launch_pw_identity(y, w, s);
@@ -351,10 +374,21 @@ dpar2_status dpar2_output_U(const dpar2_tensor* X, const dpar2_opts* o, const dp
   double* theta = reinterpret_cast<double*>(w + y.trace);
   hipError_t e = launch_theta(y, w, f->H, theta, s);
   if (e != hipSuccess) return hip_fail(e, "theta");
-  // the tiles of the U pass are those of the slab pass: same Y bit for bit
-  e = launch_output_U(static_cast<const float*>(X->slab), (int)y.J, y.L, y.R,
-                      reinterpret_cast<const float*>(w + y.om1), reinterpret_cast<const Item*>(w + y.items),
-                      y.n_items, theta, U, s);
+  // the tiles of the U pass are those of the (last) slab pass: same Y bit for bit
+  SlabArgs sa;
+  std::memset(&sa, 0, sizeof(sa));
+  sa.slab = X->slab;
+  sa.scale = X->slice_scale;
+  sa.J = (int)y.J;
+  sa.L = y.L;
+  sa.R = y.R;
+  sa.omega = o->power_iters > 0 ? reinterpret_cast<const float*>(w + y.omq)
+                                : reinterpret_cast<const float*>(w + y.om1);
+  sa.om_stride = o->power_iters > 0 ? y.J * y.L : 0;
+  sa.items = reinterpret_cast<const Item*>(w + y.items);
+  sa.theta = theta;
+  sa.U = U;
+  e = launch_slab(sa, X->dtype, y.n_items, true, s);
   if (e != hipSuccess) return hip_fail(e, "U pass");
   return DPAR2_OK;
 }

@@ -35,7 +35,7 @@ struct Layout {
   size_t xnorm2, Mt, Phi, sig1;
   size_t Y2p, Y2, B2t, S2p, U2;
   size_t D, E, F, FtFp;
-  size_t Psi, Pw, Mk, small, partA, partB, partC, partBegin, red, fitp, trace, om1;
+  size_t Psi, Pw, Mk, small, partA, partB, partC, partBegin, red, fitp, trace, om1, omq;
   size_t total;
 };
 
@@ -57,16 +57,29 @@ enum SmallSlot {
 constexpr int RED_MAXBLK = 1024;         // grid size cap of the per-slice kernels
 
 // --- launchers (each returns the hipGetLastError() of its launches) ---------
-hipError_t launch_sketch(const float* slab, int J, int L, const float* omega1,
-                         const Item* items, int64_t n_items,
-                         double* partG, double* partP, double* partS, hipStream_t s);
-hipError_t launch_output_U(const float* slab, int J, int L, int R, const float* omega1,
-                           const Item* items, int64_t n_items, const double* theta,
-                           double* U, hipStream_t s);
+// Arguments of the slab pass (sketch_impl.h, k_sketch.hip).
+struct SlabArgs {
+  const void* slab;        // N x J elements of the input type
+  const float* scale;      // per-slice dequantisation scale (fp8), else unused
+  int J, L, R;
+  const float* omega;      // J x L (om_stride 0) or K x J x L (om_stride J L)
+  int64_t om_stride;
+  const Item* items;
+  double *partG, *partP, *partS;
+  const double* theta;     // U variant: K x L x R
+  double* U;               // U variant: N x R
+};
+// Slab pass over all work items: per-item partials of Y^T Y, Y^T X and
+// ||X||^2, or (uout) U = Y Theta_k.  dtype: dpar2_dtype.
+hipError_t launch_slab(const SlabArgs& a, int dtype, int64_t n_items, bool uout, hipStream_t s);
+// Per-slice completion of the first stage; omega_next (K x J x L float32, or
+// NULL) receives the sketch matrix of a power step, the orthonormal right
+// singular vectors of B_k (Alg. 1's power iteration in stabilised form).
 hipError_t launch_slice_finish(int64_t K, int J, int L, int R, const int32_t* slice_ptr,
                                const int32_t* slice_list, const double* partG,
                                const double* partP, const double* partS, double* xnorm2,
-                               double* Mt, double* Phi, double* sig1, Ctl* ctl, hipStream_t s);
+                               double* Mt, double* Phi, double* sig1, float* omega_next, Ctl* ctl,
+                               hipStream_t s);
 hipError_t launch_stage2(const Layout& lay, char* ws, const float* omega2, hipStream_t s);
 // out[e] = sum_{b < nb} part[b * stride + e] for e < width, in a fixed order
 hipError_t launch_colsum(int64_t nb, int64_t stride, int64_t width, const double* part, double* out,
@@ -83,6 +96,6 @@ hipError_t launch_pw_identity(const Layout& lay, char* ws, hipStream_t s);
 hipError_t launch_als_end(const Layout& lay, char* ws, double* V, hipStream_t s);
 int als_blocks(int64_t K, int R);
 
-bool sketch_supported(int J, int L);
+bool sketch_supported(int J, int L, int dtype);
 
 }  // namespace dpar2

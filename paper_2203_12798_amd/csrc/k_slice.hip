@@ -18,19 +18,20 @@ namespace dpar2 {
 hipError_t slice_dispatch_1(int L, int64_t K, int J, int R, const int32_t* slice_ptr,
                             const int32_t* slice_list, const double* partG, const double* partP,
                             const double* partS, double* xnorm2, double* Mt, double* Phi, double* sig1,
-                            Ctl* ctl, hipStream_t s);
+                            float* omega_next, Ctl* ctl, hipStream_t s);
 hipError_t slice_dispatch_2(int L, int64_t K, int J, int R, const int32_t* slice_ptr,
                             const int32_t* slice_list, const double* partG, const double* partP,
                             const double* partS, double* xnorm2, double* Mt, double* Phi, double* sig1,
-                            Ctl* ctl, hipStream_t s);
+                            float* omega_next, Ctl* ctl, hipStream_t s);
 
 hipError_t launch_slice_finish(int64_t K, int J, int L, int R, const int32_t* slice_ptr,
                                const int32_t* slice_list, const double* partG,
                                const double* partP, const double* partS, double* xnorm2,
-                               double* Mt, double* Phi, double* sig1, Ctl* ctl, hipStream_t s) {
+                               double* Mt, double* Phi, double* sig1, float* omega_next, Ctl* ctl,
+                               hipStream_t s) {
   if (L <= 16)
-    return slice_dispatch_1(L, K, J, R, slice_ptr, slice_list, partG, partP, partS, xnorm2, Mt, Phi, sig1, ctl, s);
-  return slice_dispatch_2(L, K, J, R, slice_ptr, slice_list, partG, partP, partS, xnorm2, Mt, Phi, sig1, ctl, s);
+    return slice_dispatch_1(L, K, J, R, slice_ptr, slice_list, partG, partP, partS, xnorm2, Mt, Phi, sig1, omega_next, ctl, s);
+  return slice_dispatch_2(L, K, J, R, slice_ptr, slice_list, partG, partP, partS, xnorm2, Mt, Phi, sig1, omega_next, ctl, s);
 }
 
 }  // namespace dpar2

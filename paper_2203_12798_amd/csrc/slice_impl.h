@@ -27,7 +27,8 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
                                                   const double* __restrict__ partP,
                                                   const double* __restrict__ partS, double* __restrict__ xnorm2,
                                                   double* __restrict__ Mt, double* __restrict__ Phi,
-                                                  double* __restrict__ sig1, Ctl* ctl) {
+                                                  double* __restrict__ sig1, float* __restrict__ omega_next,
+                                                  Ctl* ctl) {
   constexpr int RM = SC<L>::RM, LH = SC<L>::LH, LD = SC<L>::LD, CW = SC<L>::CW, LL = L * L;
   __shared__ double Gs[L * LD];    // G, then its Cholesky factor (upper triangle)
   __shared__ double Ss[L * LD];    // S' = P P^T; then Phi
@@ -36,7 +37,7 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
   constexpr int CP = CW + 1;        // padded chunk row (conflict-free column reads)
   __shared__ double Pc[L * CP];    // chunk of P
   __shared__ double Mc[L * CP];    // chunk of C_k B_k (rows r < R)
-  __shared__ double sgn[L], row[L], rinv[L];
+  __shared__ double sgn[L], row[L], rinv[L], sv[L];
 
   const int lane = threadIdx.x, c = lane % RM, h = lane / RM;
   const int k = blockIdx.x;
@@ -218,14 +219,15 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
 #pragma unroll
   for (int ii = 0; ii < LH; ++ii) mu = fma(t[ii], t[ii], mu);
   mu = sqrt(col_sum<L>(mu));   // singular value of B
+  double inv_mu;
   {
     // directions at the rounding level of the largest carry no information
     // (their normalised columns would be noise): zero them
     double mmax = cv ? mu : 0.0;
     for (int o = 1; o < 64; o <<= 1) mmax = fmax(mmax, __shfl_xor(mmax, o, 64));
-    const double inv = (mu > 64.0 * EPS64 * mmax && mu > 0.0) ? 1.0 / mu : 0.0;
+    inv_mu = (mu > 64.0 * EPS64 * mmax && mu > 0.0) ? 1.0 / mu : 0.0;
 #pragma unroll
-    for (int ii = 0; ii < LH; ++ii) v[ii] = t[ii] * inv;
+    for (int ii = 0; ii < LH; ++ii) v[ii] = t[ii] * inv_mu;
   }
   // rank by decreasing eigenvalue (ties: lower index first)
   int rank = 0;
@@ -240,16 +242,37 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
       if (a < L) Xs[a * LD + rank] = v[ii];
     }
     if (h == 0 && rank < R) sig1[(size_t)k * R + rank] = mu;
+    if (h == 0) sv[rank] = inv_mu;
   }
   __syncthreads();
-  // Phi = Wh U~_R (into Ss)
-  for (int e = lane; e < L * R; e += 64) {
-    const int a = e / R, r = e % R;
+  // Phi = Wh U~ (into Ss): the leading R columns give A_k; a power step
+  // needs all L (its sketch matrix is P^T Phi Sigma^{-1} = the right singular
+  // vectors of B, columns with a negligible singular value set to zero)
+  const int nphi = omega_next ? L : R;
+  for (int e = lane; e < L * nphi; e += 64) {
+    const int a = e / nphi, r = e % nphi;
     double s = 0.0;
     for (int b = 0; b < L; ++b) s = fma(Ws[a * LD + b], Xs[b * LD + r], s);
     Ss[a * LD + r] = s;
   }
   __syncthreads();
+  if (omega_next) {
+    float* On = omega_next + (size_t)k * J * L;
+    for (int jc = 0; jc < J; jc += CW) {
+      load_chunk(jc);
+      __syncthreads();
+      for (int e = lane; e < L * CW; e += 64) {
+        const int jj = e / L, l = e % L;
+        double m = 0.0;
+        if (jc + jj < J) {
+#pragma unroll
+          for (int a = 0; a < L; ++a) m = fma(Ss[a * LD + l], Pc[a * CP + jj], m);
+          On[(size_t)(jc + jj) * L + l] = (float)(m * sv[l]);
+        }
+      }
+      __syncthreads();
+    }
+  }
 
   // C_k B_k = P^T Phi.  Pass 0 finds the signed leading entry of each column
   // (lane r < R scans the chunk), pass 1 writes the signed rows of M^T.
@@ -296,10 +319,11 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
 template <int L>
 hipError_t slice_fin_launch(int64_t K, int J, int R, const int32_t* slice_ptr, const int32_t* slice_list,
                             const double* partG, const double* partP, const double* partS, double* xnorm2,
-                            double* Mt, double* Phi, double* sig1, Ctl* ctl, hipStream_t s) {
+                            double* Mt, double* Phi, double* sig1, float* omega_next, Ctl* ctl,
+                            hipStream_t s) {
   if (K <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_slice_fin<L>, dim3((unsigned)K), dim3(64), 0, s, (int)K, J, R, slice_ptr, slice_list,
-                     partG, partP, partS, xnorm2, Mt, Phi, sig1, ctl);
+                     partG, partP, partS, xnorm2, Mt, Phi, sig1, omega_next, ctl);
   return hipGetLastError();
 }
 

@@ -172,3 +172,73 @@ def init_factors(J: int, K: int, R: int, seed: int = 7):
     rng = np.random.default_rng(seed)
     V = rng.standard_normal((J, R))
     return np.eye(R), V, np.ones((K, R))
+
+
+# ---------------------------------------------------------------------------
+# Low-precision encodings of a slab (input formats, not part of the method):
+# the GPU reads the encoded bytes, the oracle the decoded values.
+# ---------------------------------------------------------------------------
+
+def round_bf16(x: np.ndarray) -> np.ndarray:
+    """float32 values rounded to the nearest bfloat16 (ties to even), as float32."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32)
+
+
+def encode_bf16(x: np.ndarray) -> np.ndarray:
+    """uint16 bfloat16 bit patterns of x (round to nearest even)."""
+    return (round_bf16(x).view(np.uint32) >> 16).astype(np.uint16)
+
+
+def decode_bf16(b: np.ndarray) -> np.ndarray:
+    return (np.asarray(b, dtype=np.uint16).astype(np.uint32) << 16).view(np.float32)
+
+
+def _e4m3_table() -> np.ndarray:
+    """Values of the 256 OCP fp8 e4m3fn codes (bias 7, S.1111.111 = NaN)."""
+    v = np.zeros(256)
+    for c in range(256):
+        s, e, m = c >> 7, (c >> 3) & 15, c & 7
+        if e == 15 and m == 7:
+            v[c] = np.nan
+            continue
+        mag = (m / 8.0) * 2.0 ** -6 if e == 0 else (1.0 + m / 8.0) * 2.0 ** (e - 7)
+        v[c] = -mag if s else mag
+    return v
+
+
+E4M3 = _e4m3_table()
+E4M3_MAX = 448.0
+
+
+def encode_fp8(slab: np.ndarray, offsets: np.ndarray):
+    """Per-slice scaled fp8 e4m3 codes: scale_k = 2^ceil(log2(amax_k / 448))
+    (a power of two, so decode(code) * scale_k is exact in float32), codes the
+    nearest representable value of x / scale_k (ties to the even code).
+    Returns (uint8 codes N x J, float32 scales K)."""
+    x = np.asarray(slab, dtype=np.float64)
+    K = len(offsets) - 1
+    scale = np.ones(K, dtype=np.float32)
+    pos = E4M3[:127]                       # codes 0x00..0x7E, increasing
+    codes = np.zeros(x.shape, dtype=np.uint8)
+    for k in range(K):
+        blk = x[offsets[k]:offsets[k + 1]]
+        amax = float(np.max(np.abs(blk))) if blk.size else 0.0
+        sc = 2.0 ** math.ceil(math.log2(amax / E4M3_MAX)) if amax > 0 else 1.0
+        scale[k] = sc
+        a = np.minimum(np.abs(blk) / sc, E4M3_MAX)
+        i = np.clip(np.searchsorted(pos, a), 1, 126)
+        lo, hi = pos[i - 1], pos[i]
+        pick_hi = (a - lo > hi - a) | ((a - lo == hi - a) & ((i & 1) == 0))
+        c = np.where(pick_hi, i, i - 1).astype(np.uint8)
+        c = np.where(a <= 0, 0, c).astype(np.uint8)
+        codes[offsets[k]:offsets[k + 1]] = c | np.where(blk < 0, 0x80, 0).astype(np.uint8)
+    return codes, scale
+
+
+def decode_fp8(codes: np.ndarray, offsets: np.ndarray, scale: np.ndarray) -> np.ndarray:
+    """float32 values decode(code) * scale_k (exact: scales are powers of two)."""
+    v = E4M3[np.asarray(codes, dtype=np.uint8)].astype(np.float32)
+    rows = np.repeat(np.arange(len(offsets) - 1), np.diff(offsets))
+    return (v * np.asarray(scale, dtype=np.float32)[rows][:, None]).astype(np.float32)

@@ -93,3 +93,32 @@ def test_status_strings():
     _, lib = _lib()
     for st in (0, -1, -2, -3, -5, -6, 7):
         assert lib.dpar2_status_string(st)
+
+
+def test_dtype_and_power_options_validated_on_host():
+    """fp8 slabs need per-slice scales; power_iters in [0, 4]; bf16 / fp8
+    slabs are limited to J <= 128, float32 to J <= 256."""
+    binding, lib = _lib()
+    off = np.array([0, 10, 20], dtype=np.int64)
+    hp = off.ctypes.data_as(ctypes.c_void_p).value
+    o = binding.c_opts(2, 3, 3, 5, -1.0, 0, 0)
+    t = binding.c_tensor(2, 8, 0x1000, hp, 0x2000, binding.DPAR2_FP8_E4M3, None)
+    assert _status(lib, binding, t, o) == -1
+    assert b"scale" in lib.dpar2_last_error()
+    t = binding.c_tensor(2, 8, 0x1000, hp, 0x2000, 7, None)
+    assert _status(lib, binding, t, o) == -1
+    for q, st in ((-1, -1), (5, -1)):
+        oq = binding.c_opts(2, 3, 3, 5, -1.0, 0, q)
+        t = binding.c_tensor(2, 8, 0x1000, hp, 0x2000, binding.DPAR2_F32, None)
+        assert _status(lib, binding, t, oq) == st
+    offw = np.array([0, 200, 400], dtype=np.int64)
+    hw = offw.ctypes.data_as(ctypes.c_void_p).value
+    tb = binding.c_tensor(2, 160, 0x1000, hw, 0x2000, binding.DPAR2_BF16, None)
+    assert _status(lib, binding, tb, o) == -2
+    tf = binding.c_tensor(2, 160, 0x1000, hw, 0x2000, binding.DPAR2_F32, None)
+    assert lib.dpar2_workspace_size(ctypes.byref(tf), ctypes.byref(o)) > 0
+    # a power step needs one sketch matrix per slice in the workspace
+    o1 = binding.c_opts(2, 3, 3, 5, -1.0, 0, 1)
+    t8 = binding.c_tensor(2, 8, 0x1000, hp, 0x2000, binding.DPAR2_F32, None)
+    assert (lib.dpar2_workspace_size(ctypes.byref(t8), ctypes.byref(o1))
+            >= lib.dpar2_workspace_size(ctypes.byref(t8), ctypes.byref(o)) + 2 * 8 * 3 * 4)
