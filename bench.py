@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--forms", action="store_true",
+                    help="also time the precision form (bf16 and fp8-e4m3 slabs) and one power step "
+                         "on the same workload")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic.json from two rocprofv3 --pmc counter_collection.csv "
                          "files (FETCH_SIZE, WRITE_SIZE) of a --calib-copy run, then exit")
@@ -151,6 +154,59 @@ def main():
     binding.profile_enable(False)
     rep = d.report_read(T, o, ws)
     print(f"[bench] timed {args.steps} steps", file=sys.stderr, flush=True)
+    ms_f32 = (t1 - t0) * 1e3 / max(args.steps, 1)
+
+    forms = None
+    if args.forms:
+        # the same workload as bf16 bit patterns and as per-slice-scaled fp8
+        # e4m3 codes (scale 2^ceil(log2(amax_k / 448))), encoded on the device
+        # with torch's round-to-nearest casts; and float32 with one power step
+        forms = {}
+        amax = np.maximum.reduceat(np.abs(X.slab).max(axis=1), X.offsets[:-1])
+        scale = np.exp2(np.ceil(np.log2(np.maximum(amax, 1e-30) / 448.0))).astype(np.float32)
+        rows = torch.repeat_interleave(torch.arange(K, device="cuda"),
+                                       torch.from_numpy(np.diff(X.offsets)).cuda())
+        o1b = torch.from_numpy(synth.round_bf16(om1)).cuda()
+        def run_form(kind):
+            if kind == "bf16":
+                Tk = d.Tensor(T.slab.to(torch.bfloat16).view(torch.int16), T.offsets_dev, X.offsets,
+                              binding.DPAR2_BF16)
+                ok, om = o, o1b
+            elif kind == "fp8":
+                sc = torch.from_numpy(scale).cuda()
+                codes = (T.slab / sc[rows][:, None]).to(torch.float8_e4m3fn).view(torch.uint8)
+                Tk = d.Tensor(codes.contiguous(), T.offsets_dev, X.offsets, binding.DPAR2_FP8_E4M3, sc)
+                ok, om = o, o1b
+            else:
+                Tk, om = T, o1
+                ok = d.Options(rank=R, sketch=L, sketch2=L2, max_iter=iters, power_iters=1)
+            wsk = d.alloc_workspace(Tk, ok)
+
+            def stepk():
+                f.H.copy_(init[0])
+                f.V.copy_(init[1])
+                f.W.copy_(init[2])
+                d.decompose(Tk, ok, om, o2, f, wsk)
+
+            for _ in range(args.warmup):
+                stepk()
+            torch.cuda.synchronize()
+            tk0 = time.perf_counter()
+            for _ in range(args.steps):
+                stepk()
+            torch.cuda.synchronize()
+            msk = (time.perf_counter() - tk0) * 1e3 / max(args.steps, 1)
+            rk = d.report_read(Tk, ok, wsk)
+            print(f"[bench] form {kind}: {msk:.3f} ms", file=sys.stderr, flush=True)
+            return {"ms_per_step": round(msk, 3), "slices_per_s": round(K / (msk / 1e3), 1),
+                    "speedup_vs_f32": round(ms_f32 / msk, 3), "fitness": rk["fit_true"],
+                    "fitness_delta_vs_f32": rk["fit_true"] - rep["fit_true"]}
+
+        for kind in ("bf16", "fp8", "f32_q1"):
+            try:
+                forms[kind] = run_form(kind)
+            except Exception as exc:   # a form that cannot run is reported, not fatal
+                forms[kind] = {"error": str(exc)[:200]}
 
     if args.calib_copy:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
@@ -194,6 +250,8 @@ def main():
                                 "(int8 digit products combined in FP64)"},
         "fitness": {"gpu": rep["fit_true"], "iters": rep["iters"], "warn_bits": rep["warn_bits"]},
     }
+    if forms is not None:
+        out["forms"] = forms
 
     if not args.no_cpu_baseline and args.cpu_sample > 0:
         from threadpoolctl import threadpool_limits
