@@ -67,6 +67,14 @@ typedef enum {
 } dpar2_dtype;
 
 /* Warning bits reported in dpar2_report.warn_bits (device-side, never fatal). */
+/* dpar2_opts.flags: the iterations of dpar2_als_step / dpar2_decompose /
+ * dpar2_decompose_batch (begin, n_steps iterations, end) are captured once
+ * per workspace and step count into a HIP graph and replayed on later calls
+ * (kernel arguments point into the workspace only, so a replay reads the
+ * current factors, tolerances and trace through the descriptors).  This
+ * flag launches them one by one instead.  Results are identical. */
+#define DPAR2_FLAG_NO_GRAPH     0x1u
+
 #define DPAR2_WARN_JACOBI_CAP   0x1u  /* a Jacobi eigen/SVD solve hit its sweep cap   */
 #define DPAR2_WARN_RANK_DEFICIENT 0x2u /* a T_k had a (near) zero singular value      */
 
@@ -91,7 +99,7 @@ typedef struct {
                           L2 <= J and L2 <= K R                                     */
   int32_t max_iter;    /* iterations of the repeat loop of Alg. 3, >= 0             */
   double tol;          /* stop when e_{t-1} - e_t < tol * e_{t-1}; tol < 0: never   */
-  uint32_t flags;      /* reserved, must be 0                                       */
+  uint32_t flags;      /* DPAR2_FLAG_* bits, others must be 0                        */
   int32_t power_iters; /* q of Alg. 1 for the first stage, 0..4; each step is one more
                           pass over the slab with a per-slice sketch matrix (the
                           orthonormal right singular vectors of the previous B_k,
@@ -183,6 +191,27 @@ dpar2_status dpar2_compressed_view(const dpar2_tensor* X, const dpar2_opts* o, c
  * (host). */
 dpar2_status dpar2_report_read(const dpar2_tensor* X, const dpar2_opts* o, const void* ws,
                                dpar2_report* rep, dpar2_stream_t stream);
+
+/* Batched decomposition of n independent tensors (the throughput form of
+ * Alg. 3 for many small tensors).  X[t], o[t] (host arrays of n) may differ
+ * in everything; the library partitions the batch into groups of tensors that
+ * share J, dtype, rank, sketch, sketch2, power_iters, max_iter and flags (in
+ * order of first appearance), and runs each group through one set of
+ * launches: one slab pass over the work items of all its tensors, one launch
+ * per second-stage step and per iteration kernel, each tensor stopping by its
+ * own tol.  omega1[t] (J_t x L_t) and omega2[t] ((K_t R_t) x L2_t) are host
+ * arrays of device pointers; f[t] holds each tensor's initial factors and
+ * receives the result.  Each tensor's result is bit-for-bit the result of
+ * dpar2_decompose on that tensor alone (no U output here).  Workspace from
+ * dpar2_batch_workspace_size (the groups' layouts end to end); reports from
+ * dpar2_batch_report_read (rep: host array of n, in the caller's order). */
+size_t dpar2_batch_workspace_size(int32_t n, const dpar2_tensor* X, const dpar2_opts* o);
+dpar2_status dpar2_decompose_batch(int32_t n, const dpar2_tensor* X, const dpar2_opts* o,
+                                   const float* const* omega1, const float* const* omega2,
+                                   dpar2_factors* f, void* ws, size_t ws_bytes,
+                                   dpar2_stream_t stream);
+dpar2_status dpar2_batch_report_read(int32_t n, const dpar2_tensor* X, const dpar2_opts* o,
+                                     const void* ws, dpar2_report* rep, dpar2_stream_t stream);
 
 /* Kernel timing for measurement.  While enabled, every dpar2_compress records
  * a pair of HIP events around its slab pass (the first-stage kernel that reads

@@ -1,9 +1,10 @@
 """libdpar2: DPar2 (fast PARAFAC2 decomposition of irregular dense tensors)
 on AMD Instinct MI355X.  The compute path is the HIP library libdpar2.so
 (C ABI in include/dpar2.h); this package is its thin Python binding."""
-from .binding import (Dpar2Error, Factors, Options, Tensor, alloc_workspace, als_step, compress,
-                      compressed_view,
-                      decompose, fitness, load, output_U, report_read, workspace_size)
+from .binding import (Dpar2Error, Factors, Options, Tensor, alloc_batch_workspace, alloc_workspace, als_step,
+                      batch_report_read, batch_workspace_size, compress, compressed_view, decompose,
+                      decompose_batch, fitness, load, output_U, report_read, workspace_size)
 
-__all__ = ["Dpar2Error", "Factors", "Options", "Tensor", "alloc_workspace", "als_step", "compress", "compressed_view",
-           "decompose", "fitness", "load", "output_U", "report_read", "workspace_size"]
+__all__ = ["Dpar2Error", "Factors", "Options", "Tensor", "alloc_batch_workspace", "alloc_workspace", "als_step",
+           "batch_report_read", "batch_workspace_size", "compress", "compressed_view", "decompose",
+           "decompose_batch", "fitness", "load", "output_U", "report_read", "workspace_size"]

@@ -22,6 +22,7 @@ DPAR2_EWORKSPACE = -6
 DPAR2_F32 = 0
 DPAR2_BF16 = 1
 DPAR2_FP8_E4M3 = 2
+DPAR2_FLAG_NO_GRAPH = 0x1
 
 WARN_JACOBI_CAP = 0x1
 WARN_RANK_DEFICIENT = 0x2
@@ -63,6 +64,7 @@ class c_report(ctypes.Structure):
 
 EXPORTS = ["dpar2_workspace_size", "dpar2_compress", "dpar2_als_step", "dpar2_fitness",
            "dpar2_output_U", "dpar2_decompose", "dpar2_compressed_view", "dpar2_report_read",
+           "dpar2_batch_workspace_size", "dpar2_decompose_batch", "dpar2_batch_report_read",
            "dpar2_profile_enable", "dpar2_profile_read", "dpar2_status_string", "dpar2_last_error"]
 
 _lib = None
@@ -96,6 +98,13 @@ def load(path: str = LIB_PATH):
     lib.dpar2_compressed_view.argtypes = [P(c_tensor), P(c_opts), vp, ctypes.c_size_t, P(c_compressed)]
     lib.dpar2_report_read.restype = ctypes.c_int32
     lib.dpar2_report_read.argtypes = [P(c_tensor), P(c_opts), vp, P(c_report), vp]
+    lib.dpar2_batch_workspace_size.restype = ctypes.c_size_t
+    lib.dpar2_batch_workspace_size.argtypes = [ctypes.c_int32, P(c_tensor), P(c_opts)]
+    lib.dpar2_decompose_batch.restype = ctypes.c_int32
+    lib.dpar2_decompose_batch.argtypes = [ctypes.c_int32, P(c_tensor), P(c_opts), P(vp), P(vp), P(c_factors), vp,
+                                          ctypes.c_size_t, vp]
+    lib.dpar2_batch_report_read.restype = ctypes.c_int32
+    lib.dpar2_batch_report_read.argtypes = [ctypes.c_int32, P(c_tensor), P(c_opts), vp, P(c_report), vp]
     lib.dpar2_profile_enable.restype = ctypes.c_int32
     lib.dpar2_profile_enable.argtypes = [ctypes.c_int32]
     lib.dpar2_profile_read.restype = ctypes.c_int32
@@ -135,10 +144,11 @@ class Options:
     max_iter: int
     tol: float = -1.0
     power_iters: int = 0
+    graph: bool = True      # False sets DPAR2_FLAG_NO_GRAPH
 
     def c(self) -> c_opts:
-        return c_opts(self.rank, self.sketch, self.sketch2, self.max_iter, float(self.tol), 0,
-                      self.power_iters)
+        return c_opts(self.rank, self.sketch, self.sketch2, self.max_iter, float(self.tol),
+                      0 if self.graph else DPAR2_FLAG_NO_GRAPH, self.power_iters)
 
 
 class Tensor:
@@ -298,9 +308,58 @@ def report_read(X: Tensor, o: Options, ws, stream=None) -> dict:
     r = c_report()
     _check(lib.dpar2_report_read(ctypes.byref(X.c()), ctypes.byref(o.c()), p, ctypes.byref(r),
                                  _stream(stream)))
+    return _report_dict(r)
+
+
+def _report_dict(r) -> dict:
     return {"iters": r.iters, "converged": bool(r.converged), "err_last": r.err_last,
             "fit_compressed": r.fit_compressed, "fit_true": r.fit_true, "xnorm2": r.xnorm2,
             "warn_bits": r.warn_bits}
+
+
+class _Batch:
+    """ctypes arrays describing a batch of tensors (kept alive by the caller
+    for the duration of a call)."""
+
+    def __init__(self, Xs, os_, omega1s=None, omega2s=None, fs=None):
+        n = len(Xs)
+        assert n >= 1 and len(os_) == n
+        self.n = n
+        self.X = (c_tensor * n)(*[x.c() for x in Xs])
+        self.o = (c_opts * n)(*[o.c() for o in os_])
+        if omega1s is not None:
+            self.om1 = (ctypes.c_void_p * n)(*[_ptr(w) for w in omega1s])
+            self.om2 = (ctypes.c_void_p * n)(*[_ptr(w) for w in omega2s])
+        if fs is not None:
+            self.f = (c_factors * n)(*[f.c() for f in fs])
+
+
+def batch_workspace_size(Xs, os_) -> int:
+    b = _Batch(Xs, os_)
+    n = load().dpar2_batch_workspace_size(b.n, b.X, b.o)
+    if n == 0:
+        raise Dpar2Error(DPAR2_EINVAL, last_error())
+    return int(n)
+
+
+def alloc_batch_workspace(Xs, os_, device="cuda:0"):
+    import torch
+    return torch.empty(batch_workspace_size(Xs, os_) + 256, dtype=torch.uint8, device=device)
+
+
+def decompose_batch(Xs, os_, omega1s, omega2s, fs, ws, stream=None):
+    """Decomposes every tensor of the batch (factors fs updated in place)."""
+    b = _Batch(Xs, os_, omega1s, omega2s, fs)
+    p, n = _ws(ws)
+    _check(load().dpar2_decompose_batch(b.n, b.X, b.o, b.om1, b.om2, b.f, p, n, _stream(stream)))
+
+
+def batch_report_read(Xs, os_, ws, stream=None) -> list:
+    b = _Batch(Xs, os_)
+    p, _ = _ws(ws)
+    r = (c_report * b.n)()
+    _check(load().dpar2_batch_report_read(b.n, b.X, b.o, p, r, _stream(stream)))
+    return [_report_dict(r[i]) for i in range(b.n)]
 
 
 def profile_enable(on: bool = True):

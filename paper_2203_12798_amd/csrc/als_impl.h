@@ -31,16 +31,34 @@ namespace dpar2 {
 constexpr int EPI_THREADS = 1024;
 
 struct AlsArgs {
-  int K, J;
-  const double *F, *D, *E;
-  double *H, *V, *W;
-  double *Pw, *Psi, *Mk;
-  double *small, *partA, *partB, *partC, *partBegin;
-  double* red;   // column sums of the block partials: A (RR), B (RR), C (RR + 2), begin (3 RR)
-  double* trace;
-  double tol;
-  Ctl* ctl;
+  int nt, J;
+  const TDesc* td;                 // per tensor: K, first slice, factors, trace, tol
+  const Blk* blk;                  // iteration kernels: block -> (tensor, global slices)
+  const Blk* blk0;                 // begin kernel: block -> (tensor, local rows)
+  const double *F, *D, *E;         // F: global rows; D: nt x J x R; E: nt x R
+  double *Pw, *Psi, *Mk;           // global slice index
+  double* small;                   // nt x SM_COUNT x R R
+  double *partA, *partB, *partC, *partBegin;   // one partial per block
+  double* red;                     // nt x (6 R R + 2): partial sums per tensor
+  Ctl* ctl;                        // nt
 };
+
+// per-slice kernels: the block's tensor, its control block and small state
+#define ALS_BLOCK_PROLOGUE(R_)                                         \
+  const Blk bk = a.blk[blockIdx.x];                                    \
+  const int tt = bk.t;                                                 \
+  const TDesc& td = a.td[tt];                                          \
+  Ctl* ctl = a.ctl + tt;                                               \
+  if (ctl->done) return;                                               \
+  double* small = a.small + (size_t)tt * SM_COUNT * (R_) * (R_);
+// epilogues: one block per tensor
+#define ALS_EPI_PROLOGUE(R_)                                           \
+  const int tt = blockIdx.x;                                           \
+  const TDesc& td = a.td[tt];                                          \
+  Ctl* ctl = a.ctl + tt;                                               \
+  if (ctl->done) return;                                               \
+  double* small = a.small + (size_t)tt * SM_COUNT * (R_) * (R_);       \
+  double* red = a.red + (size_t)tt * (RED_WIDTH * (R_) * (R_) + 2);
 
 template <int R>
 struct RC {
@@ -251,17 +269,16 @@ __device__ inline void block_partial_out(const double (&acc)[R], double* sred, d
 // ---------------------------------------------------------------------------
 template <int R>
 __global__ __launch_bounds__(RC<R>::TPB) void k_als_A(AlsArgs a) {
-  Ctl* ctl = a.ctl;
-  if (ctl->done) return;
+  ALS_BLOCK_PROLOGUE(R)
   constexpr int RM = RC<R>::RM, GPB = RC<R>::GPB, TPB = RC<R>::TPB, RR = R * R;
   __shared__ double sH[RR], sB[RR];
   __shared__ double sF[GPB * RR], sZ[GPB * RR], sP[GPB * RR], sT[GPB * RR];
-  const int K = a.K;
+  const int64_t K = bk.s1;   // slices bk.s0 .. bk.s1 - 1 (at most GPB)
   const int tid = threadIdx.x, g = tid / RM, j = tid % RM;
   const int lane = tid & 63, gbase = lane & ~(RM - 1);
-  const double* Bm = a.small + SM_BM * RR;
+  const double* Bm = small + SM_BM * RR;
   for (int e = tid; e < RR; e += TPB) {
-    sH[e] = a.H[e];
+    sH[e] = td.H[e];
     sB[e] = Bm[e];
   }
   double* F_ = sF + g * RR;
@@ -272,7 +289,8 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_A(AlsArgs a) {
 #pragma unroll
   for (int i = 0; i < R; ++i) acc[i] = 0.0;
   unsigned warn = 0;
-  for (int64_t base = (int64_t)blockIdx.x * GPB; base < K; base += (int64_t)gridDim.x * GPB) {
+  {
+    const int64_t base = bk.s0;
     const int64_t k = base + g;
     const bool live = (k < K) && (j < R);
     __syncthreads();
@@ -294,7 +312,7 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_A(AlsArgs a) {
     double t[R], v[R], wk[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-      wk[i] = (k < K) ? a.W[(size_t)k * R + i] : 0.0;
+      wk[i] = (k < K) ? td.W[(size_t)(k - td.k0) * R + i] : 0.0;
       v[i] = live ? a.Pw[(size_t)k * RR + i * R + j] : 0.0;
     }
     // column j of T_k = F^(k) Bm diag(W(k,:)) H^T (Eq. 8)
@@ -414,16 +432,15 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_A(AlsArgs a) {
 // H = G1 (W^T W * V^T V)^dagger, unit columns; H^T H.
 template <int R>
 __global__ __launch_bounds__(EPI_THREADS) void k_als_A_epi(AlsArgs a, int nblk) {
-  Ctl* ctl = a.ctl;
-  if (ctl->done) return;
+  ALS_EPI_PROLOGUE(R)
   constexpr int LD = 33, RR = R * R;
   __shared__ double G1[32 * LD], Gm[32 * LD], Gi[32 * LD], sT[32 * LD], sV[32 * LD], sg[32], tmp[RR];
   __shared__ int sflag;
   const int tid = threadIdx.x;
   (void)nblk;
-  team_sum(a.red, 1, RR, RR, tmp);
-  const double* WtW = a.small + SM_WTW * RR;
-  const double* VtV = a.small + SM_VTV * RR;
+  team_sum(red, 1, RR, RR, tmp);
+  const double* WtW = small + SM_WTW * RR;
+  const double* VtV = small + SM_VTV * RR;
   for (int e = tid; e < RR; e += EPI_THREADS) {
     G1[(e / R) * LD + e % R] = tmp[e];
     Gm[(e / R) * LD + e % R] = WtW[e] * VtV[e];
@@ -447,11 +464,11 @@ __global__ __launch_bounds__(EPI_THREADS) void k_als_A_epi(AlsArgs a, int nblk) 
   for (int e = tid; e < RR; e += EPI_THREADS) {
     const int q = e / R, c = e % R;
     const double h = sT[q * LD + c] / sg[c];
-    a.H[e] = h;
+    td.H[e] = h;
     G1[q * LD + c] = h;
   }
   __syncthreads();
-  double* HtH = a.small + SM_HTH * RR;
+  double* HtH = small + SM_HTH * RR;
   for (int e = tid; e < RR; e += EPI_THREADS) {
     const int q = e / R, c = e % R;
     double s = 0.0;
@@ -466,26 +483,27 @@ __global__ __launch_bounds__(EPI_THREADS) void k_als_A_epi(AlsArgs a, int nblk) 
 // ---------------------------------------------------------------------------
 template <int R>
 __global__ __launch_bounds__(RC<R>::TPB) void k_als_B(AlsArgs a) {
-  Ctl* ctl = a.ctl;
-  if (ctl->done) return;
+  ALS_BLOCK_PROLOGUE(R)
+  (void)small;
   constexpr int RM = RC<R>::RM, GPB = RC<R>::GPB, TPB = RC<R>::TPB, RR = R * R;
   __shared__ double sH[RR];
   __shared__ double sM[GPB * RR];
-  const int K = a.K;
+  const int64_t K = bk.s1;
   const int tid = threadIdx.x, g = tid / RM, j = tid % RM;
-  for (int e = tid; e < RR; e += TPB) sH[e] = a.H[e];
+  for (int e = tid; e < RR; e += TPB) sH[e] = td.H[e];
   double* M_ = sM + g * RR;
   double acc[R];
 #pragma unroll
   for (int q = 0; q < R; ++q) acc[q] = 0.0;
-  for (int64_t base = (int64_t)blockIdx.x * GPB; base < K; base += (int64_t)gridDim.x * GPB) {
+  {
+    const int64_t base = bk.s0;
     const int64_t k = base + g;
     __syncthreads();
     if (k < K)
       for (int e = j; e < RR; e += RM) M_[e] = a.Mk[(size_t)k * RR + e];
     __syncthreads();
     if (k < K && j < R) {
-      const double wj = a.W[(size_t)k * R + j];
+      const double wj = td.W[(size_t)(k - td.k0) * R + j];
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         double s = 0.0;
@@ -502,18 +520,17 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_B(AlsArgs a) {
 // V^T V, Bm = E D^T V, H^T H * V^T V, (V^T V * H^T H)^dagger.
 template <int R>
 __global__ __launch_bounds__(EPI_THREADS) void k_als_B_epi(AlsArgs a, int nblk) {
-  Ctl* ctl = a.ctl;
-  if (ctl->done) return;
+  ALS_EPI_PROLOGUE(R)
   constexpr int LD = 33, RR = R * R;
   __shared__ double N[32 * LD], Gm[32 * LD], Gi[32 * LD], sT[32 * LD], sV[32 * LD], sg[32], tmp[RR];
   __shared__ int sflag;
   const int tid = threadIdx.x;
-  double* small = a.small;
   (void)nblk;
-  team_sum(a.red + RR, 1, RR, RR, tmp);
+  team_sum(red + RR, 1, RR, RR, tmp);
   const double* WtW = small + SM_WTW * RR;
   const double* HtH = small + SM_HTH * RR;
   const double* DtD = small + SM_DTD * RR;
+  const double* Et = a.E + (size_t)tt * R;
   for (int e = tid; e < RR; e += EPI_THREADS) {
     N[(e / R) * LD + e % R] = tmp[e];
     Gm[(e / R) * LD + e % R] = WtW[e] * HtH[e];
@@ -525,7 +542,7 @@ __global__ __launch_bounds__(EPI_THREADS) void k_als_B_epi(AlsArgs a, int nblk) 
     const int q = e / R, c = e % R;
     double s = 0.0;
     for (int i = 0; i < R; ++i) s = fma(N[q * LD + i], Gi[i * LD + c], s);
-    Gm[q * LD + c] = a.E[q] * s;
+    Gm[q * LD + c] = Et[q] * s;
   }
   __syncthreads();
   for (int e = tid; e < RR; e += EPI_THREADS) {            // sT <- (D^T D) VC
@@ -557,7 +574,7 @@ __global__ __launch_bounds__(EPI_THREADS) void k_als_B_epi(AlsArgs a, int nblk) 
     double s = 0.0;
     for (int i = 0; i < R; ++i) s = fma(Gm[i * LD + q], sT[i * LD + c], s);   // VC^T (D^T D) VC
     VtV[e] = s;
-    Bm[e] = a.E[q] * sT[q * LD + c];                                           // E D^T V
+    Bm[e] = Et[q] * sT[q * LD + c];                                           // E D^T V
     HV[e] = s * HtH[e];
     VC[e] = Gm[q * LD + c];
     N[q * LD + c] = s * HtH[e];
@@ -576,27 +593,27 @@ __global__ __launch_bounds__(EPI_THREADS) void k_als_B_epi(AlsArgs a, int nblk) 
 // ---------------------------------------------------------------------------
 template <int R>
 __global__ __launch_bounds__(RC<R>::TPB) void k_als_C(AlsArgs a) {
-  Ctl* ctl = a.ctl;
-  if (ctl->done) return;
+  ALS_BLOCK_PROLOGUE(R)
   constexpr int RM = RC<R>::RM, GPB = RC<R>::GPB, TPB = RC<R>::TPB, RR = R * R;
   __shared__ double sH[RR], sB[RR], sGi[RR], sHV[RR];
   __shared__ double sM[GPB * RR];
   __shared__ double sRed[TPB * 2];
-  const int K = a.K;
+  const int64_t K = bk.s1;
   const int tid = threadIdx.x, g = tid / RM, j = tid % RM;
   const int lane = tid & 63, gbase = lane & ~(RM - 1);
   for (int e = tid; e < RR; e += TPB) {
-    sH[e] = a.H[e];
-    sB[e] = a.small[SM_BM * RR + e];
-    sGi[e] = a.small[SM_G3INV * RR + e];
-    sHV[e] = a.small[SM_HV * RR + e];
+    sH[e] = td.H[e];
+    sB[e] = small[SM_BM * RR + e];
+    sGi[e] = small[SM_G3INV * RR + e];
+    sHV[e] = small[SM_HV * RR + e];
   }
   double* M_ = sM + g * RR;
   double wtw[R];
 #pragma unroll
   for (int q = 0; q < R; ++q) wtw[q] = 0.0;
   double ewg = 0.0, equad = 0.0;
-  for (int64_t base = (int64_t)blockIdx.x * GPB; base < K; base += (int64_t)gridDim.x * GPB) {
+  {
+    const int64_t base = bk.s0;
     const int64_t k = base + g;
     const bool live = (k < K) && (j < R);
     __syncthreads();
@@ -620,7 +637,7 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_C(AlsArgs a) {
     if (live) {
 #pragma unroll
       for (int s = 0; s < R; ++s) wnew = fma(gs[s], sGi[s * R + j], wnew);
-      a.W[(size_t)k * R + j] = wnew;
+      td.W[(size_t)(k - td.k0) * R + j] = wnew;
       ewg = fma(wnew, g3, ewg);
     }
     double ws[R];
@@ -659,18 +676,17 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_C(AlsArgs a) {
 // W^T W, e_t = e0 - 2 sum W.G3 + sum W (H^T H * V^T V) W^T, stop rule.
 template <int R>
 __global__ __launch_bounds__(EPI_THREADS) void k_als_C_epi(AlsArgs a, int nblk) {
-  Ctl* ctl = a.ctl;
-  if (ctl->done) return;
+  ALS_EPI_PROLOGUE(R)
   constexpr int RR = R * R;
   __shared__ double tmp[RR + 2];
   (void)nblk;
-  team_sum(a.red + 2 * RR, 1, RR + 2, RR + 2, tmp);
-  for (int e = threadIdx.x; e < RR; e += EPI_THREADS) a.small[SM_WTW * RR + e] = tmp[e];
+  team_sum(red + 2 * RR, 1, RR + 2, RR + 2, tmp);
+  for (int e = threadIdx.x; e < RR; e += EPI_THREADS) small[SM_WTW * RR + e] = tmp[e];
   if (threadIdx.x == 0) {
     const double e = ctl->e0 - 2.0 * tmp[RR] + tmp[RR + 1];
-    if (a.trace) a.trace[ctl->iters - ctl->base] = e;
+    if (td.trace) td.trace[ctl->iters - ctl->base] = e;
     ctl->iters += 1;
-    if (a.tol >= 0.0 && ctl->iters >= 2 && ctl->e_prev - e < a.tol * ctl->e_prev) ctl->done = 1;
+    if (td.tol >= 0.0 && ctl->iters >= 2 && ctl->e_prev - e < td.tol * ctl->e_prev) ctl->done = 1;
     ctl->e_prev = e;
   }
 }
@@ -682,18 +698,22 @@ template <int R>
 __global__ __launch_bounds__(RC<R>::TPB) void k_als_begin(AlsArgs a) {
   constexpr int RM = RC<R>::RM, GPB = RC<R>::GPB, RR = R * R;
   __shared__ double sM[GPB * RR];
-  const int K = a.K, J = a.J;
+  const Blk bk = a.blk0[blockIdx.x];   // local rows bk.s0 .. bk.s1 - 1 of tensor bk.t
+  const TDesc& td = a.td[bk.t];
+  const int64_t K = td.K, J = a.J;
+  const double* Dt = a.D + (size_t)bk.t * J * R;
   const int tid = threadIdx.x, g = tid / RM, j = tid % RM;
   const int lane = tid & 63, gbase = lane & ~(RM - 1);
   double acc0[R], acc1[R], acc2[R];
 #pragma unroll
   for (int q = 0; q < R; ++q) acc0[q] = acc1[q] = acc2[q] = 0.0;
-  const int64_t rows = (K > J) ? K : J;
-  for (int64_t base = (int64_t)blockIdx.x * GPB; base < rows; base += (int64_t)gridDim.x * GPB) {
+  const int64_t rows = bk.s1;
+  {
+    const int64_t base = bk.s0;
     const int64_t k = base + g;
-    const double w = (k < K && j < R) ? a.W[(size_t)k * R + j] : 0.0;
-    const double v = (k < J && j < R) ? a.V[(size_t)k * R + j] : 0.0;
-    const double d = (k < J && j < R) ? a.D[(size_t)k * R + j] : 0.0;
+    const double w = (k < rows && k < K && j < R) ? td.W[(size_t)k * R + j] : 0.0;
+    const double v = (k < rows && k < J && j < R) ? td.V[(size_t)k * R + j] : 0.0;
+    const double d = (k < rows && k < J && j < R) ? Dt[(size_t)k * R + j] : 0.0;
 #pragma unroll
     for (int s = 0; s < R; ++s) {
       const double ws = __shfl(w, gbase + s, 64);
@@ -712,15 +732,19 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_begin(AlsArgs a) {
 
 template <int R>
 __global__ __launch_bounds__(EPI_THREADS) void k_als_begin_epi(AlsArgs a, int nblk) {
-  Ctl* ctl = a.ctl;
+  const int tt = blockIdx.x;
+  Ctl* ctl = a.ctl + tt;
+  double* small = a.small + (size_t)tt * SM_COUNT * R * R;
+  const double* red = a.red + (size_t)tt * (RED_WIDTH * R * R + 2);
+  const double* Et = a.E + (size_t)tt * R;
   constexpr int RR = R * R;
   __shared__ double tmp[3 * RR];
   (void)nblk;
-  team_sum(a.red + 3 * RR + 2, 1, 3 * RR, 3 * RR, tmp);
+  team_sum(red + 3 * RR + 2, 1, 3 * RR, 3 * RR, tmp);
   for (int e = threadIdx.x; e < RR; e += EPI_THREADS) {
-    a.small[SM_WTW * RR + e] = tmp[e];
-    a.small[SM_VTV * RR + e] = tmp[RR + e];
-    a.small[SM_BM * RR + e] = a.E[e / R] * tmp[2 * RR + e];
+    small[SM_WTW * RR + e] = tmp[e];
+    small[SM_VTV * RR + e] = tmp[RR + e];
+    small[SM_BM * RR + e] = Et[e / R] * tmp[2 * RR + e];
   }
   if (threadIdx.x == 0) {
     ctl->base = ctl->iters;
@@ -729,31 +753,32 @@ __global__ __launch_bounds__(EPI_THREADS) void k_als_begin_epi(AlsArgs a, int nb
 }
 
 // Launches of one rank's kernels: phase 0 = begin (+epi), 1 = one iteration.
+// nb, nb0: blocks of the iteration / begin per-slice kernels; seg, seg0: their
+// per-tensor block offsets (device, nt + 1).
 template <int R>
-hipError_t als_launch(int phase, const AlsArgs& a, hipStream_t s) {
-  constexpr int TPB = RC<R>::TPB, GPB = RC<R>::GPB;
-  int64_t nb = ((int64_t)(phase == 0 ? ((a.K > a.J) ? a.K : a.J) : a.K) + GPB - 1) / GPB;
-  if (nb > RED_MAXBLK) nb = RED_MAXBLK;
-  if (nb < 1) nb = 1;
-  const int n = (int)nb;
-  // each per-slice kernel writes one partial per block; a many-block column
-  // sum reduces them (one load per thread) before the single-block epilogue
-  constexpr int RR = R * R;
+hipError_t als_launch(int phase, const AlsArgs& a, int nb, int nb0, const int64_t* seg, const int64_t* seg0,
+                      hipStream_t s) {
+  constexpr int TPB = RC<R>::TPB, RR = R * R;
+  constexpr int64_t RW = RED_WIDTH * RR + 2;
+  const int nt = a.nt;
+  // each per-slice kernel writes one partial per block; the segmented column
+  // sum reduces them per tensor (one load per thread) before the epilogues
   hipError_t e;
   if (phase == 0) {
-    hipLaunchKernelGGL(k_als_begin<R>, dim3(n), dim3(TPB), 0, s, a);
-    if ((e = launch_colsum(n, 3 * RR, 3 * RR, a.partBegin, a.red + 3 * RR + 2, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_als_begin_epi<R>, dim3(1), dim3(EPI_THREADS), 0, s, a, 1);
+    hipLaunchKernelGGL(k_als_begin<R>, dim3(nb0), dim3(TPB), 0, s, a);
+    if ((e = launch_segsum(nt, seg0, 3 * RR, 3 * RR, a.partBegin, a.red + 3 * RR + 2, RW, s)) != hipSuccess)
+      return e;
+    hipLaunchKernelGGL(k_als_begin_epi<R>, dim3(nt), dim3(EPI_THREADS), 0, s, a, 1);
   } else {
-    hipLaunchKernelGGL(k_als_A<R>, dim3(n), dim3(TPB), 0, s, a);
-    if ((e = launch_colsum(n, RR, RR, a.partA, a.red, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_als_A_epi<R>, dim3(1), dim3(EPI_THREADS), 0, s, a, 1);
-    hipLaunchKernelGGL(k_als_B<R>, dim3(n), dim3(TPB), 0, s, a);
-    if ((e = launch_colsum(n, RR, RR, a.partB, a.red + RR, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_als_B_epi<R>, dim3(1), dim3(EPI_THREADS), 0, s, a, 1);
-    hipLaunchKernelGGL(k_als_C<R>, dim3(n), dim3(TPB), 0, s, a);
-    if ((e = launch_colsum(n, RR + 2, RR + 2, a.partC, a.red + 2 * RR, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_als_C_epi<R>, dim3(1), dim3(EPI_THREADS), 0, s, a, 1);
+    hipLaunchKernelGGL(k_als_A<R>, dim3(nb), dim3(TPB), 0, s, a);
+    if ((e = launch_segsum(nt, seg, RR, RR, a.partA, a.red, RW, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_als_A_epi<R>, dim3(nt), dim3(EPI_THREADS), 0, s, a, 1);
+    hipLaunchKernelGGL(k_als_B<R>, dim3(nb), dim3(TPB), 0, s, a);
+    if ((e = launch_segsum(nt, seg, RR, RR, a.partB, a.red + RR, RW, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_als_B_epi<R>, dim3(nt), dim3(EPI_THREADS), 0, s, a, 1);
+    hipLaunchKernelGGL(k_als_C<R>, dim3(nb), dim3(TPB), 0, s, a);
+    if ((e = launch_segsum(nt, seg, RR + 2, RR + 2, a.partC, a.red + 2 * RR, RW, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_als_C_epi<R>, dim3(nt), dim3(EPI_THREADS), 0, s, a, 1);
   }
   return hipGetLastError();
 }

@@ -27,56 +27,29 @@ dpar2_status fail(dpar2_status st, const std::string& msg) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Host-side schedule of the slab pass.
-struct Schedule {
-  std::vector<Item> items;          // longest first
-  std::vector<int32_t> slice_ptr;   // K+1
-  std::vector<int32_t> slice_list;  // item indices of each slice
+// A group of tensors sharing J, R, L, L2, the dtype and the iteration options
+// (a single-tensor call is a group of one).
+struct Group {
+  int nt = 0;
+  std::vector<dpar2_tensor> Xv;        // nt tensors (copies of the caller's structs)
+  std::vector<dpar2_opts> ov;          // nt options
+  std::vector<int> orig;               // index of each tensor in the caller's batch
+  const dpar2_tensor* X = nullptr;     // = Xv.data()
+  const dpar2_opts* o = nullptr;       // = ov.data()
+  std::vector<int64_t> k0;             // first global slice of each tensor (nt + 1)
 };
 
-// Alg. 4 on the GPU: slices longer than MAX_CHUNK_ROWS are cut into near-equal
-// row ranges; all items are sorted by length, longest first (stable), and
-// block b of the slab pass takes item b.  The hardware dispatcher starts each
-// next block on the first compute unit that frees up, i.e. greedy list
-// scheduling of the longest remaining item on the least-loaded unit.
-void build_schedule(const int64_t* off, int64_t K, Schedule* s) {
-  std::vector<Item> raw;
-  raw.reserve((size_t)K);
-  for (int64_t k = 0; k < K; ++k) {
-    const int64_t n = off[k + 1] - off[k];
-    const int64_t nc = std::max<int64_t>(1, (n + MAX_CHUNK_ROWS - 1) / MAX_CHUNK_ROWS);
-    for (int64_t c = 0; c < nc; ++c) {
-      Item it;
-      it.row0 = off[k] + n * c / nc;
-      it.row1 = off[k] + n * (c + 1) / nc;
-      it.slice = (int32_t)k;
-      it.pad = 0;
-      raw.push_back(it);
-    }
-  }
-  std::vector<size_t> idx(raw.size());
-  std::iota(idx.begin(), idx.end(), 0);
-  std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) {
-    return (raw[a].row1 - raw[a].row0) > (raw[b].row1 - raw[b].row0);
-  });
-  s->items.resize(raw.size());
-  for (size_t i = 0; i < idx.size(); ++i) s->items[i] = raw[idx[i]];
-  s->slice_ptr.assign((size_t)K + 1, 0);
-  for (const Item& it : s->items) s->slice_ptr[(size_t)it.slice + 1]++;
-  for (int64_t k = 0; k < K; ++k) s->slice_ptr[(size_t)k + 1] += s->slice_ptr[(size_t)k];
-  s->slice_list.assign(s->items.size(), 0);
-  std::vector<int32_t> fill(s->slice_ptr.begin(), s->slice_ptr.end() - 1);
-  for (size_t i = 0; i < s->items.size(); ++i) s->slice_list[(size_t)fill[s->items[i].slice]++] = (int32_t)i;
-}
-
-int64_t count_items(const int64_t* off, int64_t K) {
-  int64_t n = 0;
-  for (int64_t k = 0; k < K; ++k) {
-    const int64_t r = off[k + 1] - off[k];
-    n += std::max<int64_t>(1, (r + MAX_CHUNK_ROWS - 1) / MAX_CHUNK_ROWS);
-  }
-  return n;
-}
+// Host-side tables of a group: the slab-pass schedule and the block / chunk
+// maps of the per-slice and second-stage kernels.
+struct Schedule {
+  std::vector<Item> items;          // longest first; Item::pad = tensor
+  std::vector<int32_t> slice_ptr;   // K+1
+  std::vector<int32_t> slice_list;  // item indices of each slice
+  std::vector<Blk> blk, blk0;
+  std::vector<Chunk> chunks;
+  std::vector<int64_t> seg_blk, seg_blk0, seg_chunk, seg_slice;
+  std::vector<int32_t> slice_t;
+};
 
 dpar2_status validate(const dpar2_tensor* X, const dpar2_opts* o) {
   if (!X || !o) return fail(DPAR2_EINVAL, "tensor or options pointer is NULL");
@@ -89,7 +62,7 @@ dpar2_status validate(const dpar2_tensor* X, const dpar2_opts* o) {
     return fail(DPAR2_EINVAL, "unsupported slab dtype");
   if (X->dtype == DPAR2_FP8_E4M3 && !X->slice_scale)
     return fail(DPAR2_EINVAL, "fp8 slabs need slice_scale");
-  if (o->flags != 0) return fail(DPAR2_EINVAL, "opts.flags must be 0");
+  if (o->flags & ~DPAR2_FLAG_NO_GRAPH) return fail(DPAR2_EINVAL, "unknown bits in opts.flags");
   if (o->power_iters < 0 || o->power_iters > 4) return fail(DPAR2_EINVAL, "power_iters must be in [0, 4]");
   const int R = o->rank, L = o->sketch, L2 = o->sketch2;
   if (R < 1 || R > 32) return fail(DPAR2_ESHAPE, "rank must be in [1, 32]");
@@ -112,32 +85,157 @@ dpar2_status validate(const dpar2_tensor* X, const dpar2_opts* o) {
   return DPAR2_OK;
 }
 
-Layout make_layout(const dpar2_tensor* X, const dpar2_opts* o) {
+// Options that tensors of one group share (everything but tol).
+bool same_group(const dpar2_tensor& a, const dpar2_opts& oa, const dpar2_tensor& b, const dpar2_opts& ob) {
+  return a.J == b.J && a.dtype == b.dtype && oa.rank == ob.rank && oa.sketch == ob.sketch &&
+         oa.sketch2 == ob.sketch2 && oa.power_iters == ob.power_iters && oa.max_iter == ob.max_iter &&
+         oa.flags == ob.flags;
+}
+
+dpar2_status make_group(int32_t n, const dpar2_tensor* X, const dpar2_opts* o, Group* g) {
+  if (n < 1) return fail(DPAR2_EINVAL, "a group needs at least one tensor");
+  if (!X || !o) return fail(DPAR2_EINVAL, "tensor or options pointer is NULL");
+  g->nt = n;
+  g->Xv.assign(X, X + n);
+  g->ov.assign(o, o + n);
+  g->X = g->Xv.data();
+  g->o = g->ov.data();
+  if (g->orig.size() != (size_t)n) {
+    g->orig.resize((size_t)n);
+    std::iota(g->orig.begin(), g->orig.end(), 0);
+  }
+  g->k0.assign((size_t)n + 1, 0);
+  for (int32_t t = 0; t < n; ++t) {
+    dpar2_status st = validate(&X[t], &o[t]);
+    if (st != DPAR2_OK) {
+      if (n > 1) g_last_error = "tensor " + std::to_string(g->orig[(size_t)t]) + ": " + g_last_error;
+      return st;
+    }
+    if (!same_group(X[t], o[t], X[0], o[0]))
+      return fail(DPAR2_EINVAL, "tensors of one group must share J, dtype, rank, sketch widths, "
+                                "power_iters, max_iter and flags (tensor " + std::to_string(t) + " differs)");
+    g->k0[(size_t)t + 1] = g->k0[(size_t)t] + X[t].K;
+  }
+  if (g->k0[(size_t)n] > ((int64_t)1 << 30)) return fail(DPAR2_EINVAL, "too many slices in one batch");
+  return DPAR2_OK;
+}
+
+// Alg. 4 on the GPU: slices longer than MAX_CHUNK_ROWS are cut into near-equal
+// row ranges; all items are sorted by length, longest first (stable), and
+// block b of the slab pass takes item b.  The hardware dispatcher starts each
+// next block on the first compute unit that frees up, i.e. greedy list
+// scheduling of the longest remaining item on the least-loaded unit.
+int64_t items_of(int64_t rows) { return std::max<int64_t>(1, (rows + MAX_CHUNK_ROWS - 1) / MAX_CHUNK_ROWS); }
+
+void build_schedule(const Group& g, Schedule* s) {
+  const int nt = g.nt;
+  const int64_t K = g.k0[(size_t)nt];
+  const int64_t J = g.X[0].J;
+  const int R = g.o[0].rank;
+  std::vector<Item> raw;
+  raw.reserve((size_t)K);
+  for (int t = 0; t < nt; ++t) {
+    const int64_t* off = g.X[t].row_offsets_host;
+    for (int64_t k = 0; k < g.X[t].K; ++k) {
+      const int64_t n = off[k + 1] - off[k], nc = items_of(n);
+      for (int64_t c = 0; c < nc; ++c) {
+        Item it;
+        it.row0 = off[k] + n * c / nc;
+        it.row1 = off[k] + n * (c + 1) / nc;
+        it.slice = (int32_t)(g.k0[(size_t)t] + k);
+        it.pad = t;
+        raw.push_back(it);
+      }
+    }
+  }
+  std::vector<size_t> idx(raw.size());
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) {
+    return (raw[a].row1 - raw[a].row0) > (raw[b].row1 - raw[b].row0);
+  });
+  s->items.resize(raw.size());
+  for (size_t i = 0; i < idx.size(); ++i) s->items[i] = raw[idx[i]];
+  s->slice_ptr.assign((size_t)K + 1, 0);
+  for (const Item& it : s->items) s->slice_ptr[(size_t)it.slice + 1]++;
+  for (int64_t k = 0; k < K; ++k) s->slice_ptr[(size_t)k + 1] += s->slice_ptr[(size_t)k];
+  s->slice_list.assign(s->items.size(), 0);
+  std::vector<int32_t> fill(s->slice_ptr.begin(), s->slice_ptr.end() - 1);
+  for (size_t i = 0; i < s->items.size(); ++i) s->slice_list[(size_t)fill[s->items[i].slice]++] = (int32_t)i;
+  // per-slice kernel blocks (never straddling tensors), begin blocks (local
+  // rows 0 .. max(K_t, J)), second-stage chunks of M^T, slice -> tensor
+  const int gpb = als_slices_per_block(R);
+  s->blk.clear();
+  s->blk0.clear();
+  s->chunks.clear();
+  s->seg_blk.assign(1, 0);
+  s->seg_blk0.assign(1, 0);
+  s->seg_chunk.assign(1, 0);
+  s->seg_slice.assign(g.k0.begin(), g.k0.end());
+  s->slice_t.assign((size_t)K, 0);
+  for (int t = 0; t < nt; ++t) {
+    const int64_t k0 = g.k0[(size_t)t], Kt = g.X[t].K;
+    for (int64_t b = 0; b < Kt; b += gpb)
+      s->blk.push_back(Blk{t, (int32_t)(k0 + b), (int32_t)(k0 + std::min<int64_t>(Kt, b + gpb)), 0});
+    const int64_t rows = std::max<int64_t>(Kt, J);
+    for (int64_t b = 0; b < rows; b += gpb)
+      s->blk0.push_back(Blk{t, (int32_t)b, (int32_t)std::min<int64_t>(rows, b + gpb), 0});
+    for (int64_t r = k0 * R; r < (k0 + Kt) * R; r += STAGE2_CHUNK)
+      s->chunks.push_back(Chunk{r, std::min<int64_t>((k0 + Kt) * R, r + STAGE2_CHUNK), t, 0});
+    s->seg_blk.push_back((int64_t)s->blk.size());
+    s->seg_blk0.push_back((int64_t)s->blk0.size());
+    s->seg_chunk.push_back((int64_t)s->chunks.size());
+    for (int64_t k = 0; k < Kt; ++k) s->slice_t[(size_t)(k0 + k)] = t;
+  }
+}
+
+Layout make_layout(const Group& g) {
   Layout y;
   std::memset(&y, 0, sizeof(y));
-  y.K = X->K;
-  y.J = X->J;
-  y.N = X->row_offsets_host[X->K];
+  const dpar2_opts* o = g.o;
+  y.nt = g.nt;
+  y.K = g.k0[(size_t)g.nt];
+  y.J = g.X[0].J;
   y.R = o->rank;
   y.L = o->sketch;
   y.L2 = o->sketch2;
   y.max_iter = o->max_iter;
-  y.n_items = count_items(X->row_offsets_host, X->K);
-  const int64_t K = y.K, J = y.J, R = y.R, L = y.L, L2 = y.L2, KR = K * R, RR = R * R;
-  y.n2 = (KR + STAGE2_CHUNK - 1) / STAGE2_CHUNK;
-  y.nblkA = y.nblkB = y.nblkC = als_blocks(K > J ? K : J, (int)R);
-  y.nblkF = (int)std::min<int64_t>(K, 1024);
-  const int64_t nbf = (KR + 255) / 256;
+  y.q = o->power_iters;
+  y.N = 0;
+  y.n_items = 0;
+  y.n2 = 0;
+  y.nblk = 0;
+  y.nblk0 = 0;
+  const int gpb = als_slices_per_block(y.R);
+  for (int t = 0; t < g.nt; ++t) {
+    const int64_t* off = g.X[t].row_offsets_host;
+    const int64_t Kt = g.X[t].K;
+    y.N += off[Kt];
+    for (int64_t k = 0; k < Kt; ++k) y.n_items += items_of(off[k + 1] - off[k]);
+    y.n2 += (Kt * y.R + STAGE2_CHUNK - 1) / STAGE2_CHUNK;
+    y.nblk += (int)((Kt + gpb - 1) / gpb);
+    y.nblk0 += (int)((std::max<int64_t>(Kt, y.J) + gpb - 1) / gpb);
+  }
+  const int64_t nt = y.nt, K = y.K, J = y.J, R = y.R, L = y.L, L2 = y.L2, KR = K * R, RR = R * R;
   size_t p = 0;
   auto take = [&](size_t bytes) {
     const size_t at = p;
     p = align256(p + bytes);
     return at;
   };
-  y.ctl = take(sizeof(Ctl));
+  y.tdesc = take(sizeof(TDesc) * (size_t)nt);
+  y.blk = take(sizeof(Blk) * (size_t)y.nblk);
+  y.blk0 = take(sizeof(Blk) * (size_t)y.nblk0);
+  y.chunks = take(sizeof(Chunk) * (size_t)y.n2);
+  y.seg_blk = take(sizeof(int64_t) * (size_t)(nt + 1));
+  y.seg_blk0 = take(sizeof(int64_t) * (size_t)(nt + 1));
+  y.seg_chunk = take(sizeof(int64_t) * (size_t)(nt + 1));
+  y.seg_slice = take(sizeof(int64_t) * (size_t)(nt + 1));
+  y.slice_t = take(sizeof(int32_t) * (size_t)K);
   y.items = take(sizeof(Item) * (size_t)y.n_items);
   y.slice_ptr = take(sizeof(int32_t) * (size_t)(K + 1));
   y.slice_list = take(sizeof(int32_t) * (size_t)y.n_items);
+  y.tables_end = p;   // [tdesc, tables_end): host-built tables, one upload
+  y.ctl = take(sizeof(Ctl) * (size_t)nt);
   y.partG = take(sizeof(double) * (size_t)(y.n_items * L * L));
   y.partP = take(sizeof(double) * (size_t)(y.n_items * L * J));
   y.partS = take(sizeof(double) * (size_t)y.n_items);
@@ -146,28 +244,28 @@ Layout make_layout(const dpar2_tensor* X, const dpar2_opts* o) {
   y.Phi = take(sizeof(double) * (size_t)(K * L * R));
   y.sig1 = take(sizeof(double) * (size_t)KR);
   y.Y2p = take(sizeof(double) * (size_t)(y.n2 * L2 * J));
-  y.Y2 = take(sizeof(double) * (size_t)(J * L2));
+  y.Y2 = take(sizeof(double) * (size_t)(nt * J * L2));
   y.B2t = take(sizeof(double) * (size_t)(KR * L2));
   y.S2p = take(sizeof(double) * (size_t)(y.n2 * L2 * (L2 + 1) / 2));
-  y.U2 = take(sizeof(double) * (size_t)(L2 * R));
-  y.D = take(sizeof(double) * (size_t)(J * R));
-  y.E = take(sizeof(double) * (size_t)R);
+  y.S2 = take(sizeof(double) * (size_t)(nt * L2 * (L2 + 1) / 2));
+  y.U2 = take(sizeof(double) * (size_t)(nt * L2 * R));
+  y.D = take(sizeof(double) * (size_t)(nt * J * R));
+  y.E = take(sizeof(double) * (size_t)(nt * R));
   y.F = take(sizeof(double) * (size_t)(KR * R));
-  y.FtFp = take(sizeof(double) * (size_t)(nbf * RR));
+  y.FtFp = take(sizeof(double) * (size_t)(y.n2 * RR));
   y.Psi = take(sizeof(double) * (size_t)(K * RR));
   y.Pw = take(sizeof(double) * (size_t)(K * RR));
   y.Mk = take(sizeof(double) * (size_t)(K * RR));
-  y.small = take(sizeof(double) * (size_t)(SM_COUNT * RR));
-  y.partA = take(sizeof(double) * (size_t)(y.nblkA * RR));
-  y.partB = take(sizeof(double) * (size_t)(y.nblkB * RR));
-  y.partC = take(sizeof(double) * (size_t)(y.nblkC * (RR + 2)));
-  y.partBegin = take(sizeof(double) * (size_t)(y.nblkC * 3 * RR));
-  y.red = take(sizeof(double) * (size_t)(6 * RR + 2));
-
-  y.fitp = take(sizeof(double) * (size_t)(2 * y.nblkF));
+  y.small = take(sizeof(double) * (size_t)(nt * SM_COUNT * RR));
+  y.partA = take(sizeof(double) * (size_t)(y.nblk * RR));
+  y.partB = take(sizeof(double) * (size_t)(y.nblk * RR));
+  y.partC = take(sizeof(double) * (size_t)(y.nblk * (RR + 2)));
+  y.partBegin = take(sizeof(double) * (size_t)(y.nblk0 * 3 * RR));
+  y.red = take(sizeof(double) * (size_t)(nt * (RED_WIDTH * RR + 2)));
+  y.fitp = take(sizeof(double) * (size_t)(2 * K + 2 * nt));
   y.trace = take(sizeof(double) * (size_t)(K * L * R));   // Theta for the U output
-  y.om1 = take(sizeof(float) * (size_t)(J * L));           // copy of Omega_1 for the U pass
-  y.omq = take(o->power_iters > 0 ? sizeof(float) * (size_t)(K * J * L) : 0);   // power-step sketches
+  y.om1 = take(sizeof(float) * (size_t)(nt * J * L));      // copy of each Omega_1 for the U pass
+  y.omq = take(y.q > 0 ? sizeof(float) * (size_t)(K * J * L) : 0);   // power-step sketches
   y.total = p;
   return y;
 }
@@ -180,19 +278,138 @@ dpar2_status check_ws(const Layout& y, const void* ws, size_t bytes) {
   return DPAR2_OK;
 }
 
+// A batch: its tensors partitioned into groups (same J, dtype, rank, sketch
+// widths, power_iters, max_iter and flags; in order of first appearance),
+// each group with its own layout in consecutive 256-byte aligned parts of
+// one workspace.
+struct Batch {
+  std::vector<Group> groups;
+  std::vector<Layout> lay;
+  std::vector<size_t> base;
+  size_t total = 0;
+};
+
+dpar2_status make_batch(int32_t n, const dpar2_tensor* X, const dpar2_opts* o, Batch* b) {
+  if (n < 1) return fail(DPAR2_EINVAL, "a batch needs at least one tensor");
+  if (!X || !o) return fail(DPAR2_EINVAL, "tensor or options pointer is NULL");
+  std::vector<std::vector<int>> members;
+  for (int32_t t = 0; t < n; ++t) {
+    const dpar2_status st = validate(&X[t], &o[t]);
+    if (st != DPAR2_OK) {
+      g_last_error = "tensor " + std::to_string(t) + ": " + g_last_error;
+      return st;
+    }
+    size_t gi = 0;
+    while (gi < members.size() && !same_group(X[t], o[t], X[members[gi][0]], o[members[gi][0]])) ++gi;
+    if (gi == members.size()) members.emplace_back();
+    members[gi].push_back(t);
+  }
+  b->groups.resize(members.size());
+  b->lay.clear();
+  b->base.clear();
+  b->total = 0;
+  for (size_t gi = 0; gi < members.size(); ++gi) {
+    std::vector<dpar2_tensor> xs;
+    std::vector<dpar2_opts> os;
+    for (int t : members[gi]) {
+      xs.push_back(X[t]);
+      os.push_back(o[t]);
+    }
+    Group& g = b->groups[gi];
+    g.orig = members[gi];
+    dpar2_status st = make_group((int32_t)xs.size(), xs.data(), os.data(), &g);
+    if (st != DPAR2_OK) return st;
+    b->lay.push_back(make_layout(g));
+    b->base.push_back(b->total);
+    b->total = align256(b->total + b->lay.back().total);
+  }
+  return DPAR2_OK;
+}
+
 dpar2_status hip_fail(hipError_t e, const char* where) {
   return fail(DPAR2_EHIP, std::string(where) + ": " + hipGetErrorString(e));
 }
 
-// Pinned staging buffer for the schedule upload, one per workspace; an event
-// guards reuse until the previous copy from it has completed.
+// Pinned staging buffers for the table uploads: a ring of STAGE_SLOTS per
+// workspace, each guarded by an event until the copy out of it has completed
+// (so the host waits only on an upload STAGE_SLOTS calls back).  Each upload
+// is ONE copy of a contiguous image of the table region of the workspace.
+constexpr int STAGE_SLOTS = 4;
 struct Staging {
-  void* host = nullptr;
-  size_t bytes = 0;
-  hipEvent_t done = nullptr;
+  void* host[STAGE_SLOTS] = {};
+  size_t bytes[STAGE_SLOTS] = {};
+  hipEvent_t done[STAGE_SLOTS] = {};
+  int next = 0;
+  // host image of the schedule tables of the last compress on this
+  // workspace, and what it was built from (reused when that is unchanged)
+  std::vector<int64_t> key;
+  std::vector<char> image;
 };
 std::mutex g_stage_mu;
 std::unordered_map<const void*, Staging> g_stage;
+
+__global__ __launch_bounds__(256) void k_upload(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                int64_t n16) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += (int64_t)gridDim.x * 256)
+    dst[i] = src[i];
+}
+
+// Copies bytes [0, n) of `img` to the workspace at offset `at`, through the
+// staging ring, asynchronously on s.  Caller holds g_stage_mu.
+dpar2_status upload_locked(Staging& sg, char* w, const char* img, size_t n, size_t at, hipStream_t s) {
+  const int i = sg.next;
+  sg.next = (i + 1) % STAGE_SLOTS;
+  hipError_t e;
+  if (sg.done[i]) {
+    if ((e = hipEventSynchronize(sg.done[i])) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+  } else if ((e = hipEventCreateWithFlags(&sg.done[i], hipEventDisableTiming)) != hipSuccess) {
+    return hip_fail(e, "hipEventCreate");
+  }
+  const size_t cap = (n + 15) / 16 * 16;
+  if (sg.bytes[i] < cap) {
+    if (sg.host[i]) (void)hipHostFree(sg.host[i]);
+    sg.host[i] = nullptr;
+    sg.bytes[i] = 0;
+    if ((e = hipHostMalloc(&sg.host[i], cap, hipHostMallocDefault)) != hipSuccess)
+      return hip_fail(e, "hipHostMalloc");
+    sg.bytes[i] = cap;
+  }
+  std::memcpy(sg.host[i], img, n);
+  // a kernel reads the pinned buffer over the bus: stream-ordered like a
+  // copy, without the host waiting for the stream
+  const int64_t n16 = (int64_t)(n + 15) / 16;
+  const unsigned blocks = (unsigned)std::min<int64_t>(1024, (n16 + 255) / 256);
+  hipLaunchKernelGGL(k_upload, dim3(blocks), dim3(256), 0, s, static_cast<const uint4*>(sg.host[i]),
+                     reinterpret_cast<uint4*>(w + at), n16);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "table upload");
+  if ((e = hipEventRecord(sg.done[i], s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+  return DPAR2_OK;
+}
+
+// Per-tensor descriptors; factor and trace pointers come from the call that
+// uses them (NULL where a call has none).
+std::vector<TDesc> descriptors(const Group& g, const float* const* om1, const float* const* om2,
+                               const dpar2_factors* f, double* const* trace) {
+  std::vector<TDesc> td((size_t)g.nt);
+  for (int t = 0; t < g.nt; ++t) {
+    TDesc& d = td[(size_t)t];
+    std::memset(&d, 0, sizeof(d));
+    d.K = g.X[t].K;
+    d.k0 = g.k0[(size_t)t];
+    d.slab = g.X[t].slab;
+    d.scale = g.X[t].dtype == DPAR2_FP8_E4M3 ? g.X[t].slice_scale : nullptr;
+    d.om1 = om1 ? om1[t] : nullptr;
+    d.om2 = om2 ? om2[t] : nullptr;
+    if (f) {
+      d.H = f[t].H;
+      d.V = f[t].V;
+      d.W = f[t].W;
+    }
+    d.trace = trace ? trace[t] : nullptr;
+    d.tol = g.o[t].tol;
+  }
+  return td;
+}
 
 // Slab-pass timing (dpar2_profile_*).
 struct Profile {
@@ -203,76 +420,81 @@ struct Profile {
 std::mutex g_prof_mu;
 Profile g_prof;
 
-__global__ void k_ctl_reset(Ctl* ctl) {
-  Ctl z;
-  std::memset(&z, 0, sizeof(z));
-  *ctl = z;
+// Start of a compress: clears each tensor's control block and keeps a copy
+// of its Omega_1 in the workspace (for a later U pass); one block per tensor.
+__global__ __launch_bounds__(256) void k_prep(const TDesc* __restrict__ td, int JL, Ctl* __restrict__ ctl,
+                                              float* __restrict__ om1_copy) {
+  const int t = blockIdx.x;
+  if (threadIdx.x == 0) {
+    Ctl z;
+    std::memset(&z, 0, sizeof(z));
+    ctl[t] = z;
+  }
+  const float* __restrict__ src = td[t].om1;
+  float* __restrict__ dst = om1_copy + (size_t)t * JL;
+  for (int e = threadIdx.x; e < JL; e += 256) dst[e] = src[e];
 }
 
-}  // namespace
-
-extern "C" {
-
-size_t dpar2_workspace_size(const dpar2_tensor* X, const dpar2_opts* o) {
-  if (validate(X, o) != DPAR2_OK) return 0;
-  return make_layout(X, o).total;
-}
-
-dpar2_status dpar2_compress(const dpar2_tensor* X, const dpar2_opts* o, const float* omega1,
-                            const float* omega2, void* ws, size_t ws_bytes, dpar2_stream_t stream) {
-  dpar2_status st = validate(X, o);
-  if (st != DPAR2_OK) return st;
-  if (!omega1 || !omega2) return fail(DPAR2_EINVAL, "omega1 and omega2 must be non-NULL");
-  const Layout y = make_layout(X, o);
-  if ((st = check_ws(y, ws, ws_bytes)) != DPAR2_OK) return st;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  char* w = static_cast<char*>(ws);
-
+// Puts the schedule tables of g (the part of [tdesc, tables_end) after the
+// descriptors) into sg.image, rebuilding them only when what they depend on
+// (J, R and every tensor's row offsets) changed since the last compress on
+// this workspace.
+void stage_tables(const Group& g, const Layout& y, Staging& sg) {
+  std::vector<int64_t> key = {g.nt, y.J, y.R};
+  for (int t = 0; t < g.nt; ++t) {
+    key.push_back(g.X[t].K);
+    key.insert(key.end(), g.X[t].row_offsets_host, g.X[t].row_offsets_host + g.X[t].K + 1);
+  }
+  const size_t n = y.tables_end - y.tdesc;
+  if (key == sg.key && sg.image.size() == n) return;
   Schedule sch;
-  build_schedule(X->row_offsets_host, X->K, &sch);
-  const size_t b_items = sizeof(Item) * sch.items.size();
-  const size_t b_ptr = sizeof(int32_t) * sch.slice_ptr.size();
-  const size_t b_list = sizeof(int32_t) * sch.slice_list.size();
+  build_schedule(g, &sch);
+  sg.image.assign(n, 0);
+  auto put = [&](const void* src, size_t bytes, size_t at) {
+    if (bytes) std::memcpy(sg.image.data() + (at - y.tdesc), src, bytes);
+  };
+  put(sch.blk.data(), sizeof(Blk) * sch.blk.size(), y.blk);
+  put(sch.blk0.data(), sizeof(Blk) * sch.blk0.size(), y.blk0);
+  put(sch.chunks.data(), sizeof(Chunk) * sch.chunks.size(), y.chunks);
+  put(sch.seg_blk.data(), sizeof(int64_t) * sch.seg_blk.size(), y.seg_blk);
+  put(sch.seg_blk0.data(), sizeof(int64_t) * sch.seg_blk0.size(), y.seg_blk0);
+  put(sch.seg_chunk.data(), sizeof(int64_t) * sch.seg_chunk.size(), y.seg_chunk);
+  put(sch.seg_slice.data(), sizeof(int64_t) * sch.seg_slice.size(), y.seg_slice);
+  put(sch.slice_t.data(), sizeof(int32_t) * sch.slice_t.size(), y.slice_t);
+  put(sch.items.data(), sizeof(Item) * sch.items.size(), y.items);
+  put(sch.slice_ptr.data(), sizeof(int32_t) * sch.slice_ptr.size(), y.slice_ptr);
+  put(sch.slice_list.data(), sizeof(int32_t) * sch.slice_list.size(), y.slice_list);
+  sg.key = std::move(key);
+}
+
+// Uploads the descriptors alone (factor and trace pointers of a call).
+dpar2_status upload_descriptors(char* w, const Layout& y, const std::vector<TDesc>& td, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_stage_mu);
+  return upload_locked(g_stage[w], w, reinterpret_cast<const char*>(td.data()), sizeof(TDesc) * td.size(),
+                       y.tdesc, s);
+}
+
+// --- group steps -------------------------------------------------------------
+
+dpar2_status group_compress(const Group& g, const float* const* om1, const float* const* om2,
+                            const dpar2_factors* f, char* w, const Layout& y, hipStream_t s) {
+  for (int t = 0; t < g.nt; ++t)
+    if (!om1[t] || !om2[t]) return fail(DPAR2_EINVAL, "omega1 and omega2 must be non-NULL");
+  const std::vector<TDesc> td = descriptors(g, om1, om2, f, nullptr);
   {
+    // descriptors + schedule tables: one copy
     std::lock_guard<std::mutex> lk(g_stage_mu);
-    Staging& sg = g_stage[ws];
-    const size_t need = b_items + b_ptr + b_list;
-    hipError_t e;
-    if (sg.done) {
-      if ((e = hipEventSynchronize(sg.done)) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
-    } else if ((e = hipEventCreateWithFlags(&sg.done, hipEventDisableTiming)) != hipSuccess) {
-      return hip_fail(e, "hipEventCreate");
-    }
-    if (sg.bytes < need) {
-      if (sg.host) (void)hipHostFree(sg.host);
-      sg.host = nullptr;
-      sg.bytes = 0;
-      if ((e = hipHostMalloc(&sg.host, need, hipHostMallocDefault)) != hipSuccess)
-        return hip_fail(e, "hipHostMalloc");
-      sg.bytes = need;
-    }
-    char* h = static_cast<char*>(sg.host);
-    std::memcpy(h, sch.items.data(), b_items);
-    std::memcpy(h + b_items, sch.slice_ptr.data(), b_ptr);
-    std::memcpy(h + b_items + b_ptr, sch.slice_list.data(), b_list);
-    if ((e = hipMemcpyAsync(w + y.items, h, b_items, hipMemcpyHostToDevice, s)) != hipSuccess)
-      return hip_fail(e, "hipMemcpyAsync");
-    if ((e = hipMemcpyAsync(w + y.slice_ptr, h + b_items, b_ptr, hipMemcpyHostToDevice, s)) != hipSuccess)
-      return hip_fail(e, "hipMemcpyAsync");
-    if ((e = hipMemcpyAsync(w + y.slice_list, h + b_items + b_ptr, b_list, hipMemcpyHostToDevice, s)) !=
-        hipSuccess)
-      return hip_fail(e, "hipMemcpyAsync");
-    if ((e = hipEventRecord(sg.done, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    Staging& sg = g_stage[w];
+    stage_tables(g, y, sg);
+    std::memcpy(sg.image.data(), td.data(), sizeof(TDesc) * td.size());
+    dpar2_status st = upload_locked(sg, w, sg.image.data(), sg.image.size(), y.tdesc, s);
+    if (st != DPAR2_OK) return st;
   }
-  {
-    hipError_t e = hipMemcpyAsync(w + y.om1, omega1, sizeof(float) * (size_t)(y.J * y.L),
-                                  hipMemcpyDeviceToDevice, s);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
-  }
+  hipError_t e;
   Ctl* ctl = reinterpret_cast<Ctl*>(w + y.ctl);
-  hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(1), 0, s, ctl);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return hip_fail(e, "ctl reset");
+  hipLaunchKernelGGL(k_prep, dim3((unsigned)g.nt), dim3(256), 0, s, reinterpret_cast<const TDesc*>(w + y.tdesc),
+                     (int)(y.J * y.L), ctl, reinterpret_cast<float*>(w + y.om1));
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "compress set-up");
 
   const Item* items = reinterpret_cast<const Item*>(w + y.items);
   double* partG = reinterpret_cast<double*>(w + y.partG);
@@ -293,10 +515,13 @@ dpar2_status dpar2_compress(const dpar2_tensor* X, const dpar2_opts* o, const fl
       g_prof.used++;
     }
   }
+  const int dtype = g.X[0].dtype;
+  const int esize = dtype == DPAR2_F32 ? 4 : (dtype == DPAR2_BF16 ? 2 : 1);
+  bool vec = y.J % 4 == 0;
+  for (int t = 0; t < g.nt; ++t) vec = vec && ((uintptr_t)g.X[t].slab % (4 * esize) == 0);
   SlabArgs sa;
   std::memset(&sa, 0, sizeof(sa));
-  sa.slab = X->slab;
-  sa.scale = X->slice_scale;
+  sa.td = reinterpret_cast<const TDesc*>(w + y.tdesc);
   sa.J = (int)y.J;
   sa.L = y.L;
   sa.R = y.R;
@@ -305,12 +530,12 @@ dpar2_status dpar2_compress(const dpar2_tensor* X, const dpar2_opts* o, const fl
   sa.partP = partP;
   sa.partS = partS;
   float* omq = reinterpret_cast<float*>(w + y.omq);
-  for (int pass = 0; pass <= o->power_iters; ++pass) {
-    // pass 0 sketches with Omega_1; a power step with each slice's own matrix
-    sa.omega = pass == 0 ? omega1 : omq;
-    sa.om_stride = pass == 0 ? 0 : y.J * y.L;
+  for (int pass = 0; pass <= y.q; ++pass) {
+    // pass 0 sketches with each tensor's Omega_1; a power step with each
+    // slice's own matrix
+    sa.omega = pass == 0 ? nullptr : omq;
     if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-    e = launch_slab(sa, X->dtype, y.n_items, false, s);
+    e = launch_slab(sa, dtype, y.n_items, vec, false, s);
     if (e != hipSuccess) return hip_fail(e, "slab pass");
     if (ev1 && (e = hipEventRecord(ev1, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     ev0 = ev1 = nullptr;   // the timing hooks cover the first pass
@@ -318,124 +543,295 @@ dpar2_status dpar2_compress(const dpar2_tensor* X, const dpar2_opts* o, const fl
                             reinterpret_cast<const int32_t*>(w + y.slice_list), partG, partP, partS,
                             reinterpret_cast<double*>(w + y.xnorm2), reinterpret_cast<double*>(w + y.Mt),
                             reinterpret_cast<double*>(w + y.Phi), reinterpret_cast<double*>(w + y.sig1),
-                            pass < o->power_iters ? omq : nullptr, ctl, s);
+                            pass < y.q ? omq : nullptr, ctl, s);
     if (e != hipSuccess) return hip_fail(e, "slice finish");
   }
-  e = launch_stage2(y, w, omega2, s);
+  e = launch_stage2(y, w, s);
   if (e != hipSuccess) return hip_fail(e, "second stage");
   e = launch_pw_identity(y, w, s);
   if (e != hipSuccess) return hip_fail(e, "iteration state init");
   return DPAR2_OK;
 }
 
+dpar2_status group_factors(const Group& g, const dpar2_factors* f, double* const* trace, char* w, const Layout& y,
+                           hipStream_t s) {
+  for (int t = 0; t < g.nt; ++t)
+    if (!f[t].H || !f[t].V || !f[t].W) return fail(DPAR2_EINVAL, "factors must be non-NULL");
+  // the Omega pointers are needed by the slab pass only: the iteration and
+  // fitness kernels read factors, trace and tolerance
+  return upload_descriptors(w, y, descriptors(g, nullptr, nullptr, f, trace), s);
+}
+
+hipError_t enqueue_als(int32_t n_steps, char* w, const Layout& y, hipStream_t s) {
+  hipError_t e = launch_als_begin(y, w, s);
+  for (int32_t i = 0; e == hipSuccess && i < n_steps; ++i) e = launch_als_iteration(y, w, s);
+  if (e == hipSuccess) e = launch_als_end(y, w, s);
+  return e;
+}
+
+// Captured iteration sequences, per workspace (a few step counts each).
+struct GraphEntry {
+  std::vector<int64_t> key;
+  hipGraphExec_t exec = nullptr;
+};
+struct GraphCache {
+  hipStream_t cap = nullptr;   // capture stream (never runs work)
+  std::vector<GraphEntry> entries;
+};
+constexpr size_t GRAPHS_PER_WS = 4;
+std::mutex g_graph_mu;
+std::unordered_map<const void*, GraphCache> g_graphs;
+
+dpar2_status group_als(const Group& g, int32_t n_steps, char* w, const Layout& y, hipStream_t s) {
+  hipError_t e;
+  if (n_steps < 2 || (g.o[0].flags & DPAR2_FLAG_NO_GRAPH)) {
+    if ((e = enqueue_als(n_steps, w, y, s)) != hipSuccess) return hip_fail(e, "iteration");
+    return DPAR2_OK;
+  }
+  // every kernel argument is a workspace address or a layout size: the graph
+  // of one (workspace, layout, step count) replays for any factors
+  const std::vector<int64_t> key = {(int64_t)y.total, y.nt, y.K, y.J, y.R, y.nblk, y.nblk0, n_steps};
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  GraphCache& gc = g_graphs[w];
+  GraphEntry* hit = nullptr;
+  for (GraphEntry& ge : gc.entries)
+    if (ge.key == key) hit = &ge;
+  if (!hit) {
+    if (!gc.cap && (e = hipStreamCreateWithFlags(&gc.cap, hipStreamNonBlocking)) != hipSuccess)
+      return hip_fail(e, "hipStreamCreate");
+    if ((e = hipStreamBeginCapture(gc.cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+      return hip_fail(e, "hipStreamBeginCapture");
+    const hipError_t el = enqueue_als(n_steps, w, y, gc.cap);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(gc.cap, &graph);
+    if (el != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return hip_fail(el, "iteration (capture)");
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    if (gc.entries.size() >= GRAPHS_PER_WS) {
+      (void)hipGraphExecDestroy(gc.entries.front().exec);
+      gc.entries.erase(gc.entries.begin());
+    }
+    gc.entries.push_back(GraphEntry{key, exec});
+    hit = &gc.entries.back();
+  }
+  if ((e = hipGraphLaunch(hit->exec, s)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return DPAR2_OK;
+}
+
+// U_k = A_k Z_k P_k^T H (Alg. 3 output) by re-running the tiles of the last
+// slab pass (same Y bit for bit) against Theta_k = Phi_k Psi_k H; the
+// descriptors on the device must hold the Omega_1 of that pass.
+dpar2_status group_output_U(const Group& g, const Layout& y, char* w, const double* H, double* U, hipStream_t s) {
+  double* theta = reinterpret_cast<double*>(w + y.trace);
+  hipError_t e = launch_theta(y, w, H, theta, s);
+  if (e != hipSuccess) return hip_fail(e, "theta");
+  const int dtype = g.X[0].dtype;
+  const int esize = dtype == DPAR2_F32 ? 4 : (dtype == DPAR2_BF16 ? 2 : 1);
+  SlabArgs sa;
+  std::memset(&sa, 0, sizeof(sa));
+  sa.td = reinterpret_cast<const TDesc*>(w + y.tdesc);
+  sa.J = (int)y.J;
+  sa.L = y.L;
+  sa.R = y.R;
+  sa.omega = y.q > 0 ? reinterpret_cast<const float*>(w + y.omq) : nullptr;
+  sa.items = reinterpret_cast<const Item*>(w + y.items);
+  sa.theta = theta;
+  sa.U = U;
+  const bool vec = (y.J % 4 == 0) && ((uintptr_t)g.X[0].slab % (4 * esize) == 0);
+  e = launch_slab(sa, dtype, y.n_items, vec, true, s);
+  if (e != hipSuccess) return hip_fail(e, "U pass");
+  return DPAR2_OK;
+}
+
+dpar2_status group_report(const Group& g, const void* ws, const Layout& y, dpar2_report* rep, hipStream_t s) {
+  std::vector<Ctl> c((size_t)g.nt);
+  hipError_t e = hipMemcpyAsync(c.data(), static_cast<const char*>(ws) + y.ctl, sizeof(Ctl) * c.size(),
+                                hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  for (int t = 0; t < g.nt; ++t) {
+    const Ctl& ct = c[(size_t)t];
+    dpar2_report& r = rep[t];
+    r.iters = ct.iters;
+    r.converged = ct.done;
+    r.err_last = ct.e_prev;
+    r.xnorm2 = ct.xnorm2;
+    r.fit_compressed = ct.xnorm2 > 0 ? 1.0 - ct.e_prev / ct.xnorm2 : 0.0;
+    r.fit_true = ct.fit_true;
+    // first-stage warnings are recorded once for the group (control block 0)
+    r.warn_bits = ct.warn | c[0].warn;
+  }
+  return DPAR2_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t dpar2_workspace_size(const dpar2_tensor* X, const dpar2_opts* o) {
+  Group g;
+  if (make_group(1, X, o, &g) != DPAR2_OK) return 0;
+  return make_layout(g).total;
+}
+
+size_t dpar2_batch_workspace_size(int32_t n, const dpar2_tensor* X, const dpar2_opts* o) {
+  Batch b;
+  if (make_batch(n, X, o, &b) != DPAR2_OK) return 0;
+  return b.total;
+}
+
+dpar2_status dpar2_compress(const dpar2_tensor* X, const dpar2_opts* o, const float* omega1,
+                            const float* omega2, void* ws, size_t ws_bytes, dpar2_stream_t stream) {
+  Group g;
+  dpar2_status st = make_group(1, X, o, &g);
+  if (st != DPAR2_OK) return st;
+  const Layout y = make_layout(g);
+  if ((st = check_ws(y, ws, ws_bytes)) != DPAR2_OK) return st;
+  return group_compress(g, &omega1, &omega2, nullptr, static_cast<char*>(ws), y,
+                        reinterpret_cast<hipStream_t>(stream));
+}
+
 dpar2_status dpar2_als_step(const dpar2_tensor* X, const dpar2_opts* o, dpar2_factors* f, int32_t n_steps,
                             double* err_trace, void* ws, size_t ws_bytes, dpar2_stream_t stream) {
-  dpar2_status st = validate(X, o);
+  Group g;
+  dpar2_status st = make_group(1, X, o, &g);
   if (st != DPAR2_OK) return st;
-  if (!f || !f->H || !f->V || !f->W) return fail(DPAR2_EINVAL, "factors must be non-NULL");
+  if (!f) return fail(DPAR2_EINVAL, "factors must be non-NULL");
   if (n_steps < 0) return fail(DPAR2_EINVAL, "n_steps must be >= 0");
-  const Layout y = make_layout(X, o);
+  const Layout y = make_layout(g);
   if ((st = check_ws(y, ws, ws_bytes)) != DPAR2_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
-  hipError_t e = launch_als_begin(y, w, f->H, f->V, f->W, s);
-  if (e != hipSuccess) return hip_fail(e, "iteration begin");
-  for (int32_t t = 0; t < n_steps; ++t) {
-    e = launch_als_iteration(y, w, f->H, f->V, f->W, err_trace, o->tol, s);
-    if (e != hipSuccess) return hip_fail(e, "iteration");
-  }
-  e = launch_als_end(y, w, f->V, s);
-  if (e != hipSuccess) return hip_fail(e, "iteration end");
-  return DPAR2_OK;
+  if ((st = group_factors(g, f, &err_trace, w, y, s)) != DPAR2_OK) return st;
+  return group_als(g, n_steps, w, y, s);
 }
 
 dpar2_status dpar2_fitness(const dpar2_tensor* X, const dpar2_opts* o, const dpar2_factors* f, double* fit,
                            void* ws, size_t ws_bytes, dpar2_stream_t stream) {
-  dpar2_status st = validate(X, o);
+  Group g;
+  dpar2_status st = make_group(1, X, o, &g);
   if (st != DPAR2_OK) return st;
-  if (!f || !f->H || !f->V || !f->W) return fail(DPAR2_EINVAL, "factors must be non-NULL");
-  const Layout y = make_layout(X, o);
+  if (!f) return fail(DPAR2_EINVAL, "factors must be non-NULL");
+  const Layout y = make_layout(g);
   if ((st = check_ws(y, ws, ws_bytes)) != DPAR2_OK) return st;
-  hipError_t e = launch_fitness(y, static_cast<char*>(ws), f->H, f->V, f->W, fit,
-                                reinterpret_cast<hipStream_t>(stream));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  double* none = nullptr;
+  if ((st = group_factors(g, f, &none, w, y, s)) != DPAR2_OK) return st;
+  hipError_t e = launch_fitness(y, w, fit, s);
   if (e != hipSuccess) return hip_fail(e, "fitness");
   return DPAR2_OK;
 }
 
 dpar2_status dpar2_output_U(const dpar2_tensor* X, const dpar2_opts* o, const dpar2_factors* f, double* U,
                             void* ws, size_t ws_bytes, dpar2_stream_t stream) {
-  dpar2_status st = validate(X, o);
+  Group g;
+  dpar2_status st = make_group(1, X, o, &g);
   if (st != DPAR2_OK) return st;
   if (!f || !f->H || !U) return fail(DPAR2_EINVAL, "H and U must be non-NULL");
-  const Layout y = make_layout(X, o);
+  const Layout y = make_layout(g);
   if ((st = check_ws(y, ws, ws_bytes)) != DPAR2_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
-  double* theta = reinterpret_cast<double*>(w + y.trace);
-  hipError_t e = launch_theta(y, w, f->H, theta, s);
-  if (e != hipSuccess) return hip_fail(e, "theta");
-  // the tiles of the U pass are those of the (last) slab pass: same Y bit for bit
-  SlabArgs sa;
-  std::memset(&sa, 0, sizeof(sa));
-  sa.slab = X->slab;
-  sa.scale = X->slice_scale;
-  sa.J = (int)y.J;
-  sa.L = y.L;
-  sa.R = y.R;
-  sa.omega = o->power_iters > 0 ? reinterpret_cast<const float*>(w + y.omq)
-                                : reinterpret_cast<const float*>(w + y.om1);
-  sa.om_stride = o->power_iters > 0 ? y.J * y.L : 0;
-  sa.items = reinterpret_cast<const Item*>(w + y.items);
-  sa.theta = theta;
-  sa.U = U;
-  e = launch_slab(sa, X->dtype, y.n_items, true, s);
-  if (e != hipSuccess) return hip_fail(e, "U pass");
-  return DPAR2_OK;
+  // the descriptor's Omega_1 is the workspace copy taken by dpar2_compress
+  const float* om1 = reinterpret_cast<const float*>(w + y.om1);
+  if ((st = upload_descriptors(w, y, descriptors(g, &om1, &om1, f, nullptr), s)) != DPAR2_OK) return st;
+  return group_output_U(g, y, w, f->H, U, s);
 }
 
 dpar2_status dpar2_decompose(const dpar2_tensor* X, const dpar2_opts* o, const float* omega1,
                              const float* omega2, dpar2_factors* f, double* U, void* ws, size_t ws_bytes,
                              dpar2_stream_t stream) {
-  dpar2_status st = dpar2_compress(X, o, omega1, omega2, ws, ws_bytes, stream);
+  Group g;
+  dpar2_status st = make_group(1, X, o, &g);
   if (st != DPAR2_OK) return st;
-  st = dpar2_als_step(X, o, f, o->max_iter, nullptr, ws, ws_bytes, stream);
+  if (!f || !f->H || !f->V || !f->W) return fail(DPAR2_EINVAL, "factors must be non-NULL");
+  const Layout y = make_layout(g);
+  if ((st = check_ws(y, ws, ws_bytes)) != DPAR2_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  // one upload: the descriptors carry Omega, the factors and (NULL) trace
+  if ((st = group_compress(g, &omega1, &omega2, f, w, y, s)) != DPAR2_OK) return st;
+  if ((st = group_als(g, o->max_iter, w, y, s)) != DPAR2_OK) return st;
+  hipError_t e = launch_fitness(y, w, nullptr, s);
+  if (e != hipSuccess) return hip_fail(e, "fitness");
+  if (U) return group_output_U(g, y, w, f->H, U, s);
+  return DPAR2_OK;
+}
+
+dpar2_status dpar2_decompose_batch(int32_t n, const dpar2_tensor* X, const dpar2_opts* o,
+                                   const float* const* omega1, const float* const* omega2, dpar2_factors* f,
+                                   void* ws, size_t ws_bytes, dpar2_stream_t stream) {
+  Batch b;
+  dpar2_status st = make_batch(n, X, o, &b);
   if (st != DPAR2_OK) return st;
-  st = dpar2_fitness(X, o, f, nullptr, ws, ws_bytes, stream);
+  if (!omega1 || !omega2 || !f) return fail(DPAR2_EINVAL, "omega and factor arrays must be non-NULL");
+  for (int32_t t = 0; t < n; ++t)
+    if (!f[t].H || !f[t].V || !f[t].W) return fail(DPAR2_EINVAL, "factors must be non-NULL");
+  if (!ws) return fail(DPAR2_EWORKSPACE, "workspace is NULL");
+  if ((uintptr_t)ws % 256 != 0) return fail(DPAR2_EWORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < b.total)
+    return fail(DPAR2_EWORKSPACE, "workspace too small: need " + std::to_string(b.total) + " bytes");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  // each group in turn, all on the caller's stream
+  for (size_t gi = 0; gi < b.groups.size(); ++gi) {
+    const Group& g = b.groups[gi];
+    const Layout& y = b.lay[gi];
+    char* w = static_cast<char*>(ws) + b.base[gi];
+    std::vector<const float*> o1, o2;
+    std::vector<dpar2_factors> fg;
+    for (int t : g.orig) {
+      o1.push_back(omega1[t]);
+      o2.push_back(omega2[t]);
+      fg.push_back(f[t]);
+    }
+    if ((st = group_compress(g, o1.data(), o2.data(), fg.data(), w, y, s)) != DPAR2_OK) return st;
+    if ((st = group_als(g, g.o[0].max_iter, w, y, s)) != DPAR2_OK) return st;
+    hipError_t e = launch_fitness(y, w, nullptr, s);
+    if (e != hipSuccess) return hip_fail(e, "fitness");
+  }
+  return DPAR2_OK;
+}
+
+dpar2_status dpar2_batch_report_read(int32_t n, const dpar2_tensor* X, const dpar2_opts* o, const void* ws,
+                                     dpar2_report* rep, dpar2_stream_t stream) {
+  Batch b;
+  dpar2_status st = make_batch(n, X, o, &b);
   if (st != DPAR2_OK) return st;
-  if (U) {
-    st = dpar2_output_U(X, o, f, U, ws, ws_bytes, stream);
+  if (!rep || !ws) return fail(DPAR2_EINVAL, "report and workspace must be non-NULL");
+  for (size_t gi = 0; gi < b.groups.size(); ++gi) {
+    const Group& g = b.groups[gi];
+    std::vector<dpar2_report> r((size_t)g.nt);
+    st = group_report(g, static_cast<const char*>(ws) + b.base[gi], b.lay[gi], r.data(),
+                      reinterpret_cast<hipStream_t>(stream));
     if (st != DPAR2_OK) return st;
+    for (int t = 0; t < g.nt; ++t) rep[g.orig[(size_t)t]] = r[(size_t)t];
   }
   return DPAR2_OK;
 }
 
 dpar2_status dpar2_report_read(const dpar2_tensor* X, const dpar2_opts* o, const void* ws, dpar2_report* rep,
                                dpar2_stream_t stream) {
-  dpar2_status st = validate(X, o);
+  Group g;
+  dpar2_status st = make_group(1, X, o, &g);
   if (st != DPAR2_OK) return st;
   if (!rep || !ws) return fail(DPAR2_EINVAL, "report and workspace must be non-NULL");
-  const Layout y = make_layout(X, o);
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  Ctl c;
-  hipError_t e = hipMemcpyAsync(&c, static_cast<const char*>(ws) + y.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s);
-  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
-  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-  rep->iters = c.iters;
-  rep->converged = c.done;
-  rep->err_last = c.e_prev;
-  rep->xnorm2 = c.xnorm2;
-  rep->fit_compressed = c.xnorm2 > 0 ? 1.0 - c.e_prev / c.xnorm2 : 0.0;
-  rep->fit_true = c.fit_true;
-  rep->warn_bits = c.warn;
-  return DPAR2_OK;
+  return group_report(g, ws, make_layout(g), rep, reinterpret_cast<hipStream_t>(stream));
 }
 
 dpar2_status dpar2_compressed_view(const dpar2_tensor* X, const dpar2_opts* o, const void* ws,
                                    size_t ws_bytes, dpar2_compressed* out) {
-  dpar2_status st = validate(X, o);
+  Group g;
+  dpar2_status st = make_group(1, X, o, &g);
   if (st != DPAR2_OK) return st;
   if (!out) return fail(DPAR2_EINVAL, "out is NULL");
-  const Layout y = make_layout(X, o);
+  const Layout y = make_layout(g);
   if ((st = check_ws(y, ws, ws_bytes)) != DPAR2_OK) return st;
   const char* w = static_cast<const char*>(ws);
   out->Mt = reinterpret_cast<const double*>(w + y.Mt);

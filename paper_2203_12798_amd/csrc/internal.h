@@ -24,18 +24,53 @@ constexpr int MAX_CHUNK_ROWS = 16384;  // longest item (rows)
 constexpr int STAGE2_CHUNK = 256;      // rows of M^T per second-stage block
 constexpr int ALS_THREADS = 256;
 
+// A group: tensors decomposed together, sharing J, R, L, L2, the dtype and the
+// iteration options (a single-tensor call is a group of one).  Per-slice work
+// runs over the concatenated slices of the group (global slice index); each
+// tensor keeps its own small state, addressed by its index t.
+struct TDesc {
+  int64_t K;            // slices of the tensor
+  int64_t k0;           // its first global slice
+  const void* slab;     // N_t x J elements
+  const float* scale;   // fp8 per-slice scales (K), else NULL
+  const float* om1;     // J x L
+  const float* om2;     // (K R) x L2
+  double *H, *V, *W;    // factors (caller memory)
+  double* trace;        // per-iteration error (caller memory) or NULL
+  double tol;
+};
+
+// One block of a per-slice kernel: rows [s0, s1) of tensor t (global slice
+// indices for the iteration kernels, local rows for the begin kernel).
+struct Blk {
+  int32_t t, s0, s1, pad;
+};
+
+// One second-stage chunk: rows [r0, r1) of M^T (global), all of tensor t.
+struct Chunk {
+  int64_t r0, r1;
+  int32_t t, pad;
+};
+
 // Byte offsets of every buffer inside the caller's workspace.
 struct Layout {
+  int nt;                 // tensors in the group
   int64_t K, J, N, n_items;
-  int R, L, L2, max_iter;
+  int R, L, L2, max_iter, q;
   int64_t n2;             // second-stage row chunks of M^T
-  int nblkA, nblkB, nblkC, nblkF;
+  int nblk, nblk0;        // blocks of the iteration / begin per-slice kernels
+  // tables (device)
+  size_t tdesc, blk, blk0, chunks, seg_blk, seg_blk0, seg_chunk, seg_slice, slice_t;
+  // first stage (global slice index)
   size_t ctl, items, slice_ptr, slice_list;
   size_t partG, partP, partS;
   size_t xnorm2, Mt, Phi, sig1;
-  size_t Y2p, Y2, B2t, S2p, U2;
+  // second stage (per chunk / per tensor)
+  size_t Y2p, Y2, B2t, S2p, S2, U2;
   size_t D, E, F, FtFp;
+  // iteration
   size_t Psi, Pw, Mk, small, partA, partB, partC, partBegin, red, fitp, trace, om1, omq;
+  size_t tables_end;     // end of the host-built tables [tdesc, tables_end)
   size_t total;
 };
 
@@ -54,24 +89,23 @@ enum SmallSlot {
   SM_COUNT
 };
 
-constexpr int RED_MAXBLK = 1024;         // grid size cap of the per-slice kernels
+constexpr int RED_WIDTH = 6;             // (6 R R + 2) doubles of column sums per tensor
 
 // --- launchers (each returns the hipGetLastError() of its launches) ---------
 // Arguments of the slab pass (sketch_impl.h, k_sketch.hip).
 struct SlabArgs {
-  const void* slab;        // N x J elements of the input type
-  const float* scale;      // per-slice dequantisation scale (fp8), else unused
+  const TDesc* td;         // tensors of the group (slab, scales, Omega_1)
   int J, L, R;
-  const float* omega;      // J x L (om_stride 0) or K x J x L (om_stride J L)
-  int64_t om_stride;
-  const Item* items;
+  const float* omega;      // NULL: each tensor's Omega_1; else K x J x L per slice
+  const Item* items;       // Item::pad = tensor index
   double *partG, *partP, *partS;
   const double* theta;     // U variant: K x L x R
-  double* U;               // U variant: N x R
+  double* U;               // U variant: N x R (single tensor)
 };
 // Slab pass over all work items: per-item partials of Y^T Y, Y^T X and
-// ||X||^2, or (uout) U = Y Theta_k.  dtype: dpar2_dtype.
-hipError_t launch_slab(const SlabArgs& a, int dtype, int64_t n_items, bool uout, hipStream_t s);
+// ||X||^2, or (uout) U = Y Theta_k.  dtype: dpar2_dtype; vec: every slab is
+// aligned for 4-element loads and J % 4 == 0.
+hipError_t launch_slab(const SlabArgs& a, int dtype, int64_t n_items, bool vec, bool uout, hipStream_t s);
 // Per-slice completion of the first stage; omega_next (K x J x L float32, or
 // NULL) receives the sketch matrix of a power step, the orthonormal right
 // singular vectors of B_k (Alg. 1's power iteration in stabilised form).
@@ -80,21 +114,18 @@ hipError_t launch_slice_finish(int64_t K, int J, int L, int R, const int32_t* sl
                                const double* partP, const double* partS, double* xnorm2,
                                double* Mt, double* Phi, double* sig1, float* omega_next, Ctl* ctl,
                                hipStream_t s);
-hipError_t launch_stage2(const Layout& lay, char* ws, const float* omega2, hipStream_t s);
-// out[e] = sum_{b < nb} part[b * stride + e] for e < width, in a fixed order
-hipError_t launch_colsum(int64_t nb, int64_t stride, int64_t width, const double* part, double* out,
-                         hipStream_t s);
-hipError_t launch_als_begin(const Layout& lay, char* ws, double* H, double* V, double* W, hipStream_t s);
-hipError_t launch_als_iteration(const Layout& lay, char* ws, double* H, double* V, double* W,
-                                double* err_trace, double tol, hipStream_t s);
-hipError_t launch_fitness(const Layout& lay, char* ws, const double* H, const double* V,
-                          const double* W, double* fit, hipStream_t s);
-hipError_t launch_theta(const Layout& lay, char* ws, const double* H, double* theta,
-                        hipStream_t s);
-
+hipError_t launch_stage2(const Layout& lay, char* ws, hipStream_t s);
+// out[t * ostride + e] = sum_{b in [seg[t], seg[t+1])} part[b * stride + e],
+// e < width, t < nt, in a fixed order (one block per (e, t))
+hipError_t launch_segsum(int nt, const int64_t* seg, int64_t stride, int64_t width, const double* part,
+                         double* out, int64_t ostride, hipStream_t s);
+hipError_t launch_als_begin(const Layout& lay, char* ws, hipStream_t s);
+hipError_t launch_als_iteration(const Layout& lay, char* ws, hipStream_t s);
+hipError_t launch_als_end(const Layout& lay, char* ws, hipStream_t s);
+hipError_t launch_fitness(const Layout& lay, char* ws, double* fit, hipStream_t s);
+hipError_t launch_theta(const Layout& lay, char* ws, const double* H, double* theta, hipStream_t s);
 hipError_t launch_pw_identity(const Layout& lay, char* ws, hipStream_t s);
-hipError_t launch_als_end(const Layout& lay, char* ws, double* V, hipStream_t s);
-int als_blocks(int64_t K, int R);
+int als_slices_per_block(int R);
 
 bool sketch_supported(int J, int L, int dtype);
 

@@ -1,97 +1,101 @@
 // Launch sequencing of the compressed ALS iteration (the rank-templated
 // kernels are in als_impl.h, instantiated by k_als_r*.hip), the write-back of
 // V, the fitness of Sec. IV-A from the compressed factors, and the U recipe.
+// Every launch covers a whole group of tensors (one for the single-tensor
+// entry points).
 #include "als_impl.h"
 
 namespace dpar2 {
 
-hipError_t als_dispatch_1(int R, int phase, const AlsArgs& a, hipStream_t s);
-hipError_t als_dispatch_2(int R, int phase, const AlsArgs& a, hipStream_t s);
-hipError_t als_dispatch_3(int R, int phase, const AlsArgs& a, hipStream_t s);
-hipError_t als_dispatch_4(int R, int phase, const AlsArgs& a, hipStream_t s);
+hipError_t als_dispatch_1(int R, int phase, const AlsArgs& a, int nb, int nb0, const int64_t* seg,
+                          const int64_t* seg0, hipStream_t s);
+hipError_t als_dispatch_2(int R, int phase, const AlsArgs& a, int nb, int nb0, const int64_t* seg,
+                          const int64_t* seg0, hipStream_t s);
+hipError_t als_dispatch_3(int R, int phase, const AlsArgs& a, int nb, int nb0, const int64_t* seg,
+                          const int64_t* seg0, hipStream_t s);
+hipError_t als_dispatch_4(int R, int phase, const AlsArgs& a, int nb, int nb0, const int64_t* seg,
+                          const int64_t* seg0, hipStream_t s);
 
-static hipError_t als_dispatch(int R, int phase, const AlsArgs& a, hipStream_t s) {
-  if (R <= 8) return als_dispatch_1(R, phase, a, s);
-  if (R <= 16) return als_dispatch_2(R, phase, a, s);
-  if (R <= 24) return als_dispatch_3(R, phase, a, s);
-  return als_dispatch_4(R, phase, a, s);
+int als_slices_per_block(int R) {
+  const int n = R + (R & 1);
+  int rm = 1;
+  while (rm < n) rm *= 2;
+  if (rm < 2) rm = 2;
+  return (R > 16 ? 128 : 256) / rm;   // RC<R>::GPB
 }
 
-// V = D VC, written when a call ends after at least one V update.
-__global__ void k_als_vmat(int J, int R, const double* __restrict__ D, const double* __restrict__ small,
-                           double* __restrict__ V, const Ctl* ctl) {
-  if (!ctl->vc_valid) return;
+// V = D VC for each tensor whose V was updated during the call.
+__global__ void k_als_vmat(int J, int R, const TDesc* __restrict__ td, const double* __restrict__ Dall,
+                           const double* __restrict__ small, const Ctl* __restrict__ ctl) {
+  const int t = blockIdx.y;
+  if (!ctl[t].vc_valid) return;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= J * R) return;
   const int jj = e / R, c = e % R, RR = R * R;
-  const double* VC = small + SM_VC * RR;
+  const double* VC = small + (size_t)t * SM_COUNT * RR + SM_VC * RR;
+  const double* D = Dall + (size_t)t * J * R;
   double s = 0.0;
   for (int i = 0; i < R; ++i) s += D[(size_t)jj * R + i] * VC[i * R + c];
-  V[e] = s;
+  td[t].V[e] = s;
 }
 
-// Fitness partials: per slice tr(V S_k H^T Psi_k^T (C_k B_k)^T) and
-// W(k,:)(H^T H * V^T V)W(k,:)^T.
-__global__ __launch_bounds__(256) void k_fit_part(int K, int J, int R, const double* __restrict__ Mt,
-                                                  const double* __restrict__ V, const double* __restrict__ H,
-                                                  const double* __restrict__ W, const double* __restrict__ Psi,
-                                                  const double* __restrict__ HV, double* __restrict__ fitp) {
+// Fitness partials, one slice per block: tr(V S_k H^T Psi_k^T (C_k B_k)^T)
+// and W(k,:)(H^T H * V^T V)W(k,:)^T.
+__global__ __launch_bounds__(256) void k_fit_part(int J, int R, const TDesc* __restrict__ td,
+                                                  const int32_t* __restrict__ slice_t,
+                                                  const double* __restrict__ Mt, const double* __restrict__ Psi,
+                                                  const double* __restrict__ small, double* __restrict__ fitp) {
   __shared__ double Q[32 * 33], sPsi[32 * 33], sH[32 * 33], red[16];
   const int tid = threadIdx.x, RR = R * R;
-  for (int e = tid; e < RR; e += 256) sH[(e / R) * 33 + e % R] = H[e];
+  const int64_t k = blockIdx.x;
+  const int t = slice_t[k];
+  const TDesc& d = td[t];
+  const double* V = d.V;
+  const double* W = d.W + (size_t)(k - d.k0) * R;
+  const double* HV = small + (size_t)t * SM_COUNT * RR + SM_HV * RR;
+  for (int e = tid; e < RR; e += 256) {
+    const int r = e / R, s = e % R;
+    sH[r * 33 + s] = d.H[e];
+    double acc = 0.0;
+    for (int jj = 0; jj < J; ++jj) acc += Mt[((size_t)k * R + r) * J + jj] * V[(size_t)jj * R + s];
+    Q[r * 33 + s] = acc;
+    sPsi[r * 33 + s] = Psi[(size_t)k * RR + e];
+  }
+  __syncthreads();
   double tr = 0.0, qd = 0.0;
-  for (int64_t k = blockIdx.x; k < K; k += gridDim.x) {
-    __syncthreads();
-    for (int e = tid; e < RR; e += 256) {
-      const int r = e / R, s = e % R;
-      double acc = 0.0;
-      for (int jj = 0; jj < J; ++jj) acc += Mt[((size_t)k * R + r) * J + jj] * V[(size_t)jj * R + s];
-      Q[r * 33 + s] = acc;
-      sPsi[r * 33 + s] = Psi[(size_t)k * RR + e];
+  if (tid < R) {
+    const int r = tid;
+    const double wr = W[r];
+    double x = 0.0;
+    for (int a = 0; a < R; ++a) {
+      double y = 0.0;
+      for (int b = 0; b < R; ++b) y += sPsi[b * 33 + a] * Q[b * 33 + r];
+      x += sH[a * 33 + r] * y;
     }
-    __syncthreads();
-    if (tid < R) {
-      const int r = tid;
-      const double wr = W[(size_t)k * R + r];
-      double x = 0.0;
-      for (int a = 0; a < R; ++a) {
-        double y = 0.0;
-        for (int b = 0; b < R; ++b) y += sPsi[b * 33 + a] * Q[b * 33 + r];
-        x += sH[a * 33 + r] * y;
-      }
-      tr += wr * x;
-      double q = 0.0;
-      for (int s = 0; s < R; ++s) q += HV[r * R + s] * W[(size_t)k * R + s];
-      qd += wr * q;
-    }
+    tr = wr * x;
+    double q = 0.0;
+    for (int s = 0; s < R; ++s) q += HV[r * R + s] * W[s];
+    qd = wr * q;
   }
   tr = block_sum(tr, red);
   qd = block_sum(qd, red);
   if (tid == 0) {
-    fitp[2 * blockIdx.x] = tr;
-    fitp[2 * blockIdx.x + 1] = qd;
+    fitp[2 * k] = tr;
+    fitp[2 * k + 1] = qd;
   }
 }
 
-__global__ __launch_bounds__(256) void k_fit_final(int nblk, const double* __restrict__ fitp,
-                                                   double* __restrict__ fit, Ctl* ctl) {
-  __shared__ double red[16];
-  double tr = 0.0, qd = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += 256) {
-    tr += fitp[2 * b];
-    qd += fitp[2 * b + 1];
-  }
-  tr = block_sum(tr, red);
-  qd = block_sum(qd, red);
-  if (threadIdx.x == 0) {
-    const double x2 = ctl->xnorm2;
-    const double f = 1.0 - (x2 - 2.0 * tr + qd) / x2;
-    ctl->fit_true = f;
-    if (fit) *fit = f;
-  }
+// fitness of each tensor from its summed partials (fits: nt x 2)
+__global__ void k_fit_final(int nt, const double* __restrict__ fits, double* __restrict__ fit, Ctl* ctl) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  const double x2 = ctl[t].xnorm2;
+  const double f = 1.0 - (x2 - 2.0 * fits[2 * t] + fits[2 * t + 1]) / x2;
+  ctl[t].fit_true = f;
+  if (fit && t == 0) *fit = f;
 }
 
-// Theta_k = Phi_k Psi_k H (L x R) for the U output.
+// Theta_k = Phi_k Psi_k H (L x R) for the U output (single tensor).
 __global__ __launch_bounds__(256) void k_theta(int K, int L, int R, const double* __restrict__ Phi,
                                                const double* __restrict__ Psi, const double* __restrict__ H,
                                                double* __restrict__ theta) {
@@ -121,25 +125,16 @@ __global__ void k_eye(int64_t K, int R, double* __restrict__ P) {
   P[e] = (w / R == w % R) ? 1.0 : 0.0;
 }
 
-int als_blocks(int64_t K, int R) {
-  (void)R;
-  int64_t nb = K;   // upper bound on blocks of any per-slice kernel (one slice per group)
-  if (nb > RED_MAXBLK) nb = RED_MAXBLK;
-  if (nb < 1) nb = 1;
-  return (int)nb;
-}
-
-static AlsArgs make_args(const Layout& lay, char* ws, double* H, double* V, double* W, double* trace,
-                         double tol) {
+static AlsArgs make_args(const Layout& lay, char* ws) {
   AlsArgs a;
-  a.K = (int)lay.K;
+  a.nt = lay.nt;
   a.J = (int)lay.J;
+  a.td = reinterpret_cast<const TDesc*>(ws + lay.tdesc);
+  a.blk = reinterpret_cast<const Blk*>(ws + lay.blk);
+  a.blk0 = reinterpret_cast<const Blk*>(ws + lay.blk0);
   a.F = reinterpret_cast<const double*>(ws + lay.F);
   a.D = reinterpret_cast<const double*>(ws + lay.D);
   a.E = reinterpret_cast<const double*>(ws + lay.E);
-  a.H = H;
-  a.V = V;
-  a.W = W;
   a.Pw = reinterpret_cast<double*>(ws + lay.Pw);
   a.Psi = reinterpret_cast<double*>(ws + lay.Psi);
   a.Mk = reinterpret_cast<double*>(ws + lay.Mk);
@@ -149,10 +144,19 @@ static AlsArgs make_args(const Layout& lay, char* ws, double* H, double* V, doub
   a.partC = reinterpret_cast<double*>(ws + lay.partC);
   a.partBegin = reinterpret_cast<double*>(ws + lay.partBegin);
   a.red = reinterpret_cast<double*>(ws + lay.red);
-  a.trace = trace;
-  a.tol = tol;
   a.ctl = reinterpret_cast<Ctl*>(ws + lay.ctl);
   return a;
+}
+
+static hipError_t als_dispatch(const Layout& lay, char* ws, int phase, hipStream_t s) {
+  const AlsArgs a = make_args(lay, ws);
+  const int64_t* seg = reinterpret_cast<const int64_t*>(ws + lay.seg_blk);
+  const int64_t* seg0 = reinterpret_cast<const int64_t*>(ws + lay.seg_blk0);
+  const int R = lay.R;
+  if (R <= 8) return als_dispatch_1(R, phase, a, lay.nblk, lay.nblk0, seg, seg0, s);
+  if (R <= 16) return als_dispatch_2(R, phase, a, lay.nblk, lay.nblk0, seg, seg0, s);
+  if (R <= 24) return als_dispatch_3(R, phase, a, lay.nblk, lay.nblk0, seg, seg0, s);
+  return als_dispatch_4(R, phase, a, lay.nblk, lay.nblk0, seg, seg0, s);
 }
 
 hipError_t launch_pw_identity(const Layout& lay, char* ws, hipStream_t s) {
@@ -162,32 +166,32 @@ hipError_t launch_pw_identity(const Layout& lay, char* ws, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_als_begin(const Layout& lay, char* ws, double* H, double* V, double* W, hipStream_t s) {
-  return als_dispatch(lay.R, 0, make_args(lay, ws, H, V, W, nullptr, -1.0), s);
+hipError_t launch_als_begin(const Layout& lay, char* ws, hipStream_t s) { return als_dispatch(lay, ws, 0, s); }
+
+hipError_t launch_als_iteration(const Layout& lay, char* ws, hipStream_t s) {
+  return als_dispatch(lay, ws, 1, s);
 }
 
-hipError_t launch_als_iteration(const Layout& lay, char* ws, double* H, double* V, double* W,
-                                double* err_trace, double tol, hipStream_t s) {
-  return als_dispatch(lay.R, 1, make_args(lay, ws, H, V, W, err_trace, tol), s);
-}
-
-hipError_t launch_als_end(const Layout& lay, char* ws, double* V, hipStream_t s) {
+hipError_t launch_als_end(const Layout& lay, char* ws, hipStream_t s) {
   const int n = (int)(lay.J * lay.R);
-  hipLaunchKernelGGL(k_als_vmat, dim3((n + 255) / 256), dim3(256), 0, s, (int)lay.J, lay.R,
-                     reinterpret_cast<const double*>(ws + lay.D), reinterpret_cast<const double*>(ws + lay.small),
-                     V, reinterpret_cast<const Ctl*>(ws + lay.ctl));
+  hipLaunchKernelGGL(k_als_vmat, dim3((n + 255) / 256, (unsigned)lay.nt), dim3(256), 0, s, (int)lay.J, lay.R,
+                     reinterpret_cast<const TDesc*>(ws + lay.tdesc), reinterpret_cast<const double*>(ws + lay.D),
+                     reinterpret_cast<const double*>(ws + lay.small), reinterpret_cast<const Ctl*>(ws + lay.ctl));
   return hipGetLastError();
 }
 
-hipError_t launch_fitness(const Layout& lay, char* ws, const double* H, const double* V,
-                          const double* W, double* fit, hipStream_t s) {
-  const int R = lay.R, RR = R * R;
-  const double* small = reinterpret_cast<const double*>(ws + lay.small);
+hipError_t launch_fitness(const Layout& lay, char* ws, double* fit, hipStream_t s) {
   double* fitp = reinterpret_cast<double*>(ws + lay.fitp);
-  hipLaunchKernelGGL(k_fit_part, dim3(lay.nblkF), dim3(256), 0, s, (int)lay.K, (int)lay.J, R,
-                     reinterpret_cast<const double*>(ws + lay.Mt), V, H, W,
-                     reinterpret_cast<const double*>(ws + lay.Psi), small + SM_HV * RR, fitp);
-  hipLaunchKernelGGL(k_fit_final, dim3(1), dim3(256), 0, s, lay.nblkF, fitp, fit,
+  double* fits = fitp + 2 * lay.K;   // nt x 2 sums after the K per-slice partials
+  hipLaunchKernelGGL(k_fit_part, dim3((unsigned)lay.K), dim3(256), 0, s, (int)lay.J, lay.R,
+                     reinterpret_cast<const TDesc*>(ws + lay.tdesc),
+                     reinterpret_cast<const int32_t*>(ws + lay.slice_t), reinterpret_cast<const double*>(ws + lay.Mt),
+                     reinterpret_cast<const double*>(ws + lay.Psi), reinterpret_cast<const double*>(ws + lay.small),
+                     fitp);
+  hipError_t e = launch_segsum(lay.nt, reinterpret_cast<const int64_t*>(ws + lay.seg_slice), 2, 2, fitp, fits, 2,
+                               s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fit_final, dim3((unsigned)((lay.nt + 63) / 64)), dim3(64), 0, s, lay.nt, fits, fit,
                      reinterpret_cast<Ctl*>(ws + lay.ctl));
   return hipGetLastError();
 }

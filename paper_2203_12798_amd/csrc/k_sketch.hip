@@ -1,4 +1,7 @@
-// First-stage slab pass (Sec. III-B, Eq. 4; Alg. 1 applied to every slice).
+// First-stage slab pass (Sec. III-B, Eq. 4; Alg. 1 applied to every slice):
+// the FP64-matrix-core variant for float32 slabs with 128 < J <= 256, and the
+// dispatcher over all variants (the int8-exact kernel of sketch_impl.h serves
+// J <= 128).
 //
 // One pass over the slab computes, for every work item (a row range of one
 // slice), the pieces of the randomized SVD that need the slab:
@@ -20,7 +23,6 @@ namespace dpar2 {
 
 template <int LT, int JT, bool VEC, bool UOUT>
 __global__ __launch_bounds__(256) void k_sketch(SlabArgs a) {
-  const float* __restrict__ slab = static_cast<const float*>(a.slab);
   const int J = a.J, L = a.L, R = a.R;
   const Item* __restrict__ items = a.items;
   double* __restrict__ partG = a.partG;
@@ -48,9 +50,10 @@ __global__ __launch_bounds__(256) void k_sketch(SlabArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   const Item it = items[blockIdx.x];
+  const float* __restrict__ slab = static_cast<const float*>(a.td[it.pad].slab);
   const int64_t nrows = it.row1 - it.row0;
   const int ntiles = (int)((nrows + TM - 1) / TM);
-  const float* __restrict__ omega1 = a.omega + (size_t)it.slice * a.om_stride;
+  const float* __restrict__ omega1 = a.omega ? a.omega + (size_t)it.slice * J * L : a.td[it.pad].om1;
 
   for (int e = tid; e < LP * XS; e += 256) {
     const int n = e / XS, j = e % XS;
@@ -247,10 +250,8 @@ hipError_t slab_launch_f32(const SlabArgs& a, int64_t n_items, bool vec, bool uo
 hipError_t slab_launch_bf16(const SlabArgs& a, int64_t n_items, bool vec, bool uout, hipStream_t s);
 hipError_t slab_launch_fp8(const SlabArgs& a, int64_t n_items, bool vec, bool uout, hipStream_t s);
 
-hipError_t launch_slab(const SlabArgs& a, int dtype, int64_t n_items, bool uout, hipStream_t s) {
+hipError_t launch_slab(const SlabArgs& a, int dtype, int64_t n_items, bool vec, bool uout, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  const int esize = dtype == DPAR2_F32 ? 4 : (dtype == DPAR2_BF16 ? 2 : 1);
-  const bool vec = (a.J % 4 == 0) && ((uintptr_t)a.slab % (4 * esize) == 0);
   if (a.J > 128) {
     if (dtype != DPAR2_F32) return hipErrorInvalidValue;
     return uout ? dispatch_wide<true>(a, n_items, vec, s) : dispatch_wide<false>(a, n_items, vec, s);

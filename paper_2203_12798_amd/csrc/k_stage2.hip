@@ -10,10 +10,11 @@
 
 namespace dpar2 {
 
-// partial Y2^T over a chunk of STAGE2_CHUNK rows of M^T:
+// partial Y2 over one chunk of rows of M^T (all of one tensor):
 // Y2p[c][j][l] = sum_rows Mt[row][j] * Omega2[row][l]
-__global__ __launch_bounds__(256) void k_s2_y(int64_t KR, int J, int L2, const float* __restrict__ om2,
-                                              const double* __restrict__ Mt, double* __restrict__ Y2p) {
+__global__ __launch_bounds__(256) void k_s2_y(int J, int L2, int R, const TDesc* __restrict__ td,
+                                              const Chunk* __restrict__ chunks, const double* __restrict__ Mt,
+                                              double* __restrict__ Y2p) {
   __shared__ double sM[64 * 64];
   __shared__ float sO[64 * 32];
   const int c = blockIdx.x, jb = blockIdx.y, tid = threadIdx.x;
@@ -21,8 +22,10 @@ __global__ __launch_bounds__(256) void k_s2_y(int64_t KR, int J, int L2, const f
   const int j = jb * 64 + jl;
   double acc[8];
   for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-  const int64_t r0 = (int64_t)c * STAGE2_CHUNK;
-  const int64_t r1 = (r0 + STAGE2_CHUNK < KR) ? r0 + STAGE2_CHUNK : KR;
+  const Chunk ch = chunks[c];
+  const int64_t r0 = ch.r0, r1 = ch.r1;
+  // Omega_2 of the chunk's tensor, indexed by its local row of M^T
+  const float* __restrict__ om2 = td[ch.t].om2 - (size_t)td[ch.t].k0 * R * L2;
   for (int64_t rb = r0; rb < r1; rb += 64) {
     const int nr = (int)((r1 - rb) < 64 ? (r1 - rb) : 64);
     __syncthreads();
@@ -41,7 +44,7 @@ __global__ __launch_bounds__(256) void k_s2_y(int64_t KR, int J, int L2, const f
       for (int u = 0; u < 8; ++u) {
         const int e = tid + 256 * u, rr = e / 32, ll = e % 32;
         const bool ok = rr < nr && ll < L2;
-        const float x = om2[ok ? (size_t)(rb + rr) * L2 + ll : 0];
+        const float x = om2[(ok ? (size_t)(rb + rr) : (size_t)r0) * L2 + (ok ? ll : 0)];
         ov[u] = ok ? x : 0.f;
       }
 #pragma unroll
@@ -63,32 +66,35 @@ __global__ __launch_bounds__(256) void k_s2_y(int64_t KR, int J, int L2, const f
     }
 }
 
-// out[e * ostride] = sum_q part[q * stride + e] for e < gridDim.x: one block
-// per e, the threads split q (four independent accumulators each) and combine
-// in a fixed order.
-__global__ __launch_bounds__(256) void k_colsum(int64_t nb, int64_t stride, const double* __restrict__ part,
-                                                double* __restrict__ out, int64_t ostride) {
+// out[t * ostride + e] = sum over b in [seg[t], seg[t+1]) of part[b * stride + e]:
+// one block per (e, t); the threads split b (four independent accumulators
+// each) and combine in a fixed order.
+__global__ __launch_bounds__(256) void k_segsum(const int64_t* __restrict__ seg, int64_t stride,
+                                                const double* __restrict__ part, double* __restrict__ out,
+                                                int64_t ostride) {
   __shared__ double red[16];
   const int64_t e = blockIdx.x;
-  const int tid = threadIdx.x;
+  const int t = blockIdx.y, tid = threadIdx.x;
+  const int64_t b0 = seg[t], nb = seg[t + 1] - b0;
+  const double* p = part + (size_t)b0 * stride + e;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   int64_t q = tid;
   for (; q + 768 < nb; q += 1024) {
-    s0 += part[(size_t)q * stride + e];
-    s1 += part[(size_t)(q + 256) * stride + e];
-    s2 += part[(size_t)(q + 512) * stride + e];
-    s3 += part[(size_t)(q + 768) * stride + e];
+    s0 += p[(size_t)q * stride];
+    s1 += p[(size_t)(q + 256) * stride];
+    s2 += p[(size_t)(q + 512) * stride];
+    s3 += p[(size_t)(q + 768) * stride];
   }
-  for (; q < nb; q += 256) s0 += part[(size_t)q * stride + e];
-  const double t = block_sum((s0 + s1) + (s2 + s3), red);
-  if (tid == 0) out[e * ostride] = t;
+  for (; q < nb; q += 256) s0 += p[(size_t)q * stride];
+  const double x = block_sum((s0 + s1) + (s2 + s3), red);
+  if (tid == 0) out[(size_t)t * ostride + e] = x;
 }
 
-// B2^T rows of one chunk: B2t[row][l] = sum_j Mt[row][j] Q2[j][l], plus the
-// chunk's partial of B2 B2^T.
-__global__ __launch_bounds__(256) void k_s2_b(int64_t KR, int J, int L2, const double* __restrict__ Mt,
-                                              const double* __restrict__ Q2, double* __restrict__ B2t,
-                                              double* __restrict__ S2p) {
+// B2^T rows of one chunk: B2t[row][l] = sum_j Mt[row][j] Q2[j][l] (Q2 of the
+// chunk's tensor), plus the chunk's partial of B2 B2^T.
+__global__ __launch_bounds__(256) void k_s2_b(int J, int L2, const Chunk* __restrict__ chunks,
+                                              const double* __restrict__ Mt, const double* __restrict__ Q2all,
+                                              double* __restrict__ B2t, double* __restrict__ S2p) {
   __shared__ double sM[64 * 65];
   __shared__ double sQ[64 * 32];
   __shared__ double sB[64 * 33];
@@ -96,8 +102,9 @@ __global__ __launch_bounds__(256) void k_s2_b(int64_t KR, int J, int L2, const d
   const int rl = tid >> 2, lg = tid & 3;
   const int npairs = L2 * (L2 + 1) / 2;
   double sacc[3] = {0.0, 0.0, 0.0};
-  const int64_t r0 = (int64_t)c * STAGE2_CHUNK;
-  const int64_t r1 = (r0 + STAGE2_CHUNK < KR) ? r0 + STAGE2_CHUNK : KR;
+  const Chunk ch = chunks[c];
+  const int64_t r0 = ch.r0, r1 = ch.r1;
+  const double* __restrict__ Q2 = Q2all + (size_t)ch.t * J * L2;
   for (int64_t rb = r0; rb < r1; rb += 64) {
     const int nr = (int)((r1 - rb) < 64 ? (r1 - rb) : 64);
     double acc[8];
@@ -162,41 +169,47 @@ __global__ __launch_bounds__(256) void k_s2_b(int64_t KR, int J, int L2, const d
   }
 }
 
-hipError_t launch_colsum(int64_t nb, int64_t stride, int64_t width, const double* part, double* out,
-                         hipStream_t s) {
-  if (width <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_colsum, dim3((unsigned)width), dim3(256), 0, s, nb, stride, part, out, (int64_t)1);
+hipError_t launch_segsum(int nt, const int64_t* seg, int64_t stride, int64_t width, const double* part,
+                         double* out, int64_t ostride, hipStream_t s) {
+  if (width <= 0 || nt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_segsum, dim3((unsigned)width, (unsigned)nt), dim3(256), 0, s, seg, stride, part, out,
+                     ostride);
   return hipGetLastError();
 }
 
-hipError_t s2_small_dispatch_1(int L2, int which, int J, int R, double* Y2, const double* S2, double* D,
-                               double* E, double* U2s, double* DtD, Ctl* ctl, hipStream_t s);
-hipError_t s2_small_dispatch_2(int L2, int which, int J, int R, double* Y2, const double* S2, double* D,
-                               double* E, double* U2s, double* DtD, Ctl* ctl, hipStream_t s);
+hipError_t s2_small_dispatch_1(int nt, int L2, int which, int J, int R, double* Y2, const double* S2,
+                               double* D, double* E, double* U2s, double* small, Ctl* ctl, hipStream_t s);
+hipError_t s2_small_dispatch_2(int nt, int L2, int which, int J, int R, double* Y2, const double* S2,
+                               double* D, double* E, double* U2s, double* small, Ctl* ctl, hipStream_t s);
 
-// orthonormalisation of Y2 (which = 0) or the small SVD and D, E (which = 1)
-static hipError_t s2_small(int L2, int which, int J, int R, double* Y2, const double* S2, double* D, double* E,
-                           double* U2s, double* DtD, Ctl* ctl, hipStream_t s) {
-  if (L2 <= 16) return s2_small_dispatch_1(L2, which, J, R, Y2, S2, D, E, U2s, DtD, ctl, s);
-  return s2_small_dispatch_2(L2, which, J, R, Y2, S2, D, E, U2s, DtD, ctl, s);
+// orthonormalisation of Y2 (which = 0) or the small SVD and D, E (which = 1),
+// one block per tensor
+static hipError_t s2_small(int nt, int L2, int which, int J, int R, double* Y2, const double* S2, double* D,
+                           double* E, double* U2s, double* small, Ctl* ctl, hipStream_t s) {
+  if (L2 <= 16) return s2_small_dispatch_1(nt, L2, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
+  return s2_small_dispatch_2(nt, L2, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
 }
 
-// F = B2^T (U2_R E^{-1}) and per-block partials of F^T F.
-__global__ __launch_bounds__(256) void k_s2_f(int64_t KR, int L2, int R, const double* __restrict__ B2t,
-                                              const double* __restrict__ U2s, double* __restrict__ F,
-                                              double* __restrict__ FtFp) {
+// F = B2^T (U2_R E^{-1}) over one chunk (U2 of the chunk's tensor) and the
+// chunk's partial of F^T F.
+__global__ __launch_bounds__(256) void k_s2_f(int L2, int R, const Chunk* __restrict__ chunks,
+                                              const double* __restrict__ B2t, const double* __restrict__ U2all,
+                                              double* __restrict__ F, double* __restrict__ FtFp) {
   __shared__ double sU[32 * 32];
   __shared__ double sF[256 * 33];
   const int tid = threadIdx.x;
+  const Chunk ch = chunks[blockIdx.x];
+  const double* U2s = U2all + (size_t)ch.t * L2 * R;
   for (int e = tid; e < L2 * R; e += 256) sU[e] = U2s[e];
   __syncthreads();
-  const int64_t row = (int64_t)blockIdx.x * 256 + tid;
+  const int64_t row = ch.r0 + tid;
+  const bool ok = row < ch.r1;
   for (int r = 0; r < R; ++r) {
     double s = 0.0;
-    if (row < KR)
+    if (ok)
       for (int l = 0; l < L2; ++l) s += B2t[(size_t)row * L2 + l] * sU[l * R + r];
     sF[tid * 33 + r] = s;
-    if (row < KR) F[(size_t)row * R + r] = s;
+    if (ok) F[(size_t)row * R + r] = s;
   }
   __syncthreads();
   for (int e = tid; e < R * R; e += 256) {
@@ -207,11 +220,15 @@ __global__ __launch_bounds__(256) void k_s2_f(int64_t KR, int L2, int R, const d
   }
 }
 
-// e0 = sum_{r,s} E_r E_s (F^T F)_{rs} (D^T D)_{rs} (Sec. III-E constant term)
-__global__ __launch_bounds__(64) void k_s2_final(int R, const double* __restrict__ FtF,
-                                                 const double* __restrict__ E, const double* __restrict__ DtD,
-                                                 Ctl* ctl) {
-  const int lane = threadIdx.x;
+// e0 = sum_{r,s} E_r E_s (F^T F)_{rs} (D^T D)_{rs} (Sec. III-E constant term),
+// one block per tensor
+__global__ __launch_bounds__(64) void k_s2_final(int R, const double* __restrict__ small,
+                                                 const double* __restrict__ Eall, Ctl* ctlall) {
+  const int lane = threadIdx.x, t = blockIdx.x, RR = R * R;
+  const double* FtF = small + (size_t)t * SM_COUNT * RR + SM_FTF * RR;
+  const double* DtD = small + (size_t)t * SM_COUNT * RR + SM_DTD * RR;
+  const double* E = Eall + (size_t)t * R;
+  Ctl* ctl = ctlall + t;
   double e0 = 0.0;
   for (int e = lane; e < R * R; e += 64) {
     const int a = e / R, c = e % R;
@@ -221,15 +238,19 @@ __global__ __launch_bounds__(64) void k_s2_final(int R, const double* __restrict
   if (lane == 0) ctl->e0 = e0;
 }
 
-hipError_t launch_stage2(const Layout& lay, char* ws, const float* omega2, hipStream_t s) {
-  const int64_t KR = lay.K * lay.R;
-  const int J = (int)lay.J, L2 = lay.L2, R = lay.R;
+hipError_t launch_stage2(const Layout& lay, char* ws, hipStream_t s) {
+  const int J = (int)lay.J, L2 = lay.L2, R = lay.R, nt = lay.nt;
   Ctl* ctl = reinterpret_cast<Ctl*>(ws + lay.ctl);
+  const TDesc* td = reinterpret_cast<const TDesc*>(ws + lay.tdesc);
+  const Chunk* chunks = reinterpret_cast<const Chunk*>(ws + lay.chunks);
+  const int64_t* seg_chunk = reinterpret_cast<const int64_t*>(ws + lay.seg_chunk);
+  const int64_t* seg_slice = reinterpret_cast<const int64_t*>(ws + lay.seg_slice);
   double* Mt = reinterpret_cast<double*>(ws + lay.Mt);
   double* Y2p = reinterpret_cast<double*>(ws + lay.Y2p);
   double* Y2 = reinterpret_cast<double*>(ws + lay.Y2);
   double* B2t = reinterpret_cast<double*>(ws + lay.B2t);
   double* S2p = reinterpret_cast<double*>(ws + lay.S2p);
+  double* S2 = reinterpret_cast<double*>(ws + lay.S2);
   double* U2s = reinterpret_cast<double*>(ws + lay.U2);
   double* D = reinterpret_cast<double*>(ws + lay.D);
   double* E = reinterpret_cast<double*>(ws + lay.E);
@@ -237,26 +258,25 @@ hipError_t launch_stage2(const Layout& lay, char* ws, const float* omega2, hipSt
   double* FtFp = reinterpret_cast<double*>(ws + lay.FtFp);
   double* small = reinterpret_cast<double*>(ws + lay.small);
   const double* xnorm2 = reinterpret_cast<const double*>(ws + lay.xnorm2);
-  const int RR = R * R;
-  hipLaunchKernelGGL(k_s2_y, dim3((unsigned)lay.n2, (unsigned)((J + 63) / 64)), dim3(256), 0, s, KR, J,
-                     L2, omega2, Mt, Y2p);
-  hipLaunchKernelGGL(k_colsum, dim3((unsigned)(J * L2)), dim3(256), 0, s, lay.n2, (int64_t)J * L2, Y2p, Y2,
-                     (int64_t)1);
-  hipError_t e = s2_small(L2, 0, J, R, Y2, nullptr, D, E, U2s, small + SM_DTD * RR, ctl, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_s2_b, dim3((unsigned)lay.n2), dim3(256), 0, s, KR, J, L2, Mt, Y2, B2t, S2p);
-  // B2 B2^T (packed pairs) into Y2p, dead by now; sum of ||X_k||^2 into ctl
-  const int npairs = L2 * (L2 + 1) / 2;
-  hipLaunchKernelGGL(k_colsum, dim3((unsigned)npairs), dim3(256), 0, s, lay.n2, (int64_t)npairs, S2p, Y2p,
-                     (int64_t)1);
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, s, lay.K, (int64_t)1, xnorm2, &ctl->xnorm2, (int64_t)1);
-  e = s2_small(L2, 1, J, R, Y2, Y2p, D, E, U2s, small + SM_DTD * RR, ctl, s);
-  if (e != hipSuccess) return e;
-  const unsigned nbf = (unsigned)((KR + 255) / 256);
-  hipLaunchKernelGGL(k_s2_f, dim3(nbf), dim3(256), 0, s, KR, L2, R, B2t, U2s, F, FtFp);
-  hipLaunchKernelGGL(k_colsum, dim3((unsigned)RR), dim3(256), 0, s, (int64_t)nbf, (int64_t)RR, FtFp,
-                     small + SM_FTF * RR, (int64_t)1);
-  hipLaunchKernelGGL(k_s2_final, dim3(1), dim3(64), 0, s, R, small + SM_FTF * RR, E, small + SM_DTD * RR, ctl);
+  const int RR = R * R, npairs = L2 * (L2 + 1) / 2;
+  const int64_t cstride = sizeof(Ctl) / sizeof(double);
+  hipError_t e;
+  hipLaunchKernelGGL(k_s2_y, dim3((unsigned)lay.n2, (unsigned)((J + 63) / 64)), dim3(256), 0, s, J, L2, R,
+                     td, chunks, Mt, Y2p);
+  if ((e = launch_segsum(nt, seg_chunk, (int64_t)J * L2, (int64_t)J * L2, Y2p, Y2, (int64_t)J * L2, s)) !=
+      hipSuccess)
+    return e;
+  if ((e = s2_small(nt, L2, 0, J, R, Y2, nullptr, D, E, U2s, small, ctl, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_s2_b, dim3((unsigned)lay.n2), dim3(256), 0, s, J, L2, chunks, Mt, Y2, B2t, S2p);
+  if ((e = launch_segsum(nt, seg_chunk, npairs, npairs, S2p, S2, npairs, s)) != hipSuccess) return e;
+  // sum_k ||X_k||^2 of each tensor into its control block
+  if ((e = launch_segsum(nt, seg_slice, 1, 1, xnorm2, &ctl->xnorm2, cstride, s)) != hipSuccess) return e;
+  if ((e = s2_small(nt, L2, 1, J, R, Y2, S2, D, E, U2s, small, ctl, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_s2_f, dim3((unsigned)lay.n2), dim3(256), 0, s, L2, R, chunks, B2t, U2s, F, FtFp);
+  if ((e = launch_segsum(nt, seg_chunk, RR, RR, FtFp, small + SM_FTF * RR, (int64_t)SM_COUNT * RR, s)) !=
+      hipSuccess)
+    return e;
+  hipLaunchKernelGGL(k_s2_final, dim3((unsigned)nt), dim3(64), 0, s, R, small, E, ctl);
   return hipGetLastError();
 }
 

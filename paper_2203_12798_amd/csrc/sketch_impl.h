@@ -155,7 +155,6 @@ template <int LT, int JT, bool VEC, int TIN, bool UOUT>
 __global__ __launch_bounds__(256) void k_sketch_q(SlabArgs a) {
   typedef typename In<TIN>::E E;
   const int J = a.J, L = a.L;
-  const E* __restrict__ slab = static_cast<const E*>(a.slab);
   constexpr int TM = SKETCH_TM;
   constexpr int JP = JT * 16;
   constexpr int XS = ((JP + 31) / 32) * 32 + 4;
@@ -184,10 +183,12 @@ __global__ __launch_bounds__(256) void k_sketch_q(SlabArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   const Item it = a.items[blockIdx.x];
+  const TDesc& td = a.td[it.pad];
+  const E* __restrict__ slab = static_cast<const E*>(td.slab);
   const int64_t nrows = it.row1 - it.row0;
   const int ntiles = (int)((nrows + TM - 1) / TM);
-  const float* __restrict__ omega = a.omega + (size_t)it.slice * a.om_stride;
-  const float scale = (TIN == DPAR2_FP8_E4M3) ? a.scale[it.slice] : 1.0f;
+  const float* __restrict__ omega = a.omega ? a.omega + (size_t)it.slice * J * L : td.om1;
+  const float scale = (TIN == DPAR2_FP8_E4M3) ? td.scale[it.slice - td.k0] : 1.0f;
 
   // the low-precision inputs sketch on the bf16 matrix cores: Omega is
   // rounded to bf16 (nearest even) once, X is already bf16-representable

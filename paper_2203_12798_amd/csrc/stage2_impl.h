@@ -15,7 +15,9 @@
 namespace dpar2 {
 
 template <int L>
-__global__ __launch_bounds__(64) void k_s2_orth(int J, double* __restrict__ Y, Ctl* ctl) {
+__global__ __launch_bounds__(64) void k_s2_orth(int J, double* __restrict__ Yall, Ctl* ctlall) {
+  double* __restrict__ Y = Yall + (size_t)blockIdx.x * J * L;   // one tensor per block
+  Ctl* ctl = ctlall + blockIdx.x;
   constexpr int RM = SC<L>::RM, LH = SC<L>::LH, LD = SC<L>::LD;
   constexpr int TJ = 64;                       // rows of Y2 per LDS tile
   __shared__ double Ys[TJ * LD];
@@ -139,10 +141,19 @@ __global__ __launch_bounds__(64) void k_s2_orth(int J, double* __restrict__ Y, C
 }
 
 template <int L>
-__global__ __launch_bounds__(64) void k_s2_evd(int J, int R, const double* __restrict__ S2,
-                                               const double* __restrict__ Q2, double* __restrict__ D,
-                                               double* __restrict__ E, double* __restrict__ U2s,
-                                               double* __restrict__ DtD, Ctl* ctl) {
+__global__ __launch_bounds__(64) void k_s2_evd(int J, int R, const double* __restrict__ S2all,
+                                               const double* __restrict__ Q2all, double* __restrict__ Dall,
+                                               double* __restrict__ Eall, double* __restrict__ U2all,
+                                               double* __restrict__ small, Ctl* ctlall) {
+  // one tensor per block
+  const int tt = blockIdx.x;
+  const double* __restrict__ S2 = S2all + (size_t)tt * (L * (L + 1) / 2);
+  const double* __restrict__ Q2 = Q2all + (size_t)tt * J * L;
+  double* __restrict__ D = Dall + (size_t)tt * J * R;
+  double* __restrict__ E = Eall + (size_t)tt * R;
+  double* __restrict__ U2s = U2all + (size_t)tt * L * R;
+  double* __restrict__ DtD = small + (size_t)tt * SM_COUNT * R * R + SM_DTD * R * R;
+  Ctl* ctl = ctlall + tt;
   constexpr int RM = SC<L>::RM, LH = SC<L>::LH, LD = SC<L>::LD;
   constexpr int NP = L * (L + 1) / 2;
   __shared__ double Ss[L * LD], Us[L * LD], Es[L], row[L], rinv[L];
@@ -230,15 +241,16 @@ __global__ __launch_bounds__(64) void k_s2_evd(int J, int R, const double* __res
   if (lane == 0 && warn) atomicOr(&ctl->warn, warn);
 }
 
-// which = 0: orthonormalise Y2 in place; which = 1: small SVD of B2 B2^T
-// (packed pairs S2) and D, E, U2_R E^{-1}, D^T D
+// which = 0: orthonormalise each tensor's Y2 in place; which = 1: small SVD
+// of each B2 B2^T (packed pairs S2) and D, E, U2_R E^{-1}, D^T D; one block
+// per tensor
 template <int L>
-hipError_t s2_small_launch(int which, int J, int R, double* Y2, const double* S2, double* D, double* E,
-                           double* U2s, double* DtD, Ctl* ctl, hipStream_t s) {
+hipError_t s2_small_launch(int nt, int which, int J, int R, double* Y2, const double* S2, double* D,
+                           double* E, double* U2s, double* small, Ctl* ctl, hipStream_t s) {
   if (which == 0)
-    hipLaunchKernelGGL(k_s2_orth<L>, dim3(1), dim3(64), 0, s, J, Y2, ctl);
+    hipLaunchKernelGGL(k_s2_orth<L>, dim3((unsigned)nt), dim3(64), 0, s, J, Y2, ctl);
   else
-    hipLaunchKernelGGL(k_s2_evd<L>, dim3(1), dim3(64), 0, s, J, R, S2, Y2, D, E, U2s, DtD, ctl);
+    hipLaunchKernelGGL(k_s2_evd<L>, dim3((unsigned)nt), dim3(64), 0, s, J, R, S2, Y2, D, E, U2s, small, ctl);
   return hipGetLastError();
 }
 

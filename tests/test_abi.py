@@ -122,3 +122,51 @@ def test_dtype_and_power_options_validated_on_host():
     t8 = binding.c_tensor(2, 8, 0x1000, hp, 0x2000, binding.DPAR2_F32, None)
     assert (lib.dpar2_workspace_size(ctypes.byref(t8), ctypes.byref(o1))
             >= lib.dpar2_workspace_size(ctypes.byref(t8), ctypes.byref(o)) + 2 * 8 * 3 * 4)
+
+
+def test_batch_arguments_validated_on_host():
+    """A batch is split into groups of tensors sharing J, dtype, rank, sketch
+    widths, power_iters, max_iter and flags; K, the row offsets and tol may
+    differ inside a group.  The workspace is the groups' layouts end to end;
+    an invalid tensor is rejected before anything is enqueued, and the error
+    names it by its index in the batch."""
+    binding, lib = _lib()
+    offa = np.array([0, 10, 20], dtype=np.int64)
+    offb = np.array([0, 7, 30, 33], dtype=np.int64)
+    ha = offa.ctypes.data_as(ctypes.c_void_p).value
+    hb = offb.ctypes.data_as(ctypes.c_void_p).value
+    T = binding.c_tensor * 3
+    O = binding.c_opts * 3
+    ta = binding.c_tensor(2, 8, 0x1000, ha, 0x2000, binding.DPAR2_F32, None)
+    tb = binding.c_tensor(3, 8, 0x3000, hb, 0x4000, binding.DPAR2_F32, None)
+    tc = binding.c_tensor(3, 9, 0x3000, hb, 0x4000, binding.DPAR2_F32, None)
+    oa = binding.c_opts(2, 3, 3, 5, -1.0, 0, 0)
+    ob = binding.c_opts(2, 3, 3, 5, 1e-6, 0, 0)
+
+    def size(ts, os_):
+        return lib.dpar2_batch_workspace_size(len(ts), T(*ts), O(*os_))
+
+    def single(t, o):
+        return lib.dpar2_workspace_size(ctypes.byref(t), ctypes.byref(o))
+
+    assert size([ta], [oa]) == single(ta, oa) > 0
+    # one group (tol may differ): one layout over both tensors
+    both = size([ta, tb], [oa, ob])
+    assert both > single(ta, oa)
+    # J differs: two groups, laid out end to end (256-byte aligned)
+    al = lambda n: (n + 255) // 256 * 256
+    assert size([ta, tc], [oa, oa]) == al(single(ta, oa)) + al(single(tc, oa))
+    # grouping is by first appearance; members need not be adjacent
+    assert size([ta, tc, tb], [oa, oa, ob]) == al(both) + al(single(tc, oa))
+    for o2 in (binding.c_opts(3, 3, 3, 5, -1.0, 0, 0), binding.c_opts(2, 3, 3, 6, -1.0, 0, 0),
+               binding.c_opts(2, 3, 3, 5, -1.0, binding.DPAR2_FLAG_NO_GRAPH, 0)):
+        assert size([ta, tb], [oa, o2]) == al(single(ta, oa)) + al(single(tb, o2))
+    assert lib.dpar2_batch_workspace_size(0, T(ta, tb, tc), O(oa, ob, oa)) == 0
+    # an invalid tensor is named by its batch index
+    bad = binding.c_tensor(3, 9, 0x3000, hb, 0, binding.DPAR2_F32, None)
+    assert size([ta, tc, bad], [oa, oa, oa]) == 0
+    assert lib.dpar2_last_error().startswith(b"tensor 2")
+    assert size([ta, bad], [oa, oa]) == 0          # alone in its group
+    assert lib.dpar2_last_error().startswith(b"tensor 1")
+    # unknown flag bits are rejected
+    assert size([ta], [binding.c_opts(2, 3, 3, 5, -1.0, 0x80, 0)]) == 0
