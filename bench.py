@@ -38,9 +38,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--forms", action="store_true",
-                    help="also time the precision form (bf16 and fp8-e4m3 slabs) and one power step "
-                         "on the same workload")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the precision form (bf16 and fp8-e4m3 slabs) and the power step timed on "
+                         "the same workload")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batching form (256 independent tensors of mixed J, R, K, I_k)")
+    ap.add_argument("--batch-tensors", type=int, default=256)
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic.json from two rocprofv3 --pmc counter_collection.csv "
                          "files (FETCH_SIZE, WRITE_SIZE) of a --calib-copy run, then exit")
@@ -71,8 +74,7 @@ def write_traffic(fetch_csv, write_csv):
     f_slab, f_copy = per_dispatch(fetch_csv, "FETCH_SIZE")
     w_slab, w_copy = per_dispatch(write_csv, "WRITE_SIZE")
     f_scale, w_scale = CALIB_BYTES / f_copy, CALIB_BYTES / w_copy
-    src = os.path.join(ROOT, "paper_2203_12798_amd", "csrc", "k_sketch.hip")
-    rec = {"kernel": SLAB_KERNEL, "source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
+    rec = {"kernel": SLAB_KERNEL, "source_sha256": slab_source_sha(),
            "fetch_counter_bytes": f_slab, "write_counter_bytes": w_slab,
            "fetch_scale": f_scale, "write_scale": w_scale,
            "bytes_per_launch": int(round(f_slab * f_scale + w_slab * w_scale)),
@@ -83,7 +85,19 @@ def write_traffic(fetch_csv, write_csv):
     print(json.dumps(rec))
 
 
-def traffic_record(kernel_src):
+SLAB_SOURCES = ("sketch_impl.h", "k_slab_f32.hip", "common.h", "internal.h")
+
+
+def slab_source_sha():
+    """SHA-256 over the sources the FP32 slab-pass kernel is built from."""
+    h = hashlib.sha256()
+    for name in SLAB_SOURCES:
+        with open(os.path.join(ROOT, "paper_2203_12798_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_record():
     """HBM bytes per slab-pass launch from the committed counter summary, if
     it was taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -91,10 +105,102 @@ def traffic_record(kernel_src):
         return None
     with open(path) as f:
         rec = json.load(f)
-    sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
-    if rec.get("source_sha256") != sha:
+    if rec.get("source_sha256") != slab_source_sha():
         return None
     return rec
+
+
+def gen_batch(n, d, torch, np):
+    """The batching workload: n independent tensors; tensor t draws K ~ U{16..256},
+    J from {32, 64, 128}, R from {5, 10, 20} and I_k ~ U{32..2048} from
+    numpy's SeedSequence(4).spawn(n)[t]; its entries are a rank-R PARAFAC2
+    model (Q_k column-orthonormal from the QR of a Gaussian I_k x R matrix,
+    H, V ~ N(0, 1), W ~ U(0.5, 1.5)) plus N(0, 0.05^2) noise, drawn on the
+    GPU with torch's generator seeded by t, float32."""
+    specs, tensors = [], []
+    for t, ss in enumerate(np.random.SeedSequence(4).spawn(n)):
+        rng = np.random.default_rng(ss)
+        K = int(rng.integers(16, 257))
+        J = int(rng.choice([32, 64, 128]))
+        R = int(rng.choice([5, 10, 20]))
+        rows = rng.integers(32, 2049, size=K)
+        g = torch.Generator(device="cuda").manual_seed(t)
+        imax = int(rows.max())
+        mask = torch.arange(imax, device="cuda")[None, :] < torch.from_numpy(rows).cuda()[:, None]
+        G = torch.randn(K, imax, R, device="cuda", generator=g) * mask[:, :, None]
+        Q = torch.linalg.qr(G).Q                                     # zero rows stay zero
+        H = torch.randn(R, R, device="cuda", generator=g)
+        V = torch.randn(J, R, device="cuda", generator=g)
+        W = 0.5 + torch.rand(K, R, device="cuda", generator=g)
+        Mk = (H[None, :, :] * W[:, None, :]) @ V.t()                 # K x R x J
+        Xp = torch.bmm(Q.contiguous(), Mk.contiguous())
+        slab = Xp[mask] + 0.05 * torch.randn(int(rows.sum()), J, device="cuda", generator=g)
+        offs = np.concatenate([[0], np.cumsum(rows)]).astype(np.int64)
+        tensors.append(d.Tensor(slab.contiguous(), torch.from_numpy(offs).cuda(), offs))
+        specs.append((K, J, R))
+        del G, Q, Xp, Mk
+    return specs, tensors
+
+
+def bench_batch(args, d, torch, np):
+    n = args.batch_tensors
+    iters = 32
+    t = time.perf_counter()
+    specs, Ts = gen_batch(n, d, torch, np)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t
+    rows = sum(T.offsets_host[-1] for T in Ts)
+    slices = sum(K for K, _, _ in specs)
+    print(f"[bench] batch: {n} tensors, {slices} slices, {rows} rows (gen {gen_s:.1f}s)", file=sys.stderr,
+          flush=True)
+    res = {"tensors": n, "slices": int(slices), "rows": int(rows),
+           "slab_gb": round(sum(T.slab.numel() * 4 for T in Ts) / 1e9, 3), "iterations": iters,
+           "groups": len({(J, R) for _, J, R in specs})}
+    g = torch.Generator(device="cuda").manual_seed(12345)
+    om1 = [torch.randn(J, min(R + 10, J), device="cuda", generator=g) for K, J, R in specs]
+    om2 = [torch.randn(K * R, min(R + 10, J), device="cuda", generator=g) for K, J, R in specs]
+    # all factors in one buffer (views per tensor), re-initialised by one copy
+    sizes = [R * R + J * R + K * R for K, J, R in specs]
+    init = torch.empty(sum(sizes), dtype=torch.float64, device="cuda")
+    flat = torch.empty_like(init)
+    fs, at = [], 0
+    for (K, J, R), n_el in zip(specs, sizes):
+        Hi, Vi, Wi = (init[at:at + R * R].view(R, R), init[at + R * R:at + R * R + J * R].view(J, R),
+                      init[at + R * R + J * R:at + n_el].view(K, R))
+        Hi.copy_(torch.eye(R, dtype=torch.float64, device="cuda"))
+        Vi.copy_(torch.randn(J, R, dtype=torch.float64, device="cuda", generator=g))
+        Wi.fill_(1.0)
+        fs.append(d.Factors(flat[at:at + R * R].view(R, R), flat[at + R * R:at + R * R + J * R].view(J, R),
+                            flat[at + R * R + J * R:at + n_el].view(K, R)))
+        at += n_el
+    for graph in (False, True):
+        os_ = [d.Options(rank=R, sketch=min(R + 10, J), sketch2=min(R + 10, J), max_iter=iters, graph=graph)
+               for K, J, R in specs]
+        ws = d.alloc_batch_workspace(Ts, os_)
+
+        def step():
+            flat.copy_(init)
+            d.decompose_batch(Ts, os_, om1, om2, fs, ws)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
+        reps = d.batch_report_read(Ts, os_, ws)
+        key = "graph" if graph else "eager"
+        res[key] = {"ms_per_batch": round(ms, 3), "tensors_per_s": round(n / (ms / 1e3), 1),
+                    "slices_per_s": round(slices / (ms / 1e3), 1),
+                    "rows_per_s": round(rows / (ms / 1e3), 1)}
+        fits = np.array([r["fit_true"] for r in reps])
+        res[key]["fitness_min"] = float(fits.min())
+        res[key]["fitness_mean"] = float(fits.mean())
+        print(f"[bench] batch {key}: {ms:.3f} ms", file=sys.stderr, flush=True)
+        del ws
+    return res
 
 
 def main():
@@ -157,7 +263,7 @@ def main():
     ms_f32 = (t1 - t0) * 1e3 / max(args.steps, 1)
 
     forms = None
-    if args.forms:
+    if not args.no_forms:
         # the same workload as bf16 bit patterns and as per-slice-scaled fp8
         # e4m3 codes (scale 2^ceil(log2(amax_k / 448))), encoded on the device
         # with torch's round-to-nearest casts; and float32 with one power step
@@ -225,8 +331,7 @@ def main():
     alg_flops = 2.0 * X.N * J * L * 2 + 2.0 * X.N * L * L
     sk_ms = sketch_ms_total / max(launches, 1)
     achieved = alg_bytes / (sk_ms / 1e3) / 1e9
-    src = os.path.join(ROOT, "paper_2203_12798_amd", "csrc", "k_sketch.hip")
-    tr = traffic_record(src)
+    tr = traffic_record()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if tr is None else tr["bytes_per_launch"],
@@ -252,6 +357,11 @@ def main():
     }
     if forms is not None:
         out["forms"] = forms
+    if not args.no_batch:
+        try:
+            out["batch"] = bench_batch(args, d, torch, np)
+        except Exception as exc:   # reported, not fatal
+            out["batch"] = {"error": str(exc)[:300]}
 
     if not args.no_cpu_baseline and args.cpu_sample > 0:
         from threadpoolctl import threadpool_limits
