@@ -213,6 +213,69 @@ dpar2_status dpar2_decompose_batch(int32_t n, const dpar2_tensor* X, const dpar2
 dpar2_status dpar2_batch_report_read(int32_t n, const dpar2_tensor* X, const dpar2_opts* o,
                                      const void* ws, dpar2_report* rep, dpar2_stream_t stream);
 
+/* ---- Learned warm start ---------------------------------------------------
+ * Not part of the paper: a set encoder proposes the starting H, V, W of the
+ * iteration of Alg. 3 from the compressed representation of Sec. III-B.
+ * Tokens: per slice the upper triangle (row-major, a <= b) of
+ * R Phi_k / e_mean, Phi_k = (F^(k) E S)^T (F^(k) E S), S = diag of the signs
+ * that make the largest-magnitude entry of each column of D positive,
+ * e_mean = ||E||^2 / K; NF = R (R + 1) / 2 floats per token.  Network (FP32,
+ * width DPAR2_WARM_WIDTH): Z1 = relu(W1 x + b1), Z2 = relu(W2 Z1 + b2) per
+ * token, p = mean_k Z2; outputs H = WH p + bH (R x R), V~ = WV p + bV (R x R,
+ * V in the basis D S), W(k, :) = Ww [Z2_k; p] + bw.  Parameters are one flat
+ * float32 array of dpar2_warm_param_count(R) values, blocks in the order W1
+ * (128 x NF), b1, W2 (128 x 128), b2, WH (R^2 x 128), bH, WV (R^2 x 128), bV,
+ * Ww (R x 256), bw, each row-major. */
+#define DPAR2_WARM_WIDTH 128
+
+/* Number of float parameters for rank R (0 if R is outside 1..32). */
+int64_t dpar2_warm_param_count(int32_t rank);
+
+/* Tokens of a compressed tensor (after dpar2_compress on ws): tok device
+ * float32 K x NF. */
+dpar2_status dpar2_warm_features(const dpar2_tensor* X, const dpar2_opts* o, const void* ws, size_t ws_bytes,
+                                 float* tok, dpar2_stream_t stream);
+
+/* Training targets from factors f (e.g. converged ones) of the same
+ * tensor: the gauge is fixed by unit-norm columns of H and V (scale into W),
+ * V~ = (D S)^T V with each column signed by its largest-magnitude entry,
+ * each column of W signed to a non-negative sum (same flip on H), components
+ * sorted by decreasing ||W(:, r)||.  tH = H^T H (R x R), tV = V~ (R x R),
+ * tW = W / sqrt(e_mean / R) (K x R); device float32. */
+dpar2_status dpar2_warm_targets(const dpar2_tensor* X, const dpar2_opts* o, const void* ws, size_t ws_bytes,
+                                const dpar2_factors* f, float* tH, float* tV, float* tW, dpar2_stream_t stream);
+
+/* Starting factors from network outputs: H = pH, V = D S pV,
+ * W = pW sqrt(e_mean / R) (pH, pV: R x R, pW: K x R, device float32). */
+dpar2_status dpar2_warm_apply(const dpar2_tensor* X, const dpar2_opts* o, const void* ws, size_t ws_bytes,
+                              const float* pH, const float* pV, const float* pW, dpar2_factors* f,
+                              dpar2_stream_t stream);
+
+/* Forward pass over n tensors at once.  tok_off: device and (host) copies of
+ * n + 1 token offsets (tensor b owns tokens tok_off[b] .. tok_off[b+1]-1, at
+ * least one); tok: device float32 (tok_off[n]) x NF; act: device scratch of
+ * tok_off[n] x 4 x DPAR2_WARM_WIDTH floats (kept for the backward pass);
+ * outputs pH, pV: n x R x R, pW: tok_off[n] x R. */
+dpar2_status dpar2_warm_forward(int32_t rank, int32_t n, const int32_t* tok_off, const int32_t* tok_off_host,
+                                const float* tok, const float* theta, float* act, float* pH, float* pV, float* pW,
+                                dpar2_stream_t stream);
+
+/* Backward pass after dpar2_warm_forward on the same arguments: loss
+ * sum_b (||pH_b^T pH_b - tH_b||^2 / R^2 + ||pV_b - tV_b||^2 / R^2 +
+ * ||pW_b - tW_b||^2 / (K_b R)); grad_part: device scratch n x P; grad (P)
+ * receives the gradient summed over the n tensors (fixed order); loss: device
+ * n x 3 (the three terms per tensor). */
+dpar2_status dpar2_warm_backward(int32_t rank, int32_t n, const int32_t* tok_off, const int32_t* tok_off_host,
+                                 const float* tok, const float* theta, float* act, const float* pH, const float* pV,
+                                 const float* pW, const float* tH, const float* tV, const float* tW,
+                                 float* grad_part, float* grad, float* loss, dpar2_stream_t stream);
+
+/* One Adam step (Kingma & Ba, with bias correction; step counts from 1) on
+ * theta with gradient grad * grad_scale; m, v: device moment buffers (P). */
+dpar2_status dpar2_warm_adam(int32_t rank, float* theta, const float* grad, float* m, float* v, int32_t step,
+                             float lr, float beta1, float beta2, float eps, float grad_scale,
+                             dpar2_stream_t stream);
+
 /* Kernel timing for measurement.  While enabled, every dpar2_compress records
  * a pair of HIP events around its slab pass (the first-stage kernel that reads
  * the slab) on the launch stream.  dpar2_profile_read waits for the recorded

@@ -65,6 +65,8 @@ class c_report(ctypes.Structure):
 EXPORTS = ["dpar2_workspace_size", "dpar2_compress", "dpar2_als_step", "dpar2_fitness",
            "dpar2_output_U", "dpar2_decompose", "dpar2_compressed_view", "dpar2_report_read",
            "dpar2_batch_workspace_size", "dpar2_decompose_batch", "dpar2_batch_report_read",
+           "dpar2_warm_param_count", "dpar2_warm_features", "dpar2_warm_targets", "dpar2_warm_apply",
+           "dpar2_warm_forward", "dpar2_warm_backward", "dpar2_warm_adam",
            "dpar2_profile_enable", "dpar2_profile_read", "dpar2_status_string", "dpar2_last_error"]
 
 _lib = None
@@ -105,6 +107,24 @@ def load(path: str = LIB_PATH):
                                           ctypes.c_size_t, vp]
     lib.dpar2_batch_report_read.restype = ctypes.c_int32
     lib.dpar2_batch_report_read.argtypes = [ctypes.c_int32, P(c_tensor), P(c_opts), vp, P(c_report), vp]
+    i32, f32 = ctypes.c_int32, ctypes.c_float
+    lib.dpar2_warm_param_count.restype = ctypes.c_int64
+    lib.dpar2_warm_param_count.argtypes = [i32]
+    for name, n_dev in (("dpar2_warm_features", 1), ("dpar2_warm_targets", 4), ("dpar2_warm_apply", 4)):
+        fn = getattr(lib, name)
+        fn.restype = i32
+        if name == "dpar2_warm_features":
+            fn.argtypes = [P(c_tensor), P(c_opts), vp, ctypes.c_size_t, vp, vp]
+        elif name == "dpar2_warm_targets":
+            fn.argtypes = [P(c_tensor), P(c_opts), vp, ctypes.c_size_t, P(c_factors), vp, vp, vp, vp]
+        else:
+            fn.argtypes = [P(c_tensor), P(c_opts), vp, ctypes.c_size_t, vp, vp, vp, P(c_factors), vp]
+    lib.dpar2_warm_forward.restype = i32
+    lib.dpar2_warm_forward.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.dpar2_warm_backward.restype = i32
+    lib.dpar2_warm_backward.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.dpar2_warm_adam.restype = i32
+    lib.dpar2_warm_adam.argtypes = [i32, vp, vp, vp, vp, i32, f32, f32, f32, f32, f32, vp]
     lib.dpar2_profile_enable.restype = ctypes.c_int32
     lib.dpar2_profile_enable.argtypes = [ctypes.c_int32]
     lib.dpar2_profile_read.restype = ctypes.c_int32
@@ -360,6 +380,65 @@ def batch_report_read(Xs, os_, ws, stream=None) -> list:
     r = (c_report * b.n)()
     _check(load().dpar2_batch_report_read(b.n, b.X, b.o, p, r, _stream(stream)))
     return [_report_dict(r[i]) for i in range(b.n)]
+
+
+# --- learned warm start ----------------------------------------------------
+
+WARM_WIDTH = 128
+
+
+def warm_param_count(rank: int) -> int:
+    n = int(load().dpar2_warm_param_count(int(rank)))
+    if n == 0:
+        raise Dpar2Error(DPAR2_EINVAL, "rank must be in 1..32")
+    return n
+
+
+def warm_features(X: Tensor, o: Options, ws, tok, stream=None):
+    """tok: float32 device (K, R(R+1)/2)."""
+    p, n = _ws(ws)
+    _check(load().dpar2_warm_features(ctypes.byref(X.c()), ctypes.byref(o.c()), p, n, _ptr(tok), _stream(stream)))
+
+
+def warm_targets(X: Tensor, o: Options, ws, f: Factors, tH, tV, tW, stream=None):
+    p, n = _ws(ws)
+    fc = f.c()
+    _check(load().dpar2_warm_targets(ctypes.byref(X.c()), ctypes.byref(o.c()), p, n, ctypes.byref(fc),
+                                     _ptr(tH), _ptr(tV), _ptr(tW), _stream(stream)))
+
+
+def warm_apply(X: Tensor, o: Options, ws, pH, pV, pW, f: Factors, stream=None):
+    p, n = _ws(ws)
+    fc = f.c()
+    _check(load().dpar2_warm_apply(ctypes.byref(X.c()), ctypes.byref(o.c()), p, n, _ptr(pH), _ptr(pV),
+                                   _ptr(pW), ctypes.byref(fc), _stream(stream)))
+
+
+def _tok_off(tok_off):
+    """(device int32 tensor, host int32 array kept alive) of token offsets."""
+    import torch
+    host = np.ascontiguousarray(np.asarray(tok_off, dtype=np.int32))
+    return torch.from_numpy(host).cuda(), host
+
+
+def warm_forward(rank, tok_off, tok, theta, act, pH, pV, pW, stream=None):
+    """tok_off: host sequence of n + 1 token offsets (copied to the device)."""
+    dev, host = _tok_off(tok_off)
+    _check(load().dpar2_warm_forward(int(rank), len(host) - 1, _ptr(dev), host.ctypes.data, _ptr(tok),
+                                     _ptr(theta), _ptr(act), _ptr(pH), _ptr(pV), _ptr(pW), _stream(stream)))
+
+
+def warm_backward(rank, tok_off, tok, theta, act, pH, pV, pW, tH, tV, tW, grad_part, grad, loss, stream=None):
+    dev, host = _tok_off(tok_off)
+    _check(load().dpar2_warm_backward(int(rank), len(host) - 1, _ptr(dev), host.ctypes.data, _ptr(tok),
+                                      _ptr(theta), _ptr(act), _ptr(pH), _ptr(pV), _ptr(pW), _ptr(tH), _ptr(tV),
+                                      _ptr(tW), _ptr(grad_part), _ptr(grad), _ptr(loss), _stream(stream)))
+
+
+def warm_adam(rank, theta, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, grad_scale=1.0,
+              stream=None):
+    _check(load().dpar2_warm_adam(int(rank), _ptr(theta), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr),
+                                  float(beta1), float(beta2), float(eps), float(grad_scale), _stream(stream)))
 
 
 def profile_enable(on: bool = True):

@@ -672,6 +672,30 @@ dpar2_status group_report(const Group& g, const void* ws, const Layout& y, dpar2
 
 }  // namespace
 
+namespace {
+// the compressed representation of a single-tensor workspace
+struct Comp {
+  Group g;
+  Layout y;
+};
+dpar2_status comp_of(const dpar2_tensor* X, const dpar2_opts* o, const void* ws, size_t ws_bytes, Comp* c) {
+  dpar2_status st = make_group(1, X, o, &c->g);
+  if (st != DPAR2_OK) return st;
+  c->y = make_layout(c->g);
+  return check_ws(c->y, ws, ws_bytes);
+}
+
+dpar2_status check_tokens(int32_t rank, int32_t n, const int32_t* off_dev, const int32_t* off_host) {
+  if (rank < 1 || rank > 32) return fail(DPAR2_EINVAL, "rank must be in 1..32");
+  if (n < 1) return fail(DPAR2_EINVAL, "n must be >= 1");
+  if (!off_dev || !off_host) return fail(DPAR2_EINVAL, "token offsets must be non-NULL");
+  if (off_host[0] != 0) return fail(DPAR2_EINVAL, "token offsets must start at 0");
+  for (int32_t b = 0; b < n; ++b)
+    if (off_host[b + 1] <= off_host[b]) return fail(DPAR2_EINVAL, "every tensor needs at least one token");
+  return DPAR2_OK;
+}
+}  // namespace
+
 extern "C" {
 
 size_t dpar2_workspace_size(const dpar2_tensor* X, const dpar2_opts* o) {
@@ -842,6 +866,90 @@ dpar2_status dpar2_compressed_view(const dpar2_tensor* X, const dpar2_opts* o, c
   out->sigma = reinterpret_cast<const double*>(w + y.sig1);
   out->xnorm2 = reinterpret_cast<const double*>(w + y.xnorm2);
   return DPAR2_OK;
+}
+
+// --- learned warm start ------------------------------------------------------
+
+int64_t dpar2_warm_param_count(int32_t rank) {
+  if (rank < 1 || rank > 32) return 0;
+  return warm_layout(rank).P;
+}
+
+
+dpar2_status dpar2_warm_features(const dpar2_tensor* X, const dpar2_opts* o, const void* ws, size_t ws_bytes,
+                                 float* tok, dpar2_stream_t stream) {
+  Comp c;
+  dpar2_status st = comp_of(X, o, ws, ws_bytes, &c);
+  if (st != DPAR2_OK) return st;
+  if (!tok) return fail(DPAR2_EINVAL, "tok is NULL");
+  const char* w = static_cast<const char*>(ws);
+  hipError_t e = launch_warm_feat(c.y.K, (int)c.y.J, c.y.R, reinterpret_cast<const double*>(w + c.y.F),
+                                  reinterpret_cast<const double*>(w + c.y.E),
+                                  reinterpret_cast<const double*>(w + c.y.D), tok,
+                                  reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DPAR2_OK : hip_fail(e, "warm features");
+}
+
+dpar2_status dpar2_warm_targets(const dpar2_tensor* X, const dpar2_opts* o, const void* ws, size_t ws_bytes,
+                                const dpar2_factors* f, float* tH, float* tV, float* tW, dpar2_stream_t stream) {
+  Comp c;
+  dpar2_status st = comp_of(X, o, ws, ws_bytes, &c);
+  if (st != DPAR2_OK) return st;
+  if (!f || !f->H || !f->V || !f->W || !tH || !tV || !tW) return fail(DPAR2_EINVAL, "NULL factor or target");
+  const char* w = static_cast<const char*>(ws);
+  hipError_t e = launch_warm_targets(c.y.K, (int)c.y.J, c.y.R, reinterpret_cast<const double*>(w + c.y.D),
+                                     reinterpret_cast<const double*>(w + c.y.E), f->H, f->V, f->W, tH, tV, tW,
+                                     reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DPAR2_OK : hip_fail(e, "warm targets");
+}
+
+dpar2_status dpar2_warm_apply(const dpar2_tensor* X, const dpar2_opts* o, const void* ws, size_t ws_bytes,
+                              const float* pH, const float* pV, const float* pW, dpar2_factors* f,
+                              dpar2_stream_t stream) {
+  Comp c;
+  dpar2_status st = comp_of(X, o, ws, ws_bytes, &c);
+  if (st != DPAR2_OK) return st;
+  if (!f || !f->H || !f->V || !f->W || !pH || !pV || !pW) return fail(DPAR2_EINVAL, "NULL factor or prediction");
+  const char* w = static_cast<const char*>(ws);
+  hipError_t e = launch_warm_apply(c.y.K, (int)c.y.J, c.y.R, reinterpret_cast<const double*>(w + c.y.D),
+                                   reinterpret_cast<const double*>(w + c.y.E), pH, pV, pW, f->H, f->V, f->W,
+                                   reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DPAR2_OK : hip_fail(e, "warm apply");
+}
+
+dpar2_status dpar2_warm_forward(int32_t rank, int32_t n, const int32_t* tok_off, const int32_t* tok_off_host,
+                                const float* tok, const float* theta, float* act, float* pH, float* pV, float* pW,
+                                dpar2_stream_t stream) {
+  dpar2_status st = check_tokens(rank, n, tok_off, tok_off_host);
+  if (st != DPAR2_OK) return st;
+  if (!tok || !theta || !act || !pH || !pV || !pW) return fail(DPAR2_EINVAL, "NULL buffer");
+  hipError_t e = launch_warm_forward(rank, n, tok_off, tok, theta, act, pH, pV, pW,
+                                     reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DPAR2_OK : hip_fail(e, "warm forward");
+}
+
+dpar2_status dpar2_warm_backward(int32_t rank, int32_t n, const int32_t* tok_off, const int32_t* tok_off_host,
+                                 const float* tok, const float* theta, float* act, const float* pH, const float* pV,
+                                 const float* pW, const float* tH, const float* tV, const float* tW,
+                                 float* grad_part, float* grad, float* loss, dpar2_stream_t stream) {
+  dpar2_status st = check_tokens(rank, n, tok_off, tok_off_host);
+  if (st != DPAR2_OK) return st;
+  if (!tok || !theta || !act || !pH || !pV || !pW || !tH || !tV || !tW || !grad_part || !grad || !loss)
+    return fail(DPAR2_EINVAL, "NULL buffer");
+  hipError_t e = launch_warm_backward(rank, n, tok_off, tok, theta, act, pH, pV, pW, tH, tV, tW, grad_part, grad,
+                                      loss, reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DPAR2_OK : hip_fail(e, "warm backward");
+}
+
+dpar2_status dpar2_warm_adam(int32_t rank, float* theta, const float* grad, float* m, float* v, int32_t step,
+                             float lr, float beta1, float beta2, float eps, float grad_scale,
+                             dpar2_stream_t stream) {
+  if (rank < 1 || rank > 32) return fail(DPAR2_EINVAL, "rank must be in 1..32");
+  if (!theta || !grad || !m || !v) return fail(DPAR2_EINVAL, "NULL buffer");
+  if (step < 1) return fail(DPAR2_EINVAL, "step counts from 1");
+  hipError_t e = launch_warm_adam(rank, theta, grad, m, v, step, lr, beta1, beta2, eps, grad_scale,
+                                  reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DPAR2_OK : hip_fail(e, "warm adam");
 }
 
 dpar2_status dpar2_profile_enable(int32_t on) {

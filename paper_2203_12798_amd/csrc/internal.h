@@ -129,4 +129,27 @@ int als_slices_per_block(int R);
 
 bool sketch_supported(int J, int L, int dtype);
 
+// --- learned warm start (k_warm.hip) ------------------------------------------
+constexpr int WARM_WIDTH = 128;   // hidden width of the set encoder
+// float offsets of the parameter blocks (row-major), P = total
+struct WarmLayout {
+  int F;                                            // tokens: R (R + 1) / 2 features
+  int W1, b1, W2, b2, WH, bH, WV, bV, Ww, bw, P;
+};
+__host__ __device__ WarmLayout warm_layout(int R);
+hipError_t launch_warm_feat(int64_t K, int J, int R, const double* F, const double* E, const double* D, float* tok,
+                            hipStream_t s);
+hipError_t launch_warm_targets(int64_t K, int J, int R, const double* D, const double* E, const double* H,
+                               const double* V, const double* W, float* tH, float* tV, float* tW, hipStream_t s);
+hipError_t launch_warm_apply(int64_t K, int J, int R, const double* D, const double* E, const float* pH,
+                             const float* pV, const float* pW, double* H, double* V, double* W, hipStream_t s);
+hipError_t launch_warm_forward(int R, int n, const int32_t* tok_off, const float* tok, const float* theta,
+                               float* act, float* pH, float* pV, float* pW, hipStream_t s);
+hipError_t launch_warm_backward(int R, int n, const int32_t* tok_off, const float* tok, const float* theta,
+                                float* act, const float* pH, const float* pV, const float* pW, const float* tH,
+                                const float* tV, const float* tW, float* gpart, float* grad, float* loss,
+                                hipStream_t s);
+hipError_t launch_warm_adam(int R, float* theta, const float* grad, float* m, float* v, int step, float lr,
+                            float b1, float b2, float eps, float scale, hipStream_t s);
+
 }  // namespace dpar2

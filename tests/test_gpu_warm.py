@@ -1,0 +1,185 @@
+"""Learned warm start on the GPU: the set-encoder kernels against the FP64
+warm-start oracle (forward outputs, loss, gradient, Adam step), the feature,
+target and apply kernels against the oracle on a real compressed tensor, and
+a small training run that must lower the loss and is then compared with the
+random start on held-out tensors."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import warm_oracle as WO
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def test_network_kernels_match_oracle():
+    """Three tensors of 5, 17 and 40 tokens, R = 5: outputs within 1e-5
+    relative of the FP64 forward, per-tensor losses within 1e-5, the summed
+    gradient within 1e-4 relative (FP32 sums over tokens), one Adam step
+    within 1e-5."""
+    torch = _torch()
+    import paper_2203_12798_amd as d
+    from paper_2203_12798_amd import binding as b
+    R = 5
+    print(f"[gpu] warm network kernels R={R}", flush=True)
+    rng = np.random.default_rng(0)
+    P, NF = WO.n_params(R), WO.n_features(R)
+    assert b.warm_param_count(R) == P
+    theta = (rng.standard_normal(P) * 0.1).astype(np.float32)
+    Ks = [5, 17, 40]
+    toks = [rng.standard_normal((K, NF)).astype(np.float32) for K in Ks]
+    tHs = [rng.standard_normal((R, R)).astype(np.float32) for _ in Ks]
+    tVs = [rng.standard_normal((R, R)).astype(np.float32) for _ in Ks]
+    tWs = [rng.standard_normal((K, R)).astype(np.float32) for K in Ks]
+    off = np.concatenate([[0], np.cumsum(Ks)]).astype(np.int32)
+    cu = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    th = cu(theta)
+    tok = cu(np.concatenate(toks))
+    n, ntok = len(Ks), int(off[-1])
+    f32 = dict(dtype=torch.float32, device="cuda")
+    act = torch.empty((ntok, 4 * b.WARM_WIDTH), **f32)
+    pH, pV, pW = torch.empty((n, R, R), **f32), torch.empty((n, R, R), **f32), torch.empty((ntok, R), **f32)
+    b.warm_forward(R, off, tok, th, act, pH, pV, pW)
+    gp, grad, loss = torch.empty((n, P), **f32), torch.empty(P, **f32), torch.empty((n, 3), **f32)
+    b.warm_backward(R, off, tok, th, act, pH, pV, pW, cu(np.stack(tHs)), cu(np.stack(tVs)),
+                    cu(np.concatenate(tWs)), gp, grad, loss)
+    g_ref = np.zeros(P)
+    pHg, pVg, pWg, lg = (x.cpu().numpy() for x in (pH, pV, pW, loss))
+    for i, K in enumerate(Ks):
+        rH, rV, rW, cache = WO.forward(theta.astype(np.float64), toks[i], R)
+        np.testing.assert_allclose(pHg[i], rH, rtol=1e-5, atol=1e-5)
+        np.testing.assert_allclose(pVg[i], rV, rtol=1e-5, atol=1e-5)
+        np.testing.assert_allclose(pWg[off[i]:off[i + 1]], rW, rtol=1e-5, atol=1e-5)
+        np.testing.assert_allclose(lg[i], WO.loss(rH, rV, rW, tHs[i], tVs[i], tWs[i], R), rtol=1e-5)
+        g_ref += WO.backward(rH, rV, rW, tHs[i], tVs[i], tWs[i], cache, R)
+    gg = grad.cpu().numpy()
+    assert np.linalg.norm(gg - g_ref) <= 1e-4 * np.linalg.norm(g_ref)
+    at = 0
+    for name, shp in WO.param_shapes(R):   # every block, not just the norm
+        m = int(np.prod(shp))
+        blk = slice(at, at + m)
+        assert np.linalg.norm(gg[blk] - g_ref[blk]) <= 1e-4 * max(np.linalg.norm(g_ref[blk]), 1e-6), name
+        at += m
+    # Adam: step 3 from random moments
+    m0 = rng.standard_normal(P).astype(np.float32) * 0.01
+    v0 = np.abs(rng.standard_normal(P)).astype(np.float32) * 0.01
+    mt, vt = cu(m0), cu(v0)
+    b.warm_adam(R, th, grad, mt, vt, 3, lr=1e-3, grad_scale=1.0 / n)
+    ref, mr, vr = WO.adam(theta.astype(np.float64), gg.astype(np.float64) / n, m0.astype(np.float64),
+                          v0.astype(np.float64), 3, 1e-3, 0.9, 0.999, 1e-8)
+    np.testing.assert_allclose(th.cpu().numpy(), ref, rtol=1e-5, atol=1e-7)
+    np.testing.assert_allclose(mt.cpu().numpy(), mr, rtol=1e-5, atol=1e-9)
+    np.testing.assert_allclose(vt.cpu().numpy(), vr, rtol=1e-5, atol=1e-12)
+
+
+def test_features_targets_apply_match_oracle():
+    """On a decomposed small-parity tensor (K = 64, J = 32, R = 5): tokens,
+    canonical targets and the rebuilt starting factors against the oracle
+    applied to the same compressed representation and factors."""
+    torch = _torch()
+    import paper_2203_12798_amd as d
+    from paper_2203_12798_amd import warm
+    X = synth.small_parity(seed=21)
+    R, L = 5, 15
+    print(f"[gpu] warm features/targets K={X.K} R={R}", flush=True)
+    om1, om2 = synth.omegas(X.J, L, X.K * R)
+    T = d.Tensor.from_numpy(X.slab, X.offsets)
+    o = d.Options(rank=R, sketch=L, sketch2=L, max_iter=30)
+    ws = d.alloc_workspace(T, o)
+    f = d.Factors.from_numpy(*synth.init_factors(X.J, X.K, R))
+    d.decompose(T, o, torch.from_numpy(om1).cuda(), torch.from_numpy(om2).cuda(), f, ws)
+    comp = d.compressed_view(T, o, ws)
+    s = warm.label(T, o, ws, f)
+    tok_ref, e_mean = WO.features(comp["F"], comp["E"], comp["D"], X.K, R)
+    np.testing.assert_allclose(s.tok.cpu().numpy(), tok_ref, rtol=1e-5, atol=1e-6 * np.abs(tok_ref).max())
+    H, V, W = f.numpy()
+    tH, tV, tW = WO.targets(H, V, W, comp["D"], e_mean, R)
+    np.testing.assert_allclose(s.tH.cpu().numpy(), tH, rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(s.tV.cpu().numpy(), tV, rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(s.tW.cpu().numpy(), tW, rtol=1e-5, atol=1e-6)
+    f2 = d.Factors.from_numpy(*synth.init_factors(X.J, X.K, R))
+    from paper_2203_12798_amd import binding as b
+    b.warm_apply(T, o, ws, s.tH, s.tV, s.tW, f2)
+    H2, V2, W2 = f2.numpy()
+    rH, rV, rW = WO.apply(s.tH.cpu().numpy(), s.tV.cpu().numpy(), s.tW.cpu().numpy(), comp["D"], e_mean, R)
+    np.testing.assert_allclose(H2, rH, rtol=1e-12)
+    np.testing.assert_allclose(V2, rV, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(W2, rW, rtol=1e-12)
+
+
+def _gen(n, seed, K=(16, 48), J=32, R=5, rows=(24, 120)):
+    out = []
+    for t in range(n):
+        rng = np.random.default_rng([seed, t])
+        k = int(rng.integers(K[0], K[1] + 1))
+        X = synth.parafac2(rng.integers(rows[0], rows[1] + 1, size=k), J, R, [seed, t], noise_rel=0.01)
+        out.append(X)
+    return out
+
+
+def test_training_lowers_loss_and_reports_gain():
+    """Trains the encoder on generated tensors (K in [16, 48], J = 32, I_k in
+    [24, 120], R = 5, 1% noise) labelled by their own 150-iteration
+    decompositions (labels whose canonical W exceeds 10 in magnitude, i.e.
+    degenerate ALS solutions, are left out); the training loss must fall below
+    0.7 of its start.  On 32 held-out tensors the iterations to reach the
+    random start's 200-iteration compressed fitness minus 1e-4 are reported
+    for both starts, with the held-out loss."""
+    torch = _torch()
+    import paper_2203_12798_amd as d
+    from paper_2203_12798_amd import warm
+    R, L = 5, 15
+    print("[gpu] warm training", flush=True)
+
+    def prep(X, seed, iters):
+        T = d.Tensor.from_numpy(X.slab, X.offsets)
+        o = d.Options(rank=R, sketch=L, sketch2=L, max_iter=iters)
+        om1, om2 = synth.omegas(X.J, L, X.K * R, seed=seed)
+        ws = d.alloc_workspace(T, o)
+        return T, o, ws, torch.from_numpy(om1).cuda(), torch.from_numpy(om2).cuda()
+
+    def labelled(n, seed):
+        out = []
+        for i, X in enumerate(_gen(n, seed)):
+            T, o, ws, o1, o2 = prep(X, seed * 10000 + i, 150)
+            f = d.Factors.from_numpy(*synth.init_factors(X.J, X.K, R, seed=seed * 10000 + i))
+            d.decompose(T, o, o1, o2, f, ws)
+            s = warm.label(T, o, ws, f)
+            if float(s.tW.abs().max()) < 10.0:
+                out.append(s)
+        return out
+
+    train = labelled(600, 100)
+    test = labelled(64, 300)
+    print(f"[warm] {len(train)} training and {len(test)} held-out labels", flush=True)
+    net = warm.WarmNet(R, seed=1)
+    l0, t0 = net.loss(train), net.loss(test)
+    net.train(train, steps=2500, batch=32, lr=1e-3)
+    l1, t1 = net.loss(train), net.loss(test)
+    print(f"[warm] training loss {l0.sum():.4f} -> {l1.sum():.4f} (terms {l1.round(4)}); "
+          f"held-out {t0.sum():.4f} -> {t1.sum():.4f} (terms {t1.round(4)})", flush=True)
+    assert l1.sum() < 0.7 * l0.sum()
+    its_r, its_w, hit_r, hit_w = [], [], 0, 0
+    for i, X in enumerate(_gen(32, 200)):
+        T, o, ws, o1, o2 = prep(X, 1000 + i, 200)
+        d.compress(T, o, o1, o2, ws)
+        f = d.Factors.from_numpy(*synth.init_factors(X.J, X.K, R, seed=1000 + i))
+        _, fit_r = warm.iterations_to(T, o, ws, f, 2.0, 200)
+        target = fit_r[-1] - 1e-4
+        tr = int(np.nonzero(fit_r >= target)[0][0]) + 1
+        d.compress(T, o, o1, o2, ws)        # fresh iteration state
+        fw = d.Factors.from_numpy(*synth.init_factors(X.J, X.K, R, seed=1000 + i))
+        net.init_factors(T, o, ws, fw)
+        tw, fit_w = warm.iterations_to(T, o, ws, fw, target, 200)
+        hit_w += tw is not None
+        its_r.append(tr)
+        its_w.append(200 if tw is None else tw)
+    print(f"[warm] held-out: random start {np.mean(its_r):.1f} iterations (median {np.median(its_r):.0f}), "
+          f"warm start {np.mean(its_w):.1f} (median {np.median(its_w):.0f}; reached {hit_w}/32)", flush=True)
