@@ -44,6 +44,10 @@ def parse():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batching form (256 independent tensors of mixed J, R, K, I_k)")
     ap.add_argument("--batch-tensors", type=int, default=256)
+    ap.add_argument("--no-warm", action="store_true",
+                    help="skip the learned warm-start form (train the set encoder, compare on held-out tensors)")
+    ap.add_argument("--warm-train", type=int, default=400, help="training tensors of the warm-start form")
+    ap.add_argument("--warm-test", type=int, default=32, help="held-out tensors of the warm-start form")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic.json from two rocprofv3 --pmc counter_collection.csv "
                          "files (FETCH_SIZE, WRITE_SIZE) of a --calib-copy run, then exit")
@@ -201,6 +205,107 @@ def bench_batch(args, d, torch, np):
         print(f"[bench] batch {key}: {ms:.3f} ms", file=sys.stderr, flush=True)
         del ws
     return res
+
+
+def gen_warm_tensor(t, seed, d, torch, np):
+    """One tensor of the warm-start workload: K ~ U{32..512}, J = 64,
+    I_k ~ U{64..1024}, rank-10 PARAFAC2 (as in gen_batch) plus Gaussian noise
+    of 0.01 x the RMS of the clean entries; numpy SeedSequence(seed).spawn
+    for the shape, torch's generator seeded by (seed, t) for the entries."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, t]))
+    K, J, R = int(rng.integers(32, 513)), 64, 10
+    rows = rng.integers(64, 1025, size=K)
+    g = torch.Generator(device="cuda").manual_seed(seed * 100003 + t)
+    imax = int(rows.max())
+    mask = torch.arange(imax, device="cuda")[None, :] < torch.from_numpy(rows).cuda()[:, None]
+    Q = torch.linalg.qr(torch.randn(K, imax, R, device="cuda", generator=g) * mask[:, :, None]).Q
+    H = torch.randn(R, R, device="cuda", generator=g)
+    V = torch.randn(J, R, device="cuda", generator=g)
+    W = 0.5 + torch.rand(K, R, device="cuda", generator=g)
+    clean = torch.bmm(Q.contiguous(), ((H[None] * W[:, None, :]) @ V.t()).contiguous())[mask]
+    slab = clean + 0.01 * clean.pow(2).mean().sqrt() * torch.randn(clean.shape, device="cuda", generator=g)
+    offs = np.concatenate([[0], np.cumsum(rows)]).astype(np.int64)
+    return d.Tensor(slab.contiguous(), torch.from_numpy(offs).cuda(), offs), K, J, R
+
+
+def bench_warm(args, d, torch, np):
+    """Learned warm start: trains the set encoder on tensors labelled by their
+    own 150-iteration decompositions, then on held-out tensors measures the
+    iterations and device time each start needs to reach the random start's
+    300-iteration fitness minus 1e-3 (|delta fitness| <= 1e-3)."""
+    from paper_2203_12798_amd import warm
+    R, L, max_it = 10, 20, 300
+    t0 = time.perf_counter()
+
+    def setup(T, K, J, seed):
+        o = d.Options(rank=R, sketch=L, sketch2=L, max_iter=max_it)
+        g = torch.Generator(device="cuda").manual_seed(seed)
+        om1 = torch.randn(J, L, device="cuda", generator=g)
+        om2 = torch.randn(K * R, L, device="cuda", generator=g)
+        init = (torch.eye(R, dtype=torch.float64, device="cuda"),
+                torch.randn(J, R, dtype=torch.float64, device="cuda", generator=g),
+                torch.ones(K, R, dtype=torch.float64, device="cuda"))
+        return o, om1, om2, init
+
+    train = []
+    for t in range(args.warm_train):
+        T, K, J, _ = gen_warm_tensor(t, 5, d, torch, np)
+        o, om1, om2, init = setup(T, K, J, t)
+        o.max_iter = 150
+        ws = d.alloc_workspace(T, o)
+        f = d.Factors(*(a.clone() for a in init))
+        d.decompose(T, o, om1, om2, f, ws)
+        s = warm.label(T, o, ws, f)
+        if float(s.tW.abs().max()) < 10.0:       # degenerate ALS solutions are not labels
+            train.append(s)
+        del T, ws
+    label_s = time.perf_counter() - t0
+    net = warm.WarmNet(R, seed=1)
+    t1 = time.perf_counter()
+    net.train(train, steps=3000, batch=32, lr=1e-3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    print(f"[bench] warm: {len(train)} labels ({label_s:.1f}s), trained in {train_s:.1f}s", file=sys.stderr,
+          flush=True)
+    its_r, its_w, ms_r, ms_w, dfit = [], [], [], [], []
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    for t in range(args.warm_test):
+        T, K, J, _ = gen_warm_tensor(t, 6, d, torch, np)
+        o, om1, om2, init = setup(T, K, J, 10 ** 6 + t)
+        ws = d.alloc_workspace(T, o)
+        d.compress(T, o, om1, om2, ws)
+        f = d.Factors(*(a.clone() for a in init))
+        ev[0].record()
+        _, fit_r = warm.iterations_to(T, o, ws, f, 2.0, max_it)
+        ev[1].record()
+        torch.cuda.synchronize()
+        per_it = ev[0].elapsed_time(ev[1]) / max_it
+        target = fit_r[-1] - 1e-3
+        tr = int(np.nonzero(fit_r >= target)[0][0]) + 1
+        d.compress(T, o, om1, om2, ws)
+        fw = d.Factors(*(a.clone() for a in init))
+        ev[2].record()
+        net.init_factors(T, o, ws, fw)
+        ev[3].record()
+        tw, fit_w = warm.iterations_to(T, o, ws, fw, target, max_it)
+        torch.cuda.synchronize()
+        its_r.append(tr)
+        its_w.append(max_it if tw is None else tw)
+        ms_r.append(tr * per_it)
+        ms_w.append(ev[2].elapsed_time(ev[3]) + its_w[-1] * per_it)
+        dfit.append(fit_w[-1] - fit_r[-1])
+        del T, ws
+    return {"workload": "K~U{32..512}, J=64, I_k~U{64..1024}, rank-10 PARAFAC2 + 1% noise; R=10 L=20",
+            "train_tensors": len(train), "train_steps": 3000, "label_s": round(label_s, 1),
+            "train_s": round(train_s, 2), "test_tensors": args.warm_test,
+            "target": "random start's 300-iteration compressed fitness - 1e-3",
+            "iters_random_mean": float(np.mean(its_r)), "iters_warm_mean": float(np.mean(its_w)),
+            "iters_random_median": float(np.median(its_r)), "iters_warm_median": float(np.median(its_w)),
+            "reached_warm": int(sum(1 for i in its_w if i < max_it)),
+            "ms_to_target_random_mean": round(float(np.mean(ms_r)), 3),
+            "ms_to_target_warm_mean": round(float(np.mean(ms_w)), 3),
+            "speedup_vs_random": round(float(np.sum(ms_r) / np.sum(ms_w)), 3),
+            "fit_after_300_warm_minus_random_mean": float(np.mean(dfit))}
 
 
 def main():
@@ -362,6 +467,11 @@ def main():
             out["batch"] = bench_batch(args, d, torch, np)
         except Exception as exc:   # reported, not fatal
             out["batch"] = {"error": str(exc)[:300]}
+    if not args.no_warm:
+        try:
+            out["warm_start"] = bench_warm(args, d, torch, np)
+        except Exception as exc:   # reported, not fatal
+            out["warm_start"] = {"error": str(exc)[:300]}
 
     if not args.no_cpu_baseline and args.cpu_sample > 0:
         from threadpoolctl import threadpool_limits
