@@ -74,7 +74,7 @@ dpar2_status validate(const dpar2_tensor* X, const dpar2_opts* o) {
   if (L2 > J) return fail(DPAR2_ESHAPE, "sketch width L2 exceeds J");
   if ((int64_t)L2 > K * R) return fail(DPAR2_ESHAPE, "sketch width L2 exceeds K*R");
   if (!sketch_supported((int)J, L, X->dtype))
-    return fail(DPAR2_ESHAPE, "J exceeds the slab pass limit (256 for float32, 128 for bf16 / fp8)");
+    return fail(DPAR2_ESHAPE, "J exceeds the slab pass limit of 16384 columns");
   const int64_t* off = X->row_offsets_host;
   if (off[0] != 0) return fail(DPAR2_EINVAL, "row_offsets[0] must be 0");
   for (int64_t k = 0; k < K; ++k) {
@@ -266,6 +266,9 @@ Layout make_layout(const Group& g) {
   y.trace = take(sizeof(double) * (size_t)(K * L * R));   // Theta for the U output
   y.om1 = take(sizeof(float) * (size_t)(nt * J * L));      // copy of each Omega_1 for the U pass
   y.omq = take(y.q > 0 ? sizeof(float) * (size_t)(K * J * L) : 0);   // power-step sketches
+  // the wide slab pass keeps Y (16 LT floats per row) between its two kernels
+  const bool wide = J > narrow_j_limit(g.X[0].dtype);
+  y.ybuf = take(wide ? sizeof(float) * (size_t)y.N * (L <= 16 ? 16 : 32) : 0);
   y.total = p;
   return y;
 }
@@ -391,9 +394,12 @@ dpar2_status upload_locked(Staging& sg, char* w, const char* img, size_t n, size
 std::vector<TDesc> descriptors(const Group& g, const float* const* om1, const float* const* om2,
                                const dpar2_factors* f, double* const* trace) {
   std::vector<TDesc> td((size_t)g.nt);
+  int64_t rbase = 0;
   for (int t = 0; t < g.nt; ++t) {
     TDesc& d = td[(size_t)t];
     std::memset(&d, 0, sizeof(d));
+    d.rbase = rbase;
+    rbase += g.X[t].row_offsets_host[g.X[t].K];
     d.K = g.X[t].K;
     d.k0 = g.k0[(size_t)t];
     d.slab = g.X[t].slab;
@@ -529,6 +535,7 @@ dpar2_status group_compress(const Group& g, const float* const* om1, const float
   sa.partG = partG;
   sa.partP = partP;
   sa.partS = partS;
+  sa.ybuf = reinterpret_cast<float*>(w + y.ybuf);
   float* omq = reinterpret_cast<float*>(w + y.omq);
   for (int pass = 0; pass <= y.q; ++pass) {
     // pass 0 sketches with each tensor's Omega_1; a power step with each
@@ -643,6 +650,7 @@ dpar2_status group_output_U(const Group& g, const Layout& y, char* w, const doub
   sa.items = reinterpret_cast<const Item*>(w + y.items);
   sa.theta = theta;
   sa.U = U;
+  sa.ybuf = reinterpret_cast<float*>(w + y.ybuf);
   const bool vec = (y.J % 4 == 0) && ((uintptr_t)g.X[0].slab % (4 * esize) == 0);
   e = launch_slab(sa, dtype, y.n_items, vec, true, s);
   if (e != hipSuccess) return hip_fail(e, "U pass");

@@ -38,6 +38,7 @@ struct TDesc {
   double *H, *V, *W;    // factors (caller memory)
   double* trace;        // per-iteration error (caller memory) or NULL
   double tol;
+  int64_t rbase;        // first row of the tensor in the group's row space (wide-J sketch buffer)
 };
 
 // One block of a per-slice kernel: rows [s0, s1) of tensor t (global slice
@@ -70,6 +71,7 @@ struct Layout {
   size_t D, E, F, FtFp;
   // iteration
   size_t Psi, Pw, Mk, small, partA, partB, partC, partBegin, red, fitp, trace, om1, omq;
+  size_t ybuf;            // wide-J slab pass: Y of every row (N x 16 LT floats), else empty
   size_t tables_end;     // end of the host-built tables [tdesc, tables_end)
   size_t total;
 };
@@ -101,11 +103,18 @@ struct SlabArgs {
   double *partG, *partP, *partS;
   const double* theta;     // U variant: K x L x R
   double* U;               // U variant: N x R (single tensor)
+  float* ybuf;             // wide-J pass: Y rows (TDesc::rbase + row) x 16 LT
 };
+// J above which the slab pass takes the two-kernel wide form (sketch, then
+// projection per 128-column chunk): 256 for float32 slabs, 128 otherwise
+inline int narrow_j_limit(int dtype) { return dtype == 0 ? 256 : 128; }
+constexpr int MAX_J = 16384;
 // Slab pass over all work items: per-item partials of Y^T Y, Y^T X and
 // ||X||^2, or (uout) U = Y Theta_k.  dtype: dpar2_dtype; vec: every slab is
 // aligned for 4-element loads and J % 4 == 0.
 hipError_t launch_slab(const SlabArgs& a, int dtype, int64_t n_items, bool vec, bool uout, hipStream_t s);
+// the wide form (J above narrow_j_limit), k_slab_wide.hip
+hipError_t launch_slab_wide(const SlabArgs& a, int dtype, int64_t n_items, bool vec, bool uout, hipStream_t s);
 // Per-slice completion of the first stage; omega_next (K x J x L float32, or
 // NULL) receives the sketch matrix of a power step, the orthonormal right
 // singular vectors of B_k (Alg. 1's power iteration in stabilised form).

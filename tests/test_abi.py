@@ -96,8 +96,8 @@ def test_status_strings():
 
 
 def test_dtype_and_power_options_validated_on_host():
-    """fp8 slabs need per-slice scales; power_iters in [0, 4]; bf16 / fp8
-    slabs are limited to J <= 128, float32 to J <= 256."""
+    """fp8 slabs need per-slice scales; power_iters in [0, 4]; J up to
+    16384 for every dtype."""
     binding, lib = _lib()
     off = np.array([0, 10, 20], dtype=np.int64)
     hp = off.ctypes.data_as(ctypes.c_void_p).value
@@ -113,10 +113,18 @@ def test_dtype_and_power_options_validated_on_host():
         assert _status(lib, binding, t, oq) == st
     offw = np.array([0, 200, 400], dtype=np.int64)
     hw = offw.ctypes.data_as(ctypes.c_void_p).value
-    tb = binding.c_tensor(2, 160, 0x1000, hw, 0x2000, binding.DPAR2_BF16, None)
+    tb = binding.c_tensor(2, 16385, 0x1000, hw, 0x2000, binding.DPAR2_BF16, None)
     assert _status(lib, binding, tb, o) == -2
-    tf = binding.c_tensor(2, 160, 0x1000, hw, 0x2000, binding.DPAR2_F32, None)
-    assert lib.dpar2_workspace_size(ctypes.byref(tf), ctypes.byref(o)) > 0
+    for J in (160, 2049, 16384):
+        for dt in (binding.DPAR2_F32, binding.DPAR2_BF16):
+            tf = binding.c_tensor(2, J, 0x1000, hw, 0x2000, dt, None)
+            assert lib.dpar2_workspace_size(ctypes.byref(tf), ctypes.byref(o)) > 0
+    # the wide pass (J above 256 for float32) keeps Y: 16 floats per row at L <= 16
+    t256 = binding.c_tensor(2, 256, 0x1000, hw, 0x2000, binding.DPAR2_F32, None)
+    t257 = binding.c_tensor(2, 257, 0x1000, hw, 0x2000, binding.DPAR2_F32, None)
+    ws256 = lib.dpar2_workspace_size(ctypes.byref(t256), ctypes.byref(o))
+    ws257 = lib.dpar2_workspace_size(ctypes.byref(t257), ctypes.byref(o))
+    assert ws257 - ws256 >= 400 * 16 * 4
     # a power step needs one sketch matrix per slice in the workspace
     o1 = binding.c_opts(2, 3, 3, 5, -1.0, 0, 1)
     t8 = binding.c_tensor(2, 8, 0x1000, hp, 0x2000, binding.DPAR2_F32, None)
