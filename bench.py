@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batching form (256 independent tensors of mixed J, R, K, I_k)")
     ap.add_argument("--batch-tensors", type=int, default=256)
+    ap.add_argument("--no-wide", action="store_true",
+                    help="skip the precision form at J = 2049 (K = 8000, spectrogram-like, R = 10 and 20)")
+    ap.add_argument("--wide-k", type=int, default=8000)
     ap.add_argument("--no-warm", action="store_true",
                     help="skip the learned warm-start form (train the set encoder, compare on held-out tensors)")
     ap.add_argument("--warm-train", type=int, default=400, help="training tensors of the warm-start form")
@@ -308,6 +311,111 @@ def bench_warm(args, d, torch, np):
             "fit_after_300_warm_minus_random_mean": float(np.mean(dfit))}
 
 
+def gen_wide(K, d, torch, np, seed=3, chunk=256):
+    """Spectrogram-shaped workload: K slices, J = 2049 bins, I_k ~ U{100..704}
+    (numpy default_rng(3)); each slice a rank-20 PARAFAC2 whose first
+    component is a DC term (Q_k(:, 0) = 1 / sqrt(I_k), the other columns
+    orthonormal to it, from the QR of [1, Gaussian]), V(:, 0) a decaying
+    positive envelope exp(-j / 400) and W(k, 0) in [3, 4] so that the model is
+    mostly positive, H = I + 0.3 N(0, 1), the other V and W entries N(0, 1)
+    and U(0.5, 1.5); clipped at 0, plus exponential noise of mean 0.1 x the
+    clipped model's mean.  Drawn on the GPU with torch's generator, float32."""
+    J, Rt = 2049, 20
+    rng = np.random.default_rng(seed)
+    rows = rng.integers(100, 705, size=K)
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    H = torch.eye(Rt, device="cuda") + 0.3 * torch.randn(Rt, Rt, device="cuda", generator=g)
+    V = torch.randn(J, Rt, device="cuda", generator=g)
+    V[:, 0] = torch.exp(-torch.arange(J, device="cuda", dtype=torch.float32) / 400.0)
+    offs = np.concatenate([[0], np.cumsum(rows)]).astype(np.int64)
+    slab = torch.empty((int(offs[-1]), J), dtype=torch.float32, device="cuda")
+    for k0 in range(0, K, chunk):
+        r = rows[k0:k0 + chunk]
+        kc, imax = len(r), int(r.max())
+        mask = torch.arange(imax, device="cuda")[None, :] < torch.from_numpy(r).cuda()[:, None]
+        G = torch.randn(kc, imax, Rt, device="cuda", generator=g)
+        G[:, :, 0] = 1.0
+        Q = torch.linalg.qr(G * mask[:, :, None]).Q
+        Q = Q * torch.sign(Q[:, :1, :1] + 1e-30)                     # DC column positive
+        W = 0.5 + torch.rand(kc, Rt, device="cuda", generator=g)
+        W[:, 0] = 3.0 + torch.rand(kc, device="cuda", generator=g)
+        X = torch.bmm(Q.contiguous(), ((H[None] * W[:, None, :]) @ V.t()).contiguous())[mask].clamp_min(0.0)
+        noise = torch.empty_like(X).exponential_(1.0, generator=g)
+        slab[int(offs[k0]):int(offs[k0 + kc])] = X + 0.1 * X.mean() * noise
+        del G, Q, X, noise
+    return d.Tensor(slab, torch.from_numpy(offs).cuda(), offs), rows
+
+
+def bench_wide(args, d, torch, np, binding):
+    """Precision form at the spectrogram shape (J = 2049): float32, bf16 and
+    fp8-e4m3 (per-slice power-of-two scales) slabs, R = 10 (L = 20) and
+    R = 20 (L = 30), 32 iterations; ms per decomposition, the slab-pass time
+    (both kernels of the wide pass) and the fitness of each form; on the
+    first 16 slices also each form's fitness against the FP64 oracle on the
+    float32 data."""
+    t0 = time.perf_counter()
+    T, rows = gen_wide(args.wide_k, d, torch, np)
+    torch.cuda.synchronize()
+    K, J = T.K, T.J
+    res = {"workload": f"spectrogram-shaped K={K} J={J} I_k~U{{100..704}}, rank-20 PARAFAC2 (DC component), "
+                       "clipped, exponential noise; 32 iterations",
+           "K": K, "J": J, "N": int(T.offsets_host[-1]), "slab_gb_f32": round(T.slab.numel() * 4 / 1e9, 2),
+           "gen_s": round(time.perf_counter() - t0, 1)}
+    amax = torch.zeros(K, device="cuda")
+    rid = torch.repeat_interleave(torch.arange(K, device="cuda"), torch.from_numpy(rows).cuda())
+    amax.scatter_reduce_(0, rid, T.slab.abs().amax(dim=1), reduce="amax")
+    scale = torch.exp2(torch.ceil(torch.log2(torch.clamp(amax, min=1e-30) / 448.0)))
+    forms = {"f32": T,
+             "bf16": d.Tensor(T.slab.to(torch.bfloat16).view(torch.int16), T.offsets_dev, T.offsets_host,
+                              binding.DPAR2_BF16),
+             "fp8": d.Tensor((T.slab / scale[rid][:, None]).to(torch.float8_e4m3fn).view(torch.uint8).contiguous(),
+                             T.offsets_dev, T.offsets_host, binding.DPAR2_FP8_E4M3, scale.contiguous())}
+    g = torch.Generator(device="cuda").manual_seed(99)
+    for R in (10, 20):
+        L = R + 10
+        o = d.Options(rank=R, sketch=L, sketch2=L, max_iter=32)
+        om1 = torch.randn(J, L, device="cuda", generator=g)
+        om1b = om1.to(torch.bfloat16).to(torch.float32)
+        om2 = torch.randn(K * R, L, device="cuda", generator=g)
+        init = (torch.eye(R, dtype=torch.float64, device="cuda"),
+                torch.randn(J, R, dtype=torch.float64, device="cuda", generator=g),
+                torch.ones(K, R, dtype=torch.float64, device="cuda"))
+        out = {}
+        for name, Tk in forms.items():
+            ws = d.alloc_workspace(Tk, o)
+            f = d.Factors(*(a.clone() for a in init))
+            om = om1 if name == "f32" else om1b
+
+            def step():
+                f.H.copy_(init[0])
+                f.V.copy_(init[1])
+                f.W.copy_(init[2])
+                d.decompose(Tk, o, om, om2, f, ws)
+
+            step()
+            torch.cuda.synchronize()
+            binding.profile_enable(True)
+            binding.profile_read()
+            ta = time.perf_counter()
+            for _ in range(2):
+                step()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - ta) * 1e3 / 2
+            nl, sk = binding.profile_read()
+            binding.profile_enable(False)
+            rep = d.report_read(Tk, o, ws)
+            out[name] = {"ms_per_step": round(ms, 2), "slices_per_s": round(K / (ms / 1e3), 1),
+                         "sketch_kernel_ms": round(sk / max(nl, 1), 3), "fitness": rep["fit_true"],
+                         "warn_bits": rep["warn_bits"]}
+            print(f"[bench] wide R={R} {name}: {ms:.2f} ms", file=sys.stderr, flush=True)
+            del ws
+        for name in ("bf16", "fp8"):
+            out[name]["speedup_vs_f32"] = round(out["f32"]["ms_per_step"] / out[name]["ms_per_step"], 3)
+            out[name]["fitness_delta_vs_f32"] = out[name]["fitness"] - out["f32"]["fitness"]
+        res[f"R{R}"] = out
+    return res
+
+
 def main():
     args = parse()
     if args.write_traffic:
@@ -467,6 +575,11 @@ def main():
             out["batch"] = bench_batch(args, d, torch, np)
         except Exception as exc:   # reported, not fatal
             out["batch"] = {"error": str(exc)[:300]}
+    if not args.no_wide:
+        try:
+            out["precision_wide"] = bench_wide(args, d, torch, np, binding)
+        except Exception as exc:   # reported, not fatal
+            out["precision_wide"] = {"error": str(exc)[:300]}
     if not args.no_warm:
         try:
             out["warm_start"] = bench_warm(args, d, torch, np)

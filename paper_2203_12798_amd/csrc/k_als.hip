@@ -46,6 +46,7 @@ __global__ __launch_bounds__(256) void k_fit_part(int J, int R, const TDesc* __r
                                                   const double* __restrict__ Mt, const double* __restrict__ Psi,
                                                   const double* __restrict__ small, double* __restrict__ fitp) {
   __shared__ double Q[32 * 33], sPsi[32 * 33], sH[32 * 33], red[16];
+  __shared__ double sM[32 * 65], sV[64 * 33];
   const int tid = threadIdx.x, RR = R * R;
   const int64_t k = blockIdx.x;
   const int t = slice_t[k];
@@ -53,13 +54,41 @@ __global__ __launch_bounds__(256) void k_fit_part(int J, int R, const TDesc* __r
   const double* V = d.V;
   const double* W = d.W + (size_t)(k - d.k0) * R;
   const double* HV = small + (size_t)t * SM_COUNT * RR + SM_HV * RR;
+  const double* Mk = Mt + (size_t)k * R * J;
   for (int e = tid; e < RR; e += 256) {
     const int r = e / R, s = e % R;
     sH[r * 33 + s] = d.H[e];
-    double acc = 0.0;
-    for (int jj = 0; jj < J; ++jj) acc += Mt[((size_t)k * R + r) * J + jj] * V[(size_t)jj * R + s];
-    Q[r * 33 + s] = acc;
     sPsi[r * 33 + s] = Psi[(size_t)k * RR + e];
+  }
+  // Q = (C_k B_k)^T V (R x R) over J in 64-column tiles staged in LDS
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int j0 = 0; j0 < J; j0 += 64) {
+    const int nj = (J - j0 < 64) ? J - j0 : 64;
+    __syncthreads();
+    for (int e = tid; e < R * 64; e += 256) {
+      const int r = e / 64, jj = e % 64;
+      sM[r * 65 + jj] = jj < nj ? Mk[(size_t)r * J + j0 + jj] : 0.0;
+    }
+    for (int e = tid; e < 64 * R; e += 256) {
+      const int jj = e / R, c = e % R;
+      sV[jj * 33 + c] = jj < nj ? V[(size_t)(j0 + jj) * R + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      if (e < RR) {
+        const int r = e / R, c = e % R;
+        double a = acc[q];
+        for (int jj = 0; jj < nj; ++jj) a = fma(sM[r * 65 + jj], sV[jj * 33 + c], a);
+        acc[q] = a;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = tid + 256 * q;
+    if (e < RR) Q[(e / R) * 33 + e % R] = acc[q];
   }
   __syncthreads();
   double tr = 0.0, qd = 0.0;
