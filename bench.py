@@ -445,9 +445,14 @@ def main():
           file=sys.stderr, flush=True)
 
     T = d.Tensor.from_numpy(X.slab, X.offsets)
-    o = d.Options(rank=R, sketch=L, sketch2=L2, max_iter=iters)
-    ws = d.alloc_workspace(T, o)
+    # work-item size of the slab pass from the autotuner (median of 3 timed launches each)
+    cands = (2048, 4096, 8192, 16384)
+    ws = d.alloc_workspace(T, d.Options(rank=R, sketch=L, sketch2=L2, max_iter=iters, item_rows=min(cands)))
     o1 = torch.from_numpy(om1).cuda()
+    item_rows, tune_ms = binding.autotune_item_rows(T, d.Options(rank=R, sketch=L, sketch2=L2, max_iter=iters),
+                                                    o1, ws, candidates=cands)
+    print(f"[bench] autotune item_rows: {tune_ms} -> {item_rows}", file=sys.stderr, flush=True)
+    o = d.Options(rank=R, sketch=L, sketch2=L2, max_iter=iters, item_rows=item_rows)
     o2 = torch.from_numpy(om2).cuda()
     init = [torch.from_numpy(a).cuda() for a in (H0, V0, W0)]
     f = d.Factors.from_numpy(H0, V0, W0)
@@ -539,7 +544,7 @@ def main():
     ms_per_step = (t1 - t0) * 1e3 / max(args.steps, 1)
     sec = ms_per_step / 1e3
     # slab-pass roofline: one read of the slab plus the per-item FP64 partials
-    n_items = int(sum(max(1, -(-int(r) // 16384)) for r in X.rows))
+    n_items = int(sum(max(1, -(-int(r) // item_rows)) for r in X.rows))
     alg_bytes = X.N * J * 4 + n_items * (L * L + L * J + 1) * 8
     alg_flops = 2.0 * X.N * J * L * 2 + 2.0 * X.N * L * L
     sk_ms = sketch_ms_total / max(launches, 1)
@@ -562,6 +567,7 @@ def main():
                                "median 1500, rank-10 PARAFAC2 + 5% noise; R=10 L=20 L2=20 32 iterations",
                    "K": K, "J": J, "N": int(X.N), "rank": R, "sketch": L, "iterations": iters},
         "roofline": roofline,
+        "autotune": {"item_rows": item_rows, "slab_pass_ms_by_item_rows": tune_ms},
         "sketch_gemm": {"achieved_tflops": round(sketch_tf, 2),
                         "frac_of_fp32_mfma_peak": round(sketch_tf / FP32_MFMA_PEAK_TFLOPS, 4),
                         "note": "useful flops 4NJL+2NL^2; sketch in FP32, Gram and projection exact "

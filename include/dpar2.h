@@ -104,6 +104,10 @@ typedef struct {
                           pass over the slab with a per-slice sketch matrix (the
                           orthonormal right singular vectors of the previous B_k,
                           which spans X_k^T Q_k: the stabilised power iteration)   */
+  int32_t item_rows;   /* rows per work item of the slab pass (the unit that Alg. 4's
+                          longest-first scheduling hands to compute units): longer
+                          slices are cut into near-equal pieces; 0 = 16384, else
+                          64..65536 (dpar2_autotune_item_rows picks one)           */
 } dpar2_opts;
 
 /* Factor matrices (device, float64, row-major). */
@@ -212,6 +216,18 @@ dpar2_status dpar2_decompose_batch(int32_t n, const dpar2_tensor* X, const dpar2
                                    dpar2_stream_t stream);
 dpar2_status dpar2_batch_report_read(int32_t n, const dpar2_tensor* X, const dpar2_opts* o,
                                      const void* ws, dpar2_report* rep, dpar2_stream_t stream);
+
+/* Autotuner of the slab pass's work-item size for one tensor: times the
+ * slab pass (first stage only, as dpar2_compress runs it) for each
+ * candidate item_rows in cands (host array of n_cands values, each 0 or in
+ * 64..65536) and writes the fastest to *best (host) and, if times_ms is not
+ * NULL, the median of 3 timed launches of each (host, n_cands).  ws must be
+ * large enough for every candidate (dpar2_workspace_size with the candidate
+ * that cuts the most items).  Synchronises the stream; the workspace's
+ * decomposition state is overwritten. */
+dpar2_status dpar2_autotune_item_rows(const dpar2_tensor* X, const dpar2_opts* o, const float* omega1,
+                                      const int32_t* cands, int32_t n_cands, void* ws, size_t ws_bytes,
+                                      int32_t* best, float* times_ms, dpar2_stream_t stream);
 
 /* ---- Learned warm start ---------------------------------------------------
  * Not part of the paper: a set encoder proposes the starting H, V, W of the

@@ -43,7 +43,7 @@ class c_tensor(ctypes.Structure):
 class c_opts(ctypes.Structure):
     _fields_ = [("rank", ctypes.c_int32), ("sketch", ctypes.c_int32), ("sketch2", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("flags", ctypes.c_uint32),
-                ("power_iters", ctypes.c_int32)]
+                ("power_iters", ctypes.c_int32), ("item_rows", ctypes.c_int32)]
 
 
 class c_factors(ctypes.Structure):
@@ -66,7 +66,7 @@ EXPORTS = ["dpar2_workspace_size", "dpar2_compress", "dpar2_als_step", "dpar2_fi
            "dpar2_output_U", "dpar2_decompose", "dpar2_compressed_view", "dpar2_report_read",
            "dpar2_batch_workspace_size", "dpar2_decompose_batch", "dpar2_batch_report_read",
            "dpar2_warm_param_count", "dpar2_warm_features", "dpar2_warm_targets", "dpar2_warm_apply",
-           "dpar2_warm_forward", "dpar2_warm_backward", "dpar2_warm_adam",
+           "dpar2_warm_forward", "dpar2_warm_backward", "dpar2_warm_adam", "dpar2_autotune_item_rows",
            "dpar2_profile_enable", "dpar2_profile_read", "dpar2_status_string", "dpar2_last_error"]
 
 _lib = None
@@ -125,6 +125,9 @@ def load(path: str = LIB_PATH):
     lib.dpar2_warm_backward.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.dpar2_warm_adam.restype = i32
     lib.dpar2_warm_adam.argtypes = [i32, vp, vp, vp, vp, i32, f32, f32, f32, f32, f32, vp]
+    lib.dpar2_autotune_item_rows.restype = i32
+    lib.dpar2_autotune_item_rows.argtypes = [P(c_tensor), P(c_opts), vp, P(i32), i32, vp, ctypes.c_size_t,
+                                             P(i32), P(f32), vp]
     lib.dpar2_profile_enable.restype = ctypes.c_int32
     lib.dpar2_profile_enable.argtypes = [ctypes.c_int32]
     lib.dpar2_profile_read.restype = ctypes.c_int32
@@ -165,10 +168,11 @@ class Options:
     tol: float = -1.0
     power_iters: int = 0
     graph: bool = True      # False sets DPAR2_FLAG_NO_GRAPH
+    item_rows: int = 0      # 0: the library's default work-item size
 
     def c(self) -> c_opts:
         return c_opts(self.rank, self.sketch, self.sketch2, self.max_iter, float(self.tol),
-                      0 if self.graph else DPAR2_FLAG_NO_GRAPH, self.power_iters)
+                      0 if self.graph else DPAR2_FLAG_NO_GRAPH, self.power_iters, self.item_rows)
 
 
 class Tensor:
@@ -380,6 +384,19 @@ def batch_report_read(Xs, os_, ws, stream=None) -> list:
     r = (c_report * b.n)()
     _check(load().dpar2_batch_report_read(b.n, b.X, b.o, p, r, _stream(stream)))
     return [_report_dict(r[i]) for i in range(b.n)]
+
+
+def autotune_item_rows(X: Tensor, o: Options, omega1, ws, candidates=(2048, 4096, 8192, 16384), stream=None):
+    """(best item_rows, {candidate: median slab-pass ms}); ws must fit the
+    smallest candidate (see workspace_size with Options.item_rows)."""
+    lib = load()
+    p, n = _ws(ws)
+    c = (ctypes.c_int32 * len(candidates))(*candidates)
+    t = (ctypes.c_float * len(candidates))()
+    best = ctypes.c_int32()
+    _check(lib.dpar2_autotune_item_rows(ctypes.byref(X.c()), ctypes.byref(o.c()), _ptr(omega1), c, len(candidates),
+                                        p, n, ctypes.byref(best), t, _stream(stream)))
+    return int(best.value), {int(k): float(v) for k, v in zip(candidates, t)}
 
 
 # --- learned warm start ----------------------------------------------------

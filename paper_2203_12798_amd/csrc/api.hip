@@ -63,6 +63,8 @@ dpar2_status validate(const dpar2_tensor* X, const dpar2_opts* o) {
   if (X->dtype == DPAR2_FP8_E4M3 && !X->slice_scale)
     return fail(DPAR2_EINVAL, "fp8 slabs need slice_scale");
   if (o->flags & ~DPAR2_FLAG_NO_GRAPH) return fail(DPAR2_EINVAL, "unknown bits in opts.flags");
+  if (o->item_rows != 0 && (o->item_rows < 64 || o->item_rows > 65536))
+    return fail(DPAR2_EINVAL, "opts.item_rows must be 0 or in 64..65536");
   if (o->power_iters < 0 || o->power_iters > 4) return fail(DPAR2_EINVAL, "power_iters must be in [0, 4]");
   const int R = o->rank, L = o->sketch, L2 = o->sketch2;
   if (R < 1 || R > 32) return fail(DPAR2_ESHAPE, "rank must be in [1, 32]");
@@ -89,7 +91,7 @@ dpar2_status validate(const dpar2_tensor* X, const dpar2_opts* o) {
 bool same_group(const dpar2_tensor& a, const dpar2_opts& oa, const dpar2_tensor& b, const dpar2_opts& ob) {
   return a.J == b.J && a.dtype == b.dtype && oa.rank == ob.rank && oa.sketch == ob.sketch &&
          oa.sketch2 == ob.sketch2 && oa.power_iters == ob.power_iters && oa.max_iter == ob.max_iter &&
-         oa.flags == ob.flags;
+         oa.flags == ob.flags && oa.item_rows == ob.item_rows;
 }
 
 dpar2_status make_group(int32_t n, const dpar2_tensor* X, const dpar2_opts* o, Group* g) {
@@ -120,24 +122,27 @@ dpar2_status make_group(int32_t n, const dpar2_tensor* X, const dpar2_opts* o, G
   return DPAR2_OK;
 }
 
-// Alg. 4 on the GPU: slices longer than MAX_CHUNK_ROWS are cut into near-equal
+// Alg. 4 on the GPU: slices longer than the item size (opts.item_rows, default
+// MAX_CHUNK_ROWS) are cut into near-equal
 // row ranges; all items are sorted by length, longest first (stable), and
 // block b of the slab pass takes item b.  The hardware dispatcher starts each
 // next block on the first compute unit that frees up, i.e. greedy list
 // scheduling of the longest remaining item on the least-loaded unit.
-int64_t items_of(int64_t rows) { return std::max<int64_t>(1, (rows + MAX_CHUNK_ROWS - 1) / MAX_CHUNK_ROWS); }
+int64_t item_cap(const Group& g) { return g.o[0].item_rows > 0 ? g.o[0].item_rows : MAX_CHUNK_ROWS; }
+int64_t items_of(int64_t rows, int64_t cap) { return std::max<int64_t>(1, (rows + cap - 1) / cap); }
 
 void build_schedule(const Group& g, Schedule* s) {
   const int nt = g.nt;
   const int64_t K = g.k0[(size_t)nt];
   const int64_t J = g.X[0].J;
   const int R = g.o[0].rank;
+  const int64_t cap = item_cap(g);
   std::vector<Item> raw;
   raw.reserve((size_t)K);
   for (int t = 0; t < nt; ++t) {
     const int64_t* off = g.X[t].row_offsets_host;
     for (int64_t k = 0; k < g.X[t].K; ++k) {
-      const int64_t n = off[k + 1] - off[k], nc = items_of(n);
+      const int64_t n = off[k + 1] - off[k], nc = items_of(n, cap);
       for (int64_t c = 0; c < nc; ++c) {
         Item it;
         it.row0 = off[k] + n * c / nc;
@@ -210,7 +215,7 @@ Layout make_layout(const Group& g) {
     const int64_t* off = g.X[t].row_offsets_host;
     const int64_t Kt = g.X[t].K;
     y.N += off[Kt];
-    for (int64_t k = 0; k < Kt; ++k) y.n_items += items_of(off[k + 1] - off[k]);
+    for (int64_t k = 0; k < Kt; ++k) y.n_items += items_of(off[k + 1] - off[k], item_cap(g));
     y.n2 += (Kt * y.R + STAGE2_CHUNK - 1) / STAGE2_CHUNK;
     y.nblk += (int)((Kt + gpb - 1) / gpb);
     y.nblk0 += (int)((std::max<int64_t>(Kt, y.J) + gpb - 1) / gpb);
@@ -446,7 +451,7 @@ __global__ __launch_bounds__(256) void k_prep(const TDesc* __restrict__ td, int 
 // (J, R and every tensor's row offsets) changed since the last compress on
 // this workspace.
 void stage_tables(const Group& g, const Layout& y, Staging& sg) {
-  std::vector<int64_t> key = {g.nt, y.J, y.R};
+  std::vector<int64_t> key = {g.nt, y.J, y.R, item_cap(g)};
   for (int t = 0; t < g.nt; ++t) {
     key.push_back(g.X[t].K);
     key.insert(key.end(), g.X[t].row_offsets_host, g.X[t].row_offsets_host + g.X[t].K + 1);
@@ -958,6 +963,74 @@ dpar2_status dpar2_warm_adam(int32_t rank, float* theta, const float* grad, floa
   hipError_t e = launch_warm_adam(rank, theta, grad, m, v, step, lr, beta1, beta2, eps, grad_scale,
                                   reinterpret_cast<hipStream_t>(stream));
   return e == hipSuccess ? DPAR2_OK : hip_fail(e, "warm adam");
+}
+
+dpar2_status dpar2_autotune_item_rows(const dpar2_tensor* X, const dpar2_opts* o, const float* omega1,
+                                      const int32_t* cands, int32_t n_cands, void* ws, size_t ws_bytes,
+                                      int32_t* best, float* times_ms, dpar2_stream_t stream) {
+  if (!o || !cands || n_cands < 1 || !best || !omega1) return fail(DPAR2_EINVAL, "NULL argument or no candidates");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e;
+  if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+  if ((e = hipEventCreate(&e1)) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(e, "hipEventCreate");
+  }
+  dpar2_status st = DPAR2_OK;
+  float best_ms = 0.f;
+  for (int32_t c = 0; c < n_cands && st == DPAR2_OK; ++c) {
+    dpar2_opts oc = *o;
+    oc.item_rows = cands[c];
+    oc.power_iters = 0;
+    Group g;
+    if ((st = make_group(1, X, &oc, &g)) != DPAR2_OK) break;
+    const Layout y = make_layout(g);
+    if ((st = check_ws(y, ws, ws_bytes)) != DPAR2_OK) break;
+    // the first stage's set-up and slab pass, as in group_compress
+    const std::vector<TDesc> td = descriptors(g, &omega1, &omega1, nullptr, nullptr);
+    {
+      std::lock_guard<std::mutex> lk(g_stage_mu);
+      Staging& sg = g_stage[w];
+      stage_tables(g, y, sg);
+      std::memcpy(sg.image.data(), td.data(), sizeof(TDesc) * td.size());
+      if ((st = upload_locked(sg, w, sg.image.data(), sg.image.size(), y.tdesc, s)) != DPAR2_OK) break;
+    }
+    hipLaunchKernelGGL(k_prep, dim3(1), dim3(256), 0, s, reinterpret_cast<const TDesc*>(w + y.tdesc),
+                       (int)(y.J * y.L), reinterpret_cast<Ctl*>(w + y.ctl), reinterpret_cast<float*>(w + y.om1));
+    const int esize = X->dtype == DPAR2_F32 ? 4 : (X->dtype == DPAR2_BF16 ? 2 : 1);
+    SlabArgs sa;
+    std::memset(&sa, 0, sizeof(sa));
+    sa.td = reinterpret_cast<const TDesc*>(w + y.tdesc);
+    sa.J = (int)y.J;
+    sa.L = y.L;
+    sa.R = y.R;
+    sa.items = reinterpret_cast<const Item*>(w + y.items);
+    sa.partG = reinterpret_cast<double*>(w + y.partG);
+    sa.partP = reinterpret_cast<double*>(w + y.partP);
+    sa.partS = reinterpret_cast<double*>(w + y.partS);
+    sa.ybuf = reinterpret_cast<float*>(w + y.ybuf);
+    const bool vec = (y.J % 4 == 0) && ((uintptr_t)X->slab % (4 * esize) == 0);
+    float t[4];
+    for (int r = 0; r < 4 && st == DPAR2_OK; ++r) {   // one warm-up launch, three timed
+      if ((e = hipEventRecord(e0, s)) != hipSuccess) st = hip_fail(e, "hipEventRecord");
+      else if ((e = launch_slab(sa, X->dtype, y.n_items, vec, false, s)) != hipSuccess) st = hip_fail(e, "slab pass");
+      else if ((e = hipEventRecord(e1, s)) != hipSuccess) st = hip_fail(e, "hipEventRecord");
+      else if ((e = hipEventSynchronize(e1)) != hipSuccess) st = hip_fail(e, "hipEventSynchronize");
+      else if ((e = hipEventElapsedTime(&t[r], e0, e1)) != hipSuccess) st = hip_fail(e, "hipEventElapsedTime");
+    }
+    if (st != DPAR2_OK) break;
+    std::sort(t + 1, t + 4);
+    if (times_ms) times_ms[c] = t[2];
+    if (c == 0 || t[2] < best_ms) {
+      best_ms = t[2];
+      *best = cands[c];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
 }
 
 dpar2_status dpar2_profile_enable(int32_t on) {

@@ -178,3 +178,25 @@ def test_batch_arguments_validated_on_host():
     assert lib.dpar2_last_error().startswith(b"tensor 1")
     # unknown flag bits are rejected
     assert size([ta], [binding.c_opts(2, 3, 3, 5, -1.0, 0x80, 0)]) == 0
+
+
+def test_item_rows_option():
+    """opts.item_rows: 0 (default size) or 64..65536; smaller items mean more
+    work items (more partials in the workspace); it is part of the group key."""
+    binding, lib = _lib()
+    off = np.array([0, 5000, 5100, 12000], dtype=np.int64)
+    h = off.ctypes.data_as(ctypes.c_void_p).value
+    t = binding.c_tensor(3, 8, 0x1000, h, 0x2000, binding.DPAR2_F32, None)
+    size = lambda ir: lib.dpar2_workspace_size(ctypes.byref(t), ctypes.byref(binding.c_opts(2, 3, 3, 5, -1.0, 0, 0, ir)))
+    assert size(0) > 0 and size(64) > size(1024) > size(0) == size(16384)
+    for bad in (1, 63, 65537, -5):
+        assert size(bad) == 0
+        assert b"item_rows" in lib.dpar2_last_error()
+    T = binding.c_tensor * 2
+    O = binding.c_opts * 2
+    one = lib.dpar2_batch_workspace_size(2, T(t, t), O(binding.c_opts(2, 3, 3, 5, -1.0, 0, 0, 0),
+                                                        binding.c_opts(2, 3, 3, 5, -1.0, 0, 0, 0)))
+    two = lib.dpar2_batch_workspace_size(2, T(t, t), O(binding.c_opts(2, 3, 3, 5, -1.0, 0, 0, 0),
+                                                        binding.c_opts(2, 3, 3, 5, -1.0, 0, 0, 512)))
+    al = lambda n: (n + 255) // 256 * 256
+    assert two == al(size(0)) + al(size(512)) and one < two
