@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batching form (256 independent tensors of mixed J, R, K, I_k)")
     ap.add_argument("--batch-tensors", type=int, default=256)
+    ap.add_argument("--item-rows", type=int, default=0,
+                    help="fixed work-item size of the slab pass (0: choose it with the autotuner)")
     ap.add_argument("--no-wide", action="store_true",
                     help="skip the precision form at J = 2049 (K = 8000, spectrogram-like, R = 10 and 20)")
     ap.add_argument("--wide-k", type=int, default=8000)
@@ -67,16 +69,19 @@ def write_traffic(fetch_csv, write_csv):
     import csv
 
     def per_dispatch(path, counter):
-        slab, copy = [], []
+        # the slab pass of the decomposition is the last one launched (the
+        # autotuner's launches come first); the copy is the largest copy
+        slab, copy = {}, []
         for r in csv.DictReader(open(path)):
             if r["Counter_Name"] != counter:
                 continue
             v = float(r["Counter_Value"]) * 1024.0
             if SLAB_KERNEL in r["Kernel_Name"]:
-                slab.append(v)
+                d = int(r["Dispatch_Id"])
+                slab[d] = slab.get(d, 0.0) + v
             elif "copyBuffer" in r["Kernel_Name"]:
                 copy.append(v)
-        return sum(slab) / len(slab), max(copy)
+        return slab[max(slab)], max(copy)
 
     f_slab, f_copy = per_dispatch(fetch_csv, "FETCH_SIZE")
     w_slab, w_copy = per_dispatch(write_csv, "WRITE_SIZE")
@@ -449,8 +454,11 @@ def main():
     cands = (2048, 4096, 8192, 16384)
     ws = d.alloc_workspace(T, d.Options(rank=R, sketch=L, sketch2=L2, max_iter=iters, item_rows=min(cands)))
     o1 = torch.from_numpy(om1).cuda()
-    item_rows, tune_ms = binding.autotune_item_rows(T, d.Options(rank=R, sketch=L, sketch2=L2, max_iter=iters),
-                                                    o1, ws, candidates=cands)
+    if args.item_rows:
+        item_rows, tune_ms = args.item_rows, None
+    else:
+        item_rows, tune_ms = binding.autotune_item_rows(T, d.Options(rank=R, sketch=L, sketch2=L2, max_iter=iters),
+                                                        o1, ws, candidates=cands)
     print(f"[bench] autotune item_rows: {tune_ms} -> {item_rows}", file=sys.stderr, flush=True)
     o = d.Options(rank=R, sketch=L, sketch2=L2, max_iter=iters, item_rows=item_rows)
     o2 = torch.from_numpy(om2).cuda()
