@@ -12,7 +12,7 @@
 // Exact integer accumulation of the Gram and projection: per 64-row tile,
 // every column of Y and of X is scaled by a power of two so that its largest
 // entry is below 2^22 and written as three balanced base-256 digits
-// (q = d0 2^16 + d1 2^8 + d2, |d| <= 128); all nine digit products are
+// (q = d0 2^16 + d1 2^8 + d2, -128 <= d <= 127); all nine digit products are
 // summed exactly in int32 (one 16x16x64 instruction per digit pair covers the
 // whole tile), combined exactly in FP64 and rescaled.  The only rounding is
 // the 22-bit fixed-point representation of each column within its tile (at
@@ -117,12 +117,13 @@ __device__ __forceinline__ int col_exp(float m) {
   return e;
 }
 
-// round(x 2^(22 - e)) for |x| < 2^e: the scaled value is exact in FP32 and
-// |x 2^(22-e)| < 2^22, so adding 1.5 * 2^23 leaves the nearest integer (ties
-// to even) in the low mantissa bits.
-__device__ __forceinline__ int q22(float x, int e) {
+// round(x 2^(22 - e)) + 0x808080 for |x| < 2^e: the scaled value is exact in
+// FP32 and |x 2^(22-e)| <= 2^22, so adding 1.5 * 2^23 leaves the nearest
+// integer (ties to even) in the low mantissa bits; the bias 0x808080 is folded
+// into the same subtraction (see digits4).
+__device__ __forceinline__ int q22b(float x, int e) {
   const float m = ldexpf(x, 22 - e) + 12582912.0f;
-  return __float_as_int(m) - 0x4B400000;
+  return __float_as_int(m) - (0x4B400000 - 0x808080);
 }
 
 // byte k of each of w0..w3 packed into one word (w0 in the low byte)
@@ -135,20 +136,14 @@ __device__ __forceinline__ uint32_t bytes_k(uint32_t w0, uint32_t w1, uint32_t w
 }
 
 // Balanced base-256 digits of four values |q| <= 2^22, q = d0 2^16 + d1 2^8
-// + d2 with |d| <= 128, packed as the byte planes p0 (d0), p1, p2.  With
-// r = q - d2 (a multiple of 256) and r2 = r - 256 d1 (a multiple of 2^16),
-// d2, d1 and d0 are the signed bytes 0, 1 and 2 of q, r and r2.
-__device__ __forceinline__ void digits4(const int (&q)[4], uint32_t& p0, uint32_t& p1, uint32_t& p2) {
-  uint32_t r[4], r2[4];
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int rv = q[v] - __builtin_amdgcn_sbfe(q[v], 0, 8);
-    r[v] = (uint32_t)rv;
-    r2[v] = (uint32_t)(rv - (__builtin_amdgcn_sbfe(rv, 8, 8) << 8));
-  }
-  p2 = bytes_k<0>((uint32_t)q[0], (uint32_t)q[1], (uint32_t)q[2], (uint32_t)q[3]);
-  p1 = bytes_k<1>(r[0], r[1], r[2], r[3]);
-  p0 = bytes_k<2>(r2[0], r2[1], r2[2], r2[3]);
+// + d2 with -128 <= d <= 127 (the representation is unique), packed as the
+// signed byte planes p0 (d0), p1, p2.  Given u = q + 0x808080 (from q22b),
+// 0 <= u < 2^24 and the unsigned bytes of u are the digits plus 128, so each
+// plane is a byte of u with its top bit flipped.
+__device__ __forceinline__ void digits4(const int (&u)[4], uint32_t& p0, uint32_t& p1, uint32_t& p2) {
+  p2 = bytes_k<0>((uint32_t)u[0], (uint32_t)u[1], (uint32_t)u[2], (uint32_t)u[3]) ^ 0x80808080u;
+  p1 = bytes_k<1>((uint32_t)u[0], (uint32_t)u[1], (uint32_t)u[2], (uint32_t)u[3]) ^ 0x80808080u;
+  p0 = bytes_k<2>((uint32_t)u[0], (uint32_t)u[1], (uint32_t)u[2], (uint32_t)u[3]) ^ 0x80808080u;
 }
 
 template <int LT, int JT, bool VEC, int TIN, bool UOUT>
@@ -323,12 +318,22 @@ __global__ __launch_bounds__(256) void k_sketch_q(SlabArgs a) {
       m = fmaxf(m, __shfl_xor(m, 32, 64));
       if (lk == 0) sYm[w * LP + lt * 16 + lr] = m;
     }
-    for (int task = tid; task < JP * 4; task += 256) {
-      const int j = task % JP, q = task / JP;
-      float m = 0.f;
+    // each thread keeps the 16 values of its column quarters for the digits
+    constexpr int NXT = (JP * 4 + 255) / 256;
+    float xv[NXT][16];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) m = fmaxf(m, fabsf(sX[(16 * q + r) * XS + j]));
-      sXm[q * JP + j] = m;
+    for (int k = 0; k < NXT; ++k) {
+      const int task = tid + 256 * k;
+      if (task < JP * 4) {
+        const int j = task % JP, q = task / JP;
+        float m = 0.f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          xv[k][r] = sX[(16 * q + r) * XS + j];
+          m = fmaxf(m, fabsf(xv[k][r]));
+        }
+        sXm[q * JP + j] = m;
+      }
     }
     __syncthreads();
     // digits of Y (transposed planes: [digit][column][row byte])
@@ -339,7 +344,7 @@ __global__ __launch_bounds__(256) void k_sketch_q(SlabArgs a) {
       const int e = col_exp(m);
       int q[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) q[v] = q22(acc[lt][v], e);
+      for (int v = 0; v < 4; ++v) q[v] = q22b(acc[lt][v], e);
       uint32_t p[3];
       digits4(q, p[0], p[1], p[2]);
 #pragma unroll
@@ -347,22 +352,27 @@ __global__ __launch_bounds__(256) void k_sketch_q(SlabArgs a) {
       if (w == 0 && lk == 0) sYe[col] = e;
     }
     // digits of X
-    for (int task = tid; task < JP * 4; task += 256) {
-      const int j = task % JP, q = task / JP;
-      const float m = fmaxf(fmaxf(sXm[j], sXm[JP + j]), fmaxf(sXm[2 * JP + j], sXm[3 * JP + j]));
-      const int e = col_exp(m);
-      uint32_t pk[3][4];
 #pragma unroll
-      for (int r4 = 0; r4 < 4; ++r4) {
-        int qv[4];
+    for (int k = 0; k < NXT; ++k) {
+      const int task = tid + 256 * k;
+      if (task < JP * 4) {
+        const int j = task % JP, q = task / JP;
+        const float m = fmaxf(fmaxf(sXm[j], sXm[JP + j]), fmaxf(sXm[2 * JP + j], sXm[3 * JP + j]));
+        const int e = col_exp(m);
+        uint32_t pk[3][4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) qv[v] = q22(sX[(16 * q + 4 * r4 + v) * XS + j], e);
-        digits4(qv, pk[0][r4], pk[1][r4], pk[2][r4]);
+        for (int r4 = 0; r4 < 4; ++r4) {
+          int qv[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) qv[v] = q22b(xv[k][4 * r4 + v], e);
+          digits4(qv, pk[0][r4], pk[1][r4], pk[2][r4]);
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+          *reinterpret_cast<uint4*>(&sXq[(a * JP + j) * QW + 4 * q]) =
+              make_uint4(pk[a][0], pk[a][1], pk[a][2], pk[a][3]);
+        if (q == 0) sXe[j] = e;
       }
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-        *reinterpret_cast<uint4*>(&sXq[(a * JP + j) * QW + 4 * q]) = make_uint4(pk[a][0], pk[a][1], pk[a][2], pk[a][3]);
-      if (q == 0) sXe[j] = e;
     }
     __syncthreads();
 
