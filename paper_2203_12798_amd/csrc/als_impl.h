@@ -28,7 +28,7 @@
 
 namespace dpar2 {
 
-constexpr int EPI_THREADS = 1024;
+constexpr int EPI_THREADS = 256;
 
 struct AlsArgs {
   int nt, J;
