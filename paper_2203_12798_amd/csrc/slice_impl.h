@@ -32,10 +32,14 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
   constexpr int RM = SC<L>::RM, LH = SC<L>::LH, LD = SC<L>::LD, CW = SC<L>::CW, LL = L * L;
   __shared__ double Gs[L * LD];    // G, then its Cholesky factor (upper triangle)
   __shared__ double Ss[L * LD];    // S' = P P^T; then Phi
-  __shared__ double Ws[L * LD];    // whitening Wh
-  __shared__ double Xs[L * LD];    // S' Wh; then sorted eigenvectors U~
   constexpr int CP = CW + 1;        // padded chunk row (conflict-free column reads)
-  __shared__ double Pc[L * CP];    // chunk of P
+  // Wh and S' Wh / U~ live only between the P P^T pass and Phi; the chunks of
+  // P are streamed only outside that span, so they share the space
+  constexpr int NWX = (2 * L * LD > L * CP) ? 2 * L * LD : L * CP;
+  __shared__ double WX[NWX];
+  double* const Ws = WX;            // whitening Wh
+  double* const Xs = WX + L * LD;   // S' Wh; then sorted eigenvectors U~
+  double* const Pc = WX;            // chunk of P
   __shared__ double Mc[L * CP];    // chunk of C_k B_k (rows r < R)
   __shared__ double sgn[L], row[L], rinv[L], sv[L];
 
