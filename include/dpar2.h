@@ -203,7 +203,9 @@ dpar2_status dpar2_report_read(const dpar2_tensor* X, const dpar2_opts* o, const
  * order of first appearance), and runs each group through one set of
  * launches: one slab pass over the work items of all its tensors, one launch
  * per second-stage step and per iteration kernel, each tensor stopping by its
- * own tol.  omega1[t] (J_t x L_t) and omega2[t] ((K_t R_t) x L2_t) are host
+ * own tol; the groups run side by side on library-owned streams (default
+ * priority) forked from and joined back into `stream` with events, so the
+ * call stays ordered on `stream`.  omega1[t] (J_t x L_t) and omega2[t] ((K_t R_t) x L2_t) are host
  * arrays of device pointers; f[t] holds each tensor's initial factors and
  * receives the result.  Each tensor's result is bit-for-bit the result of
  * dpar2_decompose on that tensor alone (no U output here).  Workspace from

@@ -574,6 +574,34 @@ dpar2_status group_factors(const Group& g, const dpar2_factors* f, double* const
   return upload_descriptors(w, y, descriptors(g, nullptr, nullptr, f, trace), s);
 }
 
+// Streams on which the groups of a batch run side by side (their kernels are
+// small and latency-bound), forked from and joined back into the caller's
+// stream with events; created once, default priority.
+constexpr int BATCH_STREAMS = 8;
+struct StreamPool {
+  std::mutex mu;
+  bool ready = false;
+  hipStream_t s[BATCH_STREAMS] = {};
+  hipEvent_t done[BATCH_STREAMS] = {};
+  hipEvent_t fork = nullptr;
+};
+StreamPool g_spool;
+
+dpar2_status pool_ready_locked() {
+  if (g_spool.ready) return DPAR2_OK;
+  hipError_t e;
+  if ((e = hipEventCreateWithFlags(&g_spool.fork, hipEventDisableTiming)) != hipSuccess)
+    return hip_fail(e, "hipEventCreate");
+  for (int i = 0; i < BATCH_STREAMS; ++i) {
+    if ((e = hipStreamCreateWithFlags(&g_spool.s[i], hipStreamNonBlocking)) != hipSuccess)
+      return hip_fail(e, "hipStreamCreate");
+    if ((e = hipEventCreateWithFlags(&g_spool.done[i], hipEventDisableTiming)) != hipSuccess)
+      return hip_fail(e, "hipEventCreate");
+  }
+  g_spool.ready = true;
+  return DPAR2_OK;
+}
+
 hipError_t enqueue_als(int32_t n_steps, char* w, const Layout& y, hipStream_t s) {
   hipError_t e = launch_als_begin(y, w, s);
   for (int32_t i = 0; e == hipSuccess && i < n_steps; ++i) e = launch_als_iteration(y, w, s);
@@ -816,8 +844,7 @@ dpar2_status dpar2_decompose_batch(int32_t n, const dpar2_tensor* X, const dpar2
   if (ws_bytes < b.total)
     return fail(DPAR2_EWORKSPACE, "workspace too small: need " + std::to_string(b.total) + " bytes");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  // each group in turn, all on the caller's stream
-  for (size_t gi = 0; gi < b.groups.size(); ++gi) {
+  auto run_group = [&](size_t gi, hipStream_t gs) -> dpar2_status {
     const Group& g = b.groups[gi];
     const Layout& y = b.lay[gi];
     char* w = static_cast<char*>(ws) + b.base[gi];
@@ -828,12 +855,30 @@ dpar2_status dpar2_decompose_batch(int32_t n, const dpar2_tensor* X, const dpar2
       o2.push_back(omega2[t]);
       fg.push_back(f[t]);
     }
-    if ((st = group_compress(g, o1.data(), o2.data(), fg.data(), w, y, s)) != DPAR2_OK) return st;
-    if ((st = group_als(g, g.o[0].max_iter, w, y, s)) != DPAR2_OK) return st;
-    hipError_t e = launch_fitness(y, w, nullptr, s);
-    if (e != hipSuccess) return hip_fail(e, "fitness");
+    dpar2_status r = group_compress(g, o1.data(), o2.data(), fg.data(), w, y, gs);
+    if (r == DPAR2_OK) r = group_als(g, g.o[0].max_iter, w, y, gs);
+    if (r == DPAR2_OK) {
+      const hipError_t e = launch_fitness(y, w, nullptr, gs);
+      if (e != hipSuccess) r = hip_fail(e, "fitness");
+    }
+    return r;
+  };
+  if (b.groups.size() == 1) return run_group(0, s);
+  // several groups: each on a stream of the pool, forked from and joined
+  // back into the caller's stream
+  std::lock_guard<std::mutex> lk(g_spool.mu);
+  if ((st = pool_ready_locked()) != DPAR2_OK) return st;
+  const int used = (int)std::min<size_t>(b.groups.size(), BATCH_STREAMS);
+  hipError_t e;
+  if ((e = hipEventRecord(g_spool.fork, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+  for (int i = 0; i < used; ++i)
+    if ((e = hipStreamWaitEvent(g_spool.s[i], g_spool.fork, 0)) != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+  for (size_t gi = 0; gi < b.groups.size() && st == DPAR2_OK; ++gi) st = run_group(gi, g_spool.s[gi % BATCH_STREAMS]);
+  for (int i = 0; i < used; ++i) {
+    if ((e = hipEventRecord(g_spool.done[i], g_spool.s[i])) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    if ((e = hipStreamWaitEvent(s, g_spool.done[i], 0)) != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
   }
-  return DPAR2_OK;
+  return st;
 }
 
 dpar2_status dpar2_batch_report_read(int32_t n, const dpar2_tensor* X, const dpar2_opts* o, const void* ws,
