@@ -20,6 +20,34 @@
 
 namespace dpar2 {
 
+// D(nrow x 32) += A^T(nrow x L) B(L x 32) on the FP64 matrix cores for one
+// chunk of 32 columns, A from the L x LD matrix `a` (column r of a = row r of
+// the product), B from the chunk `b` (row stride CP); acc[tr][tj] is the
+// 16 x 16 tile (rows 16 tr, columns 16 tj), lane l holding rows
+// f64_row(l, v) and column l % 16.  All 64 lanes take part.
+template <int L, int LD, int CP>
+__device__ __forceinline__ void chunk_atb(const double* a, const double* b, int nrow, v4d (&acc)[2][2],
+                                          int lane) {
+  const int i16 = lane & 15, k4 = lane >> 4;
+#pragma unroll
+  for (int kk = 0; kk < (L + 3) / 4; ++kk) {
+    const int k = 4 * kk + k4;
+    double av[2], bv[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int r = 16 * t + i16;
+      av[t] = (k < L && r < nrow) ? a[k * LD + r] : 0.0;
+      bv[t] = (k < L) ? b[k * CP + 16 * t + i16] : 0.0;
+    }
+#pragma unroll
+    for (int tr = 0; tr < 2; ++tr) {
+      if (16 * tr >= nrow) continue;   // wave-uniform
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) acc[tr][tj] = mfma_f64(av[tr], bv[tj], acc[tr][tj]);
+    }
+  }
+}
+
 template <int L>
 __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int32_t* __restrict__ slice_ptr,
                                                   const int32_t* __restrict__ slice_list,
@@ -80,9 +108,6 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
   }
 
   // S' = P P^T, P streamed through LDS in chunks of CW columns
-  double sp[LH];
-#pragma unroll
-  for (int ii = 0; ii < LH; ++ii) sp[ii] = 0.0;
   // chunk jc of P into Pc; the loads of one item are issued together
   auto load_chunk = [&](int jc) {
     constexpr int NE = (L * CW + 63) / 64;
@@ -105,25 +130,44 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
       if (e < L * CW) Pc[(e / CW) * CP + e % CW] = pv[u];
     }
   };
-  for (int jc = 0; jc < J; jc += CW) {
-    load_chunk(jc);
-    __syncthreads();
-    if (cv) {
-      for (int jj = 0; jj < CW; ++jj) {
-        const double pc = Pc[c * CP + jj];
+  // S' = sum over chunks of P_c P_c^T on the FP64 matrix cores (16 x 16 tiles,
+  // the upper ones; P's rows as both operands)
+  v4d sacc[2][2];
 #pragma unroll
-        for (int ii = 0; ii < LH; ++ii) {
-          const int a = h * LH + ii;
-          if (a < L) sp[ii] = fma(Pc[a * CP + jj], pc, sp[ii]);
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y2 = 0; y2 < 2; ++y2) sacc[x][y2] = v4d{0.0, 0.0, 0.0, 0.0};
+  {
+    const int i16 = lane & 15, k4 = lane >> 4;
+    for (int jc = 0; jc < J; jc += CW) {
+      load_chunk(jc);
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < CW / 4; ++kk) {
+        const int j = 4 * kk + k4;
+        double pv2[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) pv2[t] = (16 * t + i16 < L) ? Pc[(16 * t + i16) * CP + j] : 0.0;
+        sacc[0][0] = mfma_f64(pv2[0], pv2[0], sacc[0][0]);
+        if (L > 16) {
+          sacc[0][1] = mfma_f64(pv2[0], pv2[1], sacc[0][1]);
+          sacc[1][1] = mfma_f64(pv2[1], pv2[1], sacc[1][1]);
         }
       }
+      __syncthreads();
     }
-    __syncthreads();
-  }
 #pragma unroll
-  for (int ii = 0; ii < LH; ++ii) {
-    const int a = h * LH + ii;
-    if (cv && a < L) Ss[a * LD + c] = sp[ii];
+    for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+      for (int tj = tr; tj < 2; ++tj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int a = 16 * tr + f64_row(lane, v), b = 16 * tj + i16;
+          if (a < L && b < L) {
+            Ss[a * LD + b] = sacc[tr][tj][v];
+            if (tr != tj) Ss[b * LD + a] = sacc[tr][tj][v];
+          }
+        }
   }
   __syncthreads();
 
@@ -265,15 +309,21 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
     for (int jc = 0; jc < J; jc += CW) {
       load_chunk(jc);
       __syncthreads();
-      for (int e = lane; e < L * CW; e += 64) {
-        const int jj = e / L, l = e % L;
-        double m = 0.0;
-        if (jc + jj < J) {
+      v4d oacc[2][2];
 #pragma unroll
-          for (int a = 0; a < L; ++a) m = fma(Ss[a * LD + l], Pc[a * CP + jj], m);
-          On[(size_t)(jc + jj) * L + l] = (float)(m * sv[l]);
-        }
-      }
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y2 = 0; y2 < 2; ++y2) oacc[x][y2] = v4d{0.0, 0.0, 0.0, 0.0};
+      chunk_atb<L, LD, CP>(Ss, Pc, L, oacc, lane);
+#pragma unroll
+      for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int l = 16 * tr + f64_row(lane, v), jj = 16 * tj + (lane & 15);
+            if (l < L && jc + jj < J) On[(size_t)(jc + jj) * L + l] = (float)(oacc[tr][tj][v] * sv[l]);
+          }
       __syncthreads();
     }
   }
@@ -286,14 +336,25 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
     for (int jc = 0; jc < J; jc += CW) {
       load_chunk(jc);
       __syncthreads();
-      for (int e = lane; e < R * CW; e += 64) {
-        const int r = e / CW, jj = e % CW;
-        double m = 0.0;
+      v4d macc[2][2];
 #pragma unroll
-        for (int a = 0; a < L; ++a) m = fma(Ss[a * LD + r], Pc[a * CP + jj], m);
-        if (pass == 0) Mc[r * CP + jj] = m;
-        else if (jc + jj < J) Mk[(size_t)r * J + jc + jj] = sgn[r] * m;
-      }
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y2 = 0; y2 < 2; ++y2) macc[x][y2] = v4d{0.0, 0.0, 0.0, 0.0};
+      chunk_atb<L, LD, CP>(Ss, Pc, R, macc, lane);
+#pragma unroll
+      for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = 16 * tr + f64_row(lane, v), jj = 16 * tj + (lane & 15);
+            if (r < R) {
+              const double m = macc[tr][tj][v];
+              if (pass == 0) Mc[r * CP + jj] = m;
+              else if (jc + jj < J) Mk[(size_t)r * J + jc + jj] = sgn[r] * m;
+            }
+          }
       __syncthreads();
       if (pass == 0 && lane < R) {
         const int nj = (J - jc < CW) ? J - jc : CW;
