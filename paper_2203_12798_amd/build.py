@@ -15,6 +15,12 @@ def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
 
+# The narrow slab pass reads its int8 matrix-core results straight into the
+# FP64 combination: accumulators in ordinary vector registers save one
+# register move per result element and lowers the register count.
+EXTRA = {f"k_slab_{t}.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"] for t in ("f32", "bf16", "fp8")}
+
+
 def build(verbose: bool = False, jobs: int = 8) -> str:
     """Compile every csrc/*.hip to an object (in parallel), then link the
     shared library.  Always recompiles."""
@@ -30,7 +36,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     for src in sources():
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
         objs.append(obj)
-        cmd = [hipcc, *flags, "-c", src, "-o", obj]
+        cmd = [hipcc, *flags, *EXTRA.get(os.path.basename(src), []), "-c", src, "-o", obj]
         procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
         while len([p for _, p in procs if p.poll() is None]) >= jobs:
             procs[[i for i, (_, p) in enumerate(procs) if p.poll() is None][0]][1].wait()

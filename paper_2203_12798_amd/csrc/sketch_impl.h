@@ -117,12 +117,23 @@ __device__ __forceinline__ int col_exp(float m) {
   return e;
 }
 
-// round(x 2^(22 - e)) + 0x808080 for |x| < 2^e: the scaled value is exact in
-// FP32 and |x 2^(22-e)| <= 2^22, so adding 1.5 * 2^23 leaves the nearest
-// integer (ties to even) in the low mantissa bits; the bias 0x808080 is folded
-// into the same subtraction (see digits4).
-__device__ __forceinline__ int q22b(float x, int e) {
-  const float m = ldexpf(x, 22 - e) + 12582912.0f;
+// Column scale for the 22-bit fixed point: sc = 2^(22 - e) for |x| < 2^e.
+// For e < -104 the power of two is beyond the FP32 range; the column's
+// values are then multiplied by 2^64 first (exact: they are below 2^-104) and
+// the scale lowered by the same amount.  Returns true when that pre-scale
+// applies.
+__device__ __forceinline__ bool col_scale(int e, float& sc) {
+  const bool tiny = e < -104;
+  sc = __int_as_float((127 + 22 - e - (tiny ? 64 : 0)) << 23);
+  return tiny;
+}
+
+// round(x sc) + 0x808080 with sc from col_scale: x sc is exact (a power-of-two
+// scaling within range) and |x sc| <= 2^22, so one fused multiply-add of
+// 1.5 * 2^23 leaves the nearest integer (ties to even) in the low mantissa
+// bits; the bias 0x808080 is folded into the same subtraction (see digits4).
+__device__ __forceinline__ int q22b(float x, float sc) {
+  const float m = fmaf(x, sc, 12582912.0f);
   return __float_as_int(m) - (0x4B400000 - 0x808080);
 }
 
@@ -218,7 +229,18 @@ __global__ __launch_bounds__(256) void k_sketch_q(SlabArgs a) {
   auto load_tile = [&](int t) {
     const E* base = slab + (size_t)(it.row0 + (int64_t)t * TM) * J;
     const int64_t rem = nrows - (int64_t)t * TM;
-    const int nvalid = rem < TM ? (int)rem : TM;
+    if (rem >= TM) {
+      // full tile: every row is in range; slots past the tile (srow = TM)
+      // load its first element and are never stored
+#pragma unroll
+      for (int s = 0; s < NV; ++s) {
+        const size_t off = srow[s] < TM ? (size_t)srow[s] * J + scol[s] : 0;
+        if constexpr (VEC) buf[s] = *reinterpret_cast<const slot_t*>(base + off);
+        else buf[s] = base[off];
+      }
+      return;
+    }
+    const int nvalid = (int)rem;
 #pragma unroll
     for (int s = 0; s < NV; ++s) {
       const bool ok = srow[s] < nvalid;
@@ -342,9 +364,16 @@ __global__ __launch_bounds__(256) void k_sketch_q(SlabArgs a) {
       const int col = lt * 16 + lr;
       const float m = fmaxf(fmaxf(sYm[col], sYm[LP + col]), fmaxf(sYm[2 * LP + col], sYm[3 * LP + col]));
       const int e = col_exp(m);
+      float sc;
+      const bool tiny = col_scale(e, sc);
+      if (__builtin_amdgcn_ballot_w64(tiny)) {   // rare: taken only when a lane needs it
+        const float pre = tiny ? 0x1p64f : 1.0f;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[lt][v] *= pre;
+      }
       int q[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) q[v] = q22b(acc[lt][v], e);
+      for (int v = 0; v < 4; ++v) q[v] = q22b(acc[lt][v], sc);
       uint32_t p[3];
       digits4(q, p[0], p[1], p[2]);
 #pragma unroll
@@ -359,12 +388,19 @@ __global__ __launch_bounds__(256) void k_sketch_q(SlabArgs a) {
         const int j = task % JP, q = task / JP;
         const float m = fmaxf(fmaxf(sXm[j], sXm[JP + j]), fmaxf(sXm[2 * JP + j], sXm[3 * JP + j]));
         const int e = col_exp(m);
+        float sc;
+        const bool tiny = col_scale(e, sc);
+        if (__builtin_amdgcn_ballot_w64(tiny)) {   // rare: taken only when a lane needs it
+          const float pre = tiny ? 0x1p64f : 1.0f;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) xv[k][r] *= pre;
+        }
         uint32_t pk[3][4];
 #pragma unroll
         for (int r4 = 0; r4 < 4; ++r4) {
           int qv[4];
 #pragma unroll
-          for (int v = 0; v < 4; ++v) qv[v] = q22b(xv[k][4 * r4 + v], e);
+          for (int v = 0; v < 4; ++v) qv[v] = q22b(xv[k][4 * r4 + v], sc);
           digits4(qv, pk[0][r4], pk[1][r4], pk[2][r4]);
         }
 #pragma unroll
@@ -413,7 +449,9 @@ __global__ __launch_bounds__(256) void k_sketch_q(SlabArgs a) {
         v4i S3 = mfma_i8(A[1], B[2], z);
         S3 = mfma_i8(A[2], B[1], S3);
         const v4i S4 = mfma_i8(A[2], B[2], z);
-        const int ecol = eb[cb + lr];
+        // 2^(erow + ecol - 44) as an FP64 bit pattern (high word only); the
+        // exponent stays within [-340, 212]
+        const int ecol = (eb[cb + lr] - 44 + 1023) << 20;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           // |S0| <= 2^18, |S1| <= 2^20, |S3| <= 2^21, |S4| <= 2^20: the two
@@ -421,7 +459,7 @@ __global__ __launch_bounds__(256) void k_sketch_q(SlabArgs a) {
           const int hi = S0[v] * 256 + S1[v], lo = S3[v] * 256 + S4[v];
           const double val = fma((double)hi, 16777216.0, fma((double)S2[v], 65536.0, (double)lo));
           const int erow = sYe[ca + f32_row(lane, v)];
-          pacc[qi][v] += ldexp(val, erow + ecol - 44);
+          pacc[qi][v] = fma(val, __hiloint2double((erow << 20) + ecol, 0), pacc[qi][v]);
         }
       }
     }

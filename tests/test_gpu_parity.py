@@ -109,6 +109,31 @@ def test_small_parity_end_to_end():
     assert g["rep"]["warn_bits"] == 0
 
 
+@pytest.mark.parametrize("exp2", [-110, 100])
+def test_extreme_magnitudes_match_oracle(exp2):
+    """The small-parity tensor times 2^-110 and times 2^100 (exact power-of-two
+    scalings).  The slab pass scales each column of each 64-row tile by a
+    power of two before its 22-bit fixed point; at 2^-110 every column maximum
+    of X and of Y lies below 2^-104, where that power of two leaves the FP32
+    range and the column is pre-multiplied by 2^64.  Every comparison is
+    relative, as in the unscaled case."""
+    X0 = synth.small_parity(seed=5)
+    assert np.abs(X0.slab).max() < 32.0
+    X = synth.IrregularTensor(slab=(X0.slab * np.float32(2.0 ** exp2)).astype(np.float32),
+                              offsets=X0.offsets)
+    R, L, iters = 5, 15, 40
+    print(f"[gpu] magnitudes 2^{exp2}", flush=True)
+    om1, om2 = synth.omegas(X.J, L, X.K * R)
+    H0, V0, W0 = synth.init_factors(X.J, X.K, R)
+    ref = O.dpar2(X.slab, X.offsets, R, om1, om2, H0, V0, W0, iters)
+    g = _run_gpu(X, R, L, L, iters, om1, om2, H0, V0, W0)
+    _check_compression(X, R, g, ref)
+    _check_errors(g, ref)
+    _check_factors(g, ref)
+    assert abs(g["rep"]["fit_true"] - ref.fit) < 1e-7
+    assert g["rep"]["warn_bits"] == 0
+
+
 def test_stock_like_scaled_down():
     """US-Stock-shaped slices (J=88, lognormal I_k, feature scales over
     1e-2..1e3, 5% noise), 120 slices, R=10, L=20, 32 iterations."""
