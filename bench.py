@@ -561,7 +561,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if tr is None else tr["bytes_per_launch"],
-                "kernel": "k_sketch_q (slab pass: FP32 MFMA sketch, exact int8 MFMA Gram and projection)",
+                "kernel": "k_sketch_q (slab pass: sketch from three-piece bf16 MFMA products, exact int8 MFMA Gram and projection)",
                 "kernel_ms": round(sk_ms, 4), "algorithmic_bytes": int(alg_bytes),
                 "timed_launches": launches}
     sketch_tf = alg_flops / (sk_ms / 1e3) / 1e12
@@ -578,7 +578,7 @@ def main():
         "autotune": {"item_rows": item_rows, "slab_pass_ms_by_item_rows": tune_ms},
         "sketch_gemm": {"achieved_tflops": round(sketch_tf, 2),
                         "frac_of_fp32_mfma_peak": round(sketch_tf / FP32_MFMA_PEAK_TFLOPS, 4),
-                        "note": "useful flops 4NJL+2NL^2; sketch in FP32, Gram and projection exact "
+                        "note": "useful flops 4NJL+2NL^2; sketch at FP32-level accuracy, Gram and projection exact "
                                 "(int8 digit products combined in FP64)"},
         "fitness": {"gpu": rep["fit_true"], "iters": rep["iters"], "warn_bits": rep["warn_bits"]},
     }

@@ -1,8 +1,9 @@
 // Slab pass on the int8 matrix cores (Sec. III-B, Eq. 4; Alg. 1 applied to
 // every slice), templated on the input type and on the output:
-//   Y  = X Omega                  (sketch step of Alg. 1; FP32 matrix cores for
-//                                  float32 slabs, bf16 matrix cores with Omega
-//                                  rounded to bf16 for bf16 / fp8 slabs)
+//   Y  = X Omega                  (sketch step of Alg. 1 on the bf16 matrix
+//                                  cores: float32 slabs as three-piece bf16
+//                                  products with FP32-level error, bf16 / fp8
+//                                  slabs exactly with Omega rounded to bf16)
 //   G  = Y^T Y, P = Y^T X         (exact: int8 digit products, FP64 totals)
 //   ss = ||X||_F^2
 // or, in the U variant, the same Y (bit for bit) times Theta_k.  Omega is the
@@ -104,6 +105,38 @@ __device__ __forceinline__ v8bf bf16x8(const float* p) {
   return r;
 }
 
+// x = h + m + l exactly: h is x rounded to bf16 (nearest even), m the
+// remainder rounded likewise and l what is left, which has at most 8
+// significant bits.  Each subtraction is exact.  Pieces below the FP32 normal
+// range may be flushed, so callers keep |x| >= 2^-100 where it matters.
+// Two values per conversion instruction; a bf16 pair unpacks to floats by a
+// shift (low half) and a mask (high half).
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v2f{a, b}, v2bf));
+}
+
+__device__ __forceinline__ void split3(const float (&x)[8], v8bf& h, v8bf& m, v8bf& l) {
+  v4u hw, mw, lw;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float a = x[2 * i], b = x[2 * i + 1];
+    const uint32_t ph = pk_bf16(a, b);
+    const float ra = a - __uint_as_float(ph << 16), rb = b - __uint_as_float(ph & 0xffff0000u);
+    const uint32_t pm = pk_bf16(ra, rb);
+    const float sa = ra - __uint_as_float(pm << 16), sb = rb - __uint_as_float(pm & 0xffff0000u);
+    hw[i] = ph;
+    mw[i] = pm;
+    lw[i] = pk_bf16(sa, sb);
+  }
+  h = __builtin_bit_cast(v8bf, hw);
+  m = __builtin_bit_cast(v8bf, mw);
+  l = __builtin_bit_cast(v8bf, lw);
+}
+
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ v4i mfma_i8(v4i a, v4i b, v4i c) {
@@ -176,7 +209,14 @@ __global__ __launch_bounds__(256) void k_sketch_q(SlabArgs a) {
   constexpr int QWORDS = 3 * JP * QW + 3 * LP * QW;
   constexpr int UWORDS = 2 * (TM * YS) + 2 * 32 * 32;
   __shared__ __align__(16) float sX[TM * XS];
-  __shared__ __align__(16) float sOm[LP * XS];
+  // float32 slabs keep Omega as three bf16 planes (split3), the others as
+  // floats already rounded to bf16
+  constexpr bool SPLIT = (TIN == DPAR2_F32);
+  constexpr int NKC = (JT + 1) / 2;                // 32-column chunks
+  constexpr int XSB = 32 * NKC + 8;                // bf16 row stride of the planes
+  constexpr int PLANE = LP * XSB;
+  __shared__ __align__(16) float sOm[SPLIT ? 4 : LP * XS];
+  __shared__ __align__(16) __bf16 sOmb[SPLIT ? 3 * PLANE : 8];
   // digit planes, or in the U variant Y (FP32) and Theta_k (FP64)
   __shared__ __align__(16) uint32_t sQ[UOUT ? UWORDS : QWORDS];
   uint32_t* sXq = sQ;
@@ -198,10 +238,23 @@ __global__ __launch_bounds__(256) void k_sketch_q(SlabArgs a) {
 
   // the low-precision inputs sketch on the bf16 matrix cores: Omega is
   // rounded to bf16 (nearest even) once, X is already bf16-representable
-  for (int e = tid; e < LP * XS; e += 256) {
-    const int n = e / XS, j = e % XS;
-    const float o = (n < L && j < J) ? omega[(size_t)j * L + n] : 0.f;
-    sOm[e] = (TIN == DPAR2_F32) ? o : round_bf16(o);
+  if constexpr (SPLIT) {
+    for (int e = tid; e < PLANE; e += 256) {
+      const int n = e / XSB, j = e % XSB;
+      const float o = (n < L && j < J) ? omega[(size_t)j * L + n] : 0.f;
+      const __bf16 h = (__bf16)o;
+      const float r = o - (float)h;
+      const __bf16 m = (__bf16)r;
+      sOmb[e] = h;
+      sOmb[PLANE + e] = m;
+      sOmb[2 * PLANE + e] = (__bf16)(r - (float)m);
+    }
+  } else {
+    for (int e = tid; e < LP * XS; e += 256) {
+      const int n = e / XS, j = e % XS;
+      const float o = (n < L && j < J) ? omega[(size_t)j * L + n] : 0.f;
+      sOm[e] = round_bf16(o);
+    }
   }
   for (int e = tid; e < TM * XS; e += 256) sX[e] = 0.f;
   float* sYf = reinterpret_cast<float*>(sQ);                  // U variant: Y of the tile
@@ -261,8 +314,13 @@ __global__ __launch_bounds__(256) void k_sketch_q(SlabArgs a) {
   for (int q = 0; q < NPW; ++q) pacc[q] = v4d{0.0, 0.0, 0.0, 0.0};
 
   if (ntiles > 0) load_tile(0);
+  // The tile loop needs no barrier at its top: sX, the only shared array
+  // written before the first barrier of a tile, was last read in the
+  // previous tile's sketch and column-maximum phase, and a barrier of that
+  // tile already follows that phase.  This one orders the fills above before
+  // the first tile.
+  __syncthreads();
   for (int t = 0; t < ntiles; ++t) {
-    __syncthreads();
 #pragma unroll
     for (int s = 0; s < NV; ++s) {
       if (srow[s] < TM) {
@@ -285,21 +343,60 @@ __global__ __launch_bounds__(256) void k_sketch_q(SlabArgs a) {
     v4f acc[LT];
 #pragma unroll
     for (int lt = 0; lt < LT; ++lt) acc[lt] = v4f{0.f, 0.f, 0.f, 0.f};
-    if constexpr (TIN == DPAR2_F32) {
-      // FP32 matrix cores (the same instruction sequence as k_sketch).  Each
-      // lane reads 4 consecutive columns; instruction m takes column 4 lk + m
-      // of every 16-column group, and B reads the same permutation.
+    if constexpr (SPLIT) {
+      // FP32 products from the bf16 matrix cores: X and Omega are each split
+      // into three bf16 pieces (split3) and the six piece products down to
+      // 2^-16 relative are summed in FP32 (the three dropped ones lie below
+      // 2^-25 of the product).  The leading product accumulates apart from
+      // the five smaller ones.  Lane (lr, lk) holds columns 8 lk .. 8 lk + 7
+      // of each 32-column chunk of row lr of X (A) and of Omega^T (B).
+      float xr[NKC][8];
+      float mx = 0.f;
 #pragma unroll
-      for (int jg = 0; jg < JT; ++jg) {
-        const float4 xa = *reinterpret_cast<const float4*>(&sX[(16 * w + lr) * XS + jg * 16 + 4 * lk]);
+      for (int kc = 0; kc < NKC; ++kc) {
+        const float* p = &sX[(16 * w + lr) * XS + kc * 32 + 8 * lk];
+        const float4 a = *reinterpret_cast<const float4*>(p);
+        const float4 b = *reinterpret_cast<const float4*>(p + 4);
+        xr[kc][0] = a.x; xr[kc][1] = a.y; xr[kc][2] = a.z; xr[kc][3] = a.w;
+        xr[kc][4] = b.x; xr[kc][5] = b.y; xr[kc][6] = b.z; xr[kc][7] = b.w;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) mx = fmaxf(mx, fabsf(xr[kc][i]));
+      }
+      // a wave whose 16 rows are all below 2^-100 (and not all zero) works on
+      // X 2^64 and scales Y back (both exact), so that no piece is subnormal
+      const bool tiny = __builtin_amdgcn_ballot_w64(mx >= 0x1p-100f) == 0 &&
+                        __builtin_amdgcn_ballot_w64(mx > 0.f) != 0;
+      if (tiny) {
+#pragma unroll
+        for (int kc = 0; kc < NKC; ++kc)
+#pragma unroll
+          for (int i = 0; i < 8; ++i) xr[kc][i] *= 0x1p64f;
+      }
+      v4f lo[LT];
+#pragma unroll
+      for (int lt = 0; lt < LT; ++lt) lo[lt] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kc = 0; kc < NKC; ++kc) {
+        v8bf xh, xm, xl;
+        split3(xr[kc], xh, xm, xl);
 #pragma unroll
         for (int lt = 0; lt < LT; ++lt) {
-          const float4 ob = *reinterpret_cast<const float4*>(&sOm[(lt * 16 + lr) * XS + jg * 16 + 4 * lk]);
-          acc[lt] = mfma_f32(xa.x, ob.x, acc[lt]);
-          acc[lt] = mfma_f32(xa.y, ob.y, acc[lt]);
-          acc[lt] = mfma_f32(xa.z, ob.z, acc[lt]);
-          acc[lt] = mfma_f32(xa.w, ob.w, acc[lt]);
+          const __bf16* ob = &sOmb[(lt * 16 + lr) * XSB + kc * 32 + 8 * lk];
+          const v8bf oh = *reinterpret_cast<const v8bf*>(ob);
+          const v8bf om = *reinterpret_cast<const v8bf*>(ob + PLANE);
+          const v8bf ol = *reinterpret_cast<const v8bf*>(ob + 2 * PLANE);
+          acc[lt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, oh, acc[lt], 0, 0, 0);
+          lo[lt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, oh, lo[lt], 0, 0, 0);
+          lo[lt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xm, om, lo[lt], 0, 0, 0);
+          lo[lt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, ol, lo[lt], 0, 0, 0);
+          lo[lt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xm, oh, lo[lt], 0, 0, 0);
+          lo[lt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, om, lo[lt], 0, 0, 0);
         }
+      }
+#pragma unroll
+      for (int lt = 0; lt < LT; ++lt) {
+        acc[lt] += lo[lt];
+        if (tiny) acc[lt] *= 0x1p-64f;
       }
     } else {
       // bf16 matrix cores, 32 columns per instruction: lane (lr, lk) holds

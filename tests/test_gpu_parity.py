@@ -49,7 +49,7 @@ def _run_gpu(X, R, L, L2, iters, om1, om2, H0, V0, W0, tol=-1.0, want_U=False, t
 
 
 def _check_compression(X, R, g, ref, tol_m=1e-6):
-    """The slab pass rounds the sketch Y = X Omega_1 to FP32 once and then
+    """The slab pass forms the sketch Y = X Omega_1 with FP32-level error and then
     represents Y and X in 22-bit fixed point per column of each 64-row tile
     (error at most 2^-22 of that column's maximum); the Gram, the projection
     and everything after them are exact or FP64.  A CPU emulation of exactly
