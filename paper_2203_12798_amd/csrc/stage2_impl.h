@@ -55,17 +55,41 @@ __global__ __launch_bounds__(64) void k_s2_orth(int J, double* __restrict__ Yall
       stage(j0, nj);
       __syncthreads();
       if (cv) {
-        for (int jj = 0; jj < nj; ++jj) {
+        // four rows per step, every LDS read of a step issued before its
+        // multiply-adds (the sums still run over the rows in order); rows
+        // a >= L read a valid entry and are cleared below
+        auto rowacc = [&](int jj) {
           const double yc = Ys[jj * LD + c];
 #pragma unroll
           for (int ii = 0; ii < LH; ++ii) {
             const int a = h * LH + ii;
-            if (a < L) t[ii] = fma(Ys[jj * LD + a], yc, t[ii]);
+            t[ii] = fma(Ys[jj * LD + (a < L ? a : L - 1)], yc, t[ii]);
           }
+        };
+        int jj = 0;
+        for (; jj + 4 <= nj; jj += 4) {
+          double yc[4], ya[4][LH];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            yc[u] = Ys[(jj + u) * LD + c];
+#pragma unroll
+            for (int ii = 0; ii < LH; ++ii) {
+              const int a = h * LH + ii;
+              ya[u][ii] = Ys[(jj + u) * LD + (a < L ? a : L - 1)];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int ii = 0; ii < LH; ++ii) t[ii] = fma(ya[u][ii], yc[u], t[ii]);
         }
+        for (; jj < nj; ++jj) rowacc(jj);
       }
       __syncthreads();
     }
+#pragma unroll
+    for (int ii = 0; ii < LH; ++ii)
+      if (h * LH + ii >= L) t[ii] = 0.0;
 #pragma unroll
     for (int ii = 0; ii < LH; ++ii) {
       const int a = h * LH + ii;
@@ -125,13 +149,32 @@ __global__ __launch_bounds__(64) void k_s2_orth(int J, double* __restrict__ Yall
         __syncthreads();
         stage(j0, nj);
         __syncthreads();
-        if (cv)
-          for (int jj = h; jj < nj; jj += H) {
-            double s = 0.0;
+        if (cv) {
+          // two rows per step, reads first
+          int jj = h;
+          for (; jj + H < nj; jj += 2 * H) {
+            double y0[L], y1[L];
 #pragma unroll
-            for (int a = 0; a < L; ++a) s = fma(Ys[jj * LD + a], w[a], s);
-            Y[(size_t)(j0 + jj) * L + c] = s;
+            for (int a = 0; a < L; ++a) {
+              y0[a] = Ys[jj * LD + a];
+              y1[a] = Ys[(jj + H) * LD + a];
+            }
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int a = 0; a < L; ++a) {
+              s0 = fma(y0[a], w[a], s0);
+              s1 = fma(y1[a], w[a], s1);
+            }
+            Y[(size_t)(j0 + jj) * L + c] = s0;
+            Y[(size_t)(j0 + jj + H) * L + c] = s1;
           }
+          for (; jj < nj; jj += H) {
+            double s0 = 0.0;
+#pragma unroll
+            for (int a = 0; a < L; ++a) s0 = fma(Ys[jj * LD + a], w[a], s0);
+            Y[(size_t)(j0 + jj) * L + c] = s0;
+          }
+        }
       }
     }
     __syncthreads();
@@ -157,6 +200,7 @@ __global__ __launch_bounds__(64) void k_s2_evd(int J, int R, const double* __res
   constexpr int RM = SC<L>::RM, LH = SC<L>::LH, LD = SC<L>::LD;
   constexpr int NP = L * (L + 1) / 2;
   __shared__ double Ss[L * LD], Us[L * LD], Es[L], row[L], rinv[L];
+  __shared__ double Ds[64 * LD];
   const int lane = threadIdx.x, c = lane % RM, h = lane / RM;
   const bool cv = c < L;
   unsigned warn = 0;
@@ -218,24 +262,44 @@ __global__ __launch_bounds__(64) void k_s2_evd(int J, int R, const double* __res
     const int l = e / R, r = e % R;
     U2s[e] = Es[r] > 0.0 ? Us[l * LD + r] / Es[r] : 0.0;
   }
-  // D = Q2 U2_R (J x R); D^T D from the same values, in a fixed order
-  for (int j = lane; j < J; j += 64) {
-    double q[L];
+  // D = Q2 U2_R (J x R), 64 rows at a time; D^T D from the same values,
+  // summed over the rows in order from a copy of each 64-row block in LDS
+  constexpr int NE = (L * L + 63) / 64;
+  double dtd[NE];
 #pragma unroll
-    for (int l = 0; l < L; ++l) q[l] = Q2[(size_t)j * L + l];
-    for (int r = 0; r < R; ++r) {
-      double s = 0.0;
+  for (int i = 0; i < NE; ++i) dtd[i] = 0.0;
+  for (int j0 = 0; j0 < J; j0 += 64) {
+    const int j = j0 + lane;
+    if (j < J) {
+      double q[L];
 #pragma unroll
-      for (int l = 0; l < L; ++l) s = fma(q[l], Us[l * LD + r], s);
-      D[(size_t)j * R + r] = s;
+      for (int l = 0; l < L; ++l) q[l] = Q2[(size_t)j * L + l];
+      for (int r = 0; r < R; ++r) {
+        double s = 0.0;
+#pragma unroll
+        for (int l = 0; l < L; ++l) s = fma(q[l], Us[l * LD + r], s);
+        D[(size_t)j * R + r] = s;
+        Ds[lane * LD + r] = s;
+      }
     }
+    __syncthreads();
+    const int nj = (J - j0 < 64) ? J - j0 : 64;
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      const int e = lane + 64 * i;
+      if (e < R * R) {
+        const int a = e / R, b = e % R;
+        double s = dtd[i];
+        for (int jj = 0; jj < nj; ++jj) s = fma(Ds[jj * LD + a], Ds[jj * LD + b], s);
+        dtd[i] = s;
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  for (int e = lane; e < R * R; e += 64) {
-    const int a = e / R, b = e % R;
-    double s = 0.0;
-    for (int j = 0; j < J; ++j) s = fma(D[(size_t)j * R + a], D[(size_t)j * R + b], s);
-    DtD[e] = s;
+#pragma unroll
+  for (int i = 0; i < NE; ++i) {
+    const int e = lane + 64 * i;
+    if (e < R * R) DtD[e] = dtd[i];
   }
   for (int o = 1; o < 64; o <<= 1) warn |= __shfl_xor((int)warn, o, 64);
   if (lane == 0 && warn) atomicOr(&ctl->warn, warn);
