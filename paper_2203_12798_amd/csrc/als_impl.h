@@ -316,34 +316,40 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_A(AlsArgs a) {
       v[i] = live ? a.Pw[(size_t)k * RR + i * R + j] : 0.0;
     }
     // column j of T_k = F^(k) Bm diag(W(k,:)) H^T (Eq. 8)
+    // (the small products below run their R sums side by side, each over
+    // its index in ascending order)
     {
-      double x[R];
+      double y[R], x[R];
 #pragma unroll
-      for (int q = 0; q < R; ++q) {
-        double s = 0.0;
-#pragma unroll
-        for (int i = 0; i < R; ++i) s = fma(sB[q * R + i], wk[i] * sH[(live ? j : 0) * R + i], s);
-        x[q] = s;
+      for (int i = 0; i < R; ++i) {
+        y[i] = wk[i] * sH[(live ? j : 0) * R + i];
+        x[i] = 0.0;
       }
-      if (live)
 #pragma unroll
-        for (int q = 0; q < R; ++q) {
-          double s = 0.0;
+      for (int i = 0; i < R; ++i)
 #pragma unroll
-          for (int i = 0; i < R; ++i) s = fma(F_[q * R + i], x[i], s);
-          T_[q * R + j] = s;
-        }
+        for (int q = 0; q < R; ++q) x[q] = fma(sB[q * R + i], y[i], x[q]);
+      if (live) {
+        double tq[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) tq[q] = 0.0;
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+#pragma unroll
+          for (int q = 0; q < R; ++q) tq[q] = fma(F_[q * R + i], x[i], tq[q]);
+#pragma unroll
+        for (int q = 0; q < R; ++q) T_[q * R + j] = tq[q];
+      }
     }
     __syncthreads();
     // t = T_k p_j, p_j the warm start (column j of the previous P_k)
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      double s = 0.0;
-      if (live)
+    for (int q = 0; q < R; ++q) t[q] = 0.0;
+    if (live)
 #pragma unroll
-        for (int i = 0; i < R; ++i) s = fma(T_[q * R + i], v[i], s);
-      t[q] = s;
-    }
+      for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int q = 0; q < R; ++q) t[q] = fma(T_[q * R + i], v[i], t[q]);
     // T_k P V' = Z Sigma (one-sided Jacobi without accumulating V'); then
     // z_j = t / sigma_j and the new p_j = T_k^T z_j / sigma_j
     if (group_jacobi<R, false>(t, v, j, gbase) == JACOBI_SWEEPS) warn |= 0x1u;
@@ -359,12 +365,13 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_A(AlsArgs a) {
 #pragma unroll
       for (int i = 0; i < R; ++i) t[i] *= inv;
 #pragma unroll
-      for (int i = 0; i < R; ++i) {
-        double s = 0.0;
+      for (int i = 0; i < R; ++i) v[i] = 0.0;
 #pragma unroll
-        for (int q = 0; q < R; ++q) s = fma(T_[q * R + i], t[q], s);
-        v[i] = s * inv;
-      }
+      for (int q = 0; q < R; ++q)
+#pragma unroll
+        for (int i = 0; i < R; ++i) v[i] = fma(T_[q * R + i], t[q], v[i]);
+#pragma unroll
+      for (int i = 0; i < R; ++i) v[i] *= inv;
 #pragma unroll
       for (int i = 0; i < R; ++i) {
         Z_[i * R + j] = t[i];
@@ -376,13 +383,12 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_A(AlsArgs a) {
     // Psi column j: Psi[q][j] = sum_c Z[q][c] P[j][c]
     double psi[R];
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      double s = 0.0;
-      if (j < R)
+    for (int q = 0; q < R; ++q) psi[q] = 0.0;
+    if (j < R)
 #pragma unroll
-        for (int c = 0; c < R; ++c) s = fma(Z_[q * R + c], P_[j * R + c], s);
-      psi[q] = s;
-    }
+      for (int c = 0; c < R; ++c)
+#pragma unroll
+        for (int q = 0; q < R; ++q) psi[q] = fma(Z_[q * R + c], P_[j * R + c], psi[q]);
     __syncthreads();
     if (live) {
 #pragma unroll
@@ -396,12 +402,11 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_A(AlsArgs a) {
     if (live) {
       double mcol[R];
 #pragma unroll
-      for (int q = 0; q < R; ++q) {
-        double s = 0.0;
+      for (int q = 0; q < R; ++q) mcol[q] = 0.0;
 #pragma unroll
-        for (int i = 0; i < R; ++i) s = fma(P_[i * R + q], F_[i * R + j], s);
-        mcol[q] = s;
-      }
+      for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int q = 0; q < R; ++q) mcol[q] = fma(P_[i * R + q], F_[i * R + j], mcol[q]);
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         Z_[q * R + j] = mcol[q];
@@ -415,13 +420,15 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_A(AlsArgs a) {
 #pragma unroll
       for (int i = 0; i < R; ++i)
         if (i == j) wj = wk[i];
+      double sq[R];
 #pragma unroll
-      for (int q = 0; q < R; ++q) {
-        double s = 0.0;
+      for (int q = 0; q < R; ++q) sq[q] = 0.0;
 #pragma unroll
-        for (int i = 0; i < R; ++i) s = fma(Z_[q * R + i], sB[i * R + j], s);
-        acc[q] = fma(wj, s, acc[q]);
-      }
+      for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int q = 0; q < R; ++q) sq[q] = fma(Z_[q * R + i], sB[i * R + j], sq[q]);
+#pragma unroll
+      for (int q = 0; q < R; ++q) acc[q] = fma(wj, sq[q], acc[q]);
     }
   }
   for (int o = 1; o < 64; o <<= 1) warn |= __shfl_xor((int)warn, o, 64);
@@ -504,13 +511,15 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_B(AlsArgs a) {
     __syncthreads();
     if (k < K && j < R) {
       const double wj = td.W[(size_t)(k - td.k0) * R + j];
+      double sq[R];
 #pragma unroll
-      for (int q = 0; q < R; ++q) {
-        double s = 0.0;
+      for (int q = 0; q < R; ++q) sq[q] = 0.0;
 #pragma unroll
-        for (int i = 0; i < R; ++i) s = fma(M_[i * R + q], sH[i * R + j], s);
-        acc[q] = fma(wj, s, acc[q]);
-      }
+      for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int q = 0; q < R; ++q) sq[q] = fma(M_[i * R + q], sH[i * R + j], sq[q]);
+#pragma unroll
+      for (int q = 0; q < R; ++q) acc[q] = fma(wj, sq[q], acc[q]);
     }
   }
   block_partial_out<R>(acc, sM, a.partB + (size_t)blockIdx.x * RR);
@@ -622,13 +631,15 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_C(AlsArgs a) {
     __syncthreads();
     double g3 = 0.0;
     if (live) {
+      double sq[R];
 #pragma unroll
-      for (int q = 0; q < R; ++q) {
-        double s = 0.0;
+      for (int q = 0; q < R; ++q) sq[q] = 0.0;
 #pragma unroll
-        for (int i = 0; i < R; ++i) s = fma(M_[q * R + i], sB[i * R + j], s);
-        g3 = fma(sH[q * R + j], s, g3);
-      }
+      for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int q = 0; q < R; ++q) sq[q] = fma(M_[q * R + i], sB[i * R + j], sq[q]);
+#pragma unroll
+      for (int q = 0; q < R; ++q) g3 = fma(sH[q * R + j], sq[q], g3);
     }
     double gs[R];
 #pragma unroll
