@@ -32,6 +32,7 @@ constexpr int EPI_THREADS = 256;
 
 struct AlsArgs {
   int nt, J;
+  int64_t K1;                      // slices of the tensor when nt == 1
   const TDesc* td;                 // per tensor: K, first slice, factors, trace, tol
   const Blk* blk;                  // iteration kernels: block -> (tensor, global slices)
   const Blk* blk0;                 // begin kernel: block -> (tensor, local rows)
@@ -43,9 +44,18 @@ struct AlsArgs {
   Ctl* ctl;                        // nt
 };
 
-// per-slice kernels: the block's tensor, its control block and small state
+// per-slice kernels: the block's tensor, its control block and small state.
+// A single tensor's block table is GPB consecutive slices per block, so the
+// block's range follows from its index without a table read first.
 #define ALS_BLOCK_PROLOGUE(R_)                                         \
-  const Blk bk = a.blk[blockIdx.x];                                    \
+  Blk bk;                                                              \
+  if (a.nt == 1) {                                                     \
+    const int64_t s0_ = (int64_t)blockIdx.x * RC<R_>::GPB;             \
+    const int64_t s1_ = s0_ + RC<R_>::GPB;                             \
+    bk = Blk{0, (int32_t)s0_, (int32_t)(s1_ < a.K1 ? s1_ : a.K1), 0};  \
+  } else {                                                             \
+    bk = a.blk[blockIdx.x];                                            \
+  }                                                                    \
   const int tt = bk.t;                                                 \
   const TDesc& td = a.td[tt];                                          \
   Ctl* ctl = a.ctl + tt;                                               \
@@ -777,18 +787,18 @@ hipError_t als_launch(int phase, const AlsArgs& a, int nb, int nb0, const int64_
   hipError_t e;
   if (phase == 0) {
     hipLaunchKernelGGL(k_als_begin<R>, dim3(nb0), dim3(TPB), 0, s, a);
-    if ((e = launch_segsum(nt, seg0, 3 * RR, 3 * RR, a.partBegin, a.red + 3 * RR + 2, RW, s)) != hipSuccess)
+    if ((e = launch_segsum(nt, seg0, nb0, 3 * RR, 3 * RR, a.partBegin, a.red + 3 * RR + 2, RW, s)) != hipSuccess)
       return e;
     hipLaunchKernelGGL(k_als_begin_epi<R>, dim3(nt), dim3(EPI_THREADS), 0, s, a, 1);
   } else {
     hipLaunchKernelGGL(k_als_A<R>, dim3(nb), dim3(TPB), 0, s, a);
-    if ((e = launch_segsum(nt, seg, RR, RR, a.partA, a.red, RW, s)) != hipSuccess) return e;
+    if ((e = launch_segsum(nt, seg, nb, RR, RR, a.partA, a.red, RW, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_als_A_epi<R>, dim3(nt), dim3(EPI_THREADS), 0, s, a, 1);
     hipLaunchKernelGGL(k_als_B<R>, dim3(nb), dim3(TPB), 0, s, a);
-    if ((e = launch_segsum(nt, seg, RR, RR, a.partB, a.red + RR, RW, s)) != hipSuccess) return e;
+    if ((e = launch_segsum(nt, seg, nb, RR, RR, a.partB, a.red + RR, RW, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_als_B_epi<R>, dim3(nt), dim3(EPI_THREADS), 0, s, a, 1);
     hipLaunchKernelGGL(k_als_C<R>, dim3(nb), dim3(TPB), 0, s, a);
-    if ((e = launch_segsum(nt, seg, RR + 2, RR + 2, a.partC, a.red + 2 * RR, RW, s)) != hipSuccess) return e;
+    if ((e = launch_segsum(nt, seg, nb, RR + 2, RR + 2, a.partC, a.red + 2 * RR, RW, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_als_C_epi<R>, dim3(nt), dim3(EPI_THREADS), 0, s, a, 1);
   }
   return hipGetLastError();

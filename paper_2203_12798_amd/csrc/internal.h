@@ -125,9 +125,11 @@ hipError_t launch_slice_finish(int64_t K, int J, int L, int R, const int32_t* sl
                                hipStream_t s);
 hipError_t launch_stage2(const Layout& lay, char* ws, hipStream_t s);
 // out[t * ostride + e] = sum_{b in [seg[t], seg[t+1])} part[b * stride + e],
-// e < width, t < nt, in a fixed order (one block per (e, t))
-hipError_t launch_segsum(int nt, const int64_t* seg, int64_t stride, int64_t width, const double* part,
-                         double* out, int64_t ostride, hipStream_t s);
+// e < width, t < nt, in a fixed order (one block per (e, t)).  n1 >= 0 gives
+// the row count of a single tensor (nt == 1, seg = {0, n1}) so that the
+// kernel need not read seg first; -1 otherwise.
+hipError_t launch_segsum(int nt, const int64_t* seg, int64_t n1, int64_t stride, int64_t width,
+                         const double* part, double* out, int64_t ostride, hipStream_t s);
 hipError_t launch_als_begin(const Layout& lay, char* ws, hipStream_t s);
 hipError_t launch_als_iteration(const Layout& lay, char* ws, hipStream_t s);
 hipError_t launch_als_end(const Layout& lay, char* ws, hipStream_t s);

@@ -158,6 +158,7 @@ static AlsArgs make_args(const Layout& lay, char* ws) {
   AlsArgs a;
   a.nt = lay.nt;
   a.J = (int)lay.J;
+  a.K1 = lay.K;
   a.td = reinterpret_cast<const TDesc*>(ws + lay.tdesc);
   a.blk = reinterpret_cast<const Blk*>(ws + lay.blk);
   a.blk0 = reinterpret_cast<const Blk*>(ws + lay.blk0);
@@ -217,7 +218,7 @@ hipError_t launch_fitness(const Layout& lay, char* ws, double* fit, hipStream_t 
                      reinterpret_cast<const int32_t*>(ws + lay.slice_t), reinterpret_cast<const double*>(ws + lay.Mt),
                      reinterpret_cast<const double*>(ws + lay.Psi), reinterpret_cast<const double*>(ws + lay.small),
                      fitp);
-  hipError_t e = launch_segsum(lay.nt, reinterpret_cast<const int64_t*>(ws + lay.seg_slice), 2, 2, fitp, fits, 2,
+  hipError_t e = launch_segsum(lay.nt, reinterpret_cast<const int64_t*>(ws + lay.seg_slice), lay.K, 2, 2, fitp, fits, 2,
                                s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_fit_final, dim3((unsigned)((lay.nt + 63) / 64)), dim3(64), 0, s, lay.nt, fits, fit,

@@ -69,13 +69,13 @@ __global__ __launch_bounds__(256) void k_s2_y(int J, int L2, int R, const TDesc*
 // out[t * ostride + e] = sum over b in [seg[t], seg[t+1]) of part[b * stride + e]:
 // one block per (e, t); the threads split b (four independent accumulators
 // each) and combine in a fixed order.
-__global__ __launch_bounds__(256) void k_segsum(const int64_t* __restrict__ seg, int64_t stride,
+__global__ __launch_bounds__(256) void k_segsum(const int64_t* __restrict__ seg, int64_t n1, int64_t stride,
                                                 const double* __restrict__ part, double* __restrict__ out,
                                                 int64_t ostride) {
   __shared__ double red[16];
   const int64_t e = blockIdx.x;
   const int t = blockIdx.y, tid = threadIdx.x;
-  const int64_t b0 = seg[t], nb = seg[t + 1] - b0;
+  const int64_t b0 = n1 >= 0 ? 0 : seg[t], nb = n1 >= 0 ? n1 : seg[t + 1] - b0;
   const double* p = part + (size_t)b0 * stride + e;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   int64_t q = tid;
@@ -169,10 +169,11 @@ __global__ __launch_bounds__(256) void k_s2_b(int J, int L2, const Chunk* __rest
   }
 }
 
-hipError_t launch_segsum(int nt, const int64_t* seg, int64_t stride, int64_t width, const double* part,
-                         double* out, int64_t ostride, hipStream_t s) {
+hipError_t launch_segsum(int nt, const int64_t* seg, int64_t n1, int64_t stride, int64_t width,
+                         const double* part, double* out, int64_t ostride, hipStream_t s) {
   if (width <= 0 || nt <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_segsum, dim3((unsigned)width, (unsigned)nt), dim3(256), 0, s, seg, stride, part, out,
+  if (nt != 1) n1 = -1;
+  hipLaunchKernelGGL(k_segsum, dim3((unsigned)width, (unsigned)nt), dim3(256), 0, s, seg, n1, stride, part, out,
                      ostride);
   return hipGetLastError();
 }
@@ -263,17 +264,17 @@ hipError_t launch_stage2(const Layout& lay, char* ws, hipStream_t s) {
   hipError_t e;
   hipLaunchKernelGGL(k_s2_y, dim3((unsigned)lay.n2, (unsigned)((J + 63) / 64)), dim3(256), 0, s, J, L2, R,
                      td, chunks, Mt, Y2p);
-  if ((e = launch_segsum(nt, seg_chunk, (int64_t)J * L2, (int64_t)J * L2, Y2p, Y2, (int64_t)J * L2, s)) !=
+  if ((e = launch_segsum(nt, seg_chunk, lay.n2, (int64_t)J * L2, (int64_t)J * L2, Y2p, Y2, (int64_t)J * L2, s)) !=
       hipSuccess)
     return e;
   if ((e = s2_small(nt, L2, 0, J, R, Y2, nullptr, D, E, U2s, small, ctl, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_s2_b, dim3((unsigned)lay.n2), dim3(256), 0, s, J, L2, chunks, Mt, Y2, B2t, S2p);
-  if ((e = launch_segsum(nt, seg_chunk, npairs, npairs, S2p, S2, npairs, s)) != hipSuccess) return e;
+  if ((e = launch_segsum(nt, seg_chunk, lay.n2, npairs, npairs, S2p, S2, npairs, s)) != hipSuccess) return e;
   // sum_k ||X_k||^2 of each tensor into its control block
-  if ((e = launch_segsum(nt, seg_slice, 1, 1, xnorm2, &ctl->xnorm2, cstride, s)) != hipSuccess) return e;
+  if ((e = launch_segsum(nt, seg_slice, lay.K, 1, 1, xnorm2, &ctl->xnorm2, cstride, s)) != hipSuccess) return e;
   if ((e = s2_small(nt, L2, 1, J, R, Y2, S2, D, E, U2s, small, ctl, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_s2_f, dim3((unsigned)lay.n2), dim3(256), 0, s, L2, R, chunks, B2t, U2s, F, FtFp);
-  if ((e = launch_segsum(nt, seg_chunk, RR, RR, FtFp, small + SM_FTF * RR, (int64_t)SM_COUNT * RR, s)) !=
+  if ((e = launch_segsum(nt, seg_chunk, lay.n2, RR, RR, FtFp, small + SM_FTF * RR, (int64_t)SM_COUNT * RR, s)) !=
       hipSuccess)
     return e;
   hipLaunchKernelGGL(k_s2_final, dim3((unsigned)nt), dim3(64), 0, s, R, small, E, ctl);
