@@ -59,16 +59,26 @@ struct AlsArgs {
   const int tt = bk.t;                                                 \
   const TDesc& td = a.td[tt];                                          \
   Ctl* ctl = a.ctl + tt;                                               \
-  if (ctl->done) return;                                               \
   double* small = a.small + (size_t)tt * SM_COUNT * (R_) * (R_);
-// epilogues: one block per tensor
+// (each kernel tests ctl->done itself, after issuing its first loads)
+// epilogues: one block per tensor.  The inputs are read into registers
+// (epi_fetch) before the stop flag is tested, so that both reads overlap.
 #define ALS_EPI_PROLOGUE(R_)                                           \
   const int tt = blockIdx.x;                                           \
   const TDesc& td = a.td[tt];                                          \
   Ctl* ctl = a.ctl + tt;                                               \
-  if (ctl->done) return;                                               \
   double* small = a.small + (size_t)tt * SM_COUNT * (R_) * (R_);       \
   double* red = a.red + (size_t)tt * (RED_WIDTH * (R_) * (R_) + 2);
+
+// v[u] = src[threadIdx.x + u * EPI_THREADS] for the indices below n
+template <int NU>
+__device__ __forceinline__ void epi_fetch(const double* __restrict__ src, int n, double (&v)[NU]) {
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const int e = threadIdx.x + u * EPI_THREADS;
+    v[u] = (e < n) ? src[e] : 0.0;
+  }
+}
 
 template <int R>
 struct RC {
@@ -287,10 +297,6 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_A(AlsArgs a) {
   const int tid = threadIdx.x, g = tid / RM, j = tid % RM;
   const int lane = tid & 63, gbase = lane & ~(RM - 1);
   const double* Bm = small + SM_BM * RR;
-  for (int e = tid; e < RR; e += TPB) {
-    sH[e] = td.H[e];
-    sB[e] = Bm[e];
-  }
   double* F_ = sF + g * RR;
   double* Z_ = sZ + g * RR;
   double* P_ = sP + g * RR;
@@ -303,28 +309,44 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_A(AlsArgs a) {
     const int64_t base = bk.s0;
     const int64_t k = base + g;
     const bool live = (k < K) && (j < R);
-    __syncthreads();
-    {
-      constexpr int NF = (RR + RM - 1) / RM;   // loads issued together (clamped index)
-      double fv[NF];
+    // every global read of the slice set-up is issued before the stop flag
+    // is tested (one round of loads)
+    constexpr int NS = (RR + TPB - 1) / TPB;
+    double hv[NS], bv[NS];
 #pragma unroll
-      for (int u = 0; u < NF; ++u) {
-        const int e = j + RM * u;
-        const bool ok = k < K && e < RR;
-        const double x = a.F[ok ? (size_t)k * RR + e : 0];
-        fv[u] = ok ? x : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < NF; ++u)
-        if (j + RM * u < RR) F_[j + RM * u] = fv[u];
+    for (int u = 0; u < NS; ++u) {
+      const int e = tid + TPB * u;
+      hv[u] = (e < RR) ? td.H[e] : 0.0;
+      bv[u] = (e < RR) ? Bm[e] : 0.0;
     }
-    __syncthreads();
+    constexpr int NF = (RR + RM - 1) / RM;   // loads issued together (clamped index)
+    double fv[NF];
+#pragma unroll
+    for (int u = 0; u < NF; ++u) {
+      const int e = j + RM * u;
+      const bool ok = k < K && e < RR;
+      const double x = a.F[ok ? (size_t)k * RR + e : 0];
+      fv[u] = ok ? x : 0.0;
+    }
     double t[R], v[R], wk[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       wk[i] = (k < K) ? td.W[(size_t)(k - td.k0) * R + i] : 0.0;
       v[i] = live ? a.Pw[(size_t)k * RR + i * R + j] : 0.0;
     }
+    if (ctl->done) return;
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int e = tid + TPB * u;
+      if (e < RR) {
+        sH[e] = hv[u];
+        sB[e] = bv[u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NF; ++u)
+      if (j + RM * u < RR) F_[j + RM * u] = fv[u];
+    __syncthreads();
     // column j of T_k = F^(k) Bm diag(W(k,:)) H^T (Eq. 8)
     // (the small products below run their R sums side by side, each over
     // its index in ascending order)
@@ -451,16 +473,24 @@ template <int R>
 __global__ __launch_bounds__(EPI_THREADS) void k_als_A_epi(AlsArgs a, int nblk) {
   ALS_EPI_PROLOGUE(R)
   constexpr int LD = 33, RR = R * R;
-  __shared__ double G1[32 * LD], Gm[32 * LD], Gi[32 * LD], sT[32 * LD], sV[32 * LD], sg[32], tmp[RR];
+  __shared__ double G1[32 * LD], Gm[32 * LD], Gi[32 * LD], sT[32 * LD], sV[32 * LD], sg[32];
   __shared__ int sflag;
   const int tid = threadIdx.x;
   (void)nblk;
-  team_sum(red, 1, RR, RR, tmp);
-  const double* WtW = small + SM_WTW * RR;
-  const double* VtV = small + SM_VTV * RR;
-  for (int e = tid; e < RR; e += EPI_THREADS) {
-    G1[(e / R) * LD + e % R] = tmp[e];
-    Gm[(e / R) * LD + e % R] = WtW[e] * VtV[e];
+  // G1 = the summed partials (one row of red), W^T W * V^T V
+  constexpr int NU = (RR + EPI_THREADS - 1) / EPI_THREADS;
+  double g1[NU], wtw[NU], vtv[NU];
+  epi_fetch(red, RR, g1);
+  epi_fetch(small + SM_WTW * RR, RR, wtw);
+  epi_fetch(small + SM_VTV * RR, RR, vtv);
+  if (ctl->done) return;
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const int e = tid + u * EPI_THREADS;
+    if (e < RR) {
+      G1[(e / R) * LD + e % R] = g1[u];
+      Gm[(e / R) * LD + e % R] = wtw[u] * vtv[u];
+    }
   }
   __syncthreads();
   const int capped = block_pinv<R>(Gm, Gi, sT, sV, sg, &sflag);
@@ -507,7 +537,6 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_B(AlsArgs a) {
   __shared__ double sM[GPB * RR];
   const int64_t K = bk.s1;
   const int tid = threadIdx.x, g = tid / RM, j = tid % RM;
-  for (int e = tid; e < RR; e += TPB) sH[e] = td.H[e];
   double* M_ = sM + g * RR;
   double acc[R];
 #pragma unroll
@@ -515,12 +544,33 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_B(AlsArgs a) {
   {
     const int64_t base = bk.s0;
     const int64_t k = base + g;
-    __syncthreads();
-    if (k < K)
-      for (int e = j; e < RR; e += RM) M_[e] = a.Mk[(size_t)k * RR + e];
+    // H, M_k and W(k, j) read before the stop flag is tested
+    constexpr int NS = (RR + TPB - 1) / TPB, NM = (RR + RM - 1) / RM;
+    double hv[NS], mv[NM];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int e = tid + TPB * u;
+      hv[u] = (e < RR) ? td.H[e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < NM; ++u) {
+      const int e = j + RM * u;
+      mv[u] = (k < K && e < RR) ? a.Mk[(size_t)k * RR + e] : 0.0;
+    }
+    const double wj = (k < K && j < R) ? td.W[(size_t)(k - td.k0) * R + j] : 0.0;
+    if (ctl->done) return;
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int e = tid + TPB * u;
+      if (e < RR) sH[e] = hv[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NM; ++u) {
+      const int e = j + RM * u;
+      if (k < K && e < RR) M_[e] = mv[u];
+    }
     __syncthreads();
     if (k < K && j < R) {
-      const double wj = td.W[(size_t)(k - td.k0) * R + j];
       double sq[R];
 #pragma unroll
       for (int q = 0; q < R; ++q) sq[q] = 0.0;
@@ -541,19 +591,30 @@ template <int R>
 __global__ __launch_bounds__(EPI_THREADS) void k_als_B_epi(AlsArgs a, int nblk) {
   ALS_EPI_PROLOGUE(R)
   constexpr int LD = 33, RR = R * R;
-  __shared__ double N[32 * LD], Gm[32 * LD], Gi[32 * LD], sT[32 * LD], sV[32 * LD], sg[32], tmp[RR];
+  __shared__ double N[32 * LD], Gm[32 * LD], Gi[32 * LD], sT[32 * LD], sV[32 * LD], sg[32];
+  __shared__ double DtD[RR], Et[R];
   __shared__ int sflag;
   const int tid = threadIdx.x;
   (void)nblk;
-  team_sum(red + RR, 1, RR, RR, tmp);
-  const double* WtW = small + SM_WTW * RR;
-  const double* HtH = small + SM_HTH * RR;
-  const double* DtD = small + SM_DTD * RR;
-  const double* Et = a.E + (size_t)tt * R;
-  for (int e = tid; e < RR; e += EPI_THREADS) {
-    N[(e / R) * LD + e % R] = tmp[e];
-    Gm[(e / R) * LD + e % R] = WtW[e] * HtH[e];
+  // N = the summed partials (second row of red), W^T W * H^T H, D^T D, E
+  constexpr int NU = (RR + EPI_THREADS - 1) / EPI_THREADS;
+  double nv[NU], wtw[NU], hth[NU], dtd[NU];
+  epi_fetch(red + RR, RR, nv);
+  epi_fetch(small + SM_WTW * RR, RR, wtw);
+  epi_fetch(small + SM_HTH * RR, RR, hth);
+  epi_fetch(small + SM_DTD * RR, RR, dtd);
+  const double ev = (tid < R) ? a.E[(size_t)tt * R + tid] : 0.0;
+  if (ctl->done) return;
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const int e = tid + u * EPI_THREADS;
+    if (e < RR) {
+      N[(e / R) * LD + e % R] = nv[u];
+      Gm[(e / R) * LD + e % R] = wtw[u] * hth[u];
+      DtD[e] = dtd[u];
+    }
   }
+  if (tid < R) Et[tid] = ev;
   __syncthreads();
   int capped = block_pinv<R>(Gm, Gi, sT, sV, sg, &sflag);
   // VC = diag(E) N Gi  (V = D VC before normalisation)
@@ -588,15 +649,18 @@ __global__ __launch_bounds__(EPI_THREADS) void k_als_B_epi(AlsArgs a, int nblk) 
   double* Bm = small + SM_BM * RR;
   double* HV = small + SM_HV * RR;
   double* VC = small + SM_VC * RR;
-  for (int e = tid; e < RR; e += EPI_THREADS) {
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const int e = tid + u * EPI_THREADS;
+    if (e >= RR) continue;
     const int q = e / R, c = e % R;
     double s = 0.0;
     for (int i = 0; i < R; ++i) s = fma(Gm[i * LD + q], sT[i * LD + c], s);   // VC^T (D^T D) VC
     VtV[e] = s;
     Bm[e] = Et[q] * sT[q * LD + c];                                           // E D^T V
-    HV[e] = s * HtH[e];
+    HV[e] = s * hth[u];
     VC[e] = Gm[q * LD + c];
-    N[q * LD + c] = s * HtH[e];
+    N[q * LD + c] = s * hth[u];
   }
   __syncthreads();
   capped |= block_pinv<R>(N, Gi, sT, sV, sg, &sflag);
@@ -620,12 +684,6 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_C(AlsArgs a) {
   const int64_t K = bk.s1;
   const int tid = threadIdx.x, g = tid / RM, j = tid % RM;
   const int lane = tid & 63, gbase = lane & ~(RM - 1);
-  for (int e = tid; e < RR; e += TPB) {
-    sH[e] = td.H[e];
-    sB[e] = small[SM_BM * RR + e];
-    sGi[e] = small[SM_G3INV * RR + e];
-    sHV[e] = small[SM_HV * RR + e];
-  }
   double* M_ = sM + g * RR;
   double wtw[R];
 #pragma unroll
@@ -635,9 +693,39 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_C(AlsArgs a) {
     const int64_t base = bk.s0;
     const int64_t k = base + g;
     const bool live = (k < K) && (j < R);
-    __syncthreads();
-    if (k < K)
-      for (int e = j; e < RR; e += RM) M_[e] = a.Mk[(size_t)k * RR + e];
+    // the small state and M_k read before the stop flag is tested
+    constexpr int NS = (RR + TPB - 1) / TPB, NM = (RR + RM - 1) / RM;
+    double hv[NS], bv[NS], gv[NS], qv[NS], mv[NM];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int e = tid + TPB * u;
+      const bool ok = e < RR;
+      hv[u] = ok ? td.H[e] : 0.0;
+      bv[u] = ok ? small[SM_BM * RR + e] : 0.0;
+      gv[u] = ok ? small[SM_G3INV * RR + e] : 0.0;
+      qv[u] = ok ? small[SM_HV * RR + e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < NM; ++u) {
+      const int e = j + RM * u;
+      mv[u] = (k < K && e < RR) ? a.Mk[(size_t)k * RR + e] : 0.0;
+    }
+    if (ctl->done) return;
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int e = tid + TPB * u;
+      if (e < RR) {
+        sH[e] = hv[u];
+        sB[e] = bv[u];
+        sGi[e] = gv[u];
+        sHV[e] = qv[u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NM; ++u) {
+      const int e = j + RM * u;
+      if (k < K && e < RR) M_[e] = mv[u];
+    }
     __syncthreads();
     double g3 = 0.0;
     if (live) {
@@ -699,15 +787,36 @@ template <int R>
 __global__ __launch_bounds__(EPI_THREADS) void k_als_C_epi(AlsArgs a, int nblk) {
   ALS_EPI_PROLOGUE(R)
   constexpr int RR = R * R;
-  __shared__ double tmp[RR + 2];
   (void)nblk;
-  team_sum(red + 2 * RR, 1, RR + 2, RR + 2, tmp);
-  for (int e = threadIdx.x; e < RR; e += EPI_THREADS) small[SM_WTW * RR + e] = tmp[e];
+  // third row of red: W^T W and the two error sums
+  constexpr int NU = (RR + 2 + EPI_THREADS - 1) / EPI_THREADS;
+  double v[NU];
+  epi_fetch(red + 2 * RR, RR + 2, v);
+  // the stop rule's inputs, read by thread 0 in the same round of loads
+  double ewg = 0.0, equad = 0.0, e0 = 0.0, eprev = 0.0, tol = -1.0;
+  int32_t it = 0, base = 0;
+  double* trace = nullptr;
   if (threadIdx.x == 0) {
-    const double e = ctl->e0 - 2.0 * tmp[RR] + tmp[RR + 1];
-    if (td.trace) td.trace[ctl->iters - ctl->base] = e;
-    ctl->iters += 1;
-    if (td.tol >= 0.0 && ctl->iters >= 2 && ctl->e_prev - e < td.tol * ctl->e_prev) ctl->done = 1;
+    ewg = red[3 * RR];
+    equad = red[3 * RR + 1];
+    e0 = ctl->e0;
+    eprev = ctl->e_prev;
+    it = ctl->iters;
+    base = ctl->base;
+    trace = td.trace;
+    tol = td.tol;
+  }
+  if (ctl->done) return;
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const int e = threadIdx.x + u * EPI_THREADS;
+    if (e < RR) small[SM_WTW * RR + e] = v[u];
+  }
+  if (threadIdx.x == 0) {
+    const double e = e0 - 2.0 * ewg + equad;
+    if (trace) trace[it - base] = e;
+    ctl->iters = it + 1;
+    if (tol >= 0.0 && it + 1 >= 2 && eprev - e < tol * eprev) ctl->done = 1;
     ctl->e_prev = e;
   }
 }
