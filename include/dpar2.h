@@ -151,9 +151,11 @@ size_t dpar2_workspace_size(const dpar2_tensor* X, const dpar2_opts* o);
  * slices); omega2: device float32 (K R) x L2 (second stage).  Leaves A_k (as a
  * recipe), M, D, E, F and sum ||X_k||^2 in the workspace.  The slab is read
  * 1 + opts.power_iters times.  For bf16 / fp8 slabs the sketch runs on the bf16
- * matrix cores with Omega rounded to bf16 (round to nearest even); the Gram
- * and projection are exact for every dtype.  Resets the iteration state and
- * report held in the workspace. */
+ * matrix cores with Omega rounded to bf16 (round to nearest even); for float32
+ * slabs of J <= 128 it sums products of three-piece bf16 splits of X and Omega
+ * (FP32-level error, Omega used as given).  The Gram and projection are exact
+ * for every dtype.  Resets the iteration state and report held in the
+ * workspace. */
 dpar2_status dpar2_compress(const dpar2_tensor* X, const dpar2_opts* o,
                             const float* omega1, const float* omega2,
                             void* ws, size_t ws_bytes, dpar2_stream_t stream);
