@@ -21,7 +21,7 @@ struct Item {
 
 constexpr int SKETCH_TM = 64;          // rows per tile of the slab pass
 constexpr int MAX_CHUNK_ROWS = 16384;  // longest item (rows)
-constexpr int STAGE2_CHUNK = 256;      // rows of M^T per second-stage block
+constexpr int STAGE2_CHUNK = 128;      // rows of M^T per second-stage block
 constexpr int ALS_THREADS = 256;
 
 // A group: tensors decomposed together, sharing J, R, L, L2, the dtype and the
