@@ -99,7 +99,7 @@ __device__ inline int group_jacobi(double (&t)[R], double (&v)[R], int j, int gb
   int sweep;
   for (sweep = 0; sweep < JACOBI_SWEEPS; ++sweep) {
     int rotated = 0;
-    double worst = 0.0;
+    int big = 0;   // some rotation had |a.b| / (|a| |b|) above 1e-7
     for (int r = 0; r < N - 1; ++r) {
       const int pc = (j < N) ? rr_partner(j, r, N) : j;
       const int src = gbase + pc;
@@ -121,7 +121,7 @@ __device__ inline int group_jacobi(double (&t)[R], double (&v)[R], int j, int gb
       const double alpha = low ? aa : bb, beta = low ? bb : aa;
       const double ab2 = ab * ab, ref = alpha * beta;
       if (j < N && pc != j && ab != 0.0 && ab2 > (JACOBI_TOL * JACOBI_TOL) * ref) {
-        worst = fmax(worst, ab2 / ref);
+        big |= (ab2 > 1e-14 * ref) ? 1 : 0;
         double c, s;
         jacobi_cs(alpha, beta, ab, &c, &s);
         rotated = 1;
@@ -135,7 +135,7 @@ __device__ inline int group_jacobi(double (&t)[R], double (&v)[R], int j, int gb
       }
     }
     if (!__any(rotated)) break;
-    if (!__any(worst > 1e-14)) {   // largest |a.b| / (|a| |b|) below 1e-7: quadratic
+    if (!__any(big)) {   // largest |a.b| / (|a| |b|) below 1e-7: quadratic
       ++sweep;                     // convergence leaves nothing for another sweep
       break;
     }

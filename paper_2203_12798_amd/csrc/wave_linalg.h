@@ -46,7 +46,7 @@ __device__ inline int split_jacobi(double (&t)[SC<L>::LH], double (&v)[SC<L>::LH
   int sweep;
   for (sweep = 0; sweep < JACOBI_SWEEPS; ++sweep) {
     int rotated = 0;
-    double worst = 0.0;
+    int big = 0;   // some rotation had |a.b| / (|a| |b|) above 1e-7
     for (int r = 0; r < N - 1; ++r) {
       const int pc = (c < N) ? rr_partner(c, r, N) : c;
       const int src = h * RM + pc;
@@ -74,7 +74,7 @@ __device__ inline int split_jacobi(double (&t)[SC<L>::LH], double (&v)[SC<L>::LH
       const double alpha = low ? aa : bb, beta = low ? bb : aa;
       const double ab2 = ab * ab, ref = alpha * beta;
       if (c < N && pc != c && ab != 0.0 && ab2 > (JACOBI_TOL * JACOBI_TOL) * ref) {
-        worst = fmax(worst, ab2 / ref);
+        big |= (ab2 > 1e-14 * ref) ? 1 : 0;
         double cs, sn;
         jacobi_cs(alpha, beta, ab, &cs, &sn);
         rotated = 1;
@@ -88,7 +88,7 @@ __device__ inline int split_jacobi(double (&t)[SC<L>::LH], double (&v)[SC<L>::LH
       }
     }
     if (!__any(rotated)) break;
-    if (!__any(worst > 1e-14)) {   // largest |a.b| / (|a| |b|) below 1e-7
+    if (!__any(big)) {   // largest |a.b| / (|a| |b|) below 1e-7
       ++sweep;
       break;
     }
