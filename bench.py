@@ -450,17 +450,22 @@ def main():
           file=sys.stderr, flush=True)
 
     T = d.Tensor.from_numpy(X.slab, X.offsets)
-    # work-item size of the slab pass from the autotuner (median of 3 timed launches each)
-    cands = (2048, 4096, 8192, 16384)
-    ws = d.alloc_workspace(T, d.Options(rank=R, sketch=L, sketch2=L2, max_iter=iters, item_rows=min(cands)))
+    # tiling of the slab pass from the autotuner (median of 3 timed launches
+    # each): work-item size, whole-row or 128-column-chunk pass
+    cands = [(2048, False), (4096, False), (8192, False), (16384, False), (4096, True), (16384, True)]
+    ws = d.alloc_workspace(T, d.Options(rank=R, sketch=L, sketch2=L2, max_iter=iters, item_rows=2048,
+                                        wide_slab=True))
     o1 = torch.from_numpy(om1).cuda()
     if args.item_rows:
-        item_rows, tune_ms = args.item_rows, None
+        item_rows, wide, tune_ms, tune_wide_ms = args.item_rows, False, None, None
     else:
-        item_rows, tune_ms = binding.autotune_item_rows(T, d.Options(rank=R, sketch=L, sketch2=L2, max_iter=iters),
-                                                        o1, ws, candidates=cands)
-    print(f"[bench] autotune item_rows: {tune_ms} -> {item_rows}", file=sys.stderr, flush=True)
-    o = d.Options(rank=R, sketch=L, sketch2=L2, max_iter=iters, item_rows=item_rows)
+        (item_rows, wide), times = binding.autotune_slab(
+            T, d.Options(rank=R, sketch=L, sketch2=L2, max_iter=iters), o1, ws, cands)
+        tune_ms = {str(r): t for (r, w), t in zip(cands, times) if not w}
+        tune_wide_ms = {str(r): t for (r, w), t in zip(cands, times) if w}
+    print(f"[bench] autotune: whole-row {tune_ms}, 128-column chunks {tune_wide_ms} -> "
+          f"{item_rows} rows per item{', chunked' if wide else ''}", file=sys.stderr, flush=True)
+    o = d.Options(rank=R, sketch=L, sketch2=L2, max_iter=iters, item_rows=item_rows, wide_slab=wide)
     o2 = torch.from_numpy(om2).cuda()
     init = [torch.from_numpy(a).cuda() for a in (H0, V0, W0)]
     f = d.Factors.from_numpy(H0, V0, W0)
@@ -560,8 +565,10 @@ def main():
     tr = traffic_record()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None if tr is None else tr["bytes_per_launch"],
-                "kernel": "k_sketch_q (slab pass: sketch from three-piece bf16 MFMA products, exact int8 MFMA Gram and projection)",
+                "traffic": None if (tr is None or wide) else tr["bytes_per_launch"],
+                "kernel": ("k_wide_y + k_wide_p (slab pass in 128-column chunks: FP32 MFMA sketch, FP64 MFMA "
+                           "Gram and projection)") if wide else
+                          "k_sketch_q (slab pass: sketch from three-piece bf16 MFMA products, exact int8 MFMA Gram and projection)",
                 "kernel_ms": round(sk_ms, 4), "algorithmic_bytes": int(alg_bytes),
                 "timed_launches": launches}
     sketch_tf = alg_flops / (sk_ms / 1e3) / 1e12
@@ -575,7 +582,8 @@ def main():
                                "median 1500, rank-10 PARAFAC2 + 5% noise; R=10 L=20 L2=20 32 iterations",
                    "K": K, "J": J, "N": int(X.N), "rank": R, "sketch": L, "iterations": iters},
         "roofline": roofline,
-        "autotune": {"item_rows": item_rows, "slab_pass_ms_by_item_rows": tune_ms},
+        "autotune": {"item_rows": item_rows, "pass": "128-column chunks" if wide else "whole rows",
+                     "slab_pass_ms_by_item_rows": tune_ms, "chunked_slab_pass_ms_by_item_rows": tune_wide_ms},
         "sketch_gemm": {"achieved_tflops": round(sketch_tf, 2),
                         "frac_of_fp32_mfma_peak": round(sketch_tf / FP32_MFMA_PEAK_TFLOPS, 4),
                         "note": "useful flops 4NJL+2NL^2; sketch at FP32-level accuracy, Gram and projection exact "

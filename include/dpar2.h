@@ -74,6 +74,14 @@ typedef enum {
  * current factors, tolerances and trace through the descriptors).  This
  * flag launches them one by one instead.  Results are identical. */
 #define DPAR2_FLAG_NO_GRAPH     0x1u
+/* dpar2_opts.flags: the first stage's slab pass (Sec. III-B, Eq. 4) in
+ * 128-column chunks (a sketch kernel that writes Y, then a projection kernel
+ * per chunk) for any J <= 16384, not only above the whole-row limit (J > 256
+ * for float32, > 128 for bf16 / fp8).  Reads the slab twice and needs
+ * N x 16 or N x 32 more floats of workspace (dpar2_workspace_size accounts
+ * for it).  Results agree with the whole-row pass to rounding;
+ * dpar2_autotune_slab chooses between the two. */
+#define DPAR2_FLAG_WIDE_SLAB    0x2u
 
 #define DPAR2_WARN_JACOBI_CAP   0x1u  /* a Jacobi eigen/SVD solve hit its sweep cap   */
 #define DPAR2_WARN_RANK_DEFICIENT 0x2u /* a T_k had a (near) zero singular value      */
@@ -232,6 +240,20 @@ dpar2_status dpar2_batch_report_read(int32_t n, const dpar2_tensor* X, const dpa
 dpar2_status dpar2_autotune_item_rows(const dpar2_tensor* X, const dpar2_opts* o, const float* omega1,
                                       const int32_t* cands, int32_t n_cands, void* ws, size_t ws_bytes,
                                       int32_t* best, float* times_ms, dpar2_stream_t stream);
+
+/* Autotuner of the slab pass's tiling for one tensor (the batching form's
+ * per-(J, L) choice): candidate c is the work-item size item_rows[c] (rows
+ * per unit of Alg. 4's scheduling, 0 or 64..65536) with the whole-row pass
+ * (wide[c] == 0) or the 128-column-chunk pass (wide[c] != 0, i.e.
+ * DPAR2_FLAG_WIDE_SLAB; the only one above the whole-row limit).  Each is
+ * timed as dpar2_autotune_item_rows does; *best (host) receives the index of
+ * the fastest, times_ms (host, n_cands, or NULL) the medians.  ws must be
+ * large enough for every candidate (dpar2_workspace_size of the options with
+ * the flag set, if any candidate sets it).  Synchronises the stream; the
+ * workspace's decomposition state is overwritten. */
+dpar2_status dpar2_autotune_slab(const dpar2_tensor* X, const dpar2_opts* o, const float* omega1,
+                                 const int32_t* item_rows, const int32_t* wide, int32_t n_cands, void* ws,
+                                 size_t ws_bytes, int32_t* best, float* times_ms, dpar2_stream_t stream);
 
 /* ---- Learned warm start ---------------------------------------------------
  * Not part of the paper: a set encoder proposes the starting H, V, W of the

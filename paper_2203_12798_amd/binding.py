@@ -23,6 +23,7 @@ DPAR2_F32 = 0
 DPAR2_BF16 = 1
 DPAR2_FP8_E4M3 = 2
 DPAR2_FLAG_NO_GRAPH = 0x1
+DPAR2_FLAG_WIDE_SLAB = 0x2
 
 WARN_JACOBI_CAP = 0x1
 WARN_RANK_DEFICIENT = 0x2
@@ -67,6 +68,7 @@ EXPORTS = ["dpar2_workspace_size", "dpar2_compress", "dpar2_als_step", "dpar2_fi
            "dpar2_batch_workspace_size", "dpar2_decompose_batch", "dpar2_batch_report_read",
            "dpar2_warm_param_count", "dpar2_warm_features", "dpar2_warm_targets", "dpar2_warm_apply",
            "dpar2_warm_forward", "dpar2_warm_backward", "dpar2_warm_adam", "dpar2_autotune_item_rows",
+           "dpar2_autotune_slab",
            "dpar2_profile_enable", "dpar2_profile_read", "dpar2_status_string", "dpar2_last_error"]
 
 _lib = None
@@ -128,6 +130,9 @@ def load(path: str = LIB_PATH):
     lib.dpar2_autotune_item_rows.restype = i32
     lib.dpar2_autotune_item_rows.argtypes = [P(c_tensor), P(c_opts), vp, P(i32), i32, vp, ctypes.c_size_t,
                                              P(i32), P(f32), vp]
+    lib.dpar2_autotune_slab.restype = i32
+    lib.dpar2_autotune_slab.argtypes = [P(c_tensor), P(c_opts), vp, P(i32), P(i32), i32, vp, ctypes.c_size_t,
+                                        P(i32), P(f32), vp]
     lib.dpar2_profile_enable.restype = ctypes.c_int32
     lib.dpar2_profile_enable.argtypes = [ctypes.c_int32]
     lib.dpar2_profile_read.restype = ctypes.c_int32
@@ -169,10 +174,12 @@ class Options:
     power_iters: int = 0
     graph: bool = True      # False sets DPAR2_FLAG_NO_GRAPH
     item_rows: int = 0      # 0: the library's default work-item size
+    wide_slab: bool = False  # True sets DPAR2_FLAG_WIDE_SLAB (128-column-chunk slab pass)
 
     def c(self) -> c_opts:
+        flags = (0 if self.graph else DPAR2_FLAG_NO_GRAPH) | (DPAR2_FLAG_WIDE_SLAB if self.wide_slab else 0)
         return c_opts(self.rank, self.sketch, self.sketch2, self.max_iter, float(self.tol),
-                      0 if self.graph else DPAR2_FLAG_NO_GRAPH, self.power_iters, self.item_rows)
+                      flags, self.power_iters, self.item_rows)
 
 
 class Tensor:
@@ -397,6 +404,22 @@ def autotune_item_rows(X: Tensor, o: Options, omega1, ws, candidates=(2048, 4096
     _check(lib.dpar2_autotune_item_rows(ctypes.byref(X.c()), ctypes.byref(o.c()), _ptr(omega1), c, len(candidates),
                                         p, n, ctypes.byref(best), t, _stream(stream)))
     return int(best.value), {int(k): float(v) for k, v in zip(candidates, t)}
+
+
+def autotune_slab(X: Tensor, o: Options, omega1, ws, candidates, stream=None):
+    """candidates: sequence of (item_rows, wide) pairs.  Returns (the fastest
+    pair, [median slab-pass ms of each]); ws must fit every candidate (see
+    workspace_size with Options.wide_slab=True if any candidate is wide)."""
+    lib = load()
+    p, n = _ws(ws)
+    m = len(candidates)
+    rows = (ctypes.c_int32 * m)(*[int(r) for r, _ in candidates])
+    wide = (ctypes.c_int32 * m)(*[1 if w else 0 for _, w in candidates])
+    t = (ctypes.c_float * m)()
+    best = ctypes.c_int32()
+    _check(lib.dpar2_autotune_slab(ctypes.byref(X.c()), ctypes.byref(o.c()), _ptr(omega1), rows, wide, m,
+                                   p, n, ctypes.byref(best), t, _stream(stream)))
+    return candidates[int(best.value)], [float(v) for v in t]
 
 
 # --- learned warm start ----------------------------------------------------

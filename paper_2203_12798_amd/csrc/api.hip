@@ -62,7 +62,7 @@ dpar2_status validate(const dpar2_tensor* X, const dpar2_opts* o) {
     return fail(DPAR2_EINVAL, "unsupported slab dtype");
   if (X->dtype == DPAR2_FP8_E4M3 && !X->slice_scale)
     return fail(DPAR2_EINVAL, "fp8 slabs need slice_scale");
-  if (o->flags & ~DPAR2_FLAG_NO_GRAPH) return fail(DPAR2_EINVAL, "unknown bits in opts.flags");
+  if (o->flags & ~(DPAR2_FLAG_NO_GRAPH | DPAR2_FLAG_WIDE_SLAB)) return fail(DPAR2_EINVAL, "unknown bits in opts.flags");
   if (o->item_rows != 0 && (o->item_rows < 64 || o->item_rows > 65536))
     return fail(DPAR2_EINVAL, "opts.item_rows must be 0 or in 64..65536");
   if (o->power_iters < 0 || o->power_iters > 4) return fail(DPAR2_EINVAL, "power_iters must be in [0, 4]");
@@ -272,8 +272,8 @@ Layout make_layout(const Group& g) {
   y.om1 = take(sizeof(float) * (size_t)(nt * J * L));      // copy of each Omega_1 for the U pass
   y.omq = take(y.q > 0 ? sizeof(float) * (size_t)(K * J * L) : 0);   // power-step sketches
   // the wide slab pass keeps Y (16 LT floats per row) between its two kernels
-  const bool wide = J > narrow_j_limit(g.X[0].dtype);
-  y.ybuf = take(wide ? sizeof(float) * (size_t)y.N * (L <= 16 ? 16 : 32) : 0);
+  y.wide = J > narrow_j_limit(g.X[0].dtype) || (o->flags & DPAR2_FLAG_WIDE_SLAB) != 0;
+  y.ybuf = take(y.wide ? sizeof(float) * (size_t)y.N * (L <= 16 ? 16 : 32) : 0);
   y.total = p;
   return y;
 }
@@ -547,7 +547,7 @@ dpar2_status group_compress(const Group& g, const float* const* om1, const float
     // slice's own matrix
     sa.omega = pass == 0 ? nullptr : omq;
     if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-    e = launch_slab(sa, dtype, y.n_items, vec, false, s);
+    e = launch_slab(sa, dtype, y.n_items, vec, false, y.wide, s);
     if (e != hipSuccess) return hip_fail(e, "slab pass");
     if (ev1 && (e = hipEventRecord(ev1, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     ev0 = ev1 = nullptr;   // the timing hooks cover the first pass
@@ -685,7 +685,7 @@ dpar2_status group_output_U(const Group& g, const Layout& y, char* w, const doub
   sa.U = U;
   sa.ybuf = reinterpret_cast<float*>(w + y.ybuf);
   const bool vec = (y.J % 4 == 0) && ((uintptr_t)g.X[0].slab % (4 * esize) == 0);
-  e = launch_slab(sa, dtype, y.n_items, vec, true, s);
+  e = launch_slab(sa, dtype, y.n_items, vec, true, y.wide, s);
   if (e != hipSuccess) return hip_fail(e, "U pass");
   return DPAR2_OK;
 }
@@ -1010,9 +1010,11 @@ dpar2_status dpar2_warm_adam(int32_t rank, float* theta, const float* grad, floa
   return e == hipSuccess ? DPAR2_OK : hip_fail(e, "warm adam");
 }
 
-dpar2_status dpar2_autotune_item_rows(const dpar2_tensor* X, const dpar2_opts* o, const float* omega1,
-                                      const int32_t* cands, int32_t n_cands, void* ws, size_t ws_bytes,
-                                      int32_t* best, float* times_ms, dpar2_stream_t stream) {
+// Times the first stage's slab pass for each candidate (work-item size,
+// whole-row or 128-column-chunk pass); *best = index of the fastest.
+static dpar2_status autotune_slab_impl(const dpar2_tensor* X, const dpar2_opts* o, const float* omega1,
+                                       const int32_t* cands, const int32_t* wide, int32_t n_cands, void* ws,
+                                       size_t ws_bytes, int32_t* best, float* times_ms, dpar2_stream_t stream) {
   if (!o || !cands || n_cands < 1 || !best || !omega1) return fail(DPAR2_EINVAL, "NULL argument or no candidates");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
@@ -1029,6 +1031,7 @@ dpar2_status dpar2_autotune_item_rows(const dpar2_tensor* X, const dpar2_opts* o
     dpar2_opts oc = *o;
     oc.item_rows = cands[c];
     oc.power_iters = 0;
+    oc.flags = (o->flags & ~DPAR2_FLAG_WIDE_SLAB) | ((wide && wide[c]) ? DPAR2_FLAG_WIDE_SLAB : 0u);
     Group g;
     if ((st = make_group(1, X, &oc, &g)) != DPAR2_OK) break;
     const Layout y = make_layout(g);
@@ -1060,7 +1063,7 @@ dpar2_status dpar2_autotune_item_rows(const dpar2_tensor* X, const dpar2_opts* o
     float t[4];
     for (int r = 0; r < 4 && st == DPAR2_OK; ++r) {   // one warm-up launch, three timed
       if ((e = hipEventRecord(e0, s)) != hipSuccess) st = hip_fail(e, "hipEventRecord");
-      else if ((e = launch_slab(sa, X->dtype, y.n_items, vec, false, s)) != hipSuccess) st = hip_fail(e, "slab pass");
+      else if ((e = launch_slab(sa, X->dtype, y.n_items, vec, false, y.wide, s)) != hipSuccess) st = hip_fail(e, "slab pass");
       else if ((e = hipEventRecord(e1, s)) != hipSuccess) st = hip_fail(e, "hipEventRecord");
       else if ((e = hipEventSynchronize(e1)) != hipSuccess) st = hip_fail(e, "hipEventSynchronize");
       else if ((e = hipEventElapsedTime(&t[r], e0, e1)) != hipSuccess) st = hip_fail(e, "hipEventElapsedTime");
@@ -1070,12 +1073,29 @@ dpar2_status dpar2_autotune_item_rows(const dpar2_tensor* X, const dpar2_opts* o
     if (times_ms) times_ms[c] = t[2];
     if (c == 0 || t[2] < best_ms) {
       best_ms = t[2];
-      *best = cands[c];
+      *best = c;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return st;
+}
+
+dpar2_status dpar2_autotune_item_rows(const dpar2_tensor* X, const dpar2_opts* o, const float* omega1,
+                                      const int32_t* cands, int32_t n_cands, void* ws, size_t ws_bytes,
+                                      int32_t* best, float* times_ms, dpar2_stream_t stream) {
+  int32_t idx = 0;
+  const dpar2_status st =
+      autotune_slab_impl(X, o, omega1, cands, nullptr, n_cands, ws, ws_bytes, &idx, times_ms, stream);
+  if (st == DPAR2_OK) *best = cands[idx];
+  return st;
+}
+
+dpar2_status dpar2_autotune_slab(const dpar2_tensor* X, const dpar2_opts* o, const float* omega1,
+                                 const int32_t* item_rows, const int32_t* wide, int32_t n_cands, void* ws,
+                                 size_t ws_bytes, int32_t* best, float* times_ms, dpar2_stream_t stream) {
+  if (!wide) return fail(DPAR2_EINVAL, "wide must be non-NULL");
+  return autotune_slab_impl(X, o, omega1, item_rows, wide, n_cands, ws, ws_bytes, best, times_ms, stream);
 }
 
 dpar2_status dpar2_profile_enable(int32_t on) {

@@ -72,6 +72,7 @@ struct Layout {
   // iteration
   size_t Psi, Pw, Mk, small, partA, partB, partC, partBegin, red, fitp, trace, om1, omq;
   size_t ybuf;            // wide-J slab pass: Y of every row (N x 16 LT floats), else empty
+  bool wide;              // slab pass in 128-column chunks (J above the narrow limit, or asked for)
   size_t tables_end;     // end of the host-built tables [tdesc, tables_end)
   size_t total;
 };
@@ -112,7 +113,8 @@ constexpr int MAX_J = 16384;
 // Slab pass over all work items: per-item partials of Y^T Y, Y^T X and
 // ||X||^2, or (uout) U = Y Theta_k.  dtype: dpar2_dtype; vec: every slab is
 // aligned for 4-element loads and J % 4 == 0.
-hipError_t launch_slab(const SlabArgs& a, int dtype, int64_t n_items, bool vec, bool uout, hipStream_t s);
+hipError_t launch_slab(const SlabArgs& a, int dtype, int64_t n_items, bool vec, bool uout, bool wide,
+                       hipStream_t s);
 // the wide form (J above narrow_j_limit), k_slab_wide.hip
 hipError_t launch_slab_wide(const SlabArgs& a, int dtype, int64_t n_items, bool vec, bool uout, hipStream_t s);
 // Per-slice completion of the first stage; omega_next (K x J x L float32, or

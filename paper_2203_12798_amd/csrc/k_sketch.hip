@@ -250,9 +250,10 @@ hipError_t slab_launch_f32(const SlabArgs& a, int64_t n_items, bool vec, bool uo
 hipError_t slab_launch_bf16(const SlabArgs& a, int64_t n_items, bool vec, bool uout, hipStream_t s);
 hipError_t slab_launch_fp8(const SlabArgs& a, int64_t n_items, bool vec, bool uout, hipStream_t s);
 
-hipError_t launch_slab(const SlabArgs& a, int dtype, int64_t n_items, bool vec, bool uout, hipStream_t s) {
+hipError_t launch_slab(const SlabArgs& a, int dtype, int64_t n_items, bool vec, bool uout, bool wide,
+                       hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  if (a.J > narrow_j_limit(dtype)) return launch_slab_wide(a, dtype, n_items, vec, uout, s);
+  if (wide || a.J > narrow_j_limit(dtype)) return launch_slab_wide(a, dtype, n_items, vec, uout, s);
   if (a.J > 128) return uout ? dispatch_wide<true>(a, n_items, vec, s) : dispatch_wide<false>(a, n_items, vec, s);
   if (dtype == DPAR2_F32) return slab_launch_f32(a, n_items, vec, uout, s);
   if (dtype == DPAR2_BF16) return slab_launch_bf16(a, n_items, vec, uout, s);

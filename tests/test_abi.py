@@ -130,6 +130,15 @@ def test_dtype_and_power_options_validated_on_host():
     t8 = binding.c_tensor(2, 8, 0x1000, hp, 0x2000, binding.DPAR2_F32, None)
     assert (lib.dpar2_workspace_size(ctypes.byref(t8), ctypes.byref(o1))
             >= lib.dpar2_workspace_size(ctypes.byref(t8), ctypes.byref(o)) + 2 * 8 * 3 * 4)
+    # the 128-column-chunk pass asked for below the limit keeps Y as well;
+    # unknown flag bits are rejected
+    ow = binding.c_opts(2, 3, 3, 5, -1.0, binding.DPAR2_FLAG_WIDE_SLAB, 0)
+    assert (lib.dpar2_workspace_size(ctypes.byref(t256), ctypes.byref(ow))
+            >= ws256 + 400 * 16 * 4)
+    assert lib.dpar2_workspace_size(ctypes.byref(t257), ctypes.byref(ow)) == ws257
+    ox = binding.c_opts(2, 3, 3, 5, -1.0, 0x4, 0)
+    assert _status(lib, binding, t8, ox) == -1
+    assert b"flags" in lib.dpar2_last_error()
 
 
 def test_batch_arguments_validated_on_host():

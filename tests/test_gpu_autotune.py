@@ -1,6 +1,7 @@
-"""The work-item size of the slab pass and its autotuner, through the C ABI:
-results with small items (long slices cut into many pieces) match the FP64
-oracle, and the autotuner times every candidate and returns the fastest."""
+"""The tiling of the slab pass and its autotuners, through the C ABI: results
+with small items (long slices cut into many pieces) and with the
+128-column-chunk pass below the whole-row limit match the FP64 oracle, and the
+autotuners time every candidate and return the fastest."""
 import numpy as np
 import pytest
 
@@ -63,3 +64,46 @@ def test_autotuner_returns_fastest_candidate():
     assert best in cands
     assert all(t > 0 for t in times.values())
     assert times[best] == min(times.values())
+
+
+@pytest.mark.parametrize("case", ["small_parity", "stock_like"])
+def test_chunked_slab_pass_below_limit_matches_oracle(case):
+    """DPAR2_FLAG_WIDE_SLAB with J below the whole-row limit: J = 32, L = 15
+    (one partial 128-column chunk, one 16-column L-tile) and the stock-shaped
+    J = 88, L = 20 (two L-tiles), with the U output; the same bounds as the
+    whole-row pass."""
+    if case == "small_parity":
+        X, R, L, iters = synth.small_parity(seed=9), 5, 15, 40
+    else:
+        X, R, L, iters = synth.stock_like(K=60, seed=4), 10, 20, 32
+    om1, om2 = synth.omegas(X.J, L, X.K * R)
+    H0, V0, W0 = synth.init_factors(X.J, X.K, R)
+    ref = O.dpar2(X.slab, X.offsets, R, om1, om2, H0, V0, W0, iters)
+    g = _run_gpu(X, R, L, L, iters, om1, om2, H0, V0, W0, want_U=True, wide_slab=True)
+    _check_compression(X, R, g, ref)
+    _check_errors(g, ref)
+    _check_factors(g, ref)
+    assert abs(g["rep"]["fit_true"] - ref.fit) < 1e-6
+    assert np.linalg.norm(g["U"] - np.concatenate(ref.U, axis=0)) <= 1e-5 * np.linalg.norm(np.concatenate(ref.U))
+    assert g["rep"]["warn_bits"] == 0
+
+
+def test_slab_autotuner_chooses_among_passes_and_item_sizes():
+    """dpar2_autotune_slab over (item_rows, chunked) pairs: every candidate is
+    timed and the index of the fastest is returned."""
+    torch = _torch()
+    import paper_2203_12798_amd as d
+    from paper_2203_12798_amd import binding as b
+    X = _long_case()
+    R, L = 4, 10
+    print("[gpu] slab autotune", flush=True)
+    om1, _ = synth.omegas(X.J, L, X.K * R)
+    T = d.Tensor.from_numpy(X.slab, X.offsets)
+    cands = [(256, False), (4096, False), (256, True), (0, True)]
+    ws = d.alloc_workspace(T, d.Options(rank=R, sketch=L, sketch2=L, max_iter=5, item_rows=256, wide_slab=True))
+    best, times = b.autotune_slab(T, d.Options(rank=R, sketch=L, sketch2=L, max_iter=5),
+                                  torch.from_numpy(om1).cuda(), ws, cands)
+    print(f"[autotune] {list(zip(cands, times))} -> {best}", flush=True)
+    assert best in cands
+    assert all(t > 0 for t in times)
+    assert times[cands.index(best)] == min(times)

@@ -21,14 +21,15 @@ def _torch():
 
 
 def _run_gpu(X, R, L, L2, iters, om1, om2, H0, V0, W0, tol=-1.0, want_U=False, trace=True, T=None,
-             power_iters=0):
+             power_iters=0, wide_slab=False):
     torch = _torch()
     import paper_2203_12798_amd as d
     print(f"[gpu] K={X.K} J={X.J} N={X.N} R={R} L={L} L2={L2} iters={iters} q={power_iters}"
-          f"{'' if T is None else ' dtype=' + str(T.dtype)}", flush=True)
+          f"{'' if T is None else ' dtype=' + str(T.dtype)}{' wide slab pass' if wide_slab else ''}", flush=True)
     if T is None:
         T = d.Tensor.from_numpy(X.slab, X.offsets)
-    o = d.Options(rank=R, sketch=L, sketch2=L2, max_iter=iters, tol=tol, power_iters=power_iters)
+    o = d.Options(rank=R, sketch=L, sketch2=L2, max_iter=iters, tol=tol, power_iters=power_iters,
+                  wide_slab=wide_slab)
     f = d.Factors.from_numpy(H0, V0, W0)
     ws = d.alloc_workspace(T, o)
     o1 = torch.from_numpy(om1).cuda()
