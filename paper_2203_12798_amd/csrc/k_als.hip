@@ -40,13 +40,24 @@ __global__ void k_als_vmat(int J, int R, const TDesc* __restrict__ td, const dou
 }
 
 // Fitness partials, one slice per block: tr(V S_k H^T Psi_k^T (C_k B_k)^T)
-// and W(k,:)(H^T H * V^T V)W(k,:)^T.
+// and W(k,:)(H^T H * V^T V)W(k,:)^T.  LDS sized for the rank
+// (fit_part_lds_bytes), so that several blocks share a compute unit.
+__host__ __device__ inline size_t fit_part_lds_doubles(int R) {
+  return (size_t)3 * R * 33 + (size_t)R * 65 + (size_t)64 * (R + 1) + 16;
+}
+
 __global__ __launch_bounds__(256) void k_fit_part(int J, int R, const TDesc* __restrict__ td,
                                                   const int32_t* __restrict__ slice_t,
                                                   const double* __restrict__ Mt, const double* __restrict__ Psi,
                                                   const double* __restrict__ small, double* __restrict__ fitp) {
-  __shared__ double Q[32 * 33], sPsi[32 * 33], sH[32 * 33], red[16];
-  __shared__ double sM[32 * 65], sV[64 * 33];
+  extern __shared__ double fit_lds[];
+  double* Q = fit_lds;                 // R x 33
+  double* sPsi = Q + R * 33;           // R x 33
+  double* sH = sPsi + R * 33;          // R x 33
+  double* sM = sH + R * 33;            // R x 65
+  double* sV = sM + R * 65;            // 64 x (R + 1)
+  double* red = sV + 64 * (R + 1);     // 16
+  const int SV = R + 1;
   const int tid = threadIdx.x, RR = R * R;
   const int64_t k = blockIdx.x;
   const int t = slice_t[k];
@@ -71,7 +82,7 @@ __global__ __launch_bounds__(256) void k_fit_part(int J, int R, const TDesc* __r
     }
     for (int e = tid; e < 64 * R; e += 256) {
       const int jj = e / R, c = e % R;
-      sV[jj * 33 + c] = jj < nj ? V[(size_t)(j0 + jj) * R + c] : 0.0;
+      sV[jj * SV + c] = jj < nj ? V[(size_t)(j0 + jj) * R + c] : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -80,7 +91,7 @@ __global__ __launch_bounds__(256) void k_fit_part(int J, int R, const TDesc* __r
       if (e < RR) {
         const int r = e / R, c = e % R;
         double a = acc[q];
-        for (int jj = 0; jj < nj; ++jj) a = fma(sM[r * 65 + jj], sV[jj * 33 + c], a);
+        for (int jj = 0; jj < nj; ++jj) a = fma(sM[r * 65 + jj], sV[jj * SV + c], a);
         acc[q] = a;
       }
     }
@@ -213,7 +224,8 @@ hipError_t launch_als_end(const Layout& lay, char* ws, hipStream_t s) {
 hipError_t launch_fitness(const Layout& lay, char* ws, double* fit, hipStream_t s) {
   double* fitp = reinterpret_cast<double*>(ws + lay.fitp);
   double* fits = fitp + 2 * lay.K;   // nt x 2 sums after the K per-slice partials
-  hipLaunchKernelGGL(k_fit_part, dim3((unsigned)lay.K), dim3(256), 0, s, (int)lay.J, lay.R,
+  hipLaunchKernelGGL(k_fit_part, dim3((unsigned)lay.K), dim3(256), sizeof(double) * fit_part_lds_doubles(lay.R), s,
+                     (int)lay.J, lay.R,
                      reinterpret_cast<const TDesc*>(ws + lay.tdesc),
                      reinterpret_cast<const int32_t*>(ws + lay.slice_t), reinterpret_cast<const double*>(ws + lay.Mt),
                      reinterpret_cast<const double*>(ws + lay.Psi), reinterpret_cast<const double*>(ws + lay.small),
