@@ -166,7 +166,8 @@ __device__ inline bool wave_spd_inverse(const double* G, double* Ginv) {
     for (int i = 0; i < R; ++i) colp[i] = __shfl(col[i], p, 64);
     const double piv = colp[p];
     ok = ok && (piv > 1e-13 * dmax);
-    const double f = col[p] / piv;
+    // a pivot that fails the test leaves garbage, discarded with ok = false
+    const double f = col[p] * nr_rcp(piv);
 #pragma unroll
     for (int i = 0; i < R; ++i)
       if (i != p) col[i] = fma(-colp[i], f, col[i]);
