@@ -209,3 +209,31 @@ def test_item_rows_option():
                                                         binding.c_opts(2, 3, 3, 5, -1.0, 0, 0, 512)))
     al = lambda n: (n + 255) // 256 * 256
     assert two == al(size(0)) + al(size(512)) and one < two
+
+
+def test_wide_slab_flag_and_autotuner_arguments():
+    """DPAR2_FLAG_WIDE_SLAB is part of the group key (a batch mixing it forms
+    two groups); the slab autotuner rejects missing candidate arrays before
+    touching the device."""
+    binding, lib = _lib()
+    off = np.array([0, 500, 900], dtype=np.int64)
+    h = off.ctypes.data_as(ctypes.c_void_p).value
+    t = binding.c_tensor(2, 24, 0x1000, h, 0x2000, binding.DPAR2_F32, None)
+    o = binding.c_opts(2, 3, 3, 5, -1.0, 0, 0, 0)
+    ow = binding.c_opts(2, 3, 3, 5, -1.0, binding.DPAR2_FLAG_WIDE_SLAB, 0, 0)
+    one = lib.dpar2_workspace_size(ctypes.byref(t), ctypes.byref(o))
+    wide = lib.dpar2_workspace_size(ctypes.byref(t), ctypes.byref(ow))
+    assert wide >= one + 900 * 16 * 4
+    T = binding.c_tensor * 2
+    O = binding.c_opts * 2
+    al = lambda n: (n + 255) // 256 * 256
+    assert lib.dpar2_batch_workspace_size(2, T(t, t), O(o, ow)) == al(one) + al(wide)
+    rows = (ctypes.c_int32 * 2)(0, 0)
+    best = ctypes.c_int32()
+    st = lib.dpar2_autotune_slab(ctypes.byref(t), ctypes.byref(o), ctypes.c_void_p(0x3000), rows, None, 2,
+                                 ctypes.c_void_p(0x4000), 1 << 30, ctypes.byref(best), None, None)
+    assert st == -1
+    assert b"wide" in lib.dpar2_last_error()
+    st = lib.dpar2_autotune_slab(ctypes.byref(t), ctypes.byref(o), ctypes.c_void_p(0x3000), None, rows, 2,
+                                 ctypes.c_void_p(0x4000), 1 << 30, ctypes.byref(best), None, None)
+    assert st == -1
