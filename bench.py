@@ -427,8 +427,8 @@ def main():
         write_traffic(*args.write_traffic)
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(slices would shard across GPUs; see the design notes)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(slices would shard across GPUs by longest-first partitioning of I_k)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
