@@ -78,6 +78,55 @@ def test_power_iteration_improves_capture():
     assert opt <= r1 + 1e-12 and r1 <= r0 + 1e-12
 
 
+def _rsvd_noop_power(A, R, omega, q=0):
+    """A deliberately broken copy of Alg. 1 whose power loop changes nothing
+    (the span stays that of A Omega).  Kept so that the power-step pin below
+    is shown to reject it."""
+    A = np.asarray(A, dtype=np.float64)
+    Y = A @ np.asarray(omega, dtype=np.float64)
+    for _ in range(q):
+        Q, _ = O.qr_pos(Y)
+        Z, _ = O.qr_pos(A.T @ Q)
+    Q, _ = O.qr_pos(Y)
+    Ut, s, Vt = np.linalg.svd(Q.T @ A, full_matrices=False)
+    return Q @ Ut[:, :R], s[:R], Vt[:R].T
+
+
+def _projector(M):
+    Q, _ = np.linalg.qr(M)
+    return Q @ Q.T
+
+
+def _power_span_error(rsvd, q):
+    """Distance between the range Alg. 1 returns with R = L (so that span(U)
+    is the whole sketch span) and span((A A^T)^q A Omega) formed literally,
+    without any re-orthonormalisation, on a well-conditioned A (singular
+    values in [1, 2], so the literal product loses nothing)."""
+    rng = np.random.default_rng(31)
+    Uo, _ = np.linalg.qr(rng.standard_normal((40, 12)))
+    Vo, _ = np.linalg.qr(rng.standard_normal((12, 12)))
+    A = Uo @ np.diag(np.linspace(2.0, 1.0, 12)) @ Vo.T
+    om = rng.standard_normal((12, 5))
+    U, _, _ = rsvd(A, 5, om, q)
+    Y = A @ om
+    for _ in range(q):
+        Y = A @ (A.T @ Y)
+    return float(np.linalg.norm(U @ U.T - _projector(Y))), float(np.linalg.norm(U @ U.T - _projector(A @ om)))
+
+
+@pytest.mark.parametrize("q", [1, 2])
+def test_power_iteration_spans_literal_power_product(q):
+    """Alg. 1 with q power steps: span(Y) = span((A A^T)^q A Omega).  The
+    oracle's stabilised loop must reach the literal product's span (1e-10),
+    which differs clearly from span(A Omega); a power loop that does nothing
+    fails the same check."""
+    err, vs_q0 = _power_span_error(O.randomized_svd, q)
+    assert err < 1e-10, err
+    assert vs_q0 > 1e-2, vs_q0            # q >= 1 really moves the subspace
+    bad, _ = _power_span_error(_rsvd_noop_power, q)
+    assert bad > 1e-2, bad
+
+
 # ---------------------------------------------------------------------------
 # Two-stage compression (Sec. III-B)
 # ---------------------------------------------------------------------------

@@ -144,3 +144,102 @@ def test_adam_without_moments_is_a_sign_step():
     np.testing.assert_allclose(new, th - 0.01 * np.sign(g), atol=1e-15)
     np.testing.assert_allclose(m, g)
     np.testing.assert_allclose(v, g * g)
+
+
+# ---------------------------------------------------------------------------
+# Forward pass: set-encoder structure, and Adam beyond the degenerate case
+# ---------------------------------------------------------------------------
+
+def _forward_sum_pool(theta, tok, R):
+    """A deliberately broken copy of the forward pass that pools by summing
+    instead of averaging; kept so that the pins below are shown to reject it."""
+    P = WO.unpack(theta, R)
+    x = np.asarray(tok, dtype=np.float64)
+    K = x.shape[0]
+    Z1 = np.maximum(x @ P["W1"].T + P["b1"], 0.0)
+    Z2 = np.maximum(Z1 @ P["W2"].T + P["b2"], 0.0)
+    p = Z2.sum(axis=0)
+    pH = (P["WH"] @ p + P["bH"]).reshape(R, R)
+    pV = (P["WV"] @ p + P["bV"]).reshape(R, R)
+    cat = np.concatenate([Z2, np.broadcast_to(p, (K, WO.WIDTH))], axis=1)
+    return pH, pV, cat @ P["Ww"].T + P["bw"], None
+
+
+def _set_encoder_ok(fwd):
+    """A set encoder with mean pooling: permuting the tokens permutes the
+    per-slice head and leaves the pooled heads alone; repeating every token
+    (the same set with each slice twice) changes neither pooled head."""
+    R = 3
+    theta, tok, *_ = _problem(5, K=6, R=R)
+    pH, pV, pW, _ = fwd(theta, tok, R)
+    perm = np.array([4, 0, 5, 2, 1, 3])
+    qH, qV, qW, _ = fwd(theta, tok[perm], R)
+    ok = np.allclose(qH, pH, atol=1e-12) and np.allclose(qV, pV, atol=1e-12) and \
+        np.allclose(qW, pW[perm], atol=1e-12)
+    dH, dV, dW, _ = fwd(theta, np.concatenate([tok, tok]), R)
+    return ok and np.allclose(dH, pH, atol=1e-12) and np.allclose(dV, pV, atol=1e-12) and \
+        np.allclose(dW, np.concatenate([pW, pW]), atol=1e-12)
+
+
+def test_forward_is_a_mean_pooled_set_encoder():
+    assert _set_encoder_ok(WO.forward)
+    assert not _set_encoder_ok(_forward_sum_pool)
+
+
+def _hand_network():
+    """R = 1 (one feature per token) with every weight zero except a few, so
+    the outputs can be worked out by hand (see the test)."""
+    R = 1
+    th = np.zeros(WO.n_params(R))
+    P = WO.unpack(th, R)            # fill the blocks, then pack them back
+    P["W1"][0, 0], P["W1"][1, 0] = 1.0, -1.0
+    P["W2"][0, 0], P["W2"][0, 1], P["W2"][1, 0], P["W2"][1, 1] = 1.0, 1.0, -1.0, 2.0
+    P["b2"][0], P["b2"][1] = -1.0, 0.5
+    P["WH"][0, 0], P["WH"][0, 1], P["bH"][0] = 0.5, -1.0, 0.25
+    P["WV"][0, 0], P["WV"][0, 1], P["bV"][0] = 2.0, 0.5, -1.0
+    P["Ww"][0, 0], P["Ww"][0, WO.WIDTH], P["Ww"][0, WO.WIDTH + 1], P["bw"][0] = 1.0, 10.0, -1.0, 0.5
+    return WO.pack(P, R), R
+
+
+def test_forward_hand_computed_two_token_network():
+    """Tokens 2 and -3.  Layer 1 (rows 1, -1 of W1): [2, 0] and [0, 3].
+    Layer 2 (rows [1 1], [-1 2], bias [-1, 0.5]): [relu(1), relu(-1.5)] = [1, 0]
+    and [relu(2), relu(6.5)] = [2, 6.5].  Mean pool p = [1.5, 3.25].
+    pH = 0.5 * 1.5 - 3.25 + 0.25 = -2.25;  pV = 2 * 1.5 + 0.5 * 3.25 - 1 = 3.625;
+    pW_k = Z2_k[0] + 10 p[0] - p[1] + 0.5 = 13.25 and 14.25."""
+    th, R = _hand_network()
+    pH, pV, pW, _ = WO.forward(th, np.array([[2.0], [-3.0]]), R)
+    assert pH.shape == (1, 1) and pV.shape == (1, 1) and pW.shape == (2, 1)
+    assert pH[0, 0] == -2.25 and pV[0, 0] == 3.625
+    np.testing.assert_array_equal(pW[:, 0], [13.25, 14.25])
+    sH, _, _, _ = _forward_sum_pool(th, np.array([[2.0], [-3.0]]), R)
+    assert sH[0, 0] != -2.25
+
+
+def _adam_no_bias_correction(theta, grad, m, v, step, lr, b1, b2, eps):
+    """A deliberately broken Adam without the 1 - beta^t corrections."""
+    m = b1 * m + (1.0 - b1) * grad
+    v = b2 * v + (1.0 - b2) * grad * grad
+    return theta - lr * m / (np.sqrt(v) + eps), m, v
+
+
+def _constant_gradient_steps_are_sign_steps(adam):
+    """With a constant gradient g the bias-corrected moments are exactly g and
+    g^2 at every step (Kingma & Ba, Sec. 3), so with eps -> 0 each of the
+    first steps moves every parameter by lr against the sign of g, for the
+    usual beta1 = 0.9, beta2 = 0.999."""
+    rng = np.random.default_rng(8)
+    th0 = rng.standard_normal(40)
+    g = rng.standard_normal(40) * 10.0 ** rng.uniform(-3, 3, 40)
+    th, m, v = th0.copy(), np.zeros(40), np.zeros(40)
+    for t in range(1, 6):
+        new, m, v = adam(th, g, m, v, t, 1e-2, 0.9, 0.999, 1e-300)
+        if not np.allclose(new, th - 1e-2 * np.sign(g), rtol=0, atol=1e-12):
+            return False
+        th = new
+    return True
+
+
+def test_adam_bias_correction_with_usual_betas():
+    assert _constant_gradient_steps_are_sign_steps(WO.adam)
+    assert not _constant_gradient_steps_are_sign_steps(_adam_no_bias_correction)
