@@ -14,14 +14,19 @@
  *   - dpar2_fitness    : fitness of Sec. IV-A against the original slices, from
  *                        the compressed factors (no second pass over the slab).
  *   - dpar2_output_U   : U_k = A_k Z_k P_k^T H (last lines of Alg. 3).
+ *   - dpar2_output_A   : the first-stage factors A_k of Eq. 4.
  *   - dpar2_decompose  : all of the above, Alg. 3 end to end.
  *
  * Conventions (all calls):
  *   - Pointers are DEVICE pointers unless marked (host).  The caller owns every
  *     buffer; the library never allocates or frees device memory.  All
  *     intermediate data lives in one caller-provided workspace whose size comes
- *     from dpar2_workspace_size(); compress, als_step, fitness and output_U of
- *     one decomposition must be given the same workspace.
+ *     from dpar2_workspace_bytes(); compress, als_step, fitness, output_U and
+ *     output_A of one decomposition must be given the same workspace.
+ *   - Host-side state: per workspace the library keeps a small ring of pinned
+ *     staging buffers for the schedule upload and the HIP graphs of captured
+ *     iterations; dpar2_release(ws) frees them (dpar2_release_all for every
+ *     workspace), after which the workspace may be freed or reused.
  *   - Work is enqueued on the caller's stream `stream` and is asynchronous;
  *     results are valid after the stream is synchronised.  Calls on different
  *     streams need different workspaces.  The only host<->device copies the
@@ -53,17 +58,21 @@ typedef enum {
   DPAR2_OK = 0,
   DPAR2_EINVAL = -1,     /* NULL pointer, bad option value, malformed row_offsets   */
   DPAR2_ESHAPE = -2,     /* rank / sketch width incompatible with K, J or some I_k  */
-  DPAR2_ENUMERIC = -3,   /* reserved for numerical failures                         */
+  DPAR2_ENUMERIC = -3,   /* the slab holds NaN or Inf (some ||X_k||^2 is not finite):
+                            reported by dpar2_report_read / dpar2_decompose (rep) */
+  DPAR2_ENOCONV = -4,    /* dpar2_decompose with a report and tol >= 0: the stop
+                            rule did not fire within max_iter (results are valid) */
   DPAR2_EHIP = -5,       /* a HIP runtime call failed (see dpar2_last_error)        */
   DPAR2_EWORKSPACE = -6  /* workspace NULL, misaligned (256 B) or too small         */
 } dpar2_status;
 
 typedef enum {
   DPAR2_F32 = 0,         /* slab of float32 values                                  */
-  DPAR2_BF16 = 1,        /* slab of bfloat16 bit patterns (uint16); J <= 128         */
+  DPAR2_BF16 = 1,        /* slab of bfloat16 bit patterns (uint16)                   */
   DPAR2_FP8_E4M3 = 2     /* slab of OCP fp8 e4m3fn bytes; value = decode(byte) *
-                            slice_scale[k] in float32 (powers of two keep it exact);
-                            J <= 128                                                 */
+                            slice_scale[k] in float32 (powers of two keep it exact)  */
+  /* every dtype: J <= 16384; the whole-row slab pass covers J <= 256 (float32)
+     or J <= 128 (bf16, fp8), the 128-column-chunk pass the rest */
 } dpar2_dtype;
 
 /* Warning bits reported in dpar2_report.warn_bits (device-side, never fatal). */
@@ -78,13 +87,23 @@ typedef enum {
  * 128-column chunks (a sketch kernel that writes Y, then a projection kernel
  * per chunk) for any J <= 16384, not only above the whole-row limit (J > 256
  * for float32, > 128 for bf16 / fp8).  Reads the slab twice and needs
- * N x 16 or N x 32 more floats of workspace (dpar2_workspace_size accounts
+ * N x 16 or N x 32 more floats of workspace (dpar2_workspace_bytes accounts
  * for it).  Results agree with the whole-row pass to rounding;
  * dpar2_autotune_slab chooses between the two. */
 #define DPAR2_FLAG_WIDE_SLAB    0x2u
 
+/* dpar2_opts.flags: resumable bit for bit.  Every iteration ends in the state
+ * a new dpar2_als_step call starts from (V written back as a J x R array and
+ * W^T W, V^T V, E D^T V recomputed from the factors as at the start of a
+ * call), so that n1 iterations followed by n2 more on the same workspace give
+ * the same bits as n1 + n2 in one call.  Costs four more launches per
+ * iteration.  Without the flag the two differ by rounding only. */
+#define DPAR2_FLAG_DETERMINISTIC 0x4u
+
 #define DPAR2_WARN_JACOBI_CAP   0x1u  /* a Jacobi eigen/SVD solve hit its sweep cap   */
 #define DPAR2_WARN_RANK_DEFICIENT 0x2u /* a T_k had a (near) zero singular value      */
+#define DPAR2_WARN_NONFINITE    0x4u  /* the slab holds NaN or Inf: the tensor's
+                                         iteration is skipped (status ENUMERIC)      */
 
 /* Irregular dense tensor {X_k}, k = 0..K-1, X_k in R^{I_k x J} (Sec. II-A). */
 typedef struct {
@@ -151,7 +170,9 @@ typedef struct {
 } dpar2_report;
 
 /* Bytes of device workspace needed for a decomposition of X with options o
- * (host only, pure; 0 on invalid arguments). */
+ * (host only, pure; 0 on invalid arguments).  dpar2_workspace_size is the
+ * same function under its earlier name. */
+size_t dpar2_workspace_bytes(const dpar2_tensor* X, const dpar2_opts* o);
 size_t dpar2_workspace_size(const dpar2_tensor* X, const dpar2_opts* o);
 
 /* Sec. III-B, two-stage compression (Alg. 3, first loop and the two lines
@@ -161,9 +182,14 @@ size_t dpar2_workspace_size(const dpar2_tensor* X, const dpar2_opts* o);
  * 1 + opts.power_iters times.  For bf16 / fp8 slabs the sketch runs on the bf16
  * matrix cores with Omega rounded to bf16 (round to nearest even); for float32
  * slabs of J <= 128 it sums products of three-piece bf16 splits of X and Omega
- * (FP32-level error, Omega used as given).  The Gram and projection are exact
- * for every dtype.  Resets the iteration state and report held in the
- * workspace. */
+ * (FP32-level error, Omega used as given).  The Gram Y^T Y and projection
+ * Y^T X of the whole-row pass (J <= 256 float32, J <= 128 otherwise) are the
+ * exact products of X and Y rounded to 22-bit fixed point per column of each
+ * 64-row tile (relative to that tile column's largest magnitude: an entry
+ * 2^22 times smaller than its tile column's maximum rounds to zero); the
+ * 128-column-chunk pass forms them from float32 Y and X on the FP64 matrix
+ * cores.  A NaN or Inf in the slab sets DPAR2_WARN_NONFINITE.  Resets the
+ * iteration state and report held in the workspace. */
 dpar2_status dpar2_compress(const dpar2_tensor* X, const dpar2_opts* o,
                             const float* omega1, const float* omega2,
                             void* ws, size_t ws_bytes, dpar2_stream_t stream);
@@ -188,12 +214,24 @@ dpar2_status dpar2_fitness(const dpar2_tensor* X, const dpar2_opts* o, const dpa
 dpar2_status dpar2_output_U(const dpar2_tensor* X, const dpar2_opts* o, const dpar2_factors* f,
                             double* U, void* ws, size_t ws_bytes, dpar2_stream_t stream);
 
+/* Alg. 3 output A_k (Eq. 4, the column-orthonormal first-stage factor of
+ * X_k, I_k x R) for all k: A device float64 N x R (row i of slice k at row
+ * row_offsets[k] + i), after dpar2_compress.  Reads the slab once more
+ * (A_k = Y_k Phi_k recomputed tile by tile; the workspace keeps only the
+ * L x R recipe Phi_k). */
+dpar2_status dpar2_output_A(const dpar2_tensor* X, const dpar2_opts* o, double* A,
+                            void* ws, size_t ws_bytes, dpar2_stream_t stream);
+
 /* Alg. 3 end to end: compress, iterate from the factors in `f` (in/out),
  * then the fitness (written into the workspace report) and, if U != NULL,
- * U_k.  Enqueue only; read the report with dpar2_report_read. */
+ * U_k.  rep (host) NULL: enqueue only, read the report later with
+ * dpar2_report_read.  rep != NULL: synchronises the stream, fills *rep and
+ * returns DPAR2_ENUMERIC if the slab held NaN or Inf, else DPAR2_ENOCONV if
+ * tol >= 0 and the stop rule did not fire within max_iter (results valid),
+ * else DPAR2_OK. */
 dpar2_status dpar2_decompose(const dpar2_tensor* X, const dpar2_opts* o,
                              const float* omega1, const float* omega2,
-                             dpar2_factors* f, double* U,
+                             dpar2_factors* f, double* U, dpar2_report* rep,
                              void* ws, size_t ws_bytes, dpar2_stream_t stream);
 
 /* Fills *out (host struct) with device pointers into the workspace (host-only
@@ -202,7 +240,8 @@ dpar2_status dpar2_compressed_view(const dpar2_tensor* X, const dpar2_opts* o, c
                                    size_t ws_bytes, dpar2_compressed* out);
 
 /* Synchronises `stream` and copies the report held in the workspace to *rep
- * (host). */
+ * (host).  Returns DPAR2_ENUMERIC (report filled) if the slab held NaN or
+ * Inf. */
 dpar2_status dpar2_report_read(const dpar2_tensor* X, const dpar2_opts* o, const void* ws,
                                dpar2_report* rep, dpar2_stream_t stream);
 
@@ -220,7 +259,9 @@ dpar2_status dpar2_report_read(const dpar2_tensor* X, const dpar2_opts* o, const
  * receives the result.  Each tensor's result is bit-for-bit the result of
  * dpar2_decompose on that tensor alone (no U output here).  Workspace from
  * dpar2_batch_workspace_size (the groups' layouts end to end); reports from
- * dpar2_batch_report_read (rep: host array of n, in the caller's order). */
+ * dpar2_batch_report_read (rep: host array of n, in the caller's order;
+ * returns DPAR2_ENUMERIC, all reports filled, if some tensor's slab held
+ * NaN or Inf). */
 size_t dpar2_batch_workspace_size(int32_t n, const dpar2_tensor* X, const dpar2_opts* o);
 dpar2_status dpar2_decompose_batch(int32_t n, const dpar2_tensor* X, const dpar2_opts* o,
                                    const float* const* omega1, const float* const* omega2,
@@ -325,6 +366,15 @@ dpar2_status dpar2_warm_adam(int32_t rank, float* theta, const float* grad, floa
  * milliseconds (host pointers), and clears the record.  Process-wide. */
 dpar2_status dpar2_profile_enable(int32_t on);
 dpar2_status dpar2_profile_read(int32_t* launches, double* total_ms);
+
+/* Frees the host-side state the library keeps for workspace ws (pinned
+ * staging buffers of the schedule upload, graphs of captured iterations),
+ * after waiting for the uploads out of that staging to finish.  Call it
+ * before freeing or repurposing ws; a later call on ws rebuilds the state.
+ * Unknown ws: no-op.  dpar2_release_all does it for every workspace and also
+ * frees the batch stream pool. */
+dpar2_status dpar2_release(const void* ws);
+dpar2_status dpar2_release_all(void);
 
 /* Static description of a status code. */
 const char* dpar2_status_string(int32_t status);

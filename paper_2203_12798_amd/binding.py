@@ -17,6 +17,7 @@ DPAR2_OK = 0
 DPAR2_EINVAL = -1
 DPAR2_ESHAPE = -2
 DPAR2_ENUMERIC = -3
+DPAR2_ENOCONV = -4
 DPAR2_EHIP = -5
 DPAR2_EWORKSPACE = -6
 DPAR2_F32 = 0
@@ -24,15 +25,22 @@ DPAR2_BF16 = 1
 DPAR2_FP8_E4M3 = 2
 DPAR2_FLAG_NO_GRAPH = 0x1
 DPAR2_FLAG_WIDE_SLAB = 0x2
+DPAR2_FLAG_DETERMINISTIC = 0x4
 
 WARN_JACOBI_CAP = 0x1
 WARN_RANK_DEFICIENT = 0x2
+WARN_NONFINITE = 0x4
 
 
 class Dpar2Error(RuntimeError):
-    def __init__(self, status: int, message: str):
+    """A non-OK status.  For DPAR2_ENUMERIC raised by the report readers
+    and by decompose(report=True), `report` holds the report(s) the library
+    filled anyway."""
+
+    def __init__(self, status: int, message: str, report=None):
         super().__init__(f"libdpar2 status {status}: {message}")
         self.status = status
+        self.report = report
 
 
 class c_tensor(ctypes.Structure):
@@ -63,8 +71,8 @@ class c_report(ctypes.Structure):
                 ("xnorm2", ctypes.c_double), ("warn_bits", ctypes.c_uint32)]
 
 
-EXPORTS = ["dpar2_workspace_size", "dpar2_compress", "dpar2_als_step", "dpar2_fitness",
-           "dpar2_output_U", "dpar2_decompose", "dpar2_compressed_view", "dpar2_report_read",
+EXPORTS = ["dpar2_workspace_bytes", "dpar2_workspace_size", "dpar2_compress", "dpar2_als_step", "dpar2_fitness",
+           "dpar2_output_U", "dpar2_output_A", "dpar2_decompose", "dpar2_release", "dpar2_release_all", "dpar2_compressed_view", "dpar2_report_read",
            "dpar2_batch_workspace_size", "dpar2_decompose_batch", "dpar2_batch_report_read",
            "dpar2_warm_param_count", "dpar2_warm_features", "dpar2_warm_targets", "dpar2_warm_apply",
            "dpar2_warm_forward", "dpar2_warm_backward", "dpar2_warm_adam", "dpar2_autotune_item_rows",
@@ -84,8 +92,9 @@ def load(path: str = LIB_PATH):
     lib = ctypes.CDLL(path)
     P = ctypes.POINTER
     vp = ctypes.c_void_p
-    lib.dpar2_workspace_size.restype = ctypes.c_size_t
-    lib.dpar2_workspace_size.argtypes = [P(c_tensor), P(c_opts)]
+    for name in ("dpar2_workspace_bytes", "dpar2_workspace_size"):
+        getattr(lib, name).restype = ctypes.c_size_t
+        getattr(lib, name).argtypes = [P(c_tensor), P(c_opts)]
     lib.dpar2_compress.restype = ctypes.c_int32
     lib.dpar2_compress.argtypes = [P(c_tensor), P(c_opts), vp, vp, vp, ctypes.c_size_t, vp]
     lib.dpar2_als_step.restype = ctypes.c_int32
@@ -95,9 +104,15 @@ def load(path: str = LIB_PATH):
     lib.dpar2_fitness.argtypes = [P(c_tensor), P(c_opts), P(c_factors), vp, vp, ctypes.c_size_t, vp]
     lib.dpar2_output_U.restype = ctypes.c_int32
     lib.dpar2_output_U.argtypes = [P(c_tensor), P(c_opts), P(c_factors), vp, vp, ctypes.c_size_t, vp]
+    lib.dpar2_output_A.restype = ctypes.c_int32
+    lib.dpar2_output_A.argtypes = [P(c_tensor), P(c_opts), vp, vp, ctypes.c_size_t, vp]
     lib.dpar2_decompose.restype = ctypes.c_int32
-    lib.dpar2_decompose.argtypes = [P(c_tensor), P(c_opts), vp, vp, P(c_factors), vp, vp,
+    lib.dpar2_decompose.argtypes = [P(c_tensor), P(c_opts), vp, vp, P(c_factors), vp, P(c_report), vp,
                                     ctypes.c_size_t, vp]
+    lib.dpar2_release.restype = ctypes.c_int32
+    lib.dpar2_release.argtypes = [vp]
+    lib.dpar2_release_all.restype = ctypes.c_int32
+    lib.dpar2_release_all.argtypes = []
     lib.dpar2_compressed_view.restype = ctypes.c_int32
     lib.dpar2_compressed_view.argtypes = [P(c_tensor), P(c_opts), vp, ctypes.c_size_t, P(c_compressed)]
     lib.dpar2_report_read.restype = ctypes.c_int32
@@ -145,10 +160,10 @@ def load(path: str = LIB_PATH):
     return lib
 
 
-def _check(st: int):
+def _check(st: int, report=None):
     if st != DPAR2_OK:
         msg = load().dpar2_last_error().decode(errors="replace")
-        raise Dpar2Error(st, msg)
+        raise Dpar2Error(st, msg, report)
 
 
 def _ptr(t) -> int | None:
@@ -175,9 +190,11 @@ class Options:
     graph: bool = True      # False sets DPAR2_FLAG_NO_GRAPH
     item_rows: int = 0      # 0: the library's default work-item size
     wide_slab: bool = False  # True sets DPAR2_FLAG_WIDE_SLAB (128-column-chunk slab pass)
+    deterministic: bool = False  # True sets DPAR2_FLAG_DETERMINISTIC (resumable bit for bit)
 
     def c(self) -> c_opts:
-        flags = (0 if self.graph else DPAR2_FLAG_NO_GRAPH) | (DPAR2_FLAG_WIDE_SLAB if self.wide_slab else 0)
+        flags = ((0 if self.graph else DPAR2_FLAG_NO_GRAPH) | (DPAR2_FLAG_WIDE_SLAB if self.wide_slab else 0)
+                 | (DPAR2_FLAG_DETERMINISTIC if self.deterministic else 0))
         return c_opts(self.rank, self.sketch, self.sketch2, self.max_iter, float(self.tol),
                       flags, self.power_iters, self.item_rows)
 
@@ -253,7 +270,7 @@ def workspace_size(X: Tensor, o: Options) -> int:
     """Bytes of workspace for (X, o); raises on invalid arguments."""
     lib = load()
     tc, oc = X.c(), o.c()
-    n = lib.dpar2_workspace_size(ctypes.byref(tc), ctypes.byref(oc))
+    n = lib.dpar2_workspace_bytes(ctypes.byref(tc), ctypes.byref(oc))
     if n == 0:
         raise Dpar2Error(DPAR2_EINVAL, last_error())
     return int(n)
@@ -302,12 +319,42 @@ def output_U(X: Tensor, o: Options, f: Factors, U, ws, stream=None):
                               p, n, _stream(stream)))
 
 
-def decompose(X: Tensor, o: Options, omega1, omega2, f: Factors, ws, U=None, stream=None):
+def decompose(X: Tensor, o: Options, omega1, omega2, f: Factors, ws, U=None, stream=None, report=False):
+    """Enqueues the decomposition.  report=True synchronises and returns the
+    report dict (with "status": 0 or DPAR2_ENOCONV); a NaN/Inf slab raises
+    Dpar2Error(DPAR2_ENUMERIC)."""
     lib = load()
     p, n = _ws(ws)
     fc = f.c()
-    _check(lib.dpar2_decompose(ctypes.byref(X.c()), ctypes.byref(o.c()), _ptr(omega1), _ptr(omega2),
-                               ctypes.byref(fc), _ptr(U), p, n, _stream(stream)))
+    r = c_report() if report else None
+    st = lib.dpar2_decompose(ctypes.byref(X.c()), ctypes.byref(o.c()), _ptr(omega1), _ptr(omega2),
+                             ctypes.byref(fc), _ptr(U), ctypes.byref(r) if report else None, p, n,
+                             _stream(stream))
+    d = None
+    if report and st in (DPAR2_OK, DPAR2_ENOCONV, DPAR2_ENUMERIC):
+        d = _report_dict(r)
+        d["status"] = st
+    if st == DPAR2_ENOCONV and report:
+        return d
+    _check(st, d)
+    return d
+
+
+def output_A(X: Tensor, o: Options, A, ws, stream=None):
+    """A: float64 device (N, R) receives the first-stage factors A_k."""
+    lib = load()
+    p, n = _ws(ws)
+    _check(lib.dpar2_output_A(ctypes.byref(X.c()), ctypes.byref(o.c()), _ptr(A), p, n, _stream(stream)))
+
+
+def release(ws):
+    """Frees the library's host-side state (staging, graphs) kept for ws."""
+    p, _ = _ws(ws)
+    _check(load().dpar2_release(p))
+
+
+def release_all():
+    _check(load().dpar2_release_all())
 
 
 def compressed_view(X: Tensor, o: Options, ws) -> dict:
@@ -337,8 +384,8 @@ def report_read(X: Tensor, o: Options, ws, stream=None) -> dict:
     lib = load()
     p, _ = _ws(ws)
     r = c_report()
-    _check(lib.dpar2_report_read(ctypes.byref(X.c()), ctypes.byref(o.c()), p, ctypes.byref(r),
-                                 _stream(stream)))
+    st = lib.dpar2_report_read(ctypes.byref(X.c()), ctypes.byref(o.c()), p, ctypes.byref(r), _stream(stream))
+    _check(st, _report_dict(r) if st == DPAR2_ENUMERIC else None)
     return _report_dict(r)
 
 
@@ -389,7 +436,8 @@ def batch_report_read(Xs, os_, ws, stream=None) -> list:
     b = _Batch(Xs, os_)
     p, _ = _ws(ws)
     r = (c_report * b.n)()
-    _check(load().dpar2_batch_report_read(b.n, b.X, b.o, p, r, _stream(stream)))
+    st = load().dpar2_batch_report_read(b.n, b.X, b.o, p, r, _stream(stream))
+    _check(st, [_report_dict(r[i]) for i in range(b.n)] if st == DPAR2_ENUMERIC else None)
     return [_report_dict(r[i]) for i in range(b.n)]
 
 

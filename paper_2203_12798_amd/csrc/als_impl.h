@@ -861,8 +861,10 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_begin(AlsArgs a) {
   block_partial_out<R>(acc2, sM, out + 2 * RR);
 }
 
+// reset_base: the start of a call (the trace of the call begins here); 0 when
+// the begin step closes an iteration of the resumable mode
 template <int R>
-__global__ __launch_bounds__(EPI_THREADS) void k_als_begin_epi(AlsArgs a, int nblk) {
+__global__ __launch_bounds__(EPI_THREADS) void k_als_begin_epi(AlsArgs a, int reset_base) {
   const int tt = blockIdx.x;
   Ctl* ctl = a.ctl + tt;
   double* small = a.small + (size_t)tt * SM_COUNT * R * R;
@@ -870,7 +872,6 @@ __global__ __launch_bounds__(EPI_THREADS) void k_als_begin_epi(AlsArgs a, int nb
   const double* Et = a.E + (size_t)tt * R;
   constexpr int RR = R * R;
   __shared__ double tmp[3 * RR];
-  (void)nblk;
   team_sum(red + 3 * RR + 2, 1, 3 * RR, 3 * RR, tmp);
   for (int e = threadIdx.x; e < RR; e += EPI_THREADS) {
     small[SM_WTW * RR + e] = tmp[e];
@@ -878,12 +879,14 @@ __global__ __launch_bounds__(EPI_THREADS) void k_als_begin_epi(AlsArgs a, int nb
     small[SM_BM * RR + e] = Et[e / R] * tmp[2 * RR + e];
   }
   if (threadIdx.x == 0) {
-    ctl->base = ctl->iters;
+    if (reset_base) ctl->base = ctl->iters;
     ctl->vc_valid = 0;
   }
 }
 
-// Launches of one rank's kernels: phase 0 = begin (+epi), 1 = one iteration.
+// Launches of one rank's kernels: phase 0 = begin (+epi) of a call, 1 = one
+// iteration, 2 = the begin step that closes an iteration in the resumable
+// mode (W^T W, V^T V, E D^T V from the factors, as at the start of a call).
 // nb, nb0: blocks of the iteration / begin per-slice kernels; seg, seg0: their
 // per-tensor block offsets (device, nt + 1).
 template <int R>
@@ -895,11 +898,11 @@ hipError_t als_launch(int phase, const AlsArgs& a, int nb, int nb0, const int64_
   // each per-slice kernel writes one partial per block; the segmented column
   // sum reduces them per tensor (one load per thread) before the epilogues
   hipError_t e;
-  if (phase == 0) {
+  if (phase == 0 || phase == 2) {
     hipLaunchKernelGGL(k_als_begin<R>, dim3(nb0), dim3(TPB), 0, s, a);
     if ((e = launch_segsum(nt, seg0, nb0, 3 * RR, 3 * RR, a.partBegin, a.red + 3 * RR + 2, RW, s)) != hipSuccess)
       return e;
-    hipLaunchKernelGGL(k_als_begin_epi<R>, dim3(nt), dim3(EPI_THREADS), 0, s, a, 1);
+    hipLaunchKernelGGL(k_als_begin_epi<R>, dim3(nt), dim3(EPI_THREADS), 0, s, a, phase == 0 ? 1 : 0);
   } else {
     hipLaunchKernelGGL(k_als_A<R>, dim3(nb), dim3(TPB), 0, s, a);
     if ((e = launch_segsum(nt, seg, nb, RR, RR, a.partA, a.red, RW, s)) != hipSuccess) return e;

@@ -62,7 +62,8 @@ dpar2_status validate(const dpar2_tensor* X, const dpar2_opts* o) {
     return fail(DPAR2_EINVAL, "unsupported slab dtype");
   if (X->dtype == DPAR2_FP8_E4M3 && !X->slice_scale)
     return fail(DPAR2_EINVAL, "fp8 slabs need slice_scale");
-  if (o->flags & ~(DPAR2_FLAG_NO_GRAPH | DPAR2_FLAG_WIDE_SLAB)) return fail(DPAR2_EINVAL, "unknown bits in opts.flags");
+  if (o->flags & ~(DPAR2_FLAG_NO_GRAPH | DPAR2_FLAG_WIDE_SLAB | DPAR2_FLAG_DETERMINISTIC))
+    return fail(DPAR2_EINVAL, "unknown bits in opts.flags");
   if (o->item_rows != 0 && (o->item_rows < 64 || o->item_rows > 65536))
     return fail(DPAR2_EINVAL, "opts.item_rows must be 0 or in 64..65536");
   if (o->power_iters < 0 || o->power_iters > 4) return fail(DPAR2_EINVAL, "power_iters must be in [0, 4]");
@@ -274,8 +275,23 @@ Layout make_layout(const Group& g) {
   // the wide slab pass keeps Y (16 LT floats per row) between its two kernels
   y.wide = J > narrow_j_limit(g.X[0].dtype) || (o->flags & DPAR2_FLAG_WIDE_SLAB) != 0;
   y.ybuf = take(y.wide ? sizeof(float) * (size_t)y.N * (L <= 16 ? 16 : 32) : 0);
+  y.det = (o->flags & DPAR2_FLAG_DETERMINISTIC) != 0;
   y.total = p;
   return y;
+}
+
+// Every field of a layout, in declaration order (the graph cache key).
+std::vector<int64_t> layout_key(const Layout& y) {
+  return {y.nt, y.K, y.J, y.N, y.n_items, y.R, y.L, y.L2, y.max_iter, y.q, y.n2, y.nblk, y.nblk0,
+          (int64_t)y.tdesc, (int64_t)y.blk, (int64_t)y.blk0, (int64_t)y.chunks, (int64_t)y.seg_blk,
+          (int64_t)y.seg_blk0, (int64_t)y.seg_chunk, (int64_t)y.seg_slice, (int64_t)y.slice_t, (int64_t)y.ctl,
+          (int64_t)y.items, (int64_t)y.slice_ptr, (int64_t)y.slice_list, (int64_t)y.partG, (int64_t)y.partP,
+          (int64_t)y.partS, (int64_t)y.xnorm2, (int64_t)y.Mt, (int64_t)y.Phi, (int64_t)y.sig1, (int64_t)y.Y2p,
+          (int64_t)y.Y2, (int64_t)y.B2t, (int64_t)y.S2p, (int64_t)y.S2, (int64_t)y.U2, (int64_t)y.D,
+          (int64_t)y.E, (int64_t)y.F, (int64_t)y.FtFp, (int64_t)y.Psi, (int64_t)y.Pw, (int64_t)y.Mk,
+          (int64_t)y.small, (int64_t)y.partA, (int64_t)y.partB, (int64_t)y.partC, (int64_t)y.partBegin,
+          (int64_t)y.red, (int64_t)y.fitp, (int64_t)y.trace, (int64_t)y.om1, (int64_t)y.omq, (int64_t)y.ybuf,
+          (int64_t)y.wide, (int64_t)y.det, (int64_t)y.tables_end, (int64_t)y.total};
 }
 
 dpar2_status check_ws(const Layout& y, const void* ws, size_t bytes) {
@@ -555,7 +571,7 @@ dpar2_status group_compress(const Group& g, const float* const* om1, const float
                             reinterpret_cast<const int32_t*>(w + y.slice_list), partG, partP, partS,
                             reinterpret_cast<double*>(w + y.xnorm2), reinterpret_cast<double*>(w + y.Mt),
                             reinterpret_cast<double*>(w + y.Phi), reinterpret_cast<double*>(w + y.sig1),
-                            pass < y.q ? omq : nullptr, ctl, s);
+                            pass < y.q ? omq : nullptr, ctl, reinterpret_cast<const int32_t*>(w + y.slice_t), s);
     if (e != hipSuccess) return hip_fail(e, "slice finish");
   }
   e = launch_stage2(y, w, s);
@@ -628,9 +644,12 @@ dpar2_status group_als(const Group& g, int32_t n_steps, char* w, const Layout& y
     if ((e = enqueue_als(n_steps, w, y, s)) != hipSuccess) return hip_fail(e, "iteration");
     return DPAR2_OK;
   }
-  // every kernel argument is a workspace address or a layout size: the graph
-  // of one (workspace, layout, step count) replays for any factors
-  const std::vector<int64_t> key = {(int64_t)y.total, y.nt, y.K, y.J, y.R, y.nblk, y.nblk0, n_steps};
+  // every kernel argument is a workspace address or a layout field: the graph
+  // of one (workspace, layout, step count) replays for any factors.  The key
+  // holds every field of the layout, so a workspace reused for another shape
+  // whose offsets differ never replays a stale graph.
+  std::vector<int64_t> key = layout_key(y);
+  key.push_back(n_steps);
   std::lock_guard<std::mutex> lk(g_graph_mu);
   GraphCache& gc = g_graphs[w];
   GraphEntry* hit = nullptr;
@@ -665,12 +684,17 @@ dpar2_status group_als(const Group& g, int32_t n_steps, char* w, const Layout& y
 }
 
 // U_k = A_k Z_k P_k^T H (Alg. 3 output) by re-running the tiles of the last
-// slab pass (same Y bit for bit) against Theta_k = Phi_k Psi_k H; the
-// descriptors on the device must hold the Omega_1 of that pass.
+// slab pass (same Y bit for bit) against Theta_k = Phi_k Psi_k H; with H ==
+// NULL, A_k = Y_k Phi_k itself (Theta_k = Phi_k).  The descriptors on the
+// device must hold the Omega_1 of that pass.
 dpar2_status group_output_U(const Group& g, const Layout& y, char* w, const double* H, double* U, hipStream_t s) {
-  double* theta = reinterpret_cast<double*>(w + y.trace);
-  hipError_t e = launch_theta(y, w, H, theta, s);
-  if (e != hipSuccess) return hip_fail(e, "theta");
+  const double* theta = reinterpret_cast<const double*>(w + y.Phi);
+  hipError_t e;
+  if (H) {
+    double* th = reinterpret_cast<double*>(w + y.trace);
+    if ((e = launch_theta(y, w, H, th, s)) != hipSuccess) return hip_fail(e, "theta");
+    theta = th;
+  }
   const int dtype = g.X[0].dtype;
   const int esize = dtype == DPAR2_F32 ? 4 : (dtype == DPAR2_BF16 ? 2 : 1);
   SlabArgs sa;
@@ -700,14 +724,16 @@ dpar2_status group_report(const Group& g, const void* ws, const Layout& y, dpar2
     const Ctl& ct = c[(size_t)t];
     dpar2_report& r = rep[t];
     r.iters = ct.iters;
-    r.converged = ct.done;
+    r.converged = ct.done && !ct.bad;
     r.err_last = ct.e_prev;
     r.xnorm2 = ct.xnorm2;
     r.fit_compressed = ct.xnorm2 > 0 ? 1.0 - ct.e_prev / ct.xnorm2 : 0.0;
     r.fit_true = ct.fit_true;
-    // first-stage warnings are recorded once for the group (control block 0)
-    r.warn_bits = ct.warn | c[0].warn;
+    r.warn_bits = ct.warn;
   }
+  for (int t = 0; t < g.nt; ++t)
+    if (c[(size_t)t].bad)
+      return fail(DPAR2_ENUMERIC, "the slab of tensor " + std::to_string(g.orig[(size_t)t]) + " holds NaN or Inf");
   return DPAR2_OK;
 }
 
@@ -739,11 +765,13 @@ dpar2_status check_tokens(int32_t rank, int32_t n, const int32_t* off_dev, const
 
 extern "C" {
 
-size_t dpar2_workspace_size(const dpar2_tensor* X, const dpar2_opts* o) {
+size_t dpar2_workspace_bytes(const dpar2_tensor* X, const dpar2_opts* o) {
   Group g;
   if (make_group(1, X, o, &g) != DPAR2_OK) return 0;
   return make_layout(g).total;
 }
+
+size_t dpar2_workspace_size(const dpar2_tensor* X, const dpar2_opts* o) { return dpar2_workspace_bytes(X, o); }
 
 size_t dpar2_batch_workspace_size(int32_t n, const dpar2_tensor* X, const dpar2_opts* o) {
   Batch b;
@@ -810,9 +838,24 @@ dpar2_status dpar2_output_U(const dpar2_tensor* X, const dpar2_opts* o, const dp
   return group_output_U(g, y, w, f->H, U, s);
 }
 
+dpar2_status dpar2_output_A(const dpar2_tensor* X, const dpar2_opts* o, double* A, void* ws, size_t ws_bytes,
+                            dpar2_stream_t stream) {
+  Group g;
+  dpar2_status st = make_group(1, X, o, &g);
+  if (st != DPAR2_OK) return st;
+  if (!A) return fail(DPAR2_EINVAL, "A must be non-NULL");
+  const Layout y = make_layout(g);
+  if ((st = check_ws(y, ws, ws_bytes)) != DPAR2_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  const float* om1 = reinterpret_cast<const float*>(w + y.om1);
+  if ((st = upload_descriptors(w, y, descriptors(g, &om1, &om1, nullptr, nullptr), s)) != DPAR2_OK) return st;
+  return group_output_U(g, y, w, nullptr, A, s);
+}
+
 dpar2_status dpar2_decompose(const dpar2_tensor* X, const dpar2_opts* o, const float* omega1,
-                             const float* omega2, dpar2_factors* f, double* U, void* ws, size_t ws_bytes,
-                             dpar2_stream_t stream) {
+                             const float* omega2, dpar2_factors* f, double* U, dpar2_report* rep, void* ws,
+                             size_t ws_bytes, dpar2_stream_t stream) {
   Group g;
   dpar2_status st = make_group(1, X, o, &g);
   if (st != DPAR2_OK) return st;
@@ -826,7 +869,11 @@ dpar2_status dpar2_decompose(const dpar2_tensor* X, const dpar2_opts* o, const f
   if ((st = group_als(g, o->max_iter, w, y, s)) != DPAR2_OK) return st;
   hipError_t e = launch_fitness(y, w, nullptr, s);
   if (e != hipSuccess) return hip_fail(e, "fitness");
-  if (U) return group_output_U(g, y, w, f->H, U, s);
+  if (U && (st = group_output_U(g, y, w, f->H, U, s)) != DPAR2_OK) return st;
+  if (!rep) return DPAR2_OK;
+  if ((st = group_report(g, ws, y, rep, s)) != DPAR2_OK) return st;
+  if (o->tol >= 0.0 && !rep->converged)
+    return fail(DPAR2_ENOCONV, "the stop rule did not fire within " + std::to_string(o->max_iter) + " iterations");
   return DPAR2_OK;
 }
 
@@ -887,14 +934,22 @@ dpar2_status dpar2_batch_report_read(int32_t n, const dpar2_tensor* X, const dpa
   dpar2_status st = make_batch(n, X, o, &b);
   if (st != DPAR2_OK) return st;
   if (!rep || !ws) return fail(DPAR2_EINVAL, "report and workspace must be non-NULL");
+  dpar2_status worst = DPAR2_OK;
+  std::string msg;
   for (size_t gi = 0; gi < b.groups.size(); ++gi) {
     const Group& g = b.groups[gi];
     std::vector<dpar2_report> r((size_t)g.nt);
     st = group_report(g, static_cast<const char*>(ws) + b.base[gi], b.lay[gi], r.data(),
                       reinterpret_cast<hipStream_t>(stream));
-    if (st != DPAR2_OK) return st;
+    if (st == DPAR2_ENUMERIC) {   // reports filled; keep going
+      if (worst == DPAR2_OK) msg = g_last_error;
+      worst = st;
+    } else if (st != DPAR2_OK) {
+      return st;
+    }
     for (int t = 0; t < g.nt; ++t) rep[g.orig[(size_t)t]] = r[(size_t)t];
   }
+  if (worst != DPAR2_OK) return fail(worst, msg);
   return DPAR2_OK;
 }
 
@@ -1122,12 +1177,72 @@ dpar2_status dpar2_profile_read(int32_t* launches, double* total_ms) {
   return DPAR2_OK;
 }
 
+dpar2_status dpar2_release(const void* ws) {
+  hipError_t first = hipSuccess;
+  {
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    auto it = g_stage.find(ws);
+    if (it != g_stage.end()) {
+      Staging& sg = it->second;
+      for (int i = 0; i < STAGE_SLOTS; ++i) {
+        if (sg.done[i]) {
+          const hipError_t e = hipEventSynchronize(sg.done[i]);
+          if (first == hipSuccess) first = e;
+          (void)hipEventDestroy(sg.done[i]);
+        }
+        if (sg.host[i]) (void)hipHostFree(sg.host[i]);
+      }
+      g_stage.erase(it);
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    auto it = g_graphs.find(ws);
+    if (it != g_graphs.end()) {
+      for (GraphEntry& ge : it->second.entries) (void)hipGraphExecDestroy(ge.exec);
+      if (it->second.cap) (void)hipStreamDestroy(it->second.cap);
+      g_graphs.erase(it);
+    }
+  }
+  if (first != hipSuccess) return hip_fail(first, "dpar2_release");
+  return DPAR2_OK;
+}
+
+dpar2_status dpar2_release_all(void) {
+  std::vector<const void*> keys;
+  {
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    for (auto& kv : g_stage) keys.push_back(kv.first);
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    for (auto& kv : g_graphs) keys.push_back(kv.first);
+  }
+  dpar2_status st = DPAR2_OK;
+  for (const void* k : keys) {
+    const dpar2_status r = dpar2_release(k);
+    if (st == DPAR2_OK) st = r;
+  }
+  std::lock_guard<std::mutex> lk(g_spool.mu);
+  if (g_spool.ready) {
+    for (int i = 0; i < BATCH_STREAMS; ++i) {
+      (void)hipStreamSynchronize(g_spool.s[i]);
+      (void)hipStreamDestroy(g_spool.s[i]);
+      (void)hipEventDestroy(g_spool.done[i]);
+    }
+    (void)hipEventDestroy(g_spool.fork);
+    g_spool.ready = false;
+  }
+  return st;
+}
+
 const char* dpar2_status_string(int32_t status) {
   switch (status) {
     case DPAR2_OK: return "ok";
     case DPAR2_EINVAL: return "invalid argument";
     case DPAR2_ESHAPE: return "shape not supported";
-    case DPAR2_ENUMERIC: return "numerical failure";
+    case DPAR2_ENUMERIC: return "the slab holds NaN or Inf";
+    case DPAR2_ENOCONV: return "the stop rule did not fire within max_iter";
     case DPAR2_EHIP: return "HIP runtime error";
     case DPAR2_EWORKSPACE: return "workspace missing, misaligned or too small";
     default: return "unknown status";

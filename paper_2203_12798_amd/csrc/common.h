@@ -35,7 +35,7 @@ struct Ctl {
   int32_t base;         // value of `iters` when the current als_step call began
   uint32_t warn;        // DPAR2_WARN_* bits
   int32_t vc_valid;     // V is held as D VC (V not yet written back)
-  int32_t pad0;
+  int32_t bad;          // the slab held NaN or Inf: the iteration is skipped
   double e_prev;        // last recorded error
   double e0;            // sum_k ||F^(k) E D^T||_F^2 (constant part of e)
   double xnorm2;        // sum_k ||X_k||_F^2

@@ -73,6 +73,7 @@ struct Layout {
   size_t Psi, Pw, Mk, small, partA, partB, partC, partBegin, red, fitp, trace, om1, omq;
   size_t ybuf;            // wide-J slab pass: Y of every row (N x 16 LT floats), else empty
   bool wide;              // slab pass in 128-column chunks (J above the narrow limit, or asked for)
+  bool det;               // resumable mode (DPAR2_FLAG_DETERMINISTIC)
   size_t tables_end;     // end of the host-built tables [tdesc, tables_end)
   size_t total;
 };
@@ -124,7 +125,7 @@ hipError_t launch_slice_finish(int64_t K, int J, int L, int R, const int32_t* sl
                                const int32_t* slice_list, const double* partG,
                                const double* partP, const double* partS, double* xnorm2,
                                double* Mt, double* Phi, double* sig1, float* omega_next, Ctl* ctl,
-                               hipStream_t s);
+                               const int32_t* slice_t, hipStream_t s);
 hipError_t launch_stage2(const Layout& lay, char* ws, hipStream_t s);
 // out[t * ostride + e] = sum_{b in [seg[t], seg[t+1])} part[b * stride + e],
 // e < width, t < nt, in a fixed order (one block per (e, t)).  n1 >= 0 gives

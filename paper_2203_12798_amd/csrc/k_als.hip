@@ -210,7 +210,11 @@ hipError_t launch_pw_identity(const Layout& lay, char* ws, hipStream_t s) {
 hipError_t launch_als_begin(const Layout& lay, char* ws, hipStream_t s) { return als_dispatch(lay, ws, 0, s); }
 
 hipError_t launch_als_iteration(const Layout& lay, char* ws, hipStream_t s) {
-  return als_dispatch(lay, ws, 1, s);
+  hipError_t e = als_dispatch(lay, ws, 1, s);
+  if (e != hipSuccess || !lay.det) return e;
+  // resumable mode: end the iteration in the state a new call starts from
+  if ((e = launch_als_end(lay, ws, s)) != hipSuccess) return e;
+  return als_dispatch(lay, ws, 2, s);
 }
 
 hipError_t launch_als_end(const Layout& lay, char* ws, hipStream_t s) {

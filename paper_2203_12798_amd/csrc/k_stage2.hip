@@ -236,7 +236,17 @@ __global__ __launch_bounds__(64) void k_s2_final(int R, const double* __restrict
     e0 += E[a] * E[c] * FtF[e] * DtD[e];
   }
   for (int o = 1; o < 64; o <<= 1) e0 += __shfl_xor(e0, o, 64);
-  if (lane == 0) ctl->e0 = e0;
+  if (lane == 0) {
+    ctl->e0 = e0;
+    // a NaN or Inf anywhere in the slab makes sum_k ||X_k||^2 non-finite
+    // (squares of finite float32 values cannot overflow in FP64): flag the
+    // tensor and skip its iteration
+    if (!isfinite(ctl->xnorm2)) {
+      ctl->bad = 1;
+      ctl->done = 1;
+      ctl->warn |= 0x4u;
+    }
+  }
 }
 
 hipError_t launch_stage2(const Layout& lay, char* ws, hipStream_t s) {

@@ -56,7 +56,7 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
                                                   const double* __restrict__ partS, double* __restrict__ xnorm2,
                                                   double* __restrict__ Mt, double* __restrict__ Phi,
                                                   double* __restrict__ sig1, float* __restrict__ omega_next,
-                                                  Ctl* ctl) {
+                                                  Ctl* ctl, const int32_t* __restrict__ slice_t) {
   constexpr int RM = SC<L>::RM, LH = SC<L>::LH, LD = SC<L>::LD, CW = SC<L>::CW, LL = L * L;
   __shared__ double Gs[L * LD];    // G, then its Cholesky factor (upper triangle)
   __shared__ double Ss[L * LD];    // S' = P P^T; then Phi
@@ -378,17 +378,17 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
     Phi[(size_t)k * L * R + e] = sgn[r] * Ss[a * LD + r];
   }
   for (int o = 1; o < 64; o <<= 1) warn |= __shfl_xor((int)warn, o, 64);
-  if (lane == 0 && warn) atomicOr(&ctl->warn, warn);
+  if (lane == 0 && warn) atomicOr(&ctl[slice_t[k]].warn, warn);   // the slice's tensor
 }
 
 template <int L>
 hipError_t slice_fin_launch(int64_t K, int J, int R, const int32_t* slice_ptr, const int32_t* slice_list,
                             const double* partG, const double* partP, const double* partS, double* xnorm2,
                             double* Mt, double* Phi, double* sig1, float* omega_next, Ctl* ctl,
-                            hipStream_t s) {
+                            const int32_t* slice_t, hipStream_t s) {
   if (K <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_slice_fin<L>, dim3((unsigned)K), dim3(64), 0, s, (int)K, J, R, slice_ptr, slice_list,
-                     partG, partP, partS, xnorm2, Mt, Phi, sig1, omega_next, ctl);
+                     partG, partP, partS, xnorm2, Mt, Phi, sig1, omega_next, ctl, slice_t);
   return hipGetLastError();
 }
 

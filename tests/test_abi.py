@@ -26,8 +26,9 @@ def declared_functions():
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for n in ["dpar2_compress", "dpar2_als_step", "dpar2_decompose", "dpar2_workspace_size",
-              "dpar2_fitness", "dpar2_output_U", "dpar2_report_read", "dpar2_compressed_view"]:
+    for n in ["dpar2_compress", "dpar2_als_step", "dpar2_decompose", "dpar2_workspace_bytes",
+              "dpar2_workspace_size", "dpar2_fitness", "dpar2_output_U", "dpar2_output_A",
+              "dpar2_report_read", "dpar2_compressed_view", "dpar2_release", "dpar2_release_all"]:
         assert n in names
 
 
@@ -91,8 +92,14 @@ def test_null_pointers_rejected():
 
 def test_status_strings():
     _, lib = _lib()
-    for st in (0, -1, -2, -3, -5, -6, 7):
-        assert lib.dpar2_status_string(st)
+    seen = set()
+    for st in (0, -1, -2, -3, -4, -5, -6):
+        s = lib.dpar2_status_string(st)
+        assert s and s != b"unknown status"
+        seen.add(s)
+    assert len(seen) == 7
+    assert lib.dpar2_status_string(7) == b"unknown status"
+    assert b"NaN" in lib.dpar2_status_string(-3)
 
 
 def test_dtype_and_power_options_validated_on_host():
@@ -136,7 +143,7 @@ def test_dtype_and_power_options_validated_on_host():
     assert (lib.dpar2_workspace_size(ctypes.byref(t256), ctypes.byref(ow))
             >= ws256 + 400 * 16 * 4)
     assert lib.dpar2_workspace_size(ctypes.byref(t257), ctypes.byref(ow)) == ws257
-    ox = binding.c_opts(2, 3, 3, 5, -1.0, 0x4, 0)
+    ox = binding.c_opts(2, 3, 3, 5, -1.0, 0x8, 0)
     assert _status(lib, binding, t8, ox) == -1
     assert b"flags" in lib.dpar2_last_error()
 
@@ -237,3 +244,35 @@ def test_wide_slab_flag_and_autotuner_arguments():
     st = lib.dpar2_autotune_slab(ctypes.byref(t), ctypes.byref(o), ctypes.c_void_p(0x3000), None, rows, 2,
                                  ctypes.c_void_p(0x4000), 1 << 30, ctypes.byref(best), None, None)
     assert st == -1
+
+
+def test_workspace_bytes_and_new_entry_points_validate_on_host():
+    """dpar2_workspace_bytes (and its earlier name) agree; the resumable flag
+    is accepted and is part of the group key; decompose, output_A and
+    release reject bad arguments before touching the device; release of a
+    workspace the library never saw is a no-op."""
+    binding, lib = _lib()
+    t, _keep = _tensor(binding, [0, 10, 25, 40])
+    o = binding.c_opts(2, 3, 3, 5, -1.0, 0)
+    od = binding.c_opts(2, 3, 3, 5, -1.0, binding.DPAR2_FLAG_DETERMINISTIC)
+    n = lib.dpar2_workspace_bytes(ctypes.byref(t), ctypes.byref(o))
+    assert n > 0 and n == lib.dpar2_workspace_size(ctypes.byref(t), ctypes.byref(o))
+    assert lib.dpar2_workspace_bytes(ctypes.byref(t), ctypes.byref(od)) == n
+    T = binding.c_tensor * 2
+    O = binding.c_opts * 2
+    al = lambda x: (x + 255) // 256 * 256
+    assert lib.dpar2_batch_workspace_size(2, T(t, t), O(o, od)) == 2 * al(n)
+    f = binding.c_factors(0x5000, 0x6000, 0x7000)
+    rep = binding.c_report()
+    # NULL omega, NULL factor pointer, workspace too small: no device work
+    assert lib.dpar2_decompose(ctypes.byref(t), ctypes.byref(o), None, 0x4000, ctypes.byref(f), None,
+                               ctypes.byref(rep), 0x10000, n, None) == -1
+    fz = binding.c_factors(0x5000, None, 0x7000)
+    assert lib.dpar2_decompose(ctypes.byref(t), ctypes.byref(o), 0x3000, 0x4000, ctypes.byref(fz), None,
+                               ctypes.byref(rep), 0x10000, n, None) == -1
+    assert lib.dpar2_decompose(ctypes.byref(t), ctypes.byref(o), 0x3000, 0x4000, ctypes.byref(f), None,
+                               ctypes.byref(rep), 0x10000, n - 1, None) == -6
+    assert lib.dpar2_output_A(ctypes.byref(t), ctypes.byref(o), None, 0x10000, n, None) == -1
+    assert lib.dpar2_output_A(ctypes.byref(t), ctypes.byref(o), 0x8000, 0x10000, n - 1, None) == -6
+    assert lib.dpar2_release(ctypes.c_void_p(0x123400)) == 0
+    assert lib.dpar2_release(None) == 0
