@@ -234,6 +234,28 @@ dpar2_status dpar2_decompose(const dpar2_tensor* X, const dpar2_opts* o,
                              dpar2_factors* f, double* U, dpar2_report* rep,
                              void* ws, size_t ws_bytes, dpar2_stream_t stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): dpar2_decompose without a
+ * workspace argument.  The workspace is a static device array of
+ * DPAR2_NOALLOC_SCRATCH_BYTES that each GPU the library runs on holds until
+ * the process ends (its address is looked up on the first call on a device).
+ * The call allocates no device or pinned host memory and instantiates no
+ * graph: the schedule tables reach the device as by-value kernel arguments
+ * (at most 1 MiB of them, roughly 30k slices), the iterations are launched
+ * one by one.  Decompositions whose workspace (dpar2_workspace_bytes) exceeds
+ * the scratch, or whose tables exceed 1 MiB, are rejected with
+ * DPAR2_EWORKSPACE before anything is enqueued.  Results equal
+ * dpar2_decompose's bit for bit.  Every call on one GPU shares that GPU's
+ * scratch (the previous call's contents stay; everything a call reads is
+ * written by it first): calls that overlap on one GPU, on any streams or
+ * threads, race and must be serialised by the caller.  rep as in
+ * dpar2_decompose. */
+#define DPAR2_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+dpar2_status dpar2_decompose_noalloc(const dpar2_tensor* X, const dpar2_opts* o,
+                                     const float* omega1, const float* omega2,
+                                     dpar2_factors* f, double* U, dpar2_report* rep,
+                                     dpar2_stream_t stream);
+
 /* Fills *out (host struct) with device pointers into the workspace (host-only
  * pointer arithmetic; nothing is enqueued). */
 dpar2_status dpar2_compressed_view(const dpar2_tensor* X, const dpar2_opts* o, const void* ws,

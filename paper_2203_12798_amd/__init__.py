@@ -3,10 +3,10 @@ on AMD Instinct MI355X.  The compute path is the HIP library libdpar2.so
 (C ABI in include/dpar2.h); this package is its thin Python binding."""
 from .binding import (Dpar2Error, Factors, Options, Tensor, alloc_batch_workspace, alloc_workspace, als_step,
                       batch_report_read, batch_workspace_size, compress, compressed_view, decompose,
-                      decompose_batch, fitness, load, output_A, output_U, release, release_all, report_read,
+                      decompose_batch, decompose_noalloc, fitness, load, output_A, output_U, release, release_all, report_read,
                       workspace_size)
 
 __all__ = ["Dpar2Error", "Factors", "Options", "Tensor", "alloc_batch_workspace", "alloc_workspace", "als_step",
            "batch_report_read", "batch_workspace_size", "compress", "compressed_view", "decompose",
-           "decompose_batch", "fitness", "load", "output_A", "output_U", "release", "release_all", "report_read",
+           "decompose_batch", "decompose_noalloc", "fitness", "load", "output_A", "output_U", "release", "release_all", "report_read",
            "workspace_size"]

@@ -72,7 +72,8 @@ class c_report(ctypes.Structure):
 
 
 EXPORTS = ["dpar2_workspace_bytes", "dpar2_workspace_size", "dpar2_compress", "dpar2_als_step", "dpar2_fitness",
-           "dpar2_output_U", "dpar2_output_A", "dpar2_decompose", "dpar2_release", "dpar2_release_all", "dpar2_compressed_view", "dpar2_report_read",
+           "dpar2_output_U", "dpar2_output_A", "dpar2_decompose", "dpar2_decompose_noalloc", "dpar2_release",
+           "dpar2_release_all", "dpar2_compressed_view", "dpar2_report_read",
            "dpar2_batch_workspace_size", "dpar2_decompose_batch", "dpar2_batch_report_read",
            "dpar2_warm_param_count", "dpar2_warm_features", "dpar2_warm_targets", "dpar2_warm_apply",
            "dpar2_warm_forward", "dpar2_warm_backward", "dpar2_warm_adam", "dpar2_autotune_item_rows",
@@ -109,6 +110,8 @@ def load(path: str = LIB_PATH):
     lib.dpar2_decompose.restype = ctypes.c_int32
     lib.dpar2_decompose.argtypes = [P(c_tensor), P(c_opts), vp, vp, P(c_factors), vp, P(c_report), vp,
                                     ctypes.c_size_t, vp]
+    lib.dpar2_decompose_noalloc.restype = ctypes.c_int32
+    lib.dpar2_decompose_noalloc.argtypes = [P(c_tensor), P(c_opts), vp, vp, P(c_factors), vp, P(c_report), vp]
     lib.dpar2_release.restype = ctypes.c_int32
     lib.dpar2_release.argtypes = [vp]
     lib.dpar2_release_all.restype = ctypes.c_int32
@@ -338,6 +341,28 @@ def decompose(X: Tensor, o: Options, omega1, omega2, f: Factors, ws, U=None, str
         return d
     _check(st, d)
     return d
+
+
+def decompose_noalloc(X: Tensor, o: Options, omega1, omega2, f: Factors, U=None, stream=None, report=False):
+    """decompose() on the library's static device scratch (no workspace, no
+    allocation); same report convention as decompose()."""
+    lib = load()
+    fc = f.c()
+    r = c_report() if report else None
+    st = lib.dpar2_decompose_noalloc(ctypes.byref(X.c()), ctypes.byref(o.c()), _ptr(omega1), _ptr(omega2),
+                                     ctypes.byref(fc), _ptr(U), ctypes.byref(r) if report else None,
+                                     _stream(stream))
+    d = None
+    if report and st in (DPAR2_OK, DPAR2_ENOCONV, DPAR2_ENUMERIC):
+        d = _report_dict(r)
+        d["status"] = st
+    if st == DPAR2_ENOCONV and report:
+        return d
+    _check(st, d)
+    return d
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def output_A(X: Tensor, o: Options, A, ws, stream=None):

@@ -37,6 +37,8 @@ struct Group {
   const dpar2_tensor* X = nullptr;     // = Xv.data()
   const dpar2_opts* o = nullptr;       // = ov.data()
   std::vector<int64_t> k0;             // first global slice of each tensor (nt + 1)
+  bool noalloc = false;                // dpar2_decompose_noalloc: tables as kernel arguments,
+                                       // no pinned staging, no graphs, no profiling events
 };
 
 // Host-side tables of a group: the slab-pass schedule and the block / chunk
@@ -410,6 +412,27 @@ dpar2_status upload_locked(Staging& sg, char* w, const char* img, size_t n, size
   return DPAR2_OK;
 }
 
+// Upload without any allocation (dpar2_decompose_noalloc): the bytes travel
+// as the by-value argument of a copy kernel, PUT_BYTES per launch, so no
+// pinned buffer and no copy from pageable host memory is involved.
+constexpr int PUT_BYTES = 3072;
+struct PutArg {
+  unsigned char b[PUT_BYTES];
+};
+__global__ __launch_bounds__(256) void k_put(PutArg a, unsigned char* __restrict__ dst, int n) {
+  for (int i = threadIdx.x; i < n; i += 256) dst[i] = a.b[i];
+}
+dpar2_status upload_args(char* w, const char* img, size_t n, size_t at, hipStream_t s) {
+  PutArg a;
+  for (size_t o = 0; o < n; o += PUT_BYTES) {
+    const int m = (int)std::min<size_t>(PUT_BYTES, n - o);
+    std::memcpy(a.b, img + o, (size_t)m);
+    hipLaunchKernelGGL(k_put, dim3(1), dim3(256), 0, s, a, reinterpret_cast<unsigned char*>(w + at + o), m);
+  }
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? DPAR2_OK : hip_fail(e, "table upload (kernel arguments)");
+}
+
 // Per-tensor descriptors; factor and trace pointers come from the call that
 // uses them (NULL where a call has none).
 std::vector<TDesc> descriptors(const Group& g, const float* const* om1, const float* const* om2,
@@ -514,7 +537,8 @@ dpar2_status group_compress(const Group& g, const float* const* om1, const float
     Staging& sg = g_stage[w];
     stage_tables(g, y, sg);
     std::memcpy(sg.image.data(), td.data(), sizeof(TDesc) * td.size());
-    dpar2_status st = upload_locked(sg, w, sg.image.data(), sg.image.size(), y.tdesc, s);
+    dpar2_status st = g.noalloc ? upload_args(w, sg.image.data(), sg.image.size(), y.tdesc, s)
+                                : upload_locked(sg, w, sg.image.data(), sg.image.size(), y.tdesc, s);
     if (st != DPAR2_OK) return st;
   }
   hipError_t e;
@@ -530,7 +554,7 @@ dpar2_status group_compress(const Group& g, const float* const* om1, const float
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_prof_mu);
-    if (g_prof.on) {
+    if (g_prof.on && !g.noalloc) {
       if (g_prof.used == g_prof.pool.size()) {
         hipEvent_t a0, a1;
         if ((e = hipEventCreate(&a0)) != hipSuccess) return hip_fail(e, "hipEventCreate");
@@ -640,7 +664,7 @@ std::unordered_map<const void*, GraphCache> g_graphs;
 
 dpar2_status group_als(const Group& g, int32_t n_steps, char* w, const Layout& y, hipStream_t s) {
   hipError_t e;
-  if (n_steps < 2 || (g.o[0].flags & DPAR2_FLAG_NO_GRAPH)) {
+  if (n_steps < 2 || g.noalloc || (g.o[0].flags & DPAR2_FLAG_NO_GRAPH)) {
     if ((e = enqueue_als(n_steps, w, y, s)) != hipSuccess) return hip_fail(e, "iteration");
     return DPAR2_OK;
   }
@@ -740,6 +764,35 @@ dpar2_status group_report(const Group& g, const void* ws, const Layout& y, dpar2
 }  // namespace
 
 namespace {
+// Device scratch of dpar2_decompose_noalloc: the workspace of its
+// decomposition, one copy per GPU, held until the process ends.  Host code
+// never uses the array's name as an address: g_scratch_dev[d] is its device
+// address on device d, looked up once with that device current.
+constexpr size_t NOALLOC_BYTES = DPAR2_NOALLOC_SCRATCH_BYTES;
+constexpr size_t NOALLOC_TABLE_BYTES = size_t(1) << 20;   // schedule tables, sent as kernel arguments
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on that device).
+dpar2_status scratch_address(char** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(DPAR2_EINVAL, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess) return hip_fail(e, "hipGetSymbolAddress");
+    if (!p || (uintptr_t)p % 256 != 0) return fail(DPAR2_EHIP, "scratch symbol address missing or misaligned");
+    g_scratch_dev[dev] = p;
+  }
+  *out = static_cast<char*>(g_scratch_dev[dev]);
+  return DPAR2_OK;
+}
+
 // the compressed representation of a single-tensor workspace
 struct Comp {
   Group g;
@@ -872,6 +925,38 @@ dpar2_status dpar2_decompose(const dpar2_tensor* X, const dpar2_opts* o, const f
   if (U && (st = group_output_U(g, y, w, f->H, U, s)) != DPAR2_OK) return st;
   if (!rep) return DPAR2_OK;
   if ((st = group_report(g, ws, y, rep, s)) != DPAR2_OK) return st;
+  if (o->tol >= 0.0 && !rep->converged)
+    return fail(DPAR2_ENOCONV, "the stop rule did not fire within " + std::to_string(o->max_iter) + " iterations");
+  return DPAR2_OK;
+}
+
+dpar2_status dpar2_decompose_noalloc(const dpar2_tensor* X, const dpar2_opts* o, const float* omega1,
+                                     const float* omega2, dpar2_factors* f, double* U, dpar2_report* rep,
+                                     dpar2_stream_t stream) {
+  Group g;
+  dpar2_status st = make_group(1, X, o, &g);
+  if (st != DPAR2_OK) return st;
+  if (!f || !f->H || !f->V || !f->W) return fail(DPAR2_EINVAL, "factors must be non-NULL");
+  g.noalloc = true;
+  const Layout y = make_layout(g);
+  if (y.total > NOALLOC_BYTES)
+    return fail(DPAR2_EWORKSPACE, "dpar2_decompose_noalloc: this decomposition needs " + std::to_string(y.total) +
+                                      " bytes of workspace; the static scratch holds " +
+                                      std::to_string(NOALLOC_BYTES));
+  if (y.tables_end - y.tdesc > NOALLOC_TABLE_BYTES)
+    return fail(DPAR2_EWORKSPACE, "dpar2_decompose_noalloc: the schedule tables need " +
+                                      std::to_string(y.tables_end - y.tdesc) + " bytes, above the limit of " +
+                                      std::to_string(NOALLOC_TABLE_BYTES));
+  char* w = nullptr;
+  if ((st = scratch_address(&w)) != DPAR2_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if ((st = group_compress(g, &omega1, &omega2, f, w, y, s)) != DPAR2_OK) return st;
+  if ((st = group_als(g, o->max_iter, w, y, s)) != DPAR2_OK) return st;
+  hipError_t e = launch_fitness(y, w, nullptr, s);
+  if (e != hipSuccess) return hip_fail(e, "fitness");
+  if (U && (st = group_output_U(g, y, w, f->H, U, s)) != DPAR2_OK) return st;
+  if (!rep) return DPAR2_OK;
+  if ((st = group_report(g, w, y, rep, s)) != DPAR2_OK) return st;
   if (o->tol >= 0.0 && !rep->converged)
     return fail(DPAR2_ENOCONV, "the stop rule did not fire within " + std::to_string(o->max_iter) + " iterations");
   return DPAR2_OK;
