@@ -87,8 +87,8 @@ typedef enum {
  * 128-column chunks (a sketch kernel that writes Y, then a projection kernel
  * per chunk) for any J <= 16384, not only above the whole-row limit (J > 256
  * for float32, > 128 for bf16 / fp8).  Reads the slab twice and needs
- * N x 16 or N x 32 more floats of workspace (dpar2_workspace_bytes accounts
- * for it).  Results agree with the whole-row pass to rounding;
+ * about 1.6 (L <= 16) or 3.1 (L > 16) KiB per 64 rows of workspace for the
+ * digit planes of Y (dpar2_workspace_bytes accounts for it).  Results agree with the whole-row pass to rounding;
  * dpar2_autotune_slab chooses between the two. */
 #define DPAR2_FLAG_WIDE_SLAB    0x2u
 
@@ -255,6 +255,58 @@ dpar2_status dpar2_decompose_noalloc(const dpar2_tensor* X, const dpar2_opts* o,
                                      const float* omega1, const float* omega2,
                                      dpar2_factors* f, double* U, dpar2_report* rep,
                                      dpar2_stream_t stream);
+
+/* PARAFAC2-ALS on the uncompressed slices (Alg. 2, the iteration DPar2
+ * accelerates; its accuracy reference): per iteration, Q_k = the polar
+ * factor of X_k V S_k H^T, Y_k = Q_k^T X_k, then one CP-ALS sweep (H, V, W,
+ * each a least-squares update with a pseudoinverse, H and V with unit
+ * columns) on the R x J x K tensor {Y_k}, and the error
+ * e = sum_k ||X_k - Q_k H S_k V^T||^2 with its stop rule.  Every iteration
+ * reads the slab once (the first stage's slab kernel sketching with V:
+ * X_k V and its exact Gram and projection); everything else is FP64.  Uses
+ * opts.rank, max_iter, tol, item_rows and DPAR2_FLAG_WIDE_SLAB (sketch,
+ * sketch2 and power_iters are ignored); needs I_k >= R and J >= R.
+ * f: starting factors in, result out.  err_trace: device, max_iter doubles
+ * or NULL.  U (device, N x R float64, or NULL) receives U_k = Q_k H of the
+ * last iteration (one more slab pass).  rep (host) as in dpar2_decompose
+ * (fit_true = fit_compressed = 1 - e / sum_k ||X_k||^2 of the last
+ * iteration).  Workspace from dpar2_plain_workspace_bytes. */
+size_t dpar2_plain_workspace_bytes(const dpar2_tensor* X, const dpar2_opts* o);
+dpar2_status dpar2_als_plain(const dpar2_tensor* X, const dpar2_opts* o, dpar2_factors* f,
+                             double* err_trace, double* U, dpar2_report* rep,
+                             void* ws, size_t ws_bytes, dpar2_stream_t stream);
+
+/* ---- Post-processing of the factors (Sec. IV-E, discovery) ----------------
+ * Feature similarity: C (device, J x J float64) = the Pearson correlation
+ * coefficients between the rows V(i,:) (device, J x R float64, row-major,
+ * e.g. the V of a decomposition); a row of zero variance has no defined
+ * correlation and gets 0 in its row and column. */
+dpar2_status dpar2_feature_pcc(int64_t J, int32_t R, const double* V, double* C, dpar2_stream_t stream);
+
+/* Slice similarity of Eq. 9: S (device, n x n float64) with
+ * S[i][j] = exp(-gamma ||U_{idx[i]} - U_{idx[j]}||_F^2), U the N x R float64
+ * output of dpar2_output_U (rows row_offsets[k] .. of slice k; X supplies
+ * the offsets, device and host).  idx: device int32 n slice indices and its
+ * host copy; every listed slice must have the same number of rows (else
+ * DPAR2_ESHAPE, checked on the host). */
+dpar2_status dpar2_slice_similarity(const dpar2_tensor* X, int32_t R, const double* U, int32_t n,
+                                    const int32_t* idx, const int32_t* idx_host, double gamma, double* S,
+                                    dpar2_stream_t stream);
+
+/* The k-nearest-neighbour ranking of Sec. IV-E: out (device, k int32) = the
+ * indices of the k largest entries of v (device, n float64) in decreasing
+ * order, entry `exclude` (the target; -1 for none) left out, ties to the
+ * lower index, NaN below every number.  k <= the entries available. */
+dpar2_status dpar2_top_k(const double* v, int32_t n, int32_t exclude, int32_t k, int32_t* out,
+                         dpar2_stream_t stream);
+
+/* Random walk with restart on the similarity graph (Eqs. 10-11): A = S
+ * (device, n x n float64) with its diagonal taken as 0, A~ = A with each row
+ * divided by its sum (a row summing to 0 stays 0), q = e_target; r (device,
+ * n) starts at q and takes `iters` steps r <- (1 - c) A~^T r + c q (the
+ * paper's c = 0.15, 100 steps).  work: device scratch of 3 n doubles. */
+dpar2_status dpar2_rwr(const double* S, int32_t n, int32_t target, double c, int32_t iters, double* r,
+                       double* work, dpar2_stream_t stream);
 
 /* Fills *out (host struct) with device pointers into the workspace (host-only
  * pointer arithmetic; nothing is enqueued). */

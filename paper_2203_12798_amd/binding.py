@@ -73,7 +73,8 @@ class c_report(ctypes.Structure):
 
 EXPORTS = ["dpar2_workspace_bytes", "dpar2_workspace_size", "dpar2_compress", "dpar2_als_step", "dpar2_fitness",
            "dpar2_output_U", "dpar2_output_A", "dpar2_decompose", "dpar2_decompose_noalloc", "dpar2_release",
-           "dpar2_release_all", "dpar2_compressed_view", "dpar2_report_read",
+           "dpar2_release_all", "dpar2_plain_workspace_bytes", "dpar2_als_plain", "dpar2_feature_pcc",
+           "dpar2_slice_similarity", "dpar2_top_k", "dpar2_rwr", "dpar2_compressed_view", "dpar2_report_read",
            "dpar2_batch_workspace_size", "dpar2_decompose_batch", "dpar2_batch_report_read",
            "dpar2_warm_param_count", "dpar2_warm_features", "dpar2_warm_targets", "dpar2_warm_apply",
            "dpar2_warm_forward", "dpar2_warm_backward", "dpar2_warm_adam", "dpar2_autotune_item_rows",
@@ -112,6 +113,20 @@ def load(path: str = LIB_PATH):
                                     ctypes.c_size_t, vp]
     lib.dpar2_decompose_noalloc.restype = ctypes.c_int32
     lib.dpar2_decompose_noalloc.argtypes = [P(c_tensor), P(c_opts), vp, vp, P(c_factors), vp, P(c_report), vp]
+    lib.dpar2_plain_workspace_bytes.restype = ctypes.c_size_t
+    lib.dpar2_plain_workspace_bytes.argtypes = [P(c_tensor), P(c_opts)]
+    lib.dpar2_als_plain.restype = ctypes.c_int32
+    lib.dpar2_als_plain.argtypes = [P(c_tensor), P(c_opts), P(c_factors), vp, vp, P(c_report), vp,
+                                    ctypes.c_size_t, vp]
+    lib.dpar2_feature_pcc.restype = ctypes.c_int32
+    lib.dpar2_feature_pcc.argtypes = [ctypes.c_int64, ctypes.c_int32, vp, vp, vp]
+    lib.dpar2_slice_similarity.restype = ctypes.c_int32
+    lib.dpar2_slice_similarity.argtypes = [P(c_tensor), ctypes.c_int32, vp, ctypes.c_int32, vp, vp, ctypes.c_double,
+                                           vp, vp]
+    lib.dpar2_top_k.restype = ctypes.c_int32
+    lib.dpar2_top_k.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp]
+    lib.dpar2_rwr.restype = ctypes.c_int32
+    lib.dpar2_rwr.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, vp, vp, vp]
     lib.dpar2_release.restype = ctypes.c_int32
     lib.dpar2_release.argtypes = [vp]
     lib.dpar2_release_all.restype = ctypes.c_int32
@@ -365,6 +380,38 @@ def decompose_noalloc(X: Tensor, o: Options, omega1, omega2, f: Factors, U=None,
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
+def plain_workspace_size(X: Tensor, o: Options) -> int:
+    n = load().dpar2_plain_workspace_bytes(ctypes.byref(X.c()), ctypes.byref(o.c()))
+    if n == 0:
+        raise Dpar2Error(DPAR2_EINVAL, last_error())
+    return int(n)
+
+
+def alloc_plain_workspace(X: Tensor, o: Options, device="cuda:0"):
+    import torch
+    return torch.empty(plain_workspace_size(X, o) + 256, dtype=torch.uint8, device=device)
+
+
+def als_plain(X: Tensor, o: Options, f: Factors, ws, err_trace=None, U=None, stream=None, report=False):
+    """PARAFAC2-ALS on the uncompressed slices (Alg. 2), o.max_iter
+    iterations from the factors in f (updated in place); same report
+    convention as decompose()."""
+    lib = load()
+    p, n = _ws(ws)
+    fc = f.c()
+    r = c_report() if report else None
+    st = lib.dpar2_als_plain(ctypes.byref(X.c()), ctypes.byref(o.c()), ctypes.byref(fc), _ptr(err_trace), _ptr(U),
+                             ctypes.byref(r) if report else None, p, n, _stream(stream))
+    d = None
+    if report and st in (DPAR2_OK, DPAR2_ENOCONV, DPAR2_ENUMERIC):
+        d = _report_dict(r)
+        d["status"] = st
+    if st == DPAR2_ENOCONV and report:
+        return d
+    _check(st, d)
+    return d
+
+
 def output_A(X: Tensor, o: Options, A, ws, stream=None):
     """A: float64 device (N, R) receives the first-stage factors A_k."""
     lib = load()
@@ -572,3 +619,32 @@ def last_error() -> str:
 
 def status_string(st: int) -> str:
     return load().dpar2_status_string(int(st)).decode()
+
+
+# --- post-processing of the factors (Sec. IV-E) ------------------------------
+
+def feature_pcc(V, C, stream=None):
+    """C (J x J float64) <- Pearson correlations between the rows of V (J x R)."""
+    J, R = int(V.shape[0]), int(V.shape[1])
+    _check(load().dpar2_feature_pcc(J, R, _ptr(V), _ptr(C), _stream(stream)))
+
+
+def slice_similarity(X: Tensor, U, idx, gamma, S, stream=None):
+    """S (n x n) <- exp(-gamma ||U_i - U_j||_F^2) over the slices idx (host
+    sequence; copied to the device), all of one length."""
+    import torch
+    host = np.ascontiguousarray(np.asarray(idx, dtype=np.int32))
+    dev = torch.from_numpy(host).to(U.device)
+    R = int(U.shape[1])
+    _check(load().dpar2_slice_similarity(ctypes.byref(X.c()), R, _ptr(U), len(host), _ptr(dev), host.ctypes.data,
+                                         float(gamma), _ptr(S), _stream(stream)))
+    return dev
+
+
+def top_k(v, exclude, k, out, stream=None):
+    _check(load().dpar2_top_k(_ptr(v), int(v.numel()), int(exclude), int(k), _ptr(out), _stream(stream)))
+
+
+def rwr(S, target, r, work, c=0.15, iters=100, stream=None):
+    _check(load().dpar2_rwr(_ptr(S), int(S.shape[0]), int(target), float(c), int(iters), _ptr(r), _ptr(work),
+                            _stream(stream)))

@@ -142,6 +142,7 @@ void build_schedule(const Group& g, Schedule* s) {
   const int64_t cap = item_cap(g);
   std::vector<Item> raw;
   raw.reserve((size_t)K);
+  int64_t rbase = 0;   // first row of tensor t in the group's row space
   for (int t = 0; t < nt; ++t) {
     const int64_t* off = g.X[t].row_offsets_host;
     for (int64_t k = 0; k < g.X[t].K; ++k) {
@@ -152,9 +153,14 @@ void build_schedule(const Group& g, Schedule* s) {
         it.row1 = off[k] + n * (c + 1) / nc;
         it.slice = (int32_t)(g.k0[(size_t)t] + k);
         it.pad = t;
+        // items in row order: the slot ranges [floor(row / 64) + i, + tiles)
+        // of consecutive items never overlap, and the last one ends below
+        // ceil(N / 64) + n_items
+        it.tslot = (rbase + it.row0) / SKETCH_TM + (int64_t)raw.size();
         raw.push_back(it);
       }
     }
+    rbase += off[g.X[t].K];
   }
   std::vector<size_t> idx(raw.size());
   std::iota(idx.begin(), idx.end(), 0);
@@ -276,7 +282,7 @@ Layout make_layout(const Group& g) {
   y.omq = take(y.q > 0 ? sizeof(float) * (size_t)(K * J * L) : 0);   // power-step sketches
   // the wide slab pass keeps Y (16 LT floats per row) between its two kernels
   y.wide = J > narrow_j_limit(g.X[0].dtype) || (o->flags & DPAR2_FLAG_WIDE_SLAB) != 0;
-  y.ybuf = take(y.wide ? sizeof(float) * (size_t)y.N * (L <= 16 ? 16 : 32) : 0);
+  y.ybuf = take(y.wide ? wide_tile_bytes(y.L) * (size_t)((y.N + SKETCH_TM - 1) / SKETCH_TM + y.n_items) : 0);
   y.det = (o->flags & DPAR2_FLAG_DETERMINISTIC) != 0;
   y.total = p;
   return y;
@@ -805,6 +811,84 @@ dpar2_status comp_of(const dpar2_tensor* X, const dpar2_opts* o, const void* ws,
   return check_ws(c->y, ws, ws_bytes);
 }
 
+// PARAFAC2-ALS on the uncompressed slices (Alg. 2): a single-tensor group
+// whose slab pass sketches with V (L = R), and the buffers of the iteration.
+struct PlainLayout {
+  Layout y;                 // tables, control block, item partials (L = R), xnorm2, small, red, ybuf
+  size_t Y, theta, g1p, g2p, wp, g2, om_next, om_cur;
+  size_t total;
+};
+
+dpar2_opts plain_opts(const dpar2_opts* o) {
+  dpar2_opts q = *o;
+  q.sketch = q.sketch2 = o->rank;
+  q.power_iters = 0;
+  q.flags = o->flags & DPAR2_FLAG_WIDE_SLAB;
+  return q;
+}
+
+dpar2_status plain_group(const dpar2_tensor* X, const dpar2_opts* o, Group* g, dpar2_opts* q) {
+  if (!X || !o) return fail(DPAR2_EINVAL, "tensor or options pointer is NULL");
+  if (o->flags & ~(DPAR2_FLAG_NO_GRAPH | DPAR2_FLAG_WIDE_SLAB | DPAR2_FLAG_DETERMINISTIC))
+    return fail(DPAR2_EINVAL, "unknown bits in opts.flags");
+  *q = plain_opts(o);
+  return make_group(1, X, q, g);
+}
+
+PlainLayout make_plain_layout(const Group& g) {
+  PlainLayout p;
+  p.y = make_layout(g);
+  const int64_t K = p.y.K, J = p.y.J, R = p.y.R;
+  const int64_t nvb = (K + PL_VSLICES - 1) / PL_VSLICES;
+  size_t at = p.y.total;
+  auto take = [&](size_t bytes) {
+    const size_t r = at;
+    at = align256(at + bytes);
+    return r;
+  };
+  p.Y = take(sizeof(double) * (size_t)(K * R * J));
+  p.theta = take(sizeof(double) * (size_t)(K * R * R));
+  p.g1p = take(sizeof(double) * (size_t)(K * R * R));
+  p.g2p = take(sizeof(double) * (size_t)(nvb * J * R));
+  p.wp = take(sizeof(double) * (size_t)(K * (R * R + 2)));
+  p.g2 = take(sizeof(double) * (size_t)(J * R));
+  p.om_next = take(sizeof(float) * (size_t)(J * R));
+  p.om_cur = take(sizeof(float) * (size_t)(J * R));
+  p.total = at;
+  return p;
+}
+
+PlainArgs plain_args(const PlainLayout& p, char* w, const dpar2_factors* f, double* trace, double tol) {
+  const Layout& y = p.y;
+  PlainArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.K = y.K;
+  a.J = (int)y.J;
+  a.slice_ptr = reinterpret_cast<const int32_t*>(w + y.slice_ptr);
+  a.slice_list = reinterpret_cast<const int32_t*>(w + y.slice_list);
+  a.partG = reinterpret_cast<const double*>(w + y.partG);
+  a.partP = reinterpret_cast<const double*>(w + y.partP);
+  a.partS = reinterpret_cast<const double*>(w + y.partS);
+  a.xnorm2 = reinterpret_cast<double*>(w + y.xnorm2);
+  a.H = f->H;
+  a.V = f->V;
+  a.W = f->W;
+  a.trace = trace;
+  a.tol = tol;
+  a.Y = reinterpret_cast<double*>(w + p.Y);
+  a.theta = reinterpret_cast<double*>(w + p.theta);
+  a.g1p = reinterpret_cast<double*>(w + p.g1p);
+  a.g2p = reinterpret_cast<double*>(w + p.g2p);
+  a.wp = reinterpret_cast<double*>(w + p.wp);
+  a.small = reinterpret_cast<double*>(w + y.small);
+  a.red = reinterpret_cast<double*>(w + y.red);
+  a.g2 = reinterpret_cast<double*>(w + p.g2);
+  a.om_next = reinterpret_cast<float*>(w + p.om_next);
+  a.om_cur = reinterpret_cast<float*>(w + p.om_cur);
+  a.ctl = reinterpret_cast<Ctl*>(w + y.ctl);
+  return a;
+}
+
 dpar2_status check_tokens(int32_t rank, int32_t n, const int32_t* off_dev, const int32_t* off_host) {
   if (rank < 1 || rank > 32) return fail(DPAR2_EINVAL, "rank must be in 1..32");
   if (n < 1) return fail(DPAR2_EINVAL, "n must be >= 1");
@@ -1064,6 +1148,135 @@ dpar2_status dpar2_compressed_view(const dpar2_tensor* X, const dpar2_opts* o, c
   out->sigma = reinterpret_cast<const double*>(w + y.sig1);
   out->xnorm2 = reinterpret_cast<const double*>(w + y.xnorm2);
   return DPAR2_OK;
+}
+
+// --- PARAFAC2-ALS on the uncompressed slices (Alg. 2) ----------------------
+
+size_t dpar2_plain_workspace_bytes(const dpar2_tensor* X, const dpar2_opts* o) {
+  Group g;
+  dpar2_opts q;
+  if (plain_group(X, o, &g, &q) != DPAR2_OK) return 0;
+  return make_plain_layout(g).total;
+}
+
+dpar2_status dpar2_als_plain(const dpar2_tensor* X, const dpar2_opts* o, dpar2_factors* f, double* err_trace,
+                             double* U, dpar2_report* rep, void* ws, size_t ws_bytes, dpar2_stream_t stream) {
+  Group g;
+  dpar2_opts q;
+  dpar2_status st = plain_group(X, o, &g, &q);
+  if (st != DPAR2_OK) return st;
+  if (!f || !f->H || !f->V || !f->W) return fail(DPAR2_EINVAL, "factors must be non-NULL");
+  const PlainLayout p = make_plain_layout(g);
+  if (!ws) return fail(DPAR2_EWORKSPACE, "workspace is NULL");
+  if ((uintptr_t)ws % 256 != 0) return fail(DPAR2_EWORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < p.total) return fail(DPAR2_EWORKSPACE, "workspace too small: need " + std::to_string(p.total) + " bytes");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  const Layout& y = p.y;
+  // descriptor (the slab pass sketches with the float32 copy of V) and the
+  // schedule tables: one upload
+  float* om_cur = reinterpret_cast<float*>(w + p.om_cur);
+  const float* om = om_cur;
+  {
+    const std::vector<TDesc> td = descriptors(g, &om, &om, f, &err_trace);
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    Staging& sg = g_stage[w];
+    stage_tables(g, y, sg);
+    std::memcpy(sg.image.data(), td.data(), sizeof(TDesc) * td.size());
+    if ((st = upload_locked(sg, w, sg.image.data(), sg.image.size(), y.tdesc, s)) != DPAR2_OK) return st;
+  }
+  const PlainArgs a = plain_args(p, w, f, err_trace, o->tol);
+  const int dtype = X->dtype;
+  const int esize = dtype == DPAR2_F32 ? 4 : (dtype == DPAR2_BF16 ? 2 : 1);
+  PlainLaunch pl;
+  std::memset(&pl, 0, sizeof(pl));
+  pl.slab.td = reinterpret_cast<const TDesc*>(w + y.tdesc);
+  pl.slab.J = (int)y.J;
+  pl.slab.L = y.R;
+  pl.slab.R = y.R;
+  pl.slab.items = reinterpret_cast<const Item*>(w + y.items);
+  pl.slab.partG = reinterpret_cast<double*>(w + y.partG);
+  pl.slab.partP = reinterpret_cast<double*>(w + y.partP);
+  pl.slab.partS = reinterpret_cast<double*>(w + y.partS);
+  pl.slab.ybuf = reinterpret_cast<float*>(w + y.ybuf);
+  pl.slab.skip = &reinterpret_cast<const Ctl*>(w + y.ctl)->done;
+  pl.dtype = dtype;
+  pl.n_items = y.n_items;
+  pl.vec = (y.J % 4 == 0) && ((uintptr_t)X->slab % (4 * esize) == 0);
+  pl.wide = y.wide;
+  hipError_t e = launch_plain(0, y.R, a, pl, s);
+  for (int32_t i = 0; e == hipSuccess && i < o->max_iter; ++i) e = launch_plain(1, y.R, a, pl, s);
+  if (e != hipSuccess) return hip_fail(e, "plain ALS iteration");
+  if (U) {
+    // U_k = Q_k H = (X_k V) Theta_k H, V of the last slab pass that ran
+    if ((e = launch_plain(2, y.R, a, pl, s)) != hipSuccess) return hip_fail(e, "plain ALS theta");
+    SlabArgs sa = pl.slab;
+    sa.skip = nullptr;
+    sa.partG = sa.partP = sa.partS = nullptr;
+    sa.theta = reinterpret_cast<const double*>(w + p.theta);
+    sa.U = U;
+    if ((e = launch_slab(sa, dtype, y.n_items, pl.vec, true, y.wide, s)) != hipSuccess) return hip_fail(e, "U pass");
+  }
+  if (!rep) return DPAR2_OK;
+  if ((st = group_report(g, w, y, rep, s)) != DPAR2_OK) return st;
+  rep->fit_compressed = rep->fit_true;
+  if (o->tol >= 0.0 && !rep->converged)
+    return fail(DPAR2_ENOCONV, "the stop rule did not fire within " + std::to_string(o->max_iter) + " iterations");
+  return DPAR2_OK;
+}
+
+// --- post-processing of the factors (Sec. IV-E) -----------------------------
+
+dpar2_status dpar2_feature_pcc(int64_t J, int32_t R, const double* V, double* C, dpar2_stream_t stream) {
+  if (J < 1 || J > ((int64_t)1 << 20)) return fail(DPAR2_EINVAL, "J must be in 1..2^20");
+  if (R < 1 || R > 32) return fail(DPAR2_EINVAL, "R must be in 1..32");
+  if (!V || !C) return fail(DPAR2_EINVAL, "V and C must be non-NULL");
+  const hipError_t e = launch_pcc(J, R, V, C, reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DPAR2_OK : hip_fail(e, "feature pcc");
+}
+
+dpar2_status dpar2_slice_similarity(const dpar2_tensor* X, int32_t R, const double* U, int32_t n, const int32_t* idx,
+                                    const int32_t* idx_host, double gamma, double* S, dpar2_stream_t stream) {
+  if (!X || !X->row_offsets || !X->row_offsets_host) return fail(DPAR2_EINVAL, "tensor and row offsets must be non-NULL");
+  if (R < 1 || R > 32) return fail(DPAR2_EINVAL, "R must be in 1..32");
+  if (n < 1 || n > (1 << 20)) return fail(DPAR2_EINVAL, "n must be in 1..2^20");
+  if (!U || !idx || !idx_host || !S) return fail(DPAR2_EINVAL, "U, idx and S must be non-NULL");
+  if (!(gamma >= 0.0)) return fail(DPAR2_EINVAL, "gamma must be >= 0");
+  const int64_t* off = X->row_offsets_host;
+  int64_t rows = -1;
+  for (int32_t i = 0; i < n; ++i) {
+    const int32_t k = idx_host[i];
+    if (k < 0 || k >= X->K) return fail(DPAR2_EINVAL, "slice index " + std::to_string(k) + " out of range");
+    const int64_t r = off[k + 1] - off[k];
+    if (rows < 0) rows = r;
+    if (r != rows)
+      return fail(DPAR2_ESHAPE, "the similarity of Eq. 9 needs slices of one length (slice " + std::to_string(k) +
+                                    " has " + std::to_string(r) + " rows, not " + std::to_string(rows) + ")");
+  }
+  const hipError_t e = launch_similarity(n, rows * R, R, X->row_offsets, idx, U, gamma, S,
+                                         reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DPAR2_OK : hip_fail(e, "slice similarity");
+}
+
+dpar2_status dpar2_top_k(const double* v, int32_t n, int32_t exclude, int32_t k, int32_t* out,
+                         dpar2_stream_t stream) {
+  if (!v || !out) return fail(DPAR2_EINVAL, "v and out must be non-NULL");
+  if (n < 1) return fail(DPAR2_EINVAL, "n must be >= 1");
+  const int32_t avail = n - ((exclude >= 0 && exclude < n) ? 1 : 0);
+  if (k < 1 || k > avail) return fail(DPAR2_EINVAL, "k must be in 1.." + std::to_string(avail));
+  const hipError_t e = launch_topk(v, n, exclude, k, out, reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DPAR2_OK : hip_fail(e, "top k");
+}
+
+dpar2_status dpar2_rwr(const double* S, int32_t n, int32_t target, double c, int32_t iters, double* r, double* work,
+                       dpar2_stream_t stream) {
+  if (!S || !r || !work) return fail(DPAR2_EINVAL, "S, r and work must be non-NULL");
+  if (n < 1 || n > (1 << 20)) return fail(DPAR2_EINVAL, "n must be in 1..2^20");
+  if (target < 0 || target >= n) return fail(DPAR2_EINVAL, "target out of range");
+  if (!(c > 0.0 && c <= 1.0)) return fail(DPAR2_EINVAL, "the restart probability c must be in (0, 1]");
+  if (iters < 0) return fail(DPAR2_EINVAL, "iters must be >= 0");
+  const hipError_t e = launch_rwr(S, n, target, c, iters, r, work, reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DPAR2_OK : hip_fail(e, "rwr");
 }
 
 // --- learned warm start ------------------------------------------------------

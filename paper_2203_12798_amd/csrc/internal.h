@@ -17,6 +17,7 @@ struct Item {
   int64_t row1;
   int32_t slice;
   int32_t pad;
+  int64_t tslot;   // first slot of the item's tiles in the wide pass's Y-digit buffer
 };
 
 constexpr int SKETCH_TM = 64;          // rows per tile of the slab pass
@@ -105,11 +106,16 @@ struct SlabArgs {
   double *partG, *partP, *partS;
   const double* theta;     // U variant: K x L x R
   double* U;               // U variant: N x R (single tensor)
-  float* ybuf;             // wide-J pass: Y rows (TDesc::rbase + row) x 16 LT
+  float* ybuf;             // wide-J pass: Y digits and exponents per tile (wide_tile_bytes(L) each,
+                           // tile t of an item at slot Item::tslot + t)
+  const int32_t* skip;     // NULL, or a flag: every block returns at once while it is nonzero
 };
 // J above which the slab pass takes the two-kernel wide form (sketch, then
 // projection per 128-column chunk): 256 for float32 slabs, 128 otherwise
 inline int narrow_j_limit(int dtype) { return dtype == 0 ? 256 : 128; }
+// bytes per 64-row tile of the wide pass's Y-digit buffer: three digit planes
+// of 16 LT columns x 64 row bytes, then the 16 LT column exponents
+__host__ __device__ inline size_t wide_tile_bytes(int L) { return L <= 16 ? 3 * 16 * 64 + 16 * 4 : 3 * 32 * 64 + 32 * 4; }
 constexpr int MAX_J = 16384;
 // Slab pass over all work items: per-item partials of Y^T Y, Y^T X and
 // ||X||^2, or (uout) U = Y Theta_k.  dtype: dpar2_dtype; vec: every slab is
@@ -142,6 +148,47 @@ hipError_t launch_pw_identity(const Layout& lay, char* ws, hipStream_t s);
 int als_slices_per_block(int R);
 
 bool sketch_supported(int J, int L, int dtype);
+
+// --- PARAFAC2-ALS on the uncompressed slices (Alg. 2), k_plain.hip -----------
+constexpr int PL_VSLICES = 32;   // slices per block of the V pass
+struct PlainArgs {
+  int64_t K;
+  int J;
+  const int32_t* slice_ptr;       // K + 1: items of each slice
+  const int32_t* slice_list;
+  const double *partG, *partP, *partS;
+  double* xnorm2;                 // K
+  double *H, *V, *W;              // factors (caller memory)
+  double* trace;                  // per-iteration error or NULL
+  double tol;
+  double* Y;                      // K x R x J: Y_k = Q_k^T X_k
+  double* theta;                  // K x R x R: T_k G_k^{-1/2} (Q_k = X_k V Theta_k)
+  double* g1p;                    // K x R R
+  double* g2p;                    // ceil(K / PL_VSLICES) x J x R
+  double* wp;                     // K x (R R + 2)
+  double* small;                  // SM_COUNT x R R
+  double* red;                    // RED_WIDTH R R + 2 (summed partials)
+  double* g2;                     // J x R (summed)
+  float *om_next, *om_cur;        // J x R float32 copies of V (next pass / last pass run)
+  Ctl* ctl;
+};
+// The slab pass of an iteration: arguments and launch shape.
+struct PlainLaunch {
+  SlabArgs slab;
+  int dtype;
+  int64_t n_items;
+  bool vec, wide;
+};
+// phase 0: begin of a call; 1: one iteration; 2: Theta_k <- Theta_k H (U output)
+hipError_t launch_plain(int phase, int R, const PlainArgs& a, const PlainLaunch& pl, hipStream_t s);
+
+// --- post-processing of the factors (Sec. IV-E), k_down.hip -----------------
+hipError_t launch_pcc(int64_t J, int R, const double* V, double* C, hipStream_t s);
+hipError_t launch_similarity(int n, int64_t M, int R, const int64_t* off, const int32_t* idx, const double* U,
+                             double gamma, double* S, hipStream_t s);
+hipError_t launch_topk(const double* v, int n, int exclude, int k, int32_t* out, hipStream_t s);
+hipError_t launch_rwr(const double* S, int n, int target, double c, int iters, double* r, double* work,
+                      hipStream_t s);
 
 // --- learned warm start (k_warm.hip) ------------------------------------------
 constexpr int WARM_WIDTH = 128;   // hidden width of the set encoder

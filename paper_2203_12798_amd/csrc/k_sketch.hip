@@ -49,6 +49,7 @@ __global__ __launch_bounds__(256) void k_sketch(SlabArgs a) {
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
+  if (a.skip && *a.skip) return;
   const Item it = items[blockIdx.x];
   const float* __restrict__ slab = static_cast<const float*>(a.td[it.pad].slab);
   const int64_t nrows = it.row1 - it.row0;

@@ -89,7 +89,7 @@ __device__ __forceinline__ float4 to_f32x4(typename In<TIN>::V4 x, float scale) 
   }
 }
 
-// eight consecutive LDS floats (bf16-representable) as a bf16 vector: exact
+// eight consecutive floats (bf16-representable) as a bf16 vector: exact
 __device__ __forceinline__ v8bf bf16x8(const float* p) {
   const float4 a = *reinterpret_cast<const float4*>(p);
   const float4 b = *reinterpret_cast<const float4*>(p + 4);
@@ -190,7 +190,45 @@ __device__ __forceinline__ void digits4(const int (&u)[4], uint32_t& p0, uint32_
   p0 = bytes_k<2>((uint32_t)u[0], (uint32_t)u[1], (uint32_t)u[2], (uint32_t)u[3]) ^ 0x80808080u;
 }
 
-template <int LT, int JT, bool VEC, int TIN, bool UOUT>
+// One 16 x 16 output tile of a digit-plane product over a 64-row tile:
+// A[d], B[d] are this lane's 16 bytes (rows 16 lk .. 16 lk + 15) of digit
+// plane d of its A column (ca + lr) and B column; the nine products are summed
+// exactly in int32, combined exactly in FP64 and scaled by
+// 2^(erow + ecol - 44), erow = erow_e[ca + row] and ecol = ecol_e the column
+// exponents of the 22-bit fixed point; the result is added to acc (row
+// f32_row(lane, v), column lane % 16).
+__device__ __forceinline__ v4d digit_tile_fma(const v4i (&A)[3], const v4i (&B)[3], int ecol_e, const int* erow_e,
+                                              int ca, int lane, v4d acc) {
+  const v4i z = v4i{0, 0, 0, 0};
+  const v4i S0 = mfma_i8(A[0], B[0], z);
+  v4i S1 = mfma_i8(A[0], B[1], z);
+  S1 = mfma_i8(A[1], B[0], S1);
+  v4i S2 = mfma_i8(A[0], B[2], z);
+  S2 = mfma_i8(A[1], B[1], S2);
+  S2 = mfma_i8(A[2], B[0], S2);
+  v4i S3 = mfma_i8(A[1], B[2], z);
+  S3 = mfma_i8(A[2], B[1], S3);
+  const v4i S4 = mfma_i8(A[2], B[2], z);
+  // 2^(erow + ecol - 44) as an FP64 bit pattern (high word only); the
+  // exponent stays within [-340, 212]
+  const int ecol = (ecol_e - 44 + 1023) << 20;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    // |S0| <= 2^18, |S1| <= 2^20, |S3| <= 2^21, |S4| <= 2^20: the two
+    // pairs combine exactly in int32, the total exactly in FP64 (< 2^52)
+    const int hi = S0[v] * 256 + S1[v], lo = S3[v] * 256 + S4[v];
+    const double val = fma((double)hi, 16777216.0, fma((double)S2[v], 65536.0, (double)lo));
+    const int erow = erow_e[ca + f32_row(lane, v)];
+    acc[v] = fma(val, __hiloint2double((erow << 20) + ecol, 0), acc[v]);
+  }
+  return acc;
+}
+
+// SPL: Omega as three bf16 pieces (FP32-level products).  float32 slabs always;
+// bf16 / fp8 slabs in the passes of a power step, whose per-slice sketch
+// matrices are not rounded to bf16 (their X is bf16-exact: three products
+// per chunk instead of six).
+template <int LT, int JT, bool VEC, int TIN, bool UOUT, bool SPL>
 __global__ __launch_bounds__(256) void k_sketch_q(SlabArgs a) {
   typedef typename In<TIN>::E E;
   const int J = a.J, L = a.L;
@@ -209,9 +247,9 @@ __global__ __launch_bounds__(256) void k_sketch_q(SlabArgs a) {
   constexpr int QWORDS = 3 * JP * QW + 3 * LP * QW;
   constexpr int UWORDS = 2 * (TM * YS) + 2 * 32 * 32;
   __shared__ __align__(16) float sX[TM * XS];
-  // float32 slabs keep Omega as three bf16 planes (split3), the others as
-  // floats already rounded to bf16
-  constexpr bool SPLIT = (TIN == DPAR2_F32);
+  // Omega as three bf16 planes (split3), or as floats already rounded to bf16
+  constexpr bool SPLIT = SPL;
+  constexpr bool XSPLIT = (TIN == DPAR2_F32);      // X itself needs three pieces
   constexpr int NKC = (JT + 1) / 2;                // 32-column chunks
   constexpr int XSB = 32 * NKC + 8;                // bf16 row stride of the planes
   constexpr int PLANE = LP * XSB;
@@ -228,6 +266,7 @@ __global__ __launch_bounds__(256) void k_sketch_q(SlabArgs a) {
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
+  if (a.skip && *a.skip) return;
   const Item it = a.items[blockIdx.x];
   const TDesc& td = a.td[it.pad];
   const E* __restrict__ slab = static_cast<const E*>(td.slab);
@@ -364,7 +403,7 @@ __global__ __launch_bounds__(256) void k_sketch_q(SlabArgs a) {
       }
       // a wave whose 16 rows are all below 2^-100 (and not all zero) works on
       // X 2^64 and scales Y back (both exact), so that no piece is subnormal
-      const bool tiny = __builtin_amdgcn_ballot_w64(mx >= 0x1p-100f) == 0 &&
+      const bool tiny = XSPLIT && __builtin_amdgcn_ballot_w64(mx >= 0x1p-100f) == 0 &&
                         __builtin_amdgcn_ballot_w64(mx > 0.f) != 0;
       if (tiny) {
 #pragma unroll
@@ -378,7 +417,11 @@ __global__ __launch_bounds__(256) void k_sketch_q(SlabArgs a) {
 #pragma unroll
       for (int kc = 0; kc < NKC; ++kc) {
         v8bf xh, xm, xl;
-        split3(xr[kc], xh, xm, xl);
+        if constexpr (XSPLIT) {
+          split3(xr[kc], xh, xm, xl);
+        } else {
+          xh = bf16x8(xr[kc]);   // bf16 / fp8 rows are bf16-exact: one piece
+        }
 #pragma unroll
         for (int lt = 0; lt < LT; ++lt) {
           const __bf16* ob = &sOmb[(lt * 16 + lr) * XSB + kc * 32 + 8 * lk];
@@ -386,10 +429,12 @@ __global__ __launch_bounds__(256) void k_sketch_q(SlabArgs a) {
           const v8bf om = *reinterpret_cast<const v8bf*>(ob + PLANE);
           const v8bf ol = *reinterpret_cast<const v8bf*>(ob + 2 * PLANE);
           acc[lt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, oh, acc[lt], 0, 0, 0);
-          lo[lt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, oh, lo[lt], 0, 0, 0);
-          lo[lt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xm, om, lo[lt], 0, 0, 0);
+          if constexpr (XSPLIT) {
+            lo[lt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, oh, lo[lt], 0, 0, 0);
+            lo[lt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xm, om, lo[lt], 0, 0, 0);
+          }
           lo[lt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, ol, lo[lt], 0, 0, 0);
-          lo[lt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xm, oh, lo[lt], 0, 0, 0);
+          if constexpr (XSPLIT) lo[lt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xm, oh, lo[lt], 0, 0, 0);
           lo[lt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, om, lo[lt], 0, 0, 0);
         }
       }
@@ -536,28 +581,7 @@ __global__ __launch_bounds__(256) void k_sketch_q(SlabArgs a) {
           A[a] = *reinterpret_cast<const v4i*>(&sYq[(a * LP + ca + lr) * QW + 4 * lk]);
           B[a] = *reinterpret_cast<const v4i*>(&Bp[(a * nb + cb + lr) * QW + 4 * lk]);
         }
-        const v4i z = v4i{0, 0, 0, 0};
-        v4i S0 = mfma_i8(A[0], B[0], z);
-        v4i S1 = mfma_i8(A[0], B[1], z);
-        S1 = mfma_i8(A[1], B[0], S1);
-        v4i S2 = mfma_i8(A[0], B[2], z);
-        S2 = mfma_i8(A[1], B[1], S2);
-        S2 = mfma_i8(A[2], B[0], S2);
-        v4i S3 = mfma_i8(A[1], B[2], z);
-        S3 = mfma_i8(A[2], B[1], S3);
-        const v4i S4 = mfma_i8(A[2], B[2], z);
-        // 2^(erow + ecol - 44) as an FP64 bit pattern (high word only); the
-        // exponent stays within [-340, 212]
-        const int ecol = (eb[cb + lr] - 44 + 1023) << 20;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          // |S0| <= 2^18, |S1| <= 2^20, |S3| <= 2^21, |S4| <= 2^20: the two
-          // pairs combine exactly in int32, the total exactly in FP64 (< 2^52)
-          const int hi = S0[v] * 256 + S1[v], lo = S3[v] * 256 + S4[v];
-          const double val = fma((double)hi, 16777216.0, fma((double)S2[v], 65536.0, (double)lo));
-          const int erow = sYe[ca + f32_row(lane, v)];
-          pacc[qi][v] = fma(val, __hiloint2double((erow << 20) + ecol, 0), pacc[qi][v]);
-        }
+        pacc[qi] = digit_tile_fma(A, B, eb[cb + lr], sYe, ca, lane, pacc[qi]);
       }
     }
   }
@@ -594,7 +618,9 @@ __global__ __launch_bounds__(256) void k_sketch_q(SlabArgs a) {
 
 
 // Launch for J <= 128 (JT <= 8); returns hipErrorInvalidValue otherwise.
-template <int TIN, bool UOUT>
+// SPL: see k_sketch_q (float32 slabs always split Omega; bf16 / fp8 slabs in
+// the passes of a power step).
+template <int TIN, bool UOUT, bool SPL>
 hipError_t slab_launch(const SlabArgs& a, int64_t n_items, bool vec, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   const int lt = a.L <= 16 ? 1 : 2;
@@ -604,9 +630,9 @@ hipError_t slab_launch(const SlabArgs& a, int64_t n_items, bool vec, hipStream_t
 #define DPAR2_SQ(LT_, JT_)                                                                          \
   if (lt == LT_ && jt == JT_) {                                                                     \
     if (vec)                                                                                        \
-      hipLaunchKernelGGL((k_sketch_q<LT_, JT_, true, TIN, UOUT>), grid, block, 0, s, a);            \
+      hipLaunchKernelGGL((k_sketch_q<LT_, JT_, true, TIN, UOUT, SPL>), grid, block, 0, s, a);       \
     else                                                                                            \
-      hipLaunchKernelGGL((k_sketch_q<LT_, JT_, false, TIN, UOUT>), grid, block, 0, s, a);           \
+      hipLaunchKernelGGL((k_sketch_q<LT_, JT_, false, TIN, UOUT, SPL>), grid, block, 0, s, a);      \
     return hipGetLastError();                                                                       \
   }
   DPAR2_SQ(1, 1) DPAR2_SQ(1, 2) DPAR2_SQ(1, 3) DPAR2_SQ(1, 4) DPAR2_SQ(1, 6) DPAR2_SQ(1, 8)

@@ -6,7 +6,7 @@
 //     Cholesky factor G = R^T R; when a pivot falls below 1e-9 max_i G_ii the
 //     eigen form Wh = V Lambda^{-1/2} over the eigenvalues above
 //     64 eps lambda_max is used instead (defined also for a rank-deficient Y)
-//   S = B B^T = Wh^T (P P^T) Wh with B = Q^T X = Wh^T P (projection)
+//   B = Q^T X = Wh^T P (projection), streamed by chunks of P, and S = B B^T
 //   S = C^T C (Cholesky), one-sided Jacobi on C^T: C^T V = U~ Sigma gives the
 //     eigenvectors U~ of S and the singular values Sigma of B (small SVD)
 //   Phi = Wh U~_R (A_k = Y Phi = Q U~_R), C_k B_k = B^T U~_R = P^T Phi
@@ -59,16 +59,16 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
                                                   Ctl* ctl, const int32_t* __restrict__ slice_t) {
   constexpr int RM = SC<L>::RM, LH = SC<L>::LH, LD = SC<L>::LD, CW = SC<L>::CW, LL = L * L;
   __shared__ double Gs[L * LD];    // G, then its Cholesky factor (upper triangle)
-  __shared__ double Ss[L * LD];    // S' = P P^T; then Phi
+  __shared__ double Ss[L * LD];    // S = B B^T; then Phi
+  __shared__ double Ws[L * LD];    // whitening Wh
   constexpr int CP = CW + 1;        // padded chunk row (conflict-free column reads)
-  // Wh and S' Wh / U~ live only between the P P^T pass and Phi; the chunks of
-  // P are streamed only outside that span, so they share the space
-  constexpr int NWX = (2 * L * LD > L * CP) ? 2 * L * LD : L * CP;
-  __shared__ double WX[NWX];
-  double* const Ws = WX;            // whitening Wh
-  double* const Xs = WX + L * LD;   // S' Wh; then sorted eigenvectors U~
-  double* const Pc = WX;            // chunk of P
-  __shared__ double Mc[L * CP];    // chunk of C_k B_k (rows r < R)
+  // the sorted eigenvectors U~ live only between the Jacobi and Phi, when no
+  // chunk of P is streamed: they share the chunk's space
+  constexpr int NPX = (L * CP > L * LD) ? L * CP : L * LD;
+  __shared__ double PX[NPX];
+  double* const Pc = PX;            // chunk of P
+  double* const Xs = PX;            // sorted eigenvectors U~
+  __shared__ double Mc[L * CP];    // chunk of B = Wh^T P; chunk of C_k B_k (rows r < R)
   __shared__ double sgn[L], row[L], rinv[L], sv[L];
 
   const int lane = threadIdx.x, c = lane % RM, h = lane / RM;
@@ -107,8 +107,8 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
     xnorm2[k] = s;
   }
 
-  // S' = P P^T, P streamed through LDS in chunks of CW columns
-  // chunk jc of P into Pc; the loads of one item are issued together
+  // P is streamed through LDS in chunks of CW columns: chunk jc of P into Pc
+  // (the loads of one item are issued together)
   auto load_chunk = [&](int jc) {
     constexpr int NE = (L * CW + 63) / 64;
     double pv[NE];
@@ -130,47 +130,7 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
       if (e < L * CW) Pc[(e / CW) * CP + e % CW] = pv[u];
     }
   };
-  // S' = sum over chunks of P_c P_c^T on the FP64 matrix cores (16 x 16 tiles,
-  // the upper ones; P's rows as both operands)
-  v4d sacc[2][2];
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y2 = 0; y2 < 2; ++y2) sacc[x][y2] = v4d{0.0, 0.0, 0.0, 0.0};
-  {
-    const int i16 = lane & 15, k4 = lane >> 4;
-    for (int jc = 0; jc < J; jc += CW) {
-      load_chunk(jc);
-      __syncthreads();
-#pragma unroll
-      for (int kk = 0; kk < CW / 4; ++kk) {
-        const int j = 4 * kk + k4;
-        double pv2[2];
-#pragma unroll
-        for (int t = 0; t < 2; ++t) pv2[t] = (16 * t + i16 < L) ? Pc[(16 * t + i16) * CP + j] : 0.0;
-        sacc[0][0] = mfma_f64(pv2[0], pv2[0], sacc[0][0]);
-        if (L > 16) {
-          sacc[0][1] = mfma_f64(pv2[0], pv2[1], sacc[0][1]);
-          sacc[1][1] = mfma_f64(pv2[1], pv2[1], sacc[1][1]);
-        }
-      }
-      __syncthreads();
-    }
-#pragma unroll
-    for (int tr = 0; tr < 2; ++tr)
-#pragma unroll
-      for (int tj = tr; tj < 2; ++tj)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int a = 16 * tr + f64_row(lane, v), b = 16 * tj + i16;
-          if (a < L && b < L) {
-            Ss[a * LD + b] = sacc[tr][tj][v];
-            if (tr != tj) Ss[b * LD + a] = sacc[tr][tj][v];
-          }
-        }
-  }
-  __syncthreads();
-
+  __syncthreads();   // G complete in Gs
   // Whitening: G = R^T R (lane_cholesky), Wh = R^{-1}
   double dmax = 0.0;
   for (int a = 0; a < L; ++a) dmax = fmax(dmax, Gs[a * LD + a]);
@@ -216,27 +176,68 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
   }
   __syncthreads();
 
-  // S = Wh^T S' Wh, column c (own rows)
+  // S = B B^T with B = Wh^T P = Q^T X (the projection), streamed in chunks of
+  // CW columns on the FP64 matrix cores: each chunk of P is whitened first,
+  // B_c = Wh^T P_c, and then S += B_c B_c^T.  (Forming P P^T before the
+  // whitening would square the condition of Y as well as that of B: a slice
+  // with one dominant row then loses its small singular values.)
+  v4d sacc[2][2];
 #pragma unroll
-  for (int ii = 0; ii < LH; ++ii) {
-    const int a = h * LH + ii;
-    if (cv && a < L) {
-      double s = 0.0;
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-      for (int b = 0; b < L; ++b) s = fma(Ss[a * LD + b], Ws[b * LD + c], s);
-      Xs[a * LD + c] = s;
+    for (int y2 = 0; y2 < 2; ++y2) sacc[x][y2] = v4d{0.0, 0.0, 0.0, 0.0};
+  {
+    const int i16 = lane & 15, k4 = lane >> 4;
+    for (int jc = 0; jc < J; jc += CW) {
+      load_chunk(jc);
+      __syncthreads();
+      v4d bacc[2][2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y2 = 0; y2 < 2; ++y2) bacc[x][y2] = v4d{0.0, 0.0, 0.0, 0.0};
+      chunk_atb<L, LD, CP>(Ws, Pc, L, bacc, lane);
+#pragma unroll
+      for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int a = 16 * tr + f64_row(lane, v), jj = 16 * tj + i16;
+            if (a < L) Mc[a * CP + jj] = bacc[tr][tj][v];
+          }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < CW / 4; ++kk) {
+        const int j = 4 * kk + k4;
+        double bv2[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) bv2[t] = (16 * t + i16 < L) ? Mc[(16 * t + i16) * CP + j] : 0.0;
+        sacc[0][0] = mfma_f64(bv2[0], bv2[0], sacc[0][0]);
+        if (L > 16) {
+          sacc[0][1] = mfma_f64(bv2[0], bv2[1], sacc[0][1]);
+          sacc[1][1] = mfma_f64(bv2[1], bv2[1], sacc[1][1]);
+        }
+      }
+      __syncthreads();
     }
+#pragma unroll
+    for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+      for (int tj = tr; tj < 2; ++tj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int a = 16 * tr + f64_row(lane, v), b = 16 * tj + i16;
+          if (a < L && b < L) {
+            Ss[a * LD + b] = sacc[tr][tj][v];
+            if (tr != tj) Ss[b * LD + a] = sacc[tr][tj][v];
+          }
+        }
   }
   __syncthreads();
-  // column c of S = Wh^T (S' Wh), Cholesky S = C^T C (semidefinite)
+  // column c of S, Cholesky S = C^T C (semidefinite)
 #pragma unroll
-  for (int i = 0; i < L; ++i) {
-    double s = 0.0;
-    if (lane < L)
-#pragma unroll
-      for (int b = 0; b < L; ++b) s = fma(Ws[b * LD + i], Xs[b * LD + lane], s);
-    col[i] = s;
-  }
+  for (int i = 0; i < L; ++i) col[i] = (lane < L) ? Ss[i * LD + lane] : 0.0;
   double smax = 0.0;
 #pragma unroll
   for (int i = 0; i < L; ++i)

@@ -126,12 +126,15 @@ def test_dtype_and_power_options_validated_on_host():
         for dt in (binding.DPAR2_F32, binding.DPAR2_BF16):
             tf = binding.c_tensor(2, J, 0x1000, hw, 0x2000, dt, None)
             assert lib.dpar2_workspace_size(ctypes.byref(tf), ctypes.byref(o)) > 0
-    # the wide pass (J above 256 for float32) keeps Y: 16 floats per row at L <= 16
+    # the wide pass (J above 256 for float32) keeps the digit planes of Y:
+    # (3 * 16 * 64 + 16 * 4) bytes per 64-row tile slot at L <= 16, with
+    # ceil(N / 64) + n_items slots
     t256 = binding.c_tensor(2, 256, 0x1000, hw, 0x2000, binding.DPAR2_F32, None)
     t257 = binding.c_tensor(2, 257, 0x1000, hw, 0x2000, binding.DPAR2_F32, None)
     ws256 = lib.dpar2_workspace_size(ctypes.byref(t256), ctypes.byref(o))
     ws257 = lib.dpar2_workspace_size(ctypes.byref(t257), ctypes.byref(o))
-    assert ws257 - ws256 >= 400 * 16 * 4
+    ybuf = (3 * 16 * 64 + 16 * 4) * ((400 + 63) // 64 + 2)
+    assert ws257 - ws256 >= ybuf
     # a power step needs one sketch matrix per slice in the workspace
     o1 = binding.c_opts(2, 3, 3, 5, -1.0, 0, 1)
     t8 = binding.c_tensor(2, 8, 0x1000, hp, 0x2000, binding.DPAR2_F32, None)
@@ -141,7 +144,7 @@ def test_dtype_and_power_options_validated_on_host():
     # unknown flag bits are rejected
     ow = binding.c_opts(2, 3, 3, 5, -1.0, binding.DPAR2_FLAG_WIDE_SLAB, 0)
     assert (lib.dpar2_workspace_size(ctypes.byref(t256), ctypes.byref(ow))
-            >= ws256 + 400 * 16 * 4)
+            >= ws256 + ybuf)
     assert lib.dpar2_workspace_size(ctypes.byref(t257), ctypes.byref(ow)) == ws257
     ox = binding.c_opts(2, 3, 3, 5, -1.0, 0x8, 0)
     assert _status(lib, binding, t8, ox) == -1
@@ -230,7 +233,7 @@ def test_wide_slab_flag_and_autotuner_arguments():
     ow = binding.c_opts(2, 3, 3, 5, -1.0, binding.DPAR2_FLAG_WIDE_SLAB, 0, 0)
     one = lib.dpar2_workspace_size(ctypes.byref(t), ctypes.byref(o))
     wide = lib.dpar2_workspace_size(ctypes.byref(t), ctypes.byref(ow))
-    assert wide >= one + 900 * 16 * 4
+    assert wide >= one + (3 * 16 * 64 + 16 * 4) * ((900 + 63) // 64 + 2)
     T = binding.c_tensor * 2
     O = binding.c_opts * 2
     al = lambda n: (n + 255) // 256 * 256

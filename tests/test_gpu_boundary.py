@@ -215,3 +215,4 @@ def test_released_and_reused_workspace():
             torch.cuda.synchronize()
             d.release(ws)
     d.release(ws)
+

@@ -1,0 +1,98 @@
+"""GPU parity (through the C ABI) on the configurations the other parity tests
+leave out, with bounds derived from a CPU emulation of the slab pass's
+rounding (tests/golden/derive_parity_bounds.py writes
+tests/golden/parity_bounds.json: the largest deviation of the emulated
+arithmetic from the FP64 oracle times a safety factor of 4, per check and
+case), and per-row checks next to the Frobenius ones:
+
+  * M (J x KR) and V (J x R) row by row: max_j ||row_gpu - row_ref|| /
+    ||row_ref||, so that the small-scale feature rows of the stock-shaped
+    tensor (feature scales over five decades) cannot hide behind the large
+    ones;
+  * a 64-row tile with one row 1e4 times larger than the rest of each of its
+    columns (the 22-bit fixed point of that tile keeps few bits for the other
+    rows);
+  * rank 20 with L = 30 on a J = 128 tensor (the batching form's largest rank
+    and widest J bucket; k_als_A<20>, k_slice_fin<30>, the second stage at
+    L2 = 30);
+  * float32 slabs with 128 < J <= 256 (the FP64 matrix-core Gram and
+    projection), with 4-element and scalar loads;
+  * the rank instantiations R = 12 (L = 22) and R = 28 (L = 32, four
+    oversampled columns only)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import dpar2_oracle as O
+from tests._helpers import canonical, match_columns, model_tensor, rel
+from tests.golden.derive_parity_bounds import CASES
+from tests.test_gpu_parity import _check_compression, _check_errors, _check_factors, _run_gpu
+
+pytestmark = pytest.mark.gpu
+
+BOUNDS = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                     "parity_bounds.json")))["bounds"]
+
+
+def row_rel(a, b):
+    nb = np.linalg.norm(b, axis=1)
+    return float(np.max(np.linalg.norm(a - b, axis=1) / np.where(nb > 0, nb, 1.0)))
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_bounded_case(case):
+    make, R, L, iters = CASES[case]
+    X = make()
+    b = BOUNDS[case]
+    om1, om2 = synth.omegas(X.J, L, X.K * R)
+    H0, V0, W0 = synth.init_factors(X.J, X.K, R)
+    ref = O.dpar2(X.slab, X.offsets, R, om1, om2, H0, V0, W0, iters)
+    g = _run_gpu(X, R, L, L, iters, om1, om2, H0, V0, W0, want_U=True)
+    c = ref.comp
+    # compression (first and second stage)
+    np.testing.assert_allclose(g["comp"]["xnorm2"], c.xnorm2, rtol=1e-12)
+    assert np.max(np.abs(g["comp"]["sigma"] - c.Bdiag) / c.Bdiag) < b["sigma"]
+    Mg = g["comp"]["Mt"].T
+    assert rel(Mg, c.M) < b["M"], rel(Mg, c.M)
+    assert row_rel(Mg, c.M) < b["M_rows"], row_rel(Mg, c.M)
+    assert np.max(np.abs(g["comp"]["E"] - c.E) / c.E) < b["E"]
+    s = match_columns(g["comp"]["D"], c.D)
+    assert rel(g["comp"]["D"] * s, c.D) < b["D"]
+    assert rel(g["comp"]["F"] * s, c.F) < b["F"]
+    # factors, U_k, fitness
+    st = ref.state
+    Hg, Vg, Wg = canonical(g["H"], g["V"], g["W"])
+    Hr, Vr, Wr = canonical(st.H, st.V, st.W)
+    assert rel(Vg, Vr) < b["V"], rel(Vg, Vr)
+    assert row_rel(Vg, Vr) < b["V_rows"], row_rel(Vg, Vr)
+    assert rel(Wg, Wr) < b["W"], rel(Wg, Wr)
+    assert rel(model_tensor(g["H"], g["V"], g["W"]), model_tensor(st.H, st.V, st.W)) < b["model"]
+    assert rel(g["U"], np.concatenate(ref.U, axis=0)) < b["U"]
+    assert abs(g["rep"]["fit_true"] - ref.fit) < b["fit"]
+    print(f"[coverage] {case}: M rows {row_rel(Mg, c.M):.2e} (bound {b['M_rows']:.1e}), "
+          f"V rows {row_rel(Vg, Vr):.2e} (bound {b['V_rows']:.1e}), |dfit| {abs(g['rep']['fit_true'] - ref.fit):.1e}",
+          flush=True)
+
+
+@pytest.mark.parametrize("J", [200, 150])
+def test_fp64_matrix_core_pass_matches_oracle(J):
+    """float32 slab, 128 < J <= 256: the Gram and projection on the FP64
+    matrix cores from the float32 sketch; J = 200 with 4-element loads,
+    J = 150 with scalar loads; compression within the 1e-6 bound of the
+    narrow path, factors within 1e-5, U_k, fitness within 1e-7."""
+    rows = synth.uniform_rows(14, 40, 400, J)
+    X = synth.parafac2(rows, J, 6, J, noise_abs=0.02)
+    R, L, iters = 6, 16, 30
+    om1, om2 = synth.omegas(X.J, L, X.K * R)
+    H0, V0, W0 = synth.init_factors(X.J, X.K, R)
+    ref = O.dpar2(X.slab, X.offsets, R, om1, om2, H0, V0, W0, iters)
+    g = _run_gpu(X, R, L, L, iters, om1, om2, H0, V0, W0, want_U=True)
+    _check_compression(X, R, g, ref)
+    _check_errors(g, ref)
+    _check_factors(g, ref)
+    assert row_rel(g["comp"]["Mt"].T, ref.comp.M) < 1e-6
+    assert abs(g["rep"]["fit_true"] - ref.fit) < 1e-7
+    assert rel(g["U"], np.concatenate(ref.U, axis=0)) < 1e-5

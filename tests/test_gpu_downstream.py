@@ -1,0 +1,153 @@
+"""Post-processing of the factors (Sec. IV-E) on the GPU, through the C ABI,
+against the FP64 oracle (oracle/downstream_oracle.py): feature correlations
+from V, the slice similarity of Eq. 9, the top-k ranking (indices bit for
+bit, inputs free of near-ties), and the random walk with restart; then the
+whole discovery pipeline on a decomposition computed on the GPU (the oracle
+runs on the GPU's U_k and V, so both sides see the same input)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import downstream_oracle as D
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _pcc(V):
+    torch = _torch()
+    import paper_2203_12798_amd as d
+    Vd = torch.from_numpy(np.ascontiguousarray(V)).cuda()
+    C = torch.zeros((V.shape[0], V.shape[0]), dtype=torch.float64, device="cuda")
+    d.feature_pcc(Vd, C)
+    return C.cpu().numpy()
+
+
+def test_feature_pcc_matches_oracle():
+    """J = 70 rows of R = 10 (a constant row, an affine copy and a negated
+    copy of row 0 among them), and J = 33 rows of R = 1 (every row constant:
+    all zeros); FP64 on both sides: 1e-13."""
+    rng = np.random.default_rng(3)
+    V = rng.standard_normal((70, 10))
+    V[5] = 2.0
+    V[6] = 3.0 * V[0] - 1.0
+    V[7] = -0.5 * V[0]
+    print("[gpu] feature pcc", flush=True)
+    C = _pcc(V)
+    ref = D.feature_pcc(V)
+    np.testing.assert_allclose(C, ref, rtol=1e-13, atol=1e-14)
+    assert abs(C[0, 6] - 1.0) < 1e-14 and abs(C[0, 7] + 1.0) < 1e-14
+    assert np.all(C[5] == 0.0) and np.all(C[:, 5] == 0.0)
+    assert np.all(_pcc(rng.standard_normal((33, 1))) == 0.0)
+
+
+def _tensor_U(K, I, R, seed):
+    """K slices of I rows each (plus two slices of other lengths) and a random
+    U (N x R)."""
+    torch = _torch()
+    import paper_2203_12798_amd as d
+    rows = np.full(K, I, dtype=np.int64)
+    rows = np.concatenate([[I + 3], rows, [I - 2]])
+    off = np.concatenate([[0], np.cumsum(rows)]).astype(np.int64)
+    N = int(off[-1])
+    slab = np.zeros((N, 4), dtype=np.float32)
+    T = d.Tensor.from_numpy(slab, off)
+    U = np.random.default_rng(seed).standard_normal((N, R)) * 0.3
+    return d, T, off, U, torch.from_numpy(U).cuda()
+
+
+def test_similarity_topk_rwr_match_oracle():
+    """40 slices of 50 rows, R = 6, gamma = 0.01: Eq. 9 within 1e-12, the
+    ten nearest neighbours of slice 7 and the RWR scores (c = 0.15, 100 steps)
+    within 1e-12 with the same top ten; a list that mixes lengths is rejected
+    with DPAR2_ESHAPE."""
+    torch = _torch()
+    d, T, off, U, Ud = _tensor_U(40, 50, 6, 11)
+    idx = list(range(1, 41))
+    Ulist = [U[off[k]:off[k + 1]] for k in range(len(off) - 1)]
+    print("[gpu] similarity / top-k / rwr", flush=True)
+    S = torch.zeros((40, 40), dtype=torch.float64, device="cuda")
+    d.slice_similarity(T, Ud, idx, 0.01, S)
+    Sg = S.cpu().numpy()
+    Sr = D.similarity(Ulist, idx, 0.01)
+    np.testing.assert_allclose(Sg, Sr, rtol=1e-12)
+    # k nearest neighbours of the 8th listed slice
+    out = torch.zeros(10, dtype=torch.int32, device="cuda")
+    d.top_k(S[7].contiguous(), 7, 10, out)
+    knn = out.cpu().numpy().tolist()
+    ref = D.top_k(Sr[7], 7, 10)
+    vals = np.sort(Sr[7][np.arange(40) != 7])[::-1]
+    assert np.min(np.diff(-vals[:11])) > 1e-9   # no near-ties: the ranking is unique
+    assert knn == ref
+    # random walk with restart from the same target
+    r = torch.zeros(40, dtype=torch.float64, device="cuda")
+    work = torch.zeros(120, dtype=torch.float64, device="cuda")
+    d.rwr(S, 7, r, work, c=0.15, iters=100)
+    rg = r.cpu().numpy()
+    rr = D.rwr(Sr, 7, 0.15, 100)
+    np.testing.assert_allclose(rg, rr, rtol=1e-12, atol=1e-15)
+    d.top_k(r, 7, 10, out)
+    assert out.cpu().numpy().tolist() == D.top_k(rr, 7, 10)
+    # odd step counts end in the caller's buffer as well
+    d.rwr(S, 3, r, work, c=0.15, iters=7)
+    np.testing.assert_allclose(r.cpu().numpy(), D.rwr(Sr, 3, 0.15, 7), rtol=1e-12, atol=1e-15)
+    # slices of different lengths cannot be compared (Eq. 9)
+    with pytest.raises(d.Dpar2Error) as ei:
+        d.slice_similarity(T, Ud, [0, 1, 2], 0.01, S)
+    assert ei.value.status == -2
+
+
+def test_topk_ties_and_nan():
+    """Ties go to the lower index, NaN ranks last, the excluded entry never
+    appears."""
+    torch = _torch()
+    import paper_2203_12798_amd as d
+    v = torch.tensor([0.5, float("nan"), 0.9, 0.9, 0.1, 0.9, 0.7], dtype=torch.float64, device="cuda")
+    out = torch.zeros(6, dtype=torch.int32, device="cuda")
+    d.top_k(v, 3, 6, out)
+    assert out.cpu().numpy().tolist() == [2, 5, 6, 0, 4, 1]
+    big = torch.from_numpy(np.random.default_rng(5).permutation(100000).astype(np.float64)).cuda()
+    o2 = torch.zeros(20, dtype=torch.int32, device="cuda")
+    d.top_k(big, -1, 20, o2)
+    b = big.cpu().numpy()
+    assert o2.cpu().numpy().tolist() == np.argsort(-b)[:20].tolist()
+
+
+def test_discovery_pipeline_on_a_gpu_decomposition():
+    """Decompose 30 equal-length slices (plus one shorter) on the GPU, take
+    U_k and V, and run the feature correlations, Eq. 9, k-NN and RWR on the
+    GPU and in the oracle on the same factors."""
+    torch = _torch()
+    import paper_2203_12798_amd as d
+    rows = np.concatenate([np.full(30, 120), [80]]).astype(np.int64)
+    X = synth.parafac2(rows, 24, 4, 77, noise_abs=0.02)
+    R, L = 4, 10
+    T = d.Tensor.from_numpy(X.slab, X.offsets)
+    o = d.Options(rank=R, sketch=L, sketch2=L, max_iter=30)
+    om1, om2 = synth.omegas(X.J, L, X.K * R)
+    f = d.Factors.from_numpy(*synth.init_factors(X.J, X.K, R))
+    ws = d.alloc_workspace(T, o)
+    Ud = torch.zeros((X.N, R), dtype=torch.float64, device="cuda")
+    print("[gpu] discovery pipeline", flush=True)
+    d.decompose(T, o, torch.from_numpy(om1).cuda(), torch.from_numpy(om2).cuda(), f, ws, U=Ud)
+    U = Ud.cpu().numpy()
+    V = f.V.cpu().numpy()
+    C = torch.zeros((X.J, X.J), dtype=torch.float64, device="cuda")
+    d.feature_pcc(f.V, C)
+    np.testing.assert_allclose(C.cpu().numpy(), D.feature_pcc(V), rtol=1e-12, atol=1e-14)
+    idx = list(range(30))
+    S = torch.zeros((30, 30), dtype=torch.float64, device="cuda")
+    d.slice_similarity(T, Ud, idx, 0.01, S)
+    Ulist = [U[X.offsets[k]:X.offsets[k + 1]] for k in range(X.K)]
+    Sr = D.similarity(Ulist, idx, 0.01)
+    np.testing.assert_allclose(S.cpu().numpy(), Sr, rtol=1e-12)
+    r = torch.zeros(30, dtype=torch.float64, device="cuda")
+    work = torch.zeros(90, dtype=torch.float64, device="cuda")
+    d.rwr(S, 0, r, work)
+    np.testing.assert_allclose(r.cpu().numpy(), D.rwr(Sr, 0), rtol=1e-12, atol=1e-15)

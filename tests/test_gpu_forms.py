@@ -74,19 +74,25 @@ def test_low_precision_slab_matches_oracle_on_decoded(kind):
     assert abs(g["rep"]["fit_true"] - ref32.fit) < 1e-3
 
 
-def test_low_precision_with_power_step():
-    """bf16 slab with q = 1: the power-step sketch matrices are rounded to bf16
-    on the GPU (the oracle's are exact), so this compares at the accuracy of
-    the form: |delta fitness| <= 1e-4 and the same singular values to 1e-3."""
-    X, R, L = _case(seed=44)
+@pytest.mark.parametrize("kind", ["bf16", "fp8"])
+def test_low_precision_with_power_step(kind):
+    """bf16 / fp8 slab with q = 1: the first pass sketches with Omega_1 rounded
+    to bf16 (as the oracle does), the power step's per-slice sketch matrices
+    are split into three bf16 pieces (float32-level products, like a float32
+    slab's), so the same bounds as the float32 power step apply against the
+    oracle on the decoded slab."""
+    X, R, L = _case(seed=44 if kind == "bf16" else 45)
     iters = 40
     om1, om2 = synth.omegas(X.J, L, X.K * R)
     om1 = synth.round_bf16(om1)
     H0, V0, W0 = synth.init_factors(X.J, X.K, R)
-    T, dec = _lp_tensor(X, "bf16")
+    T, dec = _lp_tensor(X, kind)
     Xd = synth.IrregularTensor(slab=dec, offsets=X.offsets, H=X.H, V=X.V, W=X.W)
     ref = O.dpar2(dec, X.offsets, R, om1, om2, H0, V0, W0, iters, q=1)
-    g = _run_gpu(Xd, R, L, L, iters, om1, om2, H0, V0, W0, T=T, power_iters=1)
-    np.testing.assert_allclose(g["comp"]["sigma"], ref.comp.Bdiag, rtol=1e-3)
-    print(f"[forms] bf16 q=1: fitness {g['rep']['fit_true']:.8f} vs oracle {ref.fit:.8f}", flush=True)
-    assert abs(g["rep"]["fit_true"] - ref.fit) < 1e-4
+    g = _run_gpu(Xd, R, L, L, iters, om1, om2, H0, V0, W0, want_U=True, T=T, power_iters=1)
+    _check_compression(Xd, R, g, ref)
+    _check_errors(g, ref)
+    _check_factors(g, ref)
+    print(f"[forms] {kind} q=1: fitness {g['rep']['fit_true']:.8f} vs oracle {ref.fit:.8f}", flush=True)
+    assert abs(g["rep"]["fit_true"] - ref.fit) < 1e-7
+    assert rel(g["U"], np.concatenate(ref.U, axis=0)) < 1e-5

@@ -47,23 +47,26 @@ def test_wide_float32_matches_oracle(J, R, L, q):
     assert g["rep"]["warn_bits"] == 0
 
 
-@pytest.mark.parametrize("kind,J", [("bf16", 200), ("fp8", 2049)])
-def test_wide_low_precision_matches_oracle_on_decoded(kind, J):
+@pytest.mark.parametrize("kind,J,q", [("bf16", 200, 0), ("fp8", 2049, 0), ("fp8", 2049, 1), ("bf16", 2049, 1)])
+def test_wide_low_precision_matches_oracle_on_decoded(kind, J, q):
     """bf16 slab with J = 200 and fp8 with J = 2049 (above the narrow limit
-    of 128): parity with the oracle on the decoded slab and the bf16-rounded
+    of 128), and both at J = 2049 with one power step (the precision form's
+    accuracy recovery; the power step's sketch matrices on the FP32 matrix
+    cores): parity with the oracle on the decoded slab and the bf16-rounded
     Omega_1."""
     R, L = 5, 12
-    X = _case(8, J, R, 40, 200, seed=J + 7)
+    X = _case(8, J, R, 40, 200, seed=J + 7 + q)
     iters = 30
     om1, om2 = synth.omegas(X.J, L, X.K * R)
     om1 = synth.round_bf16(om1)
     H0, V0, W0 = synth.init_factors(X.J, X.K, R)
     T, dec = _lp_tensor(X, kind)
     Xd = synth.IrregularTensor(slab=dec, offsets=X.offsets, H=X.H, V=X.V, W=X.W)
-    ref = O.dpar2(dec, X.offsets, R, om1, om2, H0, V0, W0, iters)
-    g = _run_gpu(Xd, R, L, L, iters, om1, om2, H0, V0, W0, want_U=True, T=T)
+    ref = O.dpar2(dec, X.offsets, R, om1, om2, H0, V0, W0, iters, q=q)
+    g = _run_gpu(Xd, R, L, L, iters, om1, om2, H0, V0, W0, want_U=True, T=T, power_iters=q)
     _check_compression(Xd, R, g, ref)
-    _check_errors(g, ref)
+    if q == 0:
+        _check_errors(g, ref)   # (with a power step: see test_wide_float32_matches_oracle)
     _check_factors(g, ref)
     assert abs(g["rep"]["fit_true"] - ref.fit) < 1e-7
     assert rel(g["U"], np.concatenate(ref.U, axis=0)) < 1e-5
