@@ -11,6 +11,7 @@ paper's order and notation so that it can be read against the paper:
   randomized_svd     Alg. 1 (randomized SVD, after Halko et al.), Sec. II-B
   compress           Sec. III-B: first stage (Eq. 4, per-slice randomized SVD),
                      M = ||_k C_k B_k, second stage (Eq. 5), F^(k) (Eqs. 6-7)
+                     (first_stage and second_stage separately)
   als_compressed     Alg. 3 iteration: Eq. 8 (SVD of F^(k) E D^T V S_k H^T),
                      implicit Y_k (Sec. III-D), Lemmas 1-3 (G^(1), G^(2),
                      G^(3)), pseudoinverse updates, S_k = diag(W(k,:)),
@@ -141,15 +142,13 @@ def partition(rows, T: int):
     return sets, S
 
 
-def compress(slab: np.ndarray, offsets: np.ndarray, R: int, omega1: np.ndarray,
-             omega2: np.ndarray, q: int = 0, threads: int = 1) -> Compressed:
-    """Sec. III-B.  First stage: randomized SVD of every slice at rank R,
+def first_stage(slab: np.ndarray, offsets: np.ndarray, R: int, omega1: np.ndarray, q: int = 0,
+                threads: int = 1):
+    """Sec. III-B, first stage: randomized SVD of every slice at rank R,
     X_k ~ A_k B_k C_k^T (Eq. 4), slices spread over `threads` workers by
-    Alg. 4.  Then M = ||_k C_k B_k (J x KR) and the second-stage randomized
-    SVD M ~ D E F^T (Eq. 5)."""
+    Alg. 4.  Returns (A, Bdiag, C, xnorm2)."""
     offsets = np.asarray(offsets, dtype=np.int64)
     K = offsets.shape[0] - 1
-    J = slab.shape[1]
     A = [None] * K
     C = [None] * K
     Bd = np.zeros((K, R))
@@ -171,12 +170,25 @@ def compress(slab: np.ndarray, offsets: np.ndarray, R: int, omega1: np.ndarray,
                 one(k)
         with _cf.ThreadPoolExecutor(max_workers=threads) as ex:
             list(ex.map(run, sets))
+    return A, Bd, C, xn
 
+
+def second_stage(A, Bd, C, xn, omega2: np.ndarray) -> Compressed:
+    """Sec. III-B, second stage: M = ||_k C_k B_k (J x KR) and its randomized
+    SVD M ~ D E F^T (Eq. 5); F^(k) = rows kR..kR+R-1 of F (Eqs. 6-7)."""
+    K, R = Bd.shape
+    J = C[0].shape[0]
     M = np.zeros((J, K * R))
     for k in range(K):
         M[:, k * R:(k + 1) * R] = C[k] * Bd[k][None, :]
     D, E, F = randomized_svd(M, R, omega2, 0)
-    return Compressed(A=A, Bdiag=Bd, C=C, M=M, D=D, E=E, F=F, xnorm2=xn)
+    return Compressed(A=list(A), Bdiag=Bd, C=list(C), M=M, D=D, E=E, F=F, xnorm2=xn)
+
+
+def compress(slab: np.ndarray, offsets: np.ndarray, R: int, omega1: np.ndarray,
+             omega2: np.ndarray, q: int = 0, threads: int = 1) -> Compressed:
+    """Sec. III-B: the first stage over all slices, then the second stage."""
+    return second_stage(*first_stage(slab, offsets, R, omega1, q, threads), omega2)
 
 
 # ---------------------------------------------------------------------------
