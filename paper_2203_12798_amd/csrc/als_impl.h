@@ -285,6 +285,77 @@ __device__ inline void block_partial_out(const double (&acc)[R], double* sred, d
   }
 }
 
+// Q-step of a wave with a (nearly) rank-deficient T_k (see k_als_A): t, v on
+// entry hold column j of T_k P_prev and of P_prev.  On return t = z_j (unit
+// columns, orthonormal within each slice's group) and v = p_j (orthonormal),
+// T_k = Z Sigma P^T with the singular values below 1e-12 sigma_1 taken as 0
+// and their z_j completed by Gram-Schmidt: each such column in turn (lowest
+// index first) takes the unit vector e_i whose projection onto the columns
+// kept so far is smallest (lowest i on ties) minus that projection,
+// normalised.  Every lane of the wave calls it (shuffles only, no barrier).
+template <int R>
+__device__ inline void q_step_complete(const double* T_, bool live, int j, int gbase, double (&t)[R],
+                                       double (&v)[R], unsigned& warn) {
+  constexpr int RM = RC<R>::RM;
+#pragma unroll
+  for (int q = 0; q < R; ++q) t[q] = 0.0;
+  if (live)
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+      for (int q = 0; q < R; ++q) t[q] = fma(T_[q * R + i], v[i], t[q]);
+  if (group_jacobi<R, true>(t, v, j, gbase) == JACOBI_SWEEPS) warn |= 0x1u;
+  double sig = 0.0;
+#pragma unroll
+  for (int i = 0; i < R; ++i) sig = fma(t[i], t[i], sig);
+  sig = sqrt(sig);
+  double smax = sig;
+  for (int o = 1; o < RM; o <<= 1) smax = fmax(smax, __shfl_xor(smax, o, 64));
+  bool keep = live && sig > 1e-12 * smax;
+  if (live && !keep) warn |= 0x2u;
+  const double inv = keep ? 1.0 / sig : 0.0;
+#pragma unroll
+  for (int i = 0; i < R; ++i) t[i] *= inv;   // kept columns unit, the others zero
+  // complete the zero columns one by one (the same steps on every group of
+  // the wave; a group without such a column changes nothing)
+  for (int d = 0; d < R; ++d) {
+    const bool isdef = __shfl((int)(live && !keep), gbase + d, 64) != 0;
+    // squared norms of the rows of the current Z (sum over the group's lanes)
+    double rn[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      double x = (j < R) ? t[i] * t[i] : 0.0;
+      for (int o = 1; o < RM; o <<= 1) x += __shfl_xor(x, o, 64);
+      rn[i] = x;
+    }
+    int is = 0;
+#pragma unroll
+    for (int i = 1; i < R; ++i)
+      if (rn[i] < rn[is]) is = i;
+    // w = e_is - Z Z^T e_is (the group's columns), then normalised
+    double zi = 0.0;
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+      if (i == is) zi = t[i];
+    double w[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      double x = (j < R) ? zi * t[i] : 0.0;
+      for (int o = 1; o < RM; o <<= 1) x += __shfl_xor(x, o, 64);
+      w[i] = ((i == is) ? 1.0 : 0.0) - x;
+    }
+    double wn = 0.0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) wn = fma(w[i], w[i], wn);
+    const double wi = (wn > 0.0) ? 1.0 / sqrt(wn) : 0.0;
+    if (isdef && j == d) {
+#pragma unroll
+      for (int i = 0; i < R; ++i) t[i] = w[i] * wi;
+      keep = true;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // A: Q-step (Eq. 8), implicit Y_k, Lemma 1 partial
 // ---------------------------------------------------------------------------
@@ -392,9 +463,15 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_A(AlsArgs a) {
     sig = sqrt(sig);
     double smax = sig;
     for (int o = 1; o < RM; o <<= 1) smax = fmax(smax, __shfl_xor(smax, o, 64));
-    if (live && !(sig > 1e-14 * smax)) warn |= 0x2u;
-    const double inv = (sig > 0.0) ? 1.0 / sig : 0.0;
-    if (live) {
+    if (__any(live && !(sig > 1e-12 * smax))) {
+      // rare: some T_k of this wave is (nearly) rank deficient, so the polar
+      // factor is not unique and z_j = t_j / sigma_j is undefined for a
+      // vanishing sigma_j.  Redo the Jacobi accumulating the rotation
+      // (P = P_prev V' stays orthogonal) and complete Z to an orthonormal
+      // basis (q_step_complete), so that Psi_k = Z_k P_k^T is orthogonal.
+      q_step_complete<R>(T_, live, j, gbase, t, v, warn);
+    } else if (live) {
+      const double inv = 1.0 / sig;
 #pragma unroll
       for (int i = 0; i < R; ++i) t[i] *= inv;
 #pragma unroll
@@ -405,6 +482,8 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_A(AlsArgs a) {
         for (int i = 0; i < R; ++i) v[i] = fma(T_[q * R + i], t[q], v[i]);
 #pragma unroll
       for (int i = 0; i < R; ++i) v[i] *= inv;
+    }
+    if (live) {
 #pragma unroll
       for (int i = 0; i < R; ++i) {
         Z_[i * R + j] = t[i];

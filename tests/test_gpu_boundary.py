@@ -216,3 +216,32 @@ def test_released_and_reused_workspace():
             d.release(ws)
     d.release(ws)
 
+
+def test_rank_deficient_q_step_keeps_psi_orthogonal():
+    """A starting W with a zero column makes every T_k of the first Q-step
+    (Eq. 8) singular: the polar factor is then not unique, and the Q-step
+    completes Z_k so that Psi_k = Z_k P_k^T stays orthogonal.  Checked through
+    U_k = A_k Psi_k H: U_k^T U_k = H^T H for every slice (A_k has orthonormal
+    columns), with the rank-deficiency warning raised and finite factors."""
+    torch = _torch()
+    X = synth.small_parity(seed=2, K=40)
+    R, L = 5, 15
+    d, T, o, o1, o2, (H0, V0, W0) = _setup(X, R, L, 1)
+    W0 = W0.copy()
+    W0[:, 2] = 0.0
+    print("[gpu] rank-deficient Q-step", flush=True)
+    f = d.Factors.from_numpy(H0, V0, W0)
+    ws = d.alloc_workspace(T, o)
+    d.compress(T, o, o1, o2, ws)
+    d.als_step(T, o, f, 1, ws)
+    U = torch.zeros((X.N, R), dtype=torch.float64, device="cuda")
+    d.output_U(T, o, f, U, ws)
+    rep = d.report_read(T, o, ws)
+    assert rep["warn_bits"] & 0x2
+    H, V, W = f.numpy()
+    assert np.all(np.isfinite(H)) and np.all(np.isfinite(V)) and np.all(np.isfinite(W))
+    Ug = U.cpu().numpy()
+    HtH = H.T @ H
+    for k in range(X.K):
+        u = Ug[X.offsets[k]:X.offsets[k + 1]]
+        assert np.abs(u.T @ u - HtH).max() < 1e-5 * np.abs(HtH).max(), k
