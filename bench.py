@@ -51,12 +51,18 @@ def parse():
     ap.add_argument("--no-wide", action="store_true",
                     help="skip the precision form at J = 2049 (K = 8000, spectrogram-like, R = 10 and 20)")
     ap.add_argument("--wide-k", type=int, default=8000)
+    ap.add_argument("--wide-only", action="store_true",
+                    help="run only the J = 2049 form (one JSON line with its figures; for profiling)")
+    ap.add_argument("--wide-ranks", default="10,20", help="ranks of the J = 2049 form")
+    ap.add_argument("--wide-q", default="0,1", help="power steps of the J = 2049 form")
     ap.add_argument("--no-warm", action="store_true",
                     help="skip the learned warm-start form (train the set encoder, compare on held-out tensors)")
     ap.add_argument("--warm-train", type=int, default=400, help="training tensors of the warm-start form")
     ap.add_argument("--warm-test", type=int, default=32, help="held-out tensors of the warm-start form")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip PARAFAC2-ALS on the uncompressed slices (Alg. 2) on the same workload")
+    ap.add_argument("--no-stream", action="store_true",
+                    help="skip the streaming leg (the last 10%% of the slices appended to a decomposition of the rest)")
     ap.add_argument("--cpu-runs", type=int, default=3, help="timed runs of the CPU oracle (mean and median)")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic.json from two rocprofv3 --pmc counter_collection.csv "
@@ -385,7 +391,8 @@ def bench_wide(args, d, torch, np, binding):
                              T.offsets_dev, T.offsets_host, binding.DPAR2_FP8_E4M3, scale.contiguous())}
     g = torch.Generator(device="cuda").manual_seed(99)
     N = int(T.offsets_host[-1])
-    for R in (10, 20):
+    qs = [int(q) for q in args.wide_q.split(",")]
+    for R in [int(r) for r in args.wide_ranks.split(",")]:
         L = R + 10
         om1 = torch.randn(J, L, device="cuda", generator=g)
         om1b = om1.to(torch.bfloat16).to(torch.float32)
@@ -394,7 +401,7 @@ def bench_wide(args, d, torch, np, binding):
                 torch.randn(J, R, dtype=torch.float64, device="cuda", generator=g),
                 torch.ones(K, R, dtype=torch.float64, device="cuda"))
         out = {}
-        for name, Tk, q in [(n, t, q) for n, t in forms.items() for q in (0, 1)]:
+        for name, Tk, q in [(n, t, q) for n, t in forms.items() for q in qs]:
             o = d.Options(rank=R, sketch=L, sketch2=L, max_iter=32, power_iters=q)
             name = name if q == 0 else name + "_q1"
             ws = d.alloc_workspace(Tk, o)
@@ -428,7 +435,7 @@ def bench_wide(args, d, torch, np, binding):
                          "fitness": rep["fit_true"], "warn_bits": rep["warn_bits"]}
             print(f"[bench] wide R={R} {name}: {ms:.2f} ms", file=sys.stderr, flush=True)
             del ws
-        for name in ("bf16", "fp8", "f32_q1", "bf16_q1", "fp8_q1"):
+        for name in [n for n in ("bf16", "fp8", "f32_q1", "bf16_q1", "fp8_q1") if n in out and "f32" in out]:
             out[name]["speedup_vs_f32"] = round(out["f32"]["ms_per_step"] / out[name]["ms_per_step"], 3)
             out[name]["fitness_delta_vs_f32"] = out[name]["fitness"] - out["f32"]["fitness"]
         res[f"R{R}"] = out
@@ -438,6 +445,8 @@ def bench_wide(args, d, torch, np, binding):
                    "includes the encoding noise (see sample for the error against the float32 data)")
     # the first 128 slices in every form (R = 10, L = 20, 32 iterations):
     # factors and U for the oracle leg
+    if args.wide_only:
+        return res, None
     Ks = min(128, K)
     off_s = T.offsets_host[:Ks + 1].copy()
     ns = int(off_s[-1])
@@ -484,6 +493,10 @@ def main():
     from paper_2203_12798_amd import binding
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.wide_only:
+        res, _ = bench_wide(args, d, torch, np, binding)
+        print(json.dumps({"precision_wide": res}), flush=True)
+        return
     print("[bench] generating workload", file=sys.stderr, flush=True)
     t = time.perf_counter()
     X = synth.stock_like()
@@ -606,6 +619,52 @@ def main():
         except Exception as exc:   # reported, not fatal
             plain = {"error": str(exc)[:300]}
 
+    stream = None
+    if not args.no_stream:
+        # streaming: the first 90% of the slices decomposed, the last 10%
+        # appended (first stage of the new slices only, second stage over the
+        # whole M, the same 32 iterations from the earlier H and V and the
+        # mean of the earlier W rows), against the one-call decomposition
+        try:
+            kp = K - K // 10
+            Tp = d.Tensor(T.slab, T.offsets_dev, X.offsets[:kp + 1].copy())
+            wsp = d.alloc_workspace(Tp, o)
+            fpv = d.Factors.from_numpy(H0, V0, W0[:kp])
+            d.decompose(Tp, o, o1, o2[:kp * R].contiguous(), fpv, wsp)
+            Hp, Vp, Wp = fpv.numpy()
+            Ww = np.concatenate([Wp, np.repeat(Wp.mean(axis=0, keepdims=True), K - kp, axis=0)])
+            wsa = d.alloc_append_workspace(T, kp, o)
+            warm = [torch.from_numpy(a).cuda() for a in (Hp, Vp, Ww)]
+            fa = d.Factors(*(a.clone() for a in warm))
+
+            def stepa():
+                fa.H.copy_(warm[0])
+                fa.V.copy_(warm[1])
+                fa.W.copy_(warm[2])
+                d.append(T, kp, o, o1, o2, wsp, fa, wsa)
+
+            stepa()
+            torch.cuda.synchronize()
+            ta0 = time.perf_counter()
+            for _ in range(args.steps):
+                stepa()
+            torch.cuda.synchronize()
+            ms_app = (time.perf_counter() - ta0) * 1e3 / args.steps
+            ra = d.report_read(T, o, wsa)
+            new_bytes = int(X.offsets[-1] - X.offsets[kp]) * J * 4
+            stream = {"k_prev": kp, "k_appended": K - kp, "ms_per_append": round(ms_app, 3),
+                      "ms_full_decomposition": round(ms_f32, 3), "speedup_vs_full": round(ms_f32 / ms_app, 2),
+                      "slab_bytes_read": new_bytes, "fitness": ra["fit_true"],
+                      "fitness_minus_full": ra["fit_true"] - rep["fit_true"],
+                      "note": "first stage of the appended slices, second stage over all of M, 32 iterations "
+                              "warm-started from the earlier factors; slab rows of the earlier slices not read"}
+            print(f"[bench] append {K - kp} slices to {kp}: {ms_app:.2f} ms", file=sys.stderr, flush=True)
+            d.release(wsp)
+            d.release(wsa)
+            del wsp, wsa
+        except Exception as exc:   # reported, not fatal
+            stream = {"error": str(exc)[:300]}
+
     forms = None
     if not args.no_forms:
         # the same workload as bf16 bit patterns and as per-slice-scaled fp8
@@ -722,6 +781,8 @@ def main():
     out["timing"] = timing
     if plain is not None:
         out["plain_als"] = plain
+    if stream is not None:
+        out["stream"] = stream
     if forms is not None:
         out["forms"] = forms
     if not args.no_batch:

@@ -16,6 +16,8 @@
  *   - dpar2_output_U   : U_k = A_k Z_k P_k^T H (last lines of Alg. 3).
  *   - dpar2_output_A   : the first-stage factors A_k of Eq. 4.
  *   - dpar2_decompose  : all of the above, Alg. 3 end to end.
+ *   - dpar2_append     : the same after slices were appended to a decomposed
+ *                        tensor (first stage of the new slices only).
  *
  * Conventions (all calls):
  *   - Pointers are DEVICE pointers unless marked (host).  The caller owns every
@@ -233,6 +235,42 @@ dpar2_status dpar2_decompose(const dpar2_tensor* X, const dpar2_opts* o,
                              const float* omega1, const float* omega2,
                              dpar2_factors* f, double* U, dpar2_report* rep,
                              void* ws, size_t ws_bytes, dpar2_stream_t stream);
+
+/* DPar2 on a tensor that grows by appended slices (the streaming setting
+ * of Sec. VI).  The first stage of Sec. III-B factors each slice by itself
+ * (Eq. 4), so an append runs it on the new slices only; the second stage
+ * (Eq. 5) then runs again over the whole M = ||_k C_k B_k and Alg. 3 iterates
+ * from the factors in `f`, as in dpar2_decompose.
+ *   X       : the tensor after the append, K slices; slices 0..k_prev-1 are
+ *             the ones the earlier call decomposed (same row offsets), slices
+ *             k_prev..K-1 the new ones.  Only the new slices' rows are read
+ *             (and every row once more if U != NULL).
+ *   k_prev  : 1 <= k_prev < K.
+ *   o       : the options of the earlier call (rank, sketch widths,
+ *             power_iters, item_rows, flags and dtype must be the same).
+ *   omega1  : the J x L Omega_1 of the earlier call (the new slices are
+ *             sketched with it).
+ *   omega2  : (K R) x L2, for all K slices (rows kR..kR+R-1: slice k).
+ *   ws_prev : the workspace of the earlier dpar2_decompose or dpar2_append
+ *             on slices 0..k_prev-1 (read only; its per-slice first-stage
+ *             results are copied), ws_prev_bytes its size.
+ *   f       : starting factors of all K slices (W: K x R) in, result out.
+ *   U, rep  : as in dpar2_decompose; the warning bits of ws_prev's call
+ *             carry over.
+ *   ws      : workspace of dpar2_append_workspace_bytes(X, k_prev, o) bytes,
+ *             not overlapping ws_prev.  Its first dpar2_workspace_bytes(X, o)
+ *             bytes are then the workspace of a decomposition of all K
+ *             slices: a later append passes it as ws_prev.
+ * The result equals dpar2_decompose on the K slices from the same factors
+ * (the per-slice arithmetic is the same).  Errors as in dpar2_decompose;
+ * DPAR2_EINVAL also for k_prev out of range or overlapping workspaces,
+ * DPAR2_EWORKSPACE for a ws_prev smaller than the earlier layout. */
+size_t dpar2_append_workspace_bytes(const dpar2_tensor* X, int64_t k_prev, const dpar2_opts* o);
+dpar2_status dpar2_append(const dpar2_tensor* X, int64_t k_prev, const dpar2_opts* o,
+                          const float* omega1, const float* omega2,
+                          const void* ws_prev, size_t ws_prev_bytes,
+                          dpar2_factors* f, double* U, dpar2_report* rep,
+                          void* ws, size_t ws_bytes, dpar2_stream_t stream);
 
 /* For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): dpar2_decompose without a

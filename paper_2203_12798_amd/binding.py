@@ -72,7 +72,8 @@ class c_report(ctypes.Structure):
 
 
 EXPORTS = ["dpar2_workspace_bytes", "dpar2_workspace_size", "dpar2_compress", "dpar2_als_step", "dpar2_fitness",
-           "dpar2_output_U", "dpar2_output_A", "dpar2_decompose", "dpar2_decompose_noalloc", "dpar2_release",
+           "dpar2_output_U", "dpar2_output_A", "dpar2_decompose", "dpar2_decompose_noalloc", "dpar2_append_workspace_bytes",
+           "dpar2_append", "dpar2_release",
            "dpar2_release_all", "dpar2_plain_workspace_bytes", "dpar2_als_plain", "dpar2_feature_pcc",
            "dpar2_slice_similarity", "dpar2_top_k", "dpar2_rwr", "dpar2_compressed_view", "dpar2_report_read",
            "dpar2_batch_workspace_size", "dpar2_decompose_batch", "dpar2_batch_report_read",
@@ -113,6 +114,11 @@ def load(path: str = LIB_PATH):
                                     ctypes.c_size_t, vp]
     lib.dpar2_decompose_noalloc.restype = ctypes.c_int32
     lib.dpar2_decompose_noalloc.argtypes = [P(c_tensor), P(c_opts), vp, vp, P(c_factors), vp, P(c_report), vp]
+    lib.dpar2_append_workspace_bytes.restype = ctypes.c_size_t
+    lib.dpar2_append_workspace_bytes.argtypes = [P(c_tensor), ctypes.c_int64, P(c_opts)]
+    lib.dpar2_append.restype = ctypes.c_int32
+    lib.dpar2_append.argtypes = [P(c_tensor), ctypes.c_int64, P(c_opts), vp, vp, vp, ctypes.c_size_t,
+                                 P(c_factors), vp, P(c_report), vp, ctypes.c_size_t, vp]
     lib.dpar2_plain_workspace_bytes.restype = ctypes.c_size_t
     lib.dpar2_plain_workspace_bytes.argtypes = [P(c_tensor), P(c_opts)]
     lib.dpar2_als_plain.restype = ctypes.c_int32
@@ -378,6 +384,44 @@ def decompose_noalloc(X: Tensor, o: Options, omega1, omega2, f: Factors, U=None,
 
 
 NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def append_workspace_size(X: Tensor, k_prev: int, o: Options) -> int:
+    """Bytes of workspace of append(X, k_prev, o, ...); raises on invalid
+    arguments."""
+    n = load().dpar2_append_workspace_bytes(ctypes.byref(X.c()), int(k_prev), ctypes.byref(o.c()))
+    if n == 0:
+        raise Dpar2Error(DPAR2_EINVAL, last_error())
+    return int(n)
+
+
+def alloc_append_workspace(X: Tensor, k_prev: int, o: Options, device="cuda:0"):
+    import torch
+    return torch.empty(append_workspace_size(X, k_prev, o) + 256, dtype=torch.uint8, device=device)
+
+
+def append(X: Tensor, k_prev: int, o: Options, omega1, omega2, ws_prev, f: Factors, ws, U=None, stream=None,
+           report=False):
+    """DPar2 after appending slices k_prev.. of X to a tensor whose first
+    k_prev slices were decomposed with workspace ws_prev (dpar2_append); same
+    report convention as decompose().  ws (from alloc_append_workspace) then
+    serves as ws_prev of the next append."""
+    lib = load()
+    p, n = _ws(ws)
+    pp, npv = _ws(ws_prev)
+    fc = f.c()
+    r = c_report() if report else None
+    st = lib.dpar2_append(ctypes.byref(X.c()), int(k_prev), ctypes.byref(o.c()), _ptr(omega1), _ptr(omega2),
+                          pp, npv, ctypes.byref(fc), _ptr(U), ctypes.byref(r) if report else None, p, n,
+                          _stream(stream))
+    d = None
+    if report and st in (DPAR2_OK, DPAR2_ENOCONV, DPAR2_ENUMERIC):
+        d = _report_dict(r)
+        d["status"] = st
+    if st == DPAR2_ENOCONV and report:
+        return d
+    _check(st, d)
+    return d
 
 
 def plain_workspace_size(X: Tensor, o: Options) -> int:

@@ -532,8 +532,16 @@ dpar2_status upload_descriptors(char* w, const Layout& y, const std::vector<TDes
 
 // --- group steps -------------------------------------------------------------
 
+dpar2_status group_first_stage(const Group& g, char* w, const Layout& y, hipStream_t s);
+
+// Parts of a compress: the first stage (slab passes and per-slice
+// completion), the second stage (and the iteration state).  The tables,
+// descriptors and control blocks are set up in every case.
+enum : int { CP_FIRST = 1, CP_SECOND = 2, CP_ALL = 3 };
+
 dpar2_status group_compress(const Group& g, const float* const* om1, const float* const* om2,
-                            const dpar2_factors* f, char* w, const Layout& y, hipStream_t s) {
+                            const dpar2_factors* f, char* w, const Layout& y, hipStream_t s,
+                            int parts = CP_ALL) {
   for (int t = 0; t < g.nt; ++t)
     if (!om1[t] || !om2[t]) return fail(DPAR2_EINVAL, "omega1 and omega2 must be non-NULL");
   const std::vector<TDesc> td = descriptors(g, om1, om2, f, nullptr);
@@ -553,6 +561,23 @@ dpar2_status group_compress(const Group& g, const float* const* om1, const float
                      (int)(y.J * y.L), ctl, reinterpret_cast<float*>(w + y.om1));
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "compress set-up");
 
+  if (parts & CP_FIRST) {
+    const dpar2_status st = group_first_stage(g, w, y, s);
+    if (st != DPAR2_OK) return st;
+  }
+  if (!(parts & CP_SECOND)) return DPAR2_OK;
+  e = launch_stage2(y, w, s);
+  if (e != hipSuccess) return hip_fail(e, "second stage");
+  e = launch_pw_identity(y, w, s);
+  if (e != hipSuccess) return hip_fail(e, "iteration state init");
+  return DPAR2_OK;
+}
+
+// The first stage of every slice of g (Sec. III-B, Eq. 4): power_iters + 1
+// slab passes, each followed by the per-slice completion.
+dpar2_status group_first_stage(const Group& g, char* w, const Layout& y, hipStream_t s) {
+  hipError_t e;
+  Ctl* ctl = reinterpret_cast<Ctl*>(w + y.ctl);
   const Item* items = reinterpret_cast<const Item*>(w + y.items);
   double* partG = reinterpret_cast<double*>(w + y.partG);
   double* partP = reinterpret_cast<double*>(w + y.partP);
@@ -604,10 +629,6 @@ dpar2_status group_compress(const Group& g, const float* const* om1, const float
                             pass < y.q ? omq : nullptr, ctl, reinterpret_cast<const int32_t*>(w + y.slice_t), s);
     if (e != hipSuccess) return hip_fail(e, "slice finish");
   }
-  e = launch_stage2(y, w, s);
-  if (e != hipSuccess) return hip_fail(e, "second stage");
-  e = launch_pw_identity(y, w, s);
-  if (e != hipSuccess) return hip_fail(e, "iteration state init");
   return DPAR2_OK;
 }
 
@@ -990,6 +1011,25 @@ dpar2_status dpar2_output_A(const dpar2_tensor* X, const dpar2_opts* o, double* 
   return group_output_U(g, y, w, nullptr, A, s);
 }
 
+namespace {
+// Alg. 3 after the compression: the iteration, the true fitness, U_k (when U
+// is given) and the report (when rep is given; ENOCONV when a tolerance was
+// set and the stop rule never fired).
+dpar2_status decompose_tail(const Group& g, const dpar2_opts* o, const dpar2_factors* f, double* U,
+                            dpar2_report* rep, char* w, const Layout& y, hipStream_t s) {
+  dpar2_status st;
+  if ((st = group_als(g, o->max_iter, w, y, s)) != DPAR2_OK) return st;
+  hipError_t e = launch_fitness(y, w, nullptr, s);
+  if (e != hipSuccess) return hip_fail(e, "fitness");
+  if (U && (st = group_output_U(g, y, w, f->H, U, s)) != DPAR2_OK) return st;
+  if (!rep) return DPAR2_OK;
+  if ((st = group_report(g, w, y, rep, s)) != DPAR2_OK) return st;
+  if (o->tol >= 0.0 && !rep->converged)
+    return fail(DPAR2_ENOCONV, "the stop rule did not fire within " + std::to_string(o->max_iter) + " iterations");
+  return DPAR2_OK;
+}
+}  // namespace
+
 dpar2_status dpar2_decompose(const dpar2_tensor* X, const dpar2_opts* o, const float* omega1,
                              const float* omega2, dpar2_factors* f, double* U, dpar2_report* rep, void* ws,
                              size_t ws_bytes, dpar2_stream_t stream) {
@@ -1003,15 +1043,7 @@ dpar2_status dpar2_decompose(const dpar2_tensor* X, const dpar2_opts* o, const f
   char* w = static_cast<char*>(ws);
   // one upload: the descriptors carry Omega, the factors and (NULL) trace
   if ((st = group_compress(g, &omega1, &omega2, f, w, y, s)) != DPAR2_OK) return st;
-  if ((st = group_als(g, o->max_iter, w, y, s)) != DPAR2_OK) return st;
-  hipError_t e = launch_fitness(y, w, nullptr, s);
-  if (e != hipSuccess) return hip_fail(e, "fitness");
-  if (U && (st = group_output_U(g, y, w, f->H, U, s)) != DPAR2_OK) return st;
-  if (!rep) return DPAR2_OK;
-  if ((st = group_report(g, ws, y, rep, s)) != DPAR2_OK) return st;
-  if (o->tol >= 0.0 && !rep->converged)
-    return fail(DPAR2_ENOCONV, "the stop rule did not fire within " + std::to_string(o->max_iter) + " iterations");
-  return DPAR2_OK;
+  return decompose_tail(g, o, f, U, rep, w, y, s);
 }
 
 dpar2_status dpar2_decompose_noalloc(const dpar2_tensor* X, const dpar2_opts* o, const float* omega1,
@@ -1035,15 +1067,133 @@ dpar2_status dpar2_decompose_noalloc(const dpar2_tensor* X, const dpar2_opts* o,
   if ((st = scratch_address(&w)) != DPAR2_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if ((st = group_compress(g, &omega1, &omega2, f, w, y, s)) != DPAR2_OK) return st;
-  if ((st = group_als(g, o->max_iter, w, y, s)) != DPAR2_OK) return st;
-  hipError_t e = launch_fitness(y, w, nullptr, s);
-  if (e != hipSuccess) return hip_fail(e, "fitness");
-  if (U && (st = group_output_U(g, y, w, f->H, U, s)) != DPAR2_OK) return st;
-  if (!rep) return DPAR2_OK;
-  if ((st = group_report(g, w, y, rep, s)) != DPAR2_OK) return st;
-  if (o->tol >= 0.0 && !rep->converged)
-    return fail(DPAR2_ENOCONV, "the stop rule did not fire within " + std::to_string(o->max_iter) + " iterations");
+  return decompose_tail(g, o, f, U, rep, w, y, s);
+}
+
+// --- streaming: slices appended to a decomposed tensor ----------------------
+
+namespace {
+// The tensor of an append in three views: all K slices, its first k_prev
+// slices (decomposed by an earlier call), and the appended slices as a tensor
+// of their own (host row offsets rebased to 0, slab and fp8 scales advanced to
+// its first row and slice).
+struct AppendPlan {
+  std::vector<int64_t> off_add;
+  dpar2_tensor Xp, Xa;
+  dpar2_opts oa;
+  Group all, prev, add;
+  Layout y_all, y_prev, y_add;
+  size_t total = 0;   // y_all.total + y_add.total
+};
+
+dpar2_status append_plan(const dpar2_tensor* X, int64_t k_prev, const dpar2_opts* o, AppendPlan* p) {
+  dpar2_status st = make_group(1, X, o, &p->all);
+  if (st != DPAR2_OK) return st;
+  if (k_prev < 1 || k_prev >= X->K) return fail(DPAR2_EINVAL, "k_prev must be in [1, K - 1]");
+  const int64_t* off = X->row_offsets_host;
+  const int esize = X->dtype == DPAR2_F32 ? 4 : (X->dtype == DPAR2_BF16 ? 2 : 1);
+  p->Xp = *X;
+  p->Xp.K = k_prev;
+  p->off_add.assign(off + k_prev, off + X->K + 1);
+  for (int64_t& v : p->off_add) v -= off[k_prev];
+  p->Xa = *X;
+  p->Xa.K = X->K - k_prev;
+  p->Xa.row_offsets_host = p->off_add.data();
+  // the device offsets are not rebased: the first stage reads the host table
+  // only (row ranges of the work items)
+  p->Xa.row_offsets = X->row_offsets + k_prev;
+  p->Xa.slab = static_cast<const char*>(X->slab) + (size_t)off[k_prev] * (size_t)X->J * (size_t)esize;
+  p->Xa.slice_scale = X->slice_scale ? X->slice_scale + k_prev : nullptr;
+  if ((st = make_group(1, &p->Xp, o, &p->prev)) != DPAR2_OK) return st;
+  // the appended slices never run a second stage of their own: L2 <= K R
+  // need not hold for them alone
+  p->oa = *o;
+  p->oa.sketch2 = (int32_t)std::min<int64_t>(o->sketch2, p->Xa.K * o->rank);
+  if ((st = make_group(1, &p->Xa, &p->oa, &p->add)) != DPAR2_OK) return st;
+  p->y_all = make_layout(p->all);
+  p->y_prev = make_layout(p->prev);
+  p->y_add = make_layout(p->add);
+  p->total = p->y_all.total + p->y_add.total;
   return DPAR2_OK;
+}
+
+// Per-slice results of the first stage (||X_k||^2, the rows of M^T, the A_k
+// recipe Phi_k, the singular values, the power step's sketch matrices) of n
+// slices from src (layout ys, from its slice 0) to dst (layout yd, from slice
+// k_dst).
+hipError_t copy_first_stage(const char* src, const Layout& ys, char* dst, const Layout& yd, int64_t k_dst, int64_t n,
+                            hipStream_t s) {
+  const size_t J = (size_t)yd.J, R = (size_t)yd.R, L = (size_t)yd.L;
+  const size_t per[5] = {sizeof(double), sizeof(double) * R * J, sizeof(double) * L * R, sizeof(double) * R,
+                         yd.q > 0 ? sizeof(float) * J * L : 0};
+  const size_t from[5] = {ys.xnorm2, ys.Mt, ys.Phi, ys.sig1, ys.omq};
+  const size_t to[5] = {yd.xnorm2, yd.Mt, yd.Phi, yd.sig1, yd.omq};
+  for (int i = 0; i < 5; ++i) {
+    if (!per[i]) continue;
+    const hipError_t e = hipMemcpyAsync(dst + to[i] + (size_t)k_dst * per[i], src + from[i], (size_t)n * per[i],
+                                        hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Warning bits of the earlier decomposition and of the appended slices' first
+// stage into the grown tensor's control block.
+__global__ void k_merge_warn(Ctl* __restrict__ dst, const Ctl* __restrict__ a, const Ctl* __restrict__ b) {
+  if (threadIdx.x == 0) dst->warn |= a->warn | b->warn;
+}
+
+std::mutex g_sub_mu;
+std::unordered_map<const void*, const void*> g_sub;   // append workspace -> its second part
+}  // namespace
+
+size_t dpar2_append_workspace_bytes(const dpar2_tensor* X, int64_t k_prev, const dpar2_opts* o) {
+  AppendPlan p;
+  if (append_plan(X, k_prev, o, &p) != DPAR2_OK) return 0;
+  return p.total;
+}
+
+dpar2_status dpar2_append(const dpar2_tensor* X, int64_t k_prev, const dpar2_opts* o, const float* omega1,
+                          const float* omega2, const void* ws_prev, size_t ws_prev_bytes, dpar2_factors* f,
+                          double* U, dpar2_report* rep, void* ws, size_t ws_bytes, dpar2_stream_t stream) {
+  AppendPlan p;
+  dpar2_status st = append_plan(X, k_prev, o, &p);
+  if (st != DPAR2_OK) return st;
+  if (!f || !f->H || !f->V || !f->W) return fail(DPAR2_EINVAL, "factors must be non-NULL");
+  if (!omega1 || !omega2) return fail(DPAR2_EINVAL, "omega1 and omega2 must be non-NULL");
+  if ((st = check_ws(p.y_prev, ws_prev, ws_prev_bytes)) != DPAR2_OK) {
+    g_last_error = "ws_prev: " + g_last_error;
+    return st;
+  }
+  if (!ws) return fail(DPAR2_EWORKSPACE, "workspace is NULL");
+  if ((uintptr_t)ws % 256 != 0) return fail(DPAR2_EWORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < p.total)
+    return fail(DPAR2_EWORKSPACE, "workspace too small: need " + std::to_string(p.total) + " bytes");
+  const uintptr_t a0 = (uintptr_t)ws, a1 = a0 + p.total, b0 = (uintptr_t)ws_prev, b1 = b0 + p.y_prev.total;
+  if (a0 < b1 && b0 < a1) return fail(DPAR2_EINVAL, "ws and ws_prev overlap");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  char* wa = w + p.y_all.total;
+  {
+    std::lock_guard<std::mutex> lk(g_sub_mu);
+    g_sub[ws] = wa;
+  }
+  // first stage of the appended slices, in the second part of the workspace
+  if ((st = group_compress(p.add, &omega1, &omega2, nullptr, wa, p.y_add, s, CP_FIRST)) != DPAR2_OK) return st;
+  // tables, descriptors and control block of the grown tensor, then the
+  // per-slice results of both parts in slice order
+  if ((st = group_compress(p.all, &omega1, &omega2, f, w, p.y_all, s, 0)) != DPAR2_OK) return st;
+  hipError_t e = copy_first_stage(static_cast<const char*>(ws_prev), p.y_prev, w, p.y_all, 0, k_prev, s);
+  if (e == hipSuccess) e = copy_first_stage(wa, p.y_add, w, p.y_all, k_prev, X->K - k_prev, s);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  hipLaunchKernelGGL(k_merge_warn, dim3(1), dim3(64), 0, s, reinterpret_cast<Ctl*>(w + p.y_all.ctl),
+                     reinterpret_cast<const Ctl*>(static_cast<const char*>(ws_prev) + p.y_prev.ctl),
+                     reinterpret_cast<const Ctl*>(wa + p.y_add.ctl));
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "append set-up");
+  // second stage over the whole M, then Alg. 3 as in dpar2_decompose
+  if ((e = launch_stage2(p.y_all, w, s)) != hipSuccess) return hip_fail(e, "second stage");
+  if ((e = launch_pw_identity(p.y_all, w, s)) != hipSuccess) return hip_fail(e, "iteration state init");
+  return decompose_tail(p.all, o, f, U, rep, w, p.y_all, s);
 }
 
 dpar2_status dpar2_decompose_batch(int32_t n, const dpar2_tensor* X, const dpar2_opts* o,
@@ -1475,7 +1625,27 @@ dpar2_status dpar2_profile_read(int32_t* launches, double* total_ms) {
   return DPAR2_OK;
 }
 
+namespace {
+dpar2_status release_one(const void* ws);
+}
+
 dpar2_status dpar2_release(const void* ws) {
+  const void* sub = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_sub_mu);
+    auto it = g_sub.find(ws);
+    if (it != g_sub.end()) {
+      sub = it->second;
+      g_sub.erase(it);
+    }
+  }
+  const dpar2_status st = release_one(ws);
+  const dpar2_status st2 = sub ? release_one(sub) : DPAR2_OK;
+  return st != DPAR2_OK ? st : st2;
+}
+
+namespace {
+dpar2_status release_one(const void* ws) {
   hipError_t first = hipSuccess;
   {
     std::lock_guard<std::mutex> lk(g_stage_mu);
@@ -1505,6 +1675,7 @@ dpar2_status dpar2_release(const void* ws) {
   if (first != hipSuccess) return hip_fail(first, "dpar2_release");
   return DPAR2_OK;
 }
+}  // namespace
 
 dpar2_status dpar2_release_all(void) {
   std::vector<const void*> keys;

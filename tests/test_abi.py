@@ -279,3 +279,38 @@ def test_workspace_bytes_and_new_entry_points_validate_on_host():
     assert lib.dpar2_output_A(ctypes.byref(t), ctypes.byref(o), 0x8000, 0x10000, n - 1, None) == -6
     assert lib.dpar2_release(ctypes.c_void_p(0x123400)) == 0
     assert lib.dpar2_release(None) == 0
+
+
+def test_append_validates_on_host():
+    """dpar2_append_workspace_bytes: the grown tensor's layout plus the
+    appended slices' own (larger than a plain workspace, zero for a bad
+    k_prev); dpar2_append rejects k_prev out of range, NULL factors or
+    omegas, a ws_prev or ws that is too small, and overlapping workspaces,
+    all before touching the device.  An append of one slice with R = 2 and
+    L2 = 3 > 1 * R is accepted (the new slices run no second stage of their
+    own)."""
+    binding, lib = _lib()
+    t, _keep = _tensor(binding, [0, 10, 25, 40, 52])
+    o = binding.c_opts(2, 3, 3, 5, -1.0, 0)
+    tp, _kp = _tensor(binding, [0, 10, 25, 40])
+    n_all = lib.dpar2_workspace_bytes(ctypes.byref(t), ctypes.byref(o))
+    n_prev = lib.dpar2_workspace_bytes(ctypes.byref(tp), ctypes.byref(o))
+    n = lib.dpar2_append_workspace_bytes(ctypes.byref(t), 3, ctypes.byref(o))
+    assert n > n_all > n_prev > 0
+    for bad in (0, 4, -1):
+        assert lib.dpar2_append_workspace_bytes(ctypes.byref(t), bad, ctypes.byref(o)) == 0
+    f = binding.c_factors(0x5000, 0x6000, 0x7000)
+    fz = binding.c_factors(0x5000, None, 0x7000)
+    prev, ws = 0x100000000, 0x200000000
+
+    def call(k=3, om1=0x3000, om2=0x4000, wp=prev, nwp=n_prev, fac=f, w=ws, nw=n):
+        return lib.dpar2_append(ctypes.byref(t), k, ctypes.byref(o), om1, om2, wp, nwp, ctypes.byref(fac),
+                                None, None, w, nw, None)
+    assert call(k=0) == -1 and call(k=4) == -1
+    assert call(om1=None) == -1 and call(om2=None) == -1
+    assert call(fac=fz) == -1
+    assert call(nwp=n_prev - 1) == -6 and b"ws_prev" in lib.dpar2_last_error()
+    assert call(nw=n - 1) == -6
+    assert call(w=0) == -6 and call(w=ws + 16) == -6
+    assert call(w=prev + 256 * (n_prev // 512)) == -1           # overlaps ws_prev
+    assert b"overlap" in lib.dpar2_last_error()
