@@ -257,6 +257,7 @@ Layout make_layout(const Group& g) {
   y.Mt = take(sizeof(double) * (size_t)(KR * J));
   y.Phi = take(sizeof(double) * (size_t)(K * L * R));
   y.sig1 = take(sizeof(double) * (size_t)KR);
+  y.msgn = take(sizeof(float) * (size_t)KR);
   y.Y2p = take(sizeof(double) * (size_t)(y.n2 * L2 * J));
   y.Y2 = take(sizeof(double) * (size_t)(nt * J * L2));
   y.B2t = take(sizeof(double) * (size_t)(KR * L2));
@@ -294,7 +295,7 @@ std::vector<int64_t> layout_key(const Layout& y) {
           (int64_t)y.tdesc, (int64_t)y.blk, (int64_t)y.blk0, (int64_t)y.chunks, (int64_t)y.seg_blk,
           (int64_t)y.seg_blk0, (int64_t)y.seg_chunk, (int64_t)y.seg_slice, (int64_t)y.slice_t, (int64_t)y.ctl,
           (int64_t)y.items, (int64_t)y.slice_ptr, (int64_t)y.slice_list, (int64_t)y.partG, (int64_t)y.partP,
-          (int64_t)y.partS, (int64_t)y.xnorm2, (int64_t)y.Mt, (int64_t)y.Phi, (int64_t)y.sig1, (int64_t)y.Y2p,
+          (int64_t)y.partS, (int64_t)y.xnorm2, (int64_t)y.Mt, (int64_t)y.Phi, (int64_t)y.sig1, (int64_t)y.msgn, (int64_t)y.Y2p,
           (int64_t)y.Y2, (int64_t)y.B2t, (int64_t)y.S2p, (int64_t)y.S2, (int64_t)y.U2, (int64_t)y.D,
           (int64_t)y.E, (int64_t)y.F, (int64_t)y.FtFp, (int64_t)y.Psi, (int64_t)y.Pw, (int64_t)y.Mk,
           (int64_t)y.small, (int64_t)y.partA, (int64_t)y.partB, (int64_t)y.partC, (int64_t)y.partBegin,
@@ -626,7 +627,8 @@ dpar2_status group_first_stage(const Group& g, char* w, const Layout& y, hipStre
                             reinterpret_cast<const int32_t*>(w + y.slice_list), partG, partP, partS,
                             reinterpret_cast<double*>(w + y.xnorm2), reinterpret_cast<double*>(w + y.Mt),
                             reinterpret_cast<double*>(w + y.Phi), reinterpret_cast<double*>(w + y.sig1),
-                            pass < y.q ? omq : nullptr, ctl, reinterpret_cast<const int32_t*>(w + y.slice_t), s);
+                            pass < y.q ? omq : nullptr, reinterpret_cast<float*>(w + y.msgn), ctl,
+                            reinterpret_cast<const int32_t*>(w + y.slice_t), s);
     if (e != hipSuccess) return hip_fail(e, "slice finish");
   }
   return DPAR2_OK;

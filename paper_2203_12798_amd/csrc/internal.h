@@ -66,7 +66,7 @@ struct Layout {
   // first stage (global slice index)
   size_t ctl, items, slice_ptr, slice_list;
   size_t partG, partP, partS;
-  size_t xnorm2, Mt, Phi, sig1;
+  size_t xnorm2, Mt, Phi, sig1, msgn;
   // second stage (per chunk / per tensor)
   size_t Y2p, Y2, B2t, S2p, S2, U2;
   size_t D, E, F, FtFp;
@@ -126,11 +126,12 @@ hipError_t launch_slab(const SlabArgs& a, int dtype, int64_t n_items, bool vec, 
 hipError_t launch_slab_wide(const SlabArgs& a, int dtype, int64_t n_items, bool vec, bool uout, hipStream_t s);
 // Per-slice completion of the first stage; omega_next (K x J x L float32, or
 // NULL) receives the sketch matrix of a power step, the orthonormal right
-// singular vectors of B_k (Alg. 1's power iteration in stabilised form).
+// singular vectors of B_k (Alg. 1's power iteration in stabilised form);
+// msgn (K x R) is scratch for the sign gauge of C_k B_k.
 hipError_t launch_slice_finish(int64_t K, int J, int L, int R, const int32_t* slice_ptr,
                                const int32_t* slice_list, const double* partG,
                                const double* partP, const double* partS, double* xnorm2,
-                               double* Mt, double* Phi, double* sig1, float* omega_next, Ctl* ctl,
+                               double* Mt, double* Phi, double* sig1, float* omega_next, float* msgn, Ctl* ctl,
                                const int32_t* slice_t, hipStream_t s);
 hipError_t launch_stage2(const Layout& lay, char* ws, hipStream_t s);
 // out[t * ostride + e] = sum_{b in [seg[t], seg[t+1])} part[b * stride + e],

@@ -11,7 +11,10 @@
 //     eigenvectors U~ of S and the singular values Sigma of B (small SVD)
 //   Phi = Wh U~_R (A_k = Y Phi = Q U~_R), C_k B_k = B^T U~_R = P^T Phi
 // Each column of C_k B_k is signed so that its largest-magnitude entry is
-// positive (first one on ties); Phi's column follows.
+// positive (first one on ties); Phi's column follows.  P is streamed twice (for
+// S, and for C_k B_k written unsigned with the sign found on the way; a second
+// kernel flips the rows of M^T whose sign is negative), three times with a
+// power step.
 //
 // Lane layout for the L x L matrices: the split layout of wave_linalg.h.
 #pragma once
@@ -56,19 +59,23 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
                                                   const double* __restrict__ partS, double* __restrict__ xnorm2,
                                                   double* __restrict__ Mt, double* __restrict__ Phi,
                                                   double* __restrict__ sig1, float* __restrict__ omega_next,
-                                                  Ctl* ctl, const int32_t* __restrict__ slice_t) {
+                                                  float* __restrict__ msgn, Ctl* ctl,
+                                                  const int32_t* __restrict__ slice_t) {
   constexpr int RM = SC<L>::RM, LH = SC<L>::LH, LD = SC<L>::LD, CW = SC<L>::CW, LL = L * L;
-  __shared__ double Gs[L * LD];    // G, then its Cholesky factor (upper triangle)
+  constexpr int CP = CW + 1;        // padded chunk row (conflict-free column reads)
+  constexpr int NPX = (L * CP > L * LD) ? L * CP : L * LD;
+  // G and its Cholesky factors are not needed while P is streamed: the chunks
+  // of B = Wh^T P and of C_k B_k (rows r < R) share their space
+  __shared__ double GM[NPX];
+  double* const Gs = GM;            // G, its Cholesky factor (upper), later that of S
+  double* const Mc = GM;            // chunk of B; chunk of C_k B_k
   __shared__ double Ss[L * LD];    // S = B B^T; then Phi
   __shared__ double Ws[L * LD];    // whitening Wh
-  constexpr int CP = CW + 1;        // padded chunk row (conflict-free column reads)
   // the sorted eigenvectors U~ live only between the Jacobi and Phi, when no
   // chunk of P is streamed: they share the chunk's space
-  constexpr int NPX = (L * CP > L * LD) ? L * CP : L * LD;
   __shared__ double PX[NPX];
   double* const Pc = PX;            // chunk of P
   double* const Xs = PX;            // sorted eigenvectors U~
-  __shared__ double Mc[L * CP];    // chunk of B = Wh^T P; chunk of C_k B_k (rows r < R)
   __shared__ double sgn[L], row[L], rinv[L], sv[L];
 
   const int lane = threadIdx.x, c = lane % RM, h = lane / RM;
@@ -79,27 +86,27 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
 
   // G column c (own rows) and ||X_k||^2
   double t[LH], v[LH];
+  {
+    double gs[LH];
 #pragma unroll
-  for (int ii = 0; ii < LH; ++ii) {
-    t[ii] = 0.0;
-    v[ii] = (h * LH + ii == c) ? 1.0 : 0.0;
-  }
-  // loads are unconditional (clamped index, value masked) so that they are
-  // issued back to back instead of one branch and wait each
-  for (int q = i0; q < i1; ++q) {
-    const double* g = partG + (size_t)slice_list[q] * LL;
+    for (int ii = 0; ii < LH; ++ii) gs[ii] = 0.0;
+    // loads are unconditional (clamped index, value masked) so that they are
+    // issued back to back instead of one branch and wait each
+    for (int q = i0; q < i1; ++q) {
+      const double* g = partG + (size_t)slice_list[q] * LL;
+#pragma unroll
+      for (int ii = 0; ii < LH; ++ii) {
+        const int a = h * LH + ii;
+        const bool ok = cv && a < L;
+        const double x = g[ok ? a * L + c : 0];
+        gs[ii] += ok ? x : 0.0;
+      }
+    }
 #pragma unroll
     for (int ii = 0; ii < LH; ++ii) {
       const int a = h * LH + ii;
-      const bool ok = cv && a < L;
-      const double x = g[ok ? a * L + c : 0];
-      t[ii] += ok ? x : 0.0;
+      if (cv && a < L) Gs[a * LD + c] = gs[ii];
     }
-  }
-#pragma unroll
-  for (int ii = 0; ii < LH; ++ii) {
-    const int a = h * LH + ii;
-    if (cv && a < L) Gs[a * LD + c] = t[ii];
   }
   if (lane == 0) {
     double s = 0.0;
@@ -107,11 +114,12 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
     xnorm2[k] = s;
   }
 
-  // P is streamed through LDS in chunks of CW columns: chunk jc of P into Pc
-  // (the loads of one item are issued together)
-  auto load_chunk = [&](int jc) {
-    constexpr int NE = (L * CW + 63) / 64;
-    double pv[NE];
+  // P is streamed through LDS in chunks of CW columns: fetch(jc) loads chunk
+  // jc (summed over the slice's items) into registers, stash() puts it into
+  // Pc; the next chunk's loads are in flight while the current one is used
+  constexpr int NE = (L * CW + 63) / 64;
+  double pv[NE];
+  auto fetch = [&](int jc) {
 #pragma unroll
     for (int u = 0; u < NE; ++u) pv[u] = 0.0;
     for (int q = i0; q < i1; ++q) {
@@ -124,6 +132,8 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
         pv[u] += ok ? x : 0.0;
       }
     }
+  };
+  auto stash = [&]() {
 #pragma unroll
     for (int u = 0; u < NE; ++u) {
       const int e = lane + 64 * u;
@@ -160,6 +170,13 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
     }
   } else {
     // eigen form: G = V Lambda V^T, Wh column c = v_c / sqrt(lambda_c) or 0
+    // (Gs still holds G: the factor is written back only on success)
+#pragma unroll
+    for (int ii = 0; ii < LH; ++ii) {
+      const int a = h * LH + ii;
+      t[ii] = (cv && a < L) ? Gs[a * LD + c] : 0.0;
+      v[ii] = (a == c) ? 1.0 : 0.0;
+    }
     if (split_jacobi<L, true>(t, v, c, h) == JACOBI_SWEEPS) warn |= 0x1u;
     double lam = 0.0;
 #pragma unroll
@@ -188,8 +205,10 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
     for (int y2 = 0; y2 < 2; ++y2) sacc[x][y2] = v4d{0.0, 0.0, 0.0, 0.0};
   {
     const int i16 = lane & 15, k4 = lane >> 4;
+    fetch(0);
     for (int jc = 0; jc < J; jc += CW) {
-      load_chunk(jc);
+      stash();
+      if (jc + CW < J) fetch(jc + CW);
       __syncthreads();
       v4d bacc[2][2];
 #pragma unroll
@@ -307,8 +326,10 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
   __syncthreads();
   if (omega_next) {
     float* On = omega_next + (size_t)k * J * L;
+    fetch(0);
     for (int jc = 0; jc < J; jc += CW) {
-      load_chunk(jc);
+      stash();
+      if (jc + CW < J) fetch(jc + CW);
       __syncthreads();
       v4d oacc[2][2];
 #pragma unroll
@@ -329,51 +350,52 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
     }
   }
 
-  // C_k B_k = P^T Phi.  Pass 0 finds the signed leading entry of each column
-  // (lane r < R scans the chunk), pass 1 writes the signed rows of M^T.
+  // C_k B_k = P^T Phi, written unsigned into the rows of M^T while lane
+  // r < R finds the leading entry of row r (largest magnitude, first on
+  // ties); the rows whose sign is negative are flipped afterwards (msgn)
   double bv = -1.0, bs = 0.0;
   double* Mk = Mt + (size_t)k * R * J;
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int jc = 0; jc < J; jc += CW) {
-      load_chunk(jc);
-      __syncthreads();
-      v4d macc[2][2];
+  fetch(0);
+  for (int jc = 0; jc < J; jc += CW) {
+    stash();
+    if (jc + CW < J) fetch(jc + CW);
+    __syncthreads();
+    v4d macc[2][2];
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y2 = 0; y2 < 2; ++y2) macc[x][y2] = v4d{0.0, 0.0, 0.0, 0.0};
-      chunk_atb<L, LD, CP>(Ss, Pc, R, macc, lane);
+      for (int y2 = 0; y2 < 2; ++y2) macc[x][y2] = v4d{0.0, 0.0, 0.0, 0.0};
+    chunk_atb<L, LD, CP>(Ss, Pc, R, macc, lane);
 #pragma unroll
-      for (int tr = 0; tr < 2; ++tr)
+    for (int tr = 0; tr < 2; ++tr)
 #pragma unroll
-        for (int tj = 0; tj < 2; ++tj)
+      for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int r = 16 * tr + f64_row(lane, v), jj = 16 * tj + (lane & 15);
-            if (r < R) {
-              const double m = macc[tr][tj][v];
-              if (pass == 0) Mc[r * CP + jj] = m;
-              else if (jc + jj < J) Mk[(size_t)r * J + jc + jj] = sgn[r] * m;
-            }
-          }
-      __syncthreads();
-      if (pass == 0 && lane < R) {
-        const int nj = (J - jc < CW) ? J - jc : CW;
-        for (int jj = 0; jj < nj; ++jj) {
-          const double m = Mc[lane * CP + jj];
-          if (fabs(m) > bv) {
-            bv = fabs(m);
-            bs = m;
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * tr + f64_row(lane, v), jj = 16 * tj + (lane & 15);
+          if (r < R) {
+            const double m = macc[tr][tj][v];
+            Mc[r * CP + jj] = m;
+            if (jc + jj < J) Mk[(size_t)r * J + jc + jj] = m;
           }
         }
+    __syncthreads();
+    if (lane < R) {
+      const int nj = (J - jc < CW) ? J - jc : CW;
+      for (int jj = 0; jj < nj; ++jj) {
+        const double m = Mc[lane * CP + jj];
+        if (fabs(m) > bv) {
+          bv = fabs(m);
+          bs = m;
+        }
       }
-      __syncthreads();
-    }
-    if (pass == 0) {
-      if (lane < R) sgn[lane] = (bs < 0.0) ? -1.0 : 1.0;
-      __syncthreads();
     }
   }
+  if (lane < R) {
+    sgn[lane] = (bs < 0.0) ? -1.0 : 1.0;
+    msgn[(size_t)k * R + lane] = (bs < 0.0) ? -1.0f : 1.0f;
+  }
+  __syncthreads();
   for (int e = lane; e < L * R; e += 64) {
     const int a = e / R, r = e % R;
     Phi[(size_t)k * L * R + e] = sgn[r] * Ss[a * LD + r];
@@ -385,11 +407,11 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
 template <int L>
 hipError_t slice_fin_launch(int64_t K, int J, int R, const int32_t* slice_ptr, const int32_t* slice_list,
                             const double* partG, const double* partP, const double* partS, double* xnorm2,
-                            double* Mt, double* Phi, double* sig1, float* omega_next, Ctl* ctl,
+                            double* Mt, double* Phi, double* sig1, float* omega_next, float* msgn, Ctl* ctl,
                             const int32_t* slice_t, hipStream_t s) {
   if (K <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_slice_fin<L>, dim3((unsigned)K), dim3(64), 0, s, (int)K, J, R, slice_ptr, slice_list,
-                     partG, partP, partS, xnorm2, Mt, Phi, sig1, omega_next, ctl, slice_t);
+                     partG, partP, partS, xnorm2, Mt, Phi, sig1, omega_next, msgn, ctl, slice_t);
   return hipGetLastError();
 }
 
