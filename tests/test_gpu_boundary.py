@@ -217,19 +217,21 @@ def test_released_and_reused_workspace():
     d.release(ws)
 
 
-def test_rank_deficient_q_step_keeps_psi_orthogonal():
+@pytest.mark.parametrize("R,L", [(5, 15), (10, 15), (20, 24)])
+def test_rank_deficient_q_step_keeps_psi_orthogonal(R, L):
     """A starting W with a zero column makes every T_k of the first Q-step
     (Eq. 8) singular: the polar factor is then not unique, and the Q-step
     completes Z_k so that Psi_k = Z_k P_k^T stays orthogonal.  Checked through
     U_k = A_k Psi_k H: U_k^T U_k = H^T H for every slice (A_k has orthonormal
-    columns), with the rank-deficiency warning raised and finite factors."""
+    columns), with the rank-deficiency warning raised and finite factors;
+    R = 5, 10 and 20 (groups of 8, 16 and 32 lanes per slice, one lane per
+    column)."""
     torch = _torch()
     X = synth.small_parity(seed=2, K=40)
-    R, L = 5, 15
     d, T, o, o1, o2, (H0, V0, W0) = _setup(X, R, L, 1)
     W0 = W0.copy()
     W0[:, 2] = 0.0
-    print("[gpu] rank-deficient Q-step", flush=True)
+    print(f"[gpu] rank-deficient Q-step R={R}", flush=True)
     f = d.Factors.from_numpy(H0, V0, W0)
     ws = d.alloc_workspace(T, o)
     d.compress(T, o, o1, o2, ws)
