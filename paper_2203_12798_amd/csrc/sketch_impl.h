@@ -53,13 +53,10 @@ struct In<DPAR2_FP8_E4M3> {
 // bf16 (bit pattern) to float: exact
 __device__ __forceinline__ float bf16_bits_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
 
-// OCP fp8 e4m3fn (bias 7, no infinities, S.1111.111 = NaN) to float: exact
-__device__ __forceinline__ float e4m3_to_f32(uint32_t b) {
-  const uint32_t s = (b & 0x80u) << 24, e = (b >> 3) & 0xFu, m = b & 7u;
-  float v = (e == 0) ? (float)m * 0x1p-9f : __uint_as_float(((e + 120u) << 23) | (m << 20));
-  if (e == 15u && m == 7u) v = __uint_as_float(0x7fc00000u);
-  return __uint_as_float(__float_as_uint(v) | s);
-}
+// OCP fp8 e4m3fn (bias 7, no infinities, S.1111.111 = NaN) to float: exact,
+// on the conversion unit (one byte, or a pair of bytes per instruction)
+typedef float v2f_cvt __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float e4m3_to_f32(uint32_t b) { return __builtin_amdgcn_cvt_f32_fp8((int)b, 0); }
 
 // round to the nearest bf16 value (ties to even), returned as float
 __device__ __forceinline__ float round_bf16(float x) {
@@ -84,8 +81,9 @@ __device__ __forceinline__ float4 to_f32x4(typename In<TIN>::V4 x, float scale) 
     return make_float4(bf16_bits_to_f32(x.x & 0xffffu), bf16_bits_to_f32(x.x >> 16),
                        bf16_bits_to_f32(x.y & 0xffffu), bf16_bits_to_f32(x.y >> 16));
   } else {
-    return make_float4(e4m3_to_f32(x & 0xffu) * scale, e4m3_to_f32((x >> 8) & 0xffu) * scale,
-                       e4m3_to_f32((x >> 16) & 0xffu) * scale, e4m3_to_f32(x >> 24) * scale);
+    const v2f_cvt lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)x, false);   // bytes 0, 1
+    const v2f_cvt hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)x, true);    // bytes 2, 3
+    return make_float4(lo[0] * scale, lo[1] * scale, hi[0] * scale, hi[1] * scale);
   }
 }
 

@@ -96,3 +96,35 @@ def test_low_precision_with_power_step(kind):
     print(f"[forms] {kind} q=1: fitness {g['rep']['fit_true']:.8f} vs oracle {ref.fit:.8f}", flush=True)
     assert abs(g["rep"]["fit_true"] - ref.fit) < 1e-7
     assert rel(g["U"], np.concatenate(ref.U, axis=0)) < 1e-5
+
+
+@pytest.mark.parametrize("wide", [False, True])
+def test_every_fp8_code_decodes_exactly(wide):
+    """Every finite e4m3 code, both signs: slice k (of 8, 64 rows of J = 32)
+    holds the codes 16 k .. 16 k + 15 (zero, the subnormals and every binade)
+    with random signs, scaled by 2^(k - 4).  ||X_k||^2 of every slice equals
+    the sum of the exactly decoded values (FP64 on both sides: 1e-13); within a
+    slice the codes span two binades, so any code decoded wrongly moves its
+    slice's sum by more than 1e-3.  Whole-row and 128-column-chunk passes."""
+    torch = _torch()
+    import paper_2203_12798_amd as d
+    rng = np.random.default_rng(17)
+    K, I, J = 8, 64, 32
+    codes = np.zeros((K * I, J), dtype=np.uint8)
+    for k in range(K):
+        lo, hi = 16 * k, min(16 * k + 16, 127)          # 0x7f (NaN) excluded
+        c = rng.integers(lo, hi, size=(I, J)).astype(np.uint8)
+        codes[k * I:(k + 1) * I] = c | (rng.integers(0, 2, size=(I, J)) * 0x80).astype(np.uint8)
+    offsets = np.arange(K + 1, dtype=np.int64) * I
+    scale = np.exp2(np.arange(K) - 4.0).astype(np.float32)
+    dec = synth.decode_fp8(codes, offsets, scale).astype(np.float64)
+    ref = np.array([np.sum(dec[k * I:(k + 1) * I] ** 2) for k in range(K)])
+    T = d.Tensor.from_numpy(codes, offsets, dtype=d.binding.DPAR2_FP8_E4M3, scale=scale)
+    R, L = 4, 8
+    o = d.Options(rank=R, sketch=L, sketch2=L, max_iter=1, wide_slab=wide)
+    om1, om2 = synth.omegas(J, L, K * R)
+    ws = d.alloc_workspace(T, o)
+    print(f"[gpu] fp8 codes wide={wide}", flush=True)
+    d.compress(T, o, torch.from_numpy(synth.round_bf16(om1)).cuda(), torch.from_numpy(om2).cuda(), ws)
+    got = d.compressed_view(T, o, ws)["xnorm2"]
+    np.testing.assert_allclose(got, ref, rtol=1e-13)
