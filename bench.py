@@ -51,6 +51,11 @@ def parse():
     ap.add_argument("--no-wide", action="store_true",
                     help="skip the precision form at J = 2049 (K = 8000, spectrogram-like, R = 10 and 20)")
     ap.add_argument("--wide-k", type=int, default=8000)
+    ap.add_argument("--scalability", action="store_true",
+                    help="run only the tenrand scalability workloads (five sizes at R = 10, R = 10..30 at "
+                         "2000 x 2000 x 4000); one JSON line")
+    ap.add_argument("--scalability-plain", action="store_true",
+                    help="with --scalability: also time PARAFAC2-ALS (Alg. 2) at every point")
     ap.add_argument("--wide-only", action="store_true",
                     help="run only the J = 2049 form (one JSON line with its figures; for profiling)")
     ap.add_argument("--wide-ranks", default="10,20", help="ranks of the J = 2049 form")
@@ -362,6 +367,82 @@ def gen_wide(K, d, torch, np, seed=3, chunk=256):
     return d.Tensor(slab, torch.from_numpy(offs).cuda(), offs), rows
 
 
+SCALE_SIZES = [(1000, 1000, 1000), (1000, 1000, 2000), (2000, 1000, 2000), (2000, 2000, 2000), (2000, 2000, 4000)]
+SCALE_RANKS = [10, 20, 30]
+
+
+def bench_scalability(args, d, torch, np, binding):
+    """The paper's synthetic scalability workloads (Sec. IV-C): tenrand-style
+    tensors of K slices of I x J entries uniform in [0, 1) (torch's generator
+    on the GPU, seed 5), float32; the five sizes I x J x K at R = 10, and
+    R = 10, 20, 30 at 2000 x 2000 x 4000 (64 GB).  As in those experiments the
+    randomized SVD runs at the target rank (L = L2 = R) and 32 iterations.
+    Per point: ms per decomposition (mean of the timed runs), the slab-pass
+    time, the fitness, and PARAFAC2-ALS on the GPU (Alg. 2, same factors and
+    iterations) where --scalability-plain asks for it."""
+    out = {"workload": "tenrand I x J x K uniform [0, 1) float32; L = R; 32 iterations", "points": []}
+    g = torch.Generator(device="cuda").manual_seed(5)
+    runs = max(1, args.steps // 2)
+    cases = [(I, J, K, 10) for I, J, K in SCALE_SIZES] + [(2000, 2000, 4000, R) for R in SCALE_RANKS if R != 10]
+    cur = None
+    for I, J, K, R in cases:
+        if cur is None or cur[0] != (I, J, K):
+            cur = None
+            torch.cuda.empty_cache()
+            slab = torch.rand((I * K, J), device="cuda", generator=g)
+            offs = np.arange(K + 1, dtype=np.int64) * I
+            cur = ((I, J, K), d.Tensor(slab, torch.from_numpy(offs).cuda(), offs))
+        T = cur[1]
+        L = R
+        o = d.Options(rank=R, sketch=L, sketch2=L, max_iter=32)
+        om1 = torch.randn(J, L, device="cuda", generator=g)
+        om2 = torch.randn(K * R, L, device="cuda", generator=g)
+        init = (torch.eye(R, dtype=torch.float64, device="cuda"),
+                torch.randn(J, R, dtype=torch.float64, device="cuda", generator=g),
+                torch.ones(K, R, dtype=torch.float64, device="cuda"))
+        ws = d.alloc_workspace(T, o)
+        f = d.Factors(*(a.clone() for a in init))
+
+        def step():
+            f.H.copy_(init[0])
+            f.V.copy_(init[1])
+            f.W.copy_(init[2])
+            d.decompose(T, o, om1, om2, f, ws)
+
+        step()
+        torch.cuda.synchronize()
+        binding.profile_enable(True)
+        binding.profile_read()
+        t0 = time.perf_counter()
+        for _ in range(runs):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / runs
+        nl, sk = binding.profile_read()
+        binding.profile_enable(False)
+        rep = d.report_read(T, o, ws)
+        pt = {"I": I, "J": J, "K": K, "R": R, "L": L, "gb_f32": round(I * J * K * 4 / 1e9, 2),
+              "ms_per_decomposition": round(ms, 2), "slab_pass_ms": round(sk / max(nl, 1), 3),
+              "fitness": rep["fit_true"], "iters": rep["iters"]}
+        d.release(ws)
+        del ws
+        if args.scalability_plain:
+            op = d.Options(rank=R, sketch=R, sketch2=R, max_iter=32)
+            wsp = d.alloc_plain_workspace(T, op)
+            fp = d.Factors(*(a.clone() for a in init))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rp = d.als_plain(T, op, fp, wsp, report=True)
+            torch.cuda.synchronize()
+            pt["plain_als_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+            pt["plain_als_fitness"] = rp["fit_true"]
+            pt["dpar2_speedup"] = round(pt["plain_als_ms"] / ms, 2)
+            del wsp
+        print(f"[bench] scalability {I}x{J}x{K} R={R}: {ms:.2f} ms", file=sys.stderr, flush=True)
+        out["points"].append(pt)
+    return out
+
+
 def bench_wide(args, d, torch, np, binding):
     """Precision form at the spectrogram shape (J = 2049): float32, bf16 and
     fp8-e4m3 (per-slice power-of-two scales) slabs, R = 10 (L = 20) and
@@ -493,6 +574,9 @@ def main():
     from paper_2203_12798_amd import binding
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.scalability:
+        print(json.dumps({"scalability": bench_scalability(args, d, torch, np, binding)}), flush=True)
+        return
     if args.wide_only:
         res, _ = bench_wide(args, d, torch, np, binding)
         print(json.dumps({"precision_wide": res}), flush=True)
