@@ -96,3 +96,41 @@ def test_fp64_matrix_core_pass_matches_oracle(J):
     assert row_rel(g["comp"]["Mt"].T, ref.comp.M) < 1e-6
     assert abs(g["rep"]["fit_true"] - ref.fit) < 1e-7
     assert rel(g["U"], np.concatenate(ref.U, axis=0)) < 1e-5
+
+
+def test_rank_deficient_sketch_takes_the_eigen_whitening():
+    """Slices whose sketch Y_k = X_k Omega_1 has rank 5 < L = 8 (X_k of rank 5
+    up to its float32 rounding, no noise: the Gram's last pivots sit at the
+    rounding level, far below 1e-9 of its largest diagonal), between
+    noisy rank-3 slices: those slices take the eigen form of the whitening.
+    R = 3 < 5, so their leading triplets are well defined and the same
+    tolerances as elsewhere apply: compression, factors, U_k, fitness."""
+    rng = np.random.default_rng(23)
+    J, R, L = 24, 3, 8
+    X0 = synth.parafac2(synth.uniform_rows(20, 40, 120, 23), J, R, 23, noise_abs=0.02)
+    slab = X0.slab.copy()
+    deficient = [2, 7, 11, 18]
+    for k in deficient:
+        n = X0.offsets[k + 1] - X0.offsets[k]
+        A = rng.standard_normal((n, 5))
+        B = rng.standard_normal((J, 5)) * np.array([3.0, 2.2, 1.5, 0.8, 0.4])
+        slab[X0.offsets[k]:X0.offsets[k + 1]] = (A @ B.T).astype(np.float32)
+    X = synth.IrregularTensor(slab=slab, offsets=X0.offsets)
+    iters = 30
+    om1, om2 = synth.omegas(X.J, L, X.K * R)
+    H0, V0, W0 = synth.init_factors(X.J, X.K, R)
+    ref = O.dpar2(X.slab, X.offsets, R, om1, om2, H0, V0, W0, iters)
+    # those slices' sketches have rank 5 up to the float32 rounding of the
+    # slab: their Gram's sixth eigenvalue lies below 1e-12 of the largest,
+    # far below the 1e-9 pivot threshold of the Cholesky whitening
+    for k in deficient:
+        Y = X.slab[X.offsets[k]:X.offsets[k + 1]].astype(np.float64) @ om1
+        s = np.linalg.svd(Y, compute_uv=False)
+        assert s[5] < 1e-6 * s[0]
+    print("[gpu] eigen whitening", flush=True)
+    g = _run_gpu(X, R, L, L, iters, om1, om2, H0, V0, W0, want_U=True)
+    _check_compression(X, R, g, ref)
+    _check_errors(g, ref)
+    _check_factors(g, ref)
+    assert abs(g["rep"]["fit_true"] - ref.fit) < 1e-7
+    assert rel(g["U"], np.concatenate(ref.U, axis=0)) < 1e-5
