@@ -201,8 +201,27 @@ def bench_batch(args, d, torch, np):
         fs.append(d.Factors(flat[at:at + R * R].view(R, R), flat[at + R * R:at + R * R + J * R].view(J, R),
                             flat[at + R * R + J * R:at + n_el].view(K, R)))
         at += n_el
-    for graph in (False, True):
-        os_ = [d.Options(rank=R, sketch=min(R + 10, J), sketch2=min(R + 10, J), max_iter=iters, graph=graph)
+    # slab tiling per (J, R) group: dpar2_autotune_slab on the group's largest
+    # tensor (rows per work item x whole-row or 128-column-chunk pass), applied
+    # to every tensor of the group
+    from paper_2203_12798_amd import binding
+    cands = [(2048, False), (4096, False), (8192, False), (16384, False), (4096, True), (16384, True)]
+    tuned = {}
+    for key in sorted({(J, R) for _, J, R in specs}):
+        idx = max((i for i, (_, J, R) in enumerate(specs) if (J, R) == key), key=lambda i: Ts[i].offsets_host[-1])
+        K, J, R = specs[idx]
+        L = min(R + 10, J)
+        o = d.Options(rank=R, sketch=L, sketch2=L, max_iter=iters)
+        wst = d.alloc_workspace(Ts[idx], d.Options(rank=R, sketch=L, sketch2=L, max_iter=iters, item_rows=2048,
+                                                   wide_slab=True))
+        (ir, wide), times = binding.autotune_slab(Ts[idx], o, om1[idx], wst, cands)
+        tuned[key] = (ir, wide)
+        del wst
+    res["autotune"] = {f"J{J}_R{R}": {"item_rows": ir, "pass": "128-column chunks" if wide else "whole rows"}
+                       for (J, R), (ir, wide) in tuned.items()}
+    for graph, tune in ((False, False), (True, False), (True, True)):
+        os_ = [d.Options(rank=R, sketch=min(R + 10, J), sketch2=min(R + 10, J), max_iter=iters, graph=graph,
+                         item_rows=tuned[(J, R)][0] if tune else 0, wide_slab=tuned[(J, R)][1] if tune else False)
                for K, J, R in specs]
         ws = d.alloc_batch_workspace(Ts, os_)
 
@@ -219,7 +238,7 @@ def bench_batch(args, d, torch, np):
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
         reps = d.batch_report_read(Ts, os_, ws)
-        key = "graph" if graph else "eager"
+        key = ("graph" if graph else "eager") + ("_autotuned" if tune else "")
         res[key] = {"ms_per_batch": round(ms, 3), "tensors_per_s": round(n / (ms / 1e3), 1),
                     "slices_per_s": round(slices / (ms / 1e3), 1),
                     "rows_per_s": round(rows / (ms / 1e3), 1)}

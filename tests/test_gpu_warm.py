@@ -129,9 +129,10 @@ def test_training_lowers_loss_and_reports_gain():
     [24, 120], R = 5, 1% noise) labelled by their own 150-iteration
     decompositions (labels whose canonical W exceeds 10 in magnitude, i.e.
     degenerate ALS solutions, are left out); the training loss must fall below
-    0.7 of its start.  On 32 held-out tensors the iterations to reach the
-    random start's 200-iteration compressed fitness minus 1e-4 are reported
-    for both starts, with the held-out loss."""
+    0.7 of its start.  On 32 held-out tensors the warm start must reach the
+    random start's 200-iteration compressed fitness minus 1e-4 in fewer
+    iterations (mean below 0.9 of the random start's, median below it, at
+    least half of the tensors reaching the target within 200)."""
     torch = _torch()
     import paper_2203_12798_amd as d
     from paper_2203_12798_amd import warm
@@ -183,3 +184,8 @@ def test_training_lowers_loss_and_reports_gain():
         its_w.append(200 if tw is None else tw)
     print(f"[warm] held-out: random start {np.mean(its_r):.1f} iterations (median {np.median(its_r):.0f}), "
           f"warm start {np.mean(its_w):.1f} (median {np.median(its_w):.0f}; reached {hit_w}/32)", flush=True)
+    # the gain: fewer iterations on held-out tensors (a run measured 170.6
+    # against 109.9 on average, medians 178 and 112, 22 of 32 reached)
+    assert np.mean(its_w) < 0.9 * np.mean(its_r)
+    assert np.median(its_w) < np.median(its_r)
+    assert hit_w >= 16
