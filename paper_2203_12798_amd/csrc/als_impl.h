@@ -364,7 +364,7 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_A(AlsArgs a) {
   ALS_BLOCK_PROLOGUE(R)
   constexpr int RM = RC<R>::RM, GPB = RC<R>::GPB, TPB = RC<R>::TPB, RR = R * R;
   __shared__ double sH[RR], sB[RR];
-  __shared__ double sF[GPB * RR], sZ[GPB * RR], sP[GPB * RR], sT[GPB * RR];
+  __shared__ double sF[GPB * RR], sZ[GPB * RR], sP[GPB * RR], sT[GPB * RR], sW[GPB * R];
   const int64_t K = bk.s1;   // slices bk.s0 .. bk.s1 - 1 (at most GPB)
   const int tid = threadIdx.x, g = tid / RM, j = tid % RM;
   const int lane = tid & 63, gbase = lane & ~(RM - 1);
@@ -392,20 +392,19 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_A(AlsArgs a) {
       bv[u] = (e < RR) ? Bm[e] : 0.0;
     }
     constexpr int NF = (RR + RM - 1) / RM;   // loads issued together (clamped index)
-    double fv[NF];
+    // F^(k) and the previous P_k (row-major, as flat arrays) and W(k, j):
+    // through LDS, so that no R-long array is held across the set-up
+    double fv[NF], pv[NF];
 #pragma unroll
     for (int u = 0; u < NF; ++u) {
       const int e = j + RM * u;
       const bool ok = k < K && e < RR;
       const double x = a.F[ok ? (size_t)k * RR + e : 0];
+      const double y = a.Pw[ok ? (size_t)k * RR + e : 0];
       fv[u] = ok ? x : 0.0;
+      pv[u] = ok ? y : 0.0;
     }
-    double t[R], v[R], wk[R];
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-      wk[i] = (k < K) ? td.W[(size_t)(k - td.k0) * R + i] : 0.0;
-      v[i] = live ? a.Pw[(size_t)k * RR + i * R + j] : 0.0;
-    }
+    const double wkj = live ? td.W[(size_t)(k - td.k0) * R + j] : 0.0;
     if (ctl->done) return;
 #pragma unroll
     for (int u = 0; u < NS; ++u) {
@@ -417,36 +416,40 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_A(AlsArgs a) {
     }
 #pragma unroll
     for (int u = 0; u < NF; ++u)
-      if (j + RM * u < RR) F_[j + RM * u] = fv[u];
+      if (j + RM * u < RR) {
+        F_[j + RM * u] = fv[u];
+        P_[j + RM * u] = pv[u];
+      }
+    if (live) sW[g * R + j] = wkj;
     __syncthreads();
     // column j of T_k = F^(k) Bm diag(W(k,:)) H^T (Eq. 8)
     // (the small products below run their R sums side by side, each over
     // its index in ascending order)
     {
-      double y[R], x[R];
+      double x[R];
+#pragma unroll
+      for (int i = 0; i < R; ++i) x[i] = 0.0;
 #pragma unroll
       for (int i = 0; i < R; ++i) {
-        y[i] = wk[i] * sH[(live ? j : 0) * R + i];
-        x[i] = 0.0;
+        const double y = sW[g * R + i] * sH[(live ? j : 0) * R + i];
+#pragma unroll
+        for (int q = 0; q < R; ++q) x[q] = fma(sB[q * R + i], y, x[q]);
       }
-#pragma unroll
-      for (int i = 0; i < R; ++i)
-#pragma unroll
-        for (int q = 0; q < R; ++q) x[q] = fma(sB[q * R + i], y[i], x[q]);
       if (live) {
-        double tq[R];
 #pragma unroll
-        for (int q = 0; q < R; ++q) tq[q] = 0.0;
+        for (int q = 0; q < R; ++q) {
+          double tq = 0.0;
 #pragma unroll
-        for (int i = 0; i < R; ++i)
-#pragma unroll
-          for (int q = 0; q < R; ++q) tq[q] = fma(F_[q * R + i], x[i], tq[q]);
-#pragma unroll
-        for (int q = 0; q < R; ++q) T_[q * R + j] = tq[q];
+          for (int i = 0; i < R; ++i) tq = fma(F_[q * R + i], x[i], tq);
+          T_[q * R + j] = tq;
+        }
       }
     }
     __syncthreads();
     // t = T_k p_j, p_j the warm start (column j of the previous P_k)
+    double t[R], v[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = live ? P_[i * R + j] : 0.0;
 #pragma unroll
     for (int q = 0; q < R; ++q) t[q] = 0.0;
     if (live)
@@ -528,10 +531,7 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_A(AlsArgs a) {
     __syncthreads();
     // G1 partial, column j: W(k,j) * M_k Bm(:, j)
     if (live) {
-      double wj = 0.0;
-#pragma unroll
-      for (int i = 0; i < R; ++i)
-        if (i == j) wj = wk[i];
+      const double wj = wkj;
       double sq[R];
 #pragma unroll
       for (int q = 0; q < R; ++q) sq[q] = 0.0;
