@@ -64,6 +64,7 @@ def parse():
                     help="skip the learned warm-start form (train the set encoder, compare on held-out tensors)")
     ap.add_argument("--warm-train", type=int, default=400, help="training tensors of the warm-start form")
     ap.add_argument("--warm-test", type=int, default=32, help="held-out tensors of the warm-start form")
+    ap.add_argument("--warm-steps", type=int, default=3000, help="Adam steps (minibatch 32) of the warm-start training")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip PARAFAC2-ALS on the uncompressed slices (Alg. 2) on the same workload")
     ap.add_argument("--no-stream", action="store_true",
@@ -252,16 +253,24 @@ def bench_batch(args, d, torch, np):
 
 def gen_warm_tensor(t, seed, d, torch, np):
     """One tensor of the warm-start workload: K ~ U{32..512}, J = 64,
-    I_k ~ U{64..1024}, rank-10 PARAFAC2 (as in gen_batch) plus Gaussian noise
-    of 0.01 x the RMS of the clean entries; numpy SeedSequence(seed).spawn
-    for the shape, torch's generator seeded by (seed, t) for the entries."""
+    I_k ~ U{64..1024}, rank-10 PARAFAC2 plus Gaussian noise of 0.01 x the RMS
+    of the clean entries; numpy SeedSequence(seed).spawn for the shape,
+    torch's generator seeded by (seed, t) for the entries.  Q_k has
+    orthonormal columns: the Gaussian I_k x R block made orthonormal by two
+    rounds of Cholesky QR in FP64 (batched over the slices; a tall Gaussian
+    block is well conditioned, so two rounds reach rounding-level
+    orthogonality)."""
     rng = np.random.default_rng(np.random.SeedSequence([seed, t]))
     K, J, R = int(rng.integers(32, 513)), 64, 10
     rows = rng.integers(64, 1025, size=K)
     g = torch.Generator(device="cuda").manual_seed(seed * 100003 + t)
     imax = int(rows.max())
     mask = torch.arange(imax, device="cuda")[None, :] < torch.from_numpy(rows).cuda()[:, None]
-    Q = torch.linalg.qr(torch.randn(K, imax, R, device="cuda", generator=g) * mask[:, :, None]).Q
+    Q = (torch.randn(K, imax, R, device="cuda", generator=g) * mask[:, :, None]).double()
+    for _ in range(2):
+        C = torch.linalg.cholesky(torch.bmm(Q.transpose(1, 2).contiguous(), Q))
+        Q = torch.linalg.solve_triangular(C.transpose(1, 2).contiguous(), Q, upper=True, left=False)
+    Q = Q.float()
     H = torch.randn(R, R, device="cuda", generator=g)
     V = torch.randn(J, R, device="cuda", generator=g)
     W = 0.5 + torch.rand(K, R, device="cuda", generator=g)
@@ -273,7 +282,7 @@ def gen_warm_tensor(t, seed, d, torch, np):
 
 def bench_warm(args, d, torch, np):
     """Learned warm start: trains the set encoder on tensors labelled by their
-    own 150-iteration decompositions, then on held-out tensors measures the
+    own 150-iteration decompositions (batched), then on held-out tensors measures the
     iterations and device time each start needs to reach the random start's
     300-iteration fitness minus 1e-3 (|delta fitness| <= 1e-3)."""
     from paper_2203_12798_amd import warm
@@ -290,22 +299,38 @@ def bench_warm(args, d, torch, np):
                 torch.ones(K, R, dtype=torch.float64, device="cuda"))
         return o, om1, om2, init
 
+    # labels: the training tensors are decomposed 64 at a time in one batch
+    # call (bit for bit the single-tensor decompositions), then each is
+    # compressed on its own workspace for its tokens and targets
     train = []
-    for t in range(args.warm_train):
-        T, K, J, _ = gen_warm_tensor(t, 5, d, torch, np)
-        o, om1, om2, init = setup(T, K, J, t)
-        o.max_iter = 150
-        ws = d.alloc_workspace(T, o)
-        f = d.Factors(*(a.clone() for a in init))
-        d.decompose(T, o, om1, om2, f, ws)
-        s = warm.label(T, o, ws, f)
-        if float(s.tW.abs().max()) < 10.0:       # degenerate ALS solutions are not labels
-            train.append(s)
-        del T, ws
+    nb = 64
+    for t0b in range(0, args.warm_train, nb):
+        batch = []
+        for t in range(t0b, min(t0b + nb, args.warm_train)):
+            T, K, J, _ = gen_warm_tensor(t, 5, d, torch, np)
+            o, om1, om2, init = setup(T, K, J, t)
+            o.max_iter = 150
+            batch.append((T, o, om1, om2, d.Factors(*(a.clone() for a in init))))
+        Ts, os_ = [b[0] for b in batch], [b[1] for b in batch]
+        wsb = d.alloc_batch_workspace(Ts, os_)
+        d.decompose_batch(Ts, os_, [b[2] for b in batch], [b[3] for b in batch], [b[4] for b in batch], wsb)
+        d.release(wsb)
+        del wsb
+        for T, o, om1, om2, f in batch:
+            ws = d.alloc_workspace(T, o)
+            d.compress(T, o, om1, om2, ws)
+            s = warm.label(T, o, ws, f)
+            if float(s.tW.abs().max()) < 10.0:       # degenerate ALS solutions are not labels
+                train.append(s)
+            d.release(ws)
+            del ws
+        del batch, Ts
+        if (t0b // nb) % 16 == 15:
+            print(f"[bench] warm: {t0b + nb} tensors labelled", file=sys.stderr, flush=True)
     label_s = time.perf_counter() - t0
     net = warm.WarmNet(R, seed=1)
     t1 = time.perf_counter()
-    net.train(train, steps=3000, batch=32, lr=1e-3)
+    net.train(train, steps=args.warm_steps, batch=32, lr=1e-3)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t1
     print(f"[bench] warm: {len(train)} labels ({label_s:.1f}s), trained in {train_s:.1f}s", file=sys.stderr,
@@ -338,8 +363,10 @@ def bench_warm(args, d, torch, np):
         ms_w.append(ev[2].elapsed_time(ev[3]) + its_w[-1] * per_it)
         dfit.append(fit_w[-1] - fit_r[-1])
         del T, ws
+        if t % 200 == 199:
+            print(f"[bench] warm: {t + 1} held-out tensors", file=sys.stderr, flush=True)
     return {"workload": "K~U{32..512}, J=64, I_k~U{64..1024}, rank-10 PARAFAC2 + 1% noise; R=10 L=20",
-            "train_tensors": len(train), "train_steps": 3000, "label_s": round(label_s, 1),
+            "train_tensors": len(train), "train_steps": args.warm_steps, "label_s": round(label_s, 1),
             "train_s": round(train_s, 2), "test_tensors": args.warm_test,
             "target": "random start's 300-iteration compressed fitness - 1e-3",
             "iters_random_mean": float(np.mean(its_r)), "iters_warm_mean": float(np.mean(its_w)),
