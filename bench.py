@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--warm-train", type=int, default=400, help="training tensors of the warm-start form")
     ap.add_argument("--warm-test", type=int, default=32, help="held-out tensors of the warm-start form")
     ap.add_argument("--warm-steps", type=int, default=3000, help="Adam steps (minibatch 32) of the warm-start training")
+    ap.add_argument("--warm-no-match", action="store_true",
+                    help="warm-start training compares components in the targets' own order (no matching)")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip PARAFAC2-ALS on the uncompressed slices (Alg. 2) on the same workload")
     ap.add_argument("--no-stream", action="store_true",
@@ -330,7 +332,7 @@ def bench_warm(args, d, torch, np):
     label_s = time.perf_counter() - t0
     net = warm.WarmNet(R, seed=1)
     t1 = time.perf_counter()
-    net.train(train, steps=args.warm_steps, batch=32, lr=1e-3)
+    net.train(train, steps=args.warm_steps, batch=32, lr=1e-3, match=not args.warm_no_match)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t1
     print(f"[bench] warm: {len(train)} labels ({label_s:.1f}s), trained in {train_s:.1f}s", file=sys.stderr,
@@ -366,7 +368,7 @@ def bench_warm(args, d, torch, np):
         if t % 200 == 199:
             print(f"[bench] warm: {t + 1} held-out tensors", file=sys.stderr, flush=True)
     return {"workload": "K~U{32..512}, J=64, I_k~U{64..1024}, rank-10 PARAFAC2 + 1% noise; R=10 L=20",
-            "train_tensors": len(train), "train_steps": args.warm_steps, "label_s": round(label_s, 1),
+            "train_tensors": len(train), "train_steps": args.warm_steps, "matched_loss": not args.warm_no_match, "label_s": round(label_s, 1),
             "train_s": round(train_s, 2), "test_tensors": args.warm_test,
             "target": "random start's 300-iteration compressed fitness - 1e-3",
             "iters_random_mean": float(np.mean(its_r)), "iters_warm_mean": float(np.mean(its_w)),

@@ -4,7 +4,9 @@ encoder whose kernels live in libdpar2 (dpar2_warm_*).
 Orchestration only: features, targets, the forward and backward passes, the
 Adam steps and the assembly of starting factors all run in the library's
 kernels, and the labels come from the library's own decompositions; torch
-holds the device buffers and concatenates minibatches.
+holds the device buffers and concatenates minibatches, and the host solves
+the small assignment problems that order each target's components like the
+prediction's (R x R per tensor, scipy) before the loss.
 """
 import dataclasses
 
@@ -90,12 +92,15 @@ class WarmNet:
         b.warm_forward(self.R, [0, tok.shape[0]], tok, self.theta, act, pH, pV, pW)
         return pH[0], pV[0], pW
 
-    def loss(self, samples):
-        """Mean loss over samples (three terms), no parameter update."""
+    def loss(self, samples, match: bool = True):
+        """Mean loss over samples (three terms), no parameter update; match:
+        as in train."""
         import torch
         off, tok, tH, tV, tW = self._batch(samples)
         act, pH, pV, pW = self._buffers(len(samples), tok.shape[0])
         b.warm_forward(self.R, off, tok, self.theta, act, pH, pV, pW)
+        if match:
+            tH, tV, tW = self._match(off, pV, pW, tH, tV, tW)
         gp = torch.empty((len(samples), self.P), dtype=torch.float32, device="cuda")
         grad = torch.empty(self.P, dtype=torch.float32, device="cuda")
         loss = torch.empty((len(samples), 3), dtype=torch.float32, device="cuda")
@@ -109,9 +114,37 @@ class WarmNet:
         return (off, torch.cat([s.tok for s in samples]), torch.stack([s.tH for s in samples]),
                 torch.stack([s.tV for s in samples]), torch.cat([s.tW for s in samples]))
 
-    def train(self, samples, steps: int, batch: int = 16, lr: float = 1e-3, seed: int = 0, log_every: int = 0):
+    def _match(self, off, pV, pW, tH, tV, tW):
+        """Targets with their components put in the prediction's order, per
+        tensor: the assignment of target components to predicted ones that
+        minimises the V~ and W squared errors (weighted as in the loss), an
+        R x R assignment problem per tensor solved on the host."""
+        import torch
+        from scipy.optimize import linear_sum_assignment
+        R, n = self.R, len(off) - 1
+        pv, tv = pV.cpu().numpy(), tV.cpu().numpy()     # n x R x R, column = component
+        pw, tw = pW.cpu().numpy(), tW.cpu().numpy()     # tokens x R
+        perm = np.empty((n, R), dtype=np.int64)
+        for i in range(n):
+            a, c = int(off[i]), int(off[i + 1])
+            cost = ((pv[i][:, :, None] - tv[i][:, None, :]) ** 2).sum(axis=0) / (R * R)
+            cost += ((pw[a:c][:, :, None] - tw[a:c][:, None, :]) ** 2).sum(axis=0) / ((c - a) * R)
+            rows, cols = linear_sum_assignment(cost)
+            perm[i, rows] = cols
+        P = torch.from_numpy(perm).to(tV.device)
+        cols = P[:, None, :].expand(n, R, R)
+        tV2 = torch.gather(tV, 2, cols)
+        tH2 = torch.gather(torch.gather(tH, 2, cols), 1, P[:, :, None].expand(n, R, R))
+        tW2 = torch.gather(tW, 1, torch.from_numpy(np.repeat(perm, np.diff(off), axis=0)).to(tW.device))
+        return tH2.contiguous(), tV2.contiguous(), tW2.contiguous()
+
+    def train(self, samples, steps: int, batch: int = 16, lr: float = 1e-3, seed: int = 0, log_every: int = 0,
+              match: bool = True):
         """Adam on minibatches drawn (without replacement per epoch) from
-        samples; returns the mean loss of each logged step."""
+        samples; returns the mean loss of each logged step.  match: compare
+        each tensor's prediction with its target's components reordered to
+        the closest assignment (the targets' component order is a gauge
+        choice that need not follow from the tokens)."""
         import torch
         rng = np.random.default_rng(seed)
         order, at, hist = rng.permutation(len(samples)), 0, []
@@ -126,6 +159,8 @@ class WarmNet:
             off, tok, tH, tV, tW = self._batch(mb)
             act, pH, pV, pW = self._buffers(len(mb), tok.shape[0])
             b.warm_forward(self.R, off, tok, self.theta, act, pH, pV, pW)
+            if match:
+                tH, tV, tW = self._match(off, pV, pW, tH, tV, tW)
             b.warm_backward(self.R, off, tok, self.theta, act, pH, pV, pW, tH, tV, tW, gp[:len(mb)], grad,
                             loss[:len(mb)])
             self.step += 1
