@@ -48,8 +48,8 @@ struct Schedule {
   std::vector<int32_t> slice_ptr;   // K+1
   std::vector<int32_t> slice_list;  // item indices of each slice
   std::vector<Blk> blk, blk0;
-  std::vector<Chunk> chunks;
-  std::vector<int64_t> seg_blk, seg_blk0, seg_chunk, seg_slice;
+  std::vector<Chunk> chunks, ychunks;
+  std::vector<int64_t> seg_blk, seg_blk0, seg_chunk, seg_ychunk, seg_slice;
   std::vector<int32_t> slice_t;
 };
 
@@ -181,9 +181,12 @@ void build_schedule(const Group& g, Schedule* s) {
   s->blk.clear();
   s->blk0.clear();
   s->chunks.clear();
+  s->ychunks.clear();
   s->seg_blk.assign(1, 0);
   s->seg_blk0.assign(1, 0);
   s->seg_chunk.assign(1, 0);
+  s->seg_ychunk.assign(1, 0);
+  const int64_t ych = stage2_ychunk(K * R, J);
   s->seg_slice.assign(g.k0.begin(), g.k0.end());
   s->slice_t.assign((size_t)K, 0);
   for (int t = 0; t < nt; ++t) {
@@ -195,9 +198,12 @@ void build_schedule(const Group& g, Schedule* s) {
       s->blk0.push_back(Blk{t, (int32_t)b, (int32_t)std::min<int64_t>(rows, b + gpb), 0});
     for (int64_t r = k0 * R; r < (k0 + Kt) * R; r += STAGE2_CHUNK)
       s->chunks.push_back(Chunk{r, std::min<int64_t>((k0 + Kt) * R, r + STAGE2_CHUNK), t, 0});
+    for (int64_t r = k0 * R; r < (k0 + Kt) * R; r += ych)
+      s->ychunks.push_back(Chunk{r, std::min<int64_t>((k0 + Kt) * R, r + ych), t, 0});
     s->seg_blk.push_back((int64_t)s->blk.size());
     s->seg_blk0.push_back((int64_t)s->blk0.size());
     s->seg_chunk.push_back((int64_t)s->chunks.size());
+    s->seg_ychunk.push_back((int64_t)s->ychunks.size());
     for (int64_t k = 0; k < Kt; ++k) s->slice_t[(size_t)(k0 + k)] = t;
   }
 }
@@ -217,15 +223,18 @@ Layout make_layout(const Group& g) {
   y.N = 0;
   y.n_items = 0;
   y.n2 = 0;
+  y.n2y = 0;
   y.nblk = 0;
   y.nblk0 = 0;
   const int gpb = als_slices_per_block(y.R);
+  const int64_t ych = stage2_ychunk(g.k0[(size_t)g.nt] * y.R, y.J);
   for (int t = 0; t < g.nt; ++t) {
     const int64_t* off = g.X[t].row_offsets_host;
     const int64_t Kt = g.X[t].K;
     y.N += off[Kt];
     for (int64_t k = 0; k < Kt; ++k) y.n_items += items_of(off[k + 1] - off[k], item_cap(g));
     y.n2 += (Kt * y.R + STAGE2_CHUNK - 1) / STAGE2_CHUNK;
+    y.n2y += (Kt * y.R + ych - 1) / ych;
     y.nblk += (int)((Kt + gpb - 1) / gpb);
     y.nblk0 += (int)((std::max<int64_t>(Kt, y.J) + gpb - 1) / gpb);
   }
@@ -240,9 +249,11 @@ Layout make_layout(const Group& g) {
   y.blk = take(sizeof(Blk) * (size_t)y.nblk);
   y.blk0 = take(sizeof(Blk) * (size_t)y.nblk0);
   y.chunks = take(sizeof(Chunk) * (size_t)y.n2);
+  y.ychunks = take(sizeof(Chunk) * (size_t)y.n2y);
   y.seg_blk = take(sizeof(int64_t) * (size_t)(nt + 1));
   y.seg_blk0 = take(sizeof(int64_t) * (size_t)(nt + 1));
   y.seg_chunk = take(sizeof(int64_t) * (size_t)(nt + 1));
+  y.seg_ychunk = take(sizeof(int64_t) * (size_t)(nt + 1));
   y.seg_slice = take(sizeof(int64_t) * (size_t)(nt + 1));
   y.slice_t = take(sizeof(int32_t) * (size_t)K);
   y.items = take(sizeof(Item) * (size_t)y.n_items);
@@ -258,7 +269,7 @@ Layout make_layout(const Group& g) {
   y.Phi = take(sizeof(double) * (size_t)(K * L * R));
   y.sig1 = take(sizeof(double) * (size_t)KR);
   y.msgn = take(sizeof(float) * (size_t)KR);
-  y.Y2p = take(sizeof(double) * (size_t)(y.n2 * L2 * J));
+  y.Y2p = take(sizeof(double) * (size_t)(y.n2y * L2 * J));
   y.Y2 = take(sizeof(double) * (size_t)(nt * J * L2));
   y.B2t = take(sizeof(double) * (size_t)(KR * L2));
   y.S2p = take(sizeof(double) * (size_t)(y.n2 * L2 * (L2 + 1) / 2));
@@ -291,9 +302,9 @@ Layout make_layout(const Group& g) {
 
 // Every field of a layout, in declaration order (the graph cache key).
 std::vector<int64_t> layout_key(const Layout& y) {
-  return {y.nt, y.K, y.J, y.N, y.n_items, y.R, y.L, y.L2, y.max_iter, y.q, y.n2, y.nblk, y.nblk0,
-          (int64_t)y.tdesc, (int64_t)y.blk, (int64_t)y.blk0, (int64_t)y.chunks, (int64_t)y.seg_blk,
-          (int64_t)y.seg_blk0, (int64_t)y.seg_chunk, (int64_t)y.seg_slice, (int64_t)y.slice_t, (int64_t)y.ctl,
+  return {y.nt, y.K, y.J, y.N, y.n_items, y.R, y.L, y.L2, y.max_iter, y.q, y.n2, y.n2y, y.nblk, y.nblk0,
+          (int64_t)y.tdesc, (int64_t)y.blk, (int64_t)y.blk0, (int64_t)y.chunks, (int64_t)y.ychunks, (int64_t)y.seg_blk,
+          (int64_t)y.seg_blk0, (int64_t)y.seg_chunk, (int64_t)y.seg_ychunk, (int64_t)y.seg_slice, (int64_t)y.slice_t, (int64_t)y.ctl,
           (int64_t)y.items, (int64_t)y.slice_ptr, (int64_t)y.slice_list, (int64_t)y.partG, (int64_t)y.partP,
           (int64_t)y.partS, (int64_t)y.xnorm2, (int64_t)y.Mt, (int64_t)y.Phi, (int64_t)y.sig1, (int64_t)y.msgn, (int64_t)y.Y2p,
           (int64_t)y.Y2, (int64_t)y.B2t, (int64_t)y.S2p, (int64_t)y.S2, (int64_t)y.U2, (int64_t)y.D,
@@ -513,9 +524,11 @@ void stage_tables(const Group& g, const Layout& y, Staging& sg) {
   put(sch.blk.data(), sizeof(Blk) * sch.blk.size(), y.blk);
   put(sch.blk0.data(), sizeof(Blk) * sch.blk0.size(), y.blk0);
   put(sch.chunks.data(), sizeof(Chunk) * sch.chunks.size(), y.chunks);
+  put(sch.ychunks.data(), sizeof(Chunk) * sch.ychunks.size(), y.ychunks);
   put(sch.seg_blk.data(), sizeof(int64_t) * sch.seg_blk.size(), y.seg_blk);
   put(sch.seg_blk0.data(), sizeof(int64_t) * sch.seg_blk0.size(), y.seg_blk0);
   put(sch.seg_chunk.data(), sizeof(int64_t) * sch.seg_chunk.size(), y.seg_chunk);
+  put(sch.seg_ychunk.data(), sizeof(int64_t) * sch.seg_ychunk.size(), y.seg_ychunk);
   put(sch.seg_slice.data(), sizeof(int64_t) * sch.seg_slice.size(), y.seg_slice);
   put(sch.slice_t.data(), sizeof(int32_t) * sch.slice_t.size(), y.slice_t);
   put(sch.items.data(), sizeof(Item) * sch.items.size(), y.items);

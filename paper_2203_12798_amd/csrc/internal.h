@@ -22,7 +22,15 @@ struct Item {
 
 constexpr int SKETCH_TM = 64;          // rows per tile of the slab pass
 constexpr int MAX_CHUNK_ROWS = 16384;  // longest item (rows)
-constexpr int STAGE2_CHUNK = 128;      // rows of M^T per second-stage block
+constexpr int STAGE2_CHUNK = 256;      // rows of M^T per second-stage block (one per thread)
+// rows of M^T per block of the second-stage sketch Y2 = M Omega_2 (one wave
+// per 64 columns): about 8192 waves over the group's K R rows, 64 to 2048
+// rows each, a multiple of 64
+inline int64_t stage2_ychunk(int64_t KR, int64_t J) {
+  int64_t r = (KR * ((J + 63) / 64) + 8191) / 8192;
+  r = (r + 63) / 64 * 64;
+  return r < 64 ? 64 : (r > 2048 ? 2048 : r);
+}
 constexpr int ALS_THREADS = 256;
 
 // A group: tensors decomposed together, sharing J, R, L, L2, the dtype and the
@@ -60,9 +68,10 @@ struct Layout {
   int64_t K, J, N, n_items;
   int R, L, L2, max_iter, q;
   int64_t n2;             // second-stage row chunks of M^T
+  int64_t n2y;            // row chunks of the second-stage sketch (STAGE2_YCHUNK rows)
   int nblk, nblk0;        // blocks of the iteration / begin per-slice kernels
   // tables (device)
-  size_t tdesc, blk, blk0, chunks, seg_blk, seg_blk0, seg_chunk, seg_slice, slice_t;
+  size_t tdesc, blk, blk0, chunks, ychunks, seg_blk, seg_blk0, seg_chunk, seg_ychunk, seg_slice, slice_t;
   // first stage (global slice index)
   size_t ctl, items, slice_ptr, slice_list;
   size_t partG, partP, partS;

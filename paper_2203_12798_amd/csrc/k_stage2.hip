@@ -10,60 +10,79 @@
 
 namespace dpar2 {
 
-// partial Y2 over one chunk of rows of M^T (all of one tensor):
-// Y2p[c][j][l] = sum_rows Mt[row][j] * Omega2[row][l]
-__global__ __launch_bounds__(256) void k_s2_y(int J, int L2, int R, const TDesc* __restrict__ td,
-                                              const Chunk* __restrict__ chunks, const double* __restrict__ Mt,
-                                              double* __restrict__ Y2p) {
-  __shared__ double sM[64 * 64];
-  __shared__ float sO[64 * 32];
-  const int c = blockIdx.x, jb = blockIdx.y, tid = threadIdx.x;
-  const int jl = tid & 63, l0 = tid >> 6;
-  const int j = jb * 64 + jl;
-  double acc[8];
-  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-  const Chunk ch = chunks[c];
-  const int64_t r0 = ch.r0, r1 = ch.r1;
-  // Omega_2 of the chunk's tensor, indexed by its local row of M^T
-  const float* __restrict__ om2 = td[ch.t].om2 - (size_t)td[ch.t].k0 * R * L2;
-  for (int64_t rb = r0; rb < r1; rb += 64) {
-    const int nr = (int)((r1 - rb) < 64 ? (r1 - rb) : 64);
-    __syncthreads();
-    // staging loads are unrolled with clamped indices so they issue together
-    {
-      double mv[16];
-      float ov[8];
+// Omega_2 as FP64, one row of L2 values per row of M^T (global row order),
+// into `dst` (the B2t buffer, free until the projection writes it)
+__global__ __launch_bounds__(256) void k_om2d(int L2, int R, int64_t rows, const TDesc* __restrict__ td,
+                                              const int32_t* __restrict__ slice_t, double* __restrict__ dst) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= rows * L2) return;
+  const int64_t row = e / L2;
+  const TDesc& d = td[slice_t[row / R]];
+  dst[e] = (double)d.om2[(row - (int64_t)d.k0 * R) * L2 + e % L2];
+}
+
+// partial Y2 over one chunk of rows of M^T (all of one tensor), one wave
+// per 64 columns, one lane per column j (each row of M^T read once,
+// coalesced), the chunk's rows of Omega_2 (FP64) through scalar loads, the
+// rows in order: Y2p[c][j][l] = sum_rows Mt[row][j] Omega2[row][l]
+template <int L2>
+__global__ __launch_bounds__(64) void k_s2_y(int J, const Chunk* __restrict__ ychunks, const double* __restrict__ Mt,
+                                             const double* __restrict__ om2d, double* __restrict__ Y2p) {
+  const int c = blockIdx.x;
+  const int j = blockIdx.y * 64 + threadIdx.x;
+  const Chunk ch = ychunks[c];
+  const int jc = j < J ? j : 0;   // lanes past J read column 0 and store nothing
+  double acc[L2];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int e = tid + 256 * u, rr = e / 64, jj = e % 64;
-        const bool ok = rr < nr && jb * 64 + jj < J;
-        const double x = Mt[ok ? (size_t)(rb + rr) * J + jb * 64 + jj : 0];
-        mv[u] = ok ? x : 0.0;
-      }
+  for (int l = 0; l < L2; ++l) acc[l] = 0.0;
+  const double* __restrict__ mp = Mt + jc;
+  int64_t r = ch.r0;
+  for (; r + 8 <= ch.r1; r += 8) {
+    double m[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = tid + 256 * u, rr = e / 32, ll = e % 32;
-        const bool ok = rr < nr && ll < L2;
-        const float x = om2[(ok ? (size_t)(rb + rr) : (size_t)r0) * L2 + (ok ? ll : 0)];
-        ov[u] = ok ? x : 0.f;
-      }
+    for (int u = 0; u < 8; ++u) m[u] = mp[(size_t)(r + u) * J];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) sM[tid + 256 * u] = mv[u];
+    for (int u = 0; u < 8; ++u) {
+      const double* __restrict__ o = om2d + (size_t)(r + u) * L2;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) sO[tid + 256 * u] = ov[u];
-    }
-    __syncthreads();
-    for (int rr = 0; rr < nr; ++rr) {
-      const double m = sM[rr * 64 + jl];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) acc[q] += (double)sO[rr * 32 + l0 + 4 * q] * m;
+      for (int l = 0; l < L2; ++l) acc[l] = fma(m[u], o[l], acc[l]);
     }
   }
-  if (j < J)
-    for (int q = 0; q < 8; ++q) {
-      const int l = l0 + 4 * q;
-      if (l < L2) Y2p[((size_t)c * J + j) * L2 + l] = acc[q];
-    }
+  for (; r < ch.r1; ++r) {
+    const double m = mp[(size_t)r * J];
+    const double* __restrict__ o = om2d + (size_t)r * L2;
+#pragma unroll
+    for (int l = 0; l < L2; ++l) acc[l] = fma(m, o[l], acc[l]);
+  }
+  if (j < J) {
+    double* __restrict__ out = Y2p + ((size_t)c * J + j) * L2;
+#pragma unroll
+    for (int l = 0; l < L2; ++l) out[l] = acc[l];
+  }
+}
+
+// out[t * ostride + e] = sum over b of part[b * stride + e], b over [0, n1)
+// (n1 >= 0) or over [seg[t], seg[t+1]): one thread per e (the partials of
+// consecutive e are read together), the b in order into eight accumulators
+// (b mod 8) combined pairwise.  For wide sums over few partials.
+__global__ __launch_bounds__(256) void k_colsum(const int64_t* __restrict__ seg, int64_t n1, int64_t stride,
+                                                int64_t width, const double* __restrict__ part,
+                                                double* __restrict__ out, int64_t ostride) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int t = blockIdx.y;
+  if (e >= width) return;
+  const int64_t b0 = n1 >= 0 ? 0 : seg[t], nb = n1 >= 0 ? n1 : seg[t + 1] - b0;
+  const double* __restrict__ p = part + (size_t)b0 * stride + e;
+  double sv[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) sv[u] = 0.0;
+  int64_t b = 0;
+  for (; b + 8 <= nb; b += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sv[u] += p[(size_t)(b + u) * stride];
+  }
+  for (int u = 0; b < nb; ++b, ++u) sv[u] += p[(size_t)b * stride];
+  out[(size_t)t * ostride + e] = ((sv[0] + sv[1]) + (sv[2] + sv[3])) + ((sv[4] + sv[5]) + (sv[6] + sv[7]));
 }
 
 // out[t * ostride + e] = sum over b in [seg[t], seg[t+1]) of part[b * stride + e]:
@@ -91,81 +110,103 @@ __global__ __launch_bounds__(256) void k_segsum(const int64_t* __restrict__ seg,
 }
 
 // B2^T rows of one chunk: B2t[row][l] = sum_j Mt[row][j] Q2[j][l] (Q2 of the
-// chunk's tensor), plus the chunk's partial of B2 B2^T.
-__global__ __launch_bounds__(256) void k_s2_b(int J, int L2, const Chunk* __restrict__ chunks,
-                                              const double* __restrict__ Mt, const double* __restrict__ Q2all,
-                                              double* __restrict__ B2t, double* __restrict__ S2p) {
-  __shared__ double sM[64 * 65];
-  __shared__ double sQ[64 * 32];
-  __shared__ double sB[64 * 33];
-  const int c = blockIdx.x, tid = threadIdx.x;
-  const int rl = tid >> 2, lg = tid & 3;
-  const int npairs = L2 * (L2 + 1) / 2;
-  double sacc[3] = {0.0, 0.0, 0.0};
-  const Chunk ch = chunks[c];
-  const int64_t r0 = ch.r0, r1 = ch.r1;
+// chunk's tensor, FP64 J x L2, its rows through scalar loads), one lane per
+// row of M^T, j in order; then the chunk's partial of B2 B2^T (upper
+// triangle, pairs a <= b row-major), its rows through LDS 64 at a time.
+template <int L2>
+__global__ __launch_bounds__(256) void k_s2_b(int J, const Chunk* __restrict__ chunks, const double* __restrict__ Mt,
+                                              const double* __restrict__ Q2all, double* __restrict__ B2t,
+                                              double* __restrict__ S2p) {
+  constexpr int LP = L2 + 1, NPAIR = L2 * (L2 + 1) / 2, NQ = (NPAIR + 255) / 256;
+  __shared__ double sB[64 * LP];
+  const int tid = threadIdx.x;
+  const Chunk ch = chunks[blockIdx.x];
+  const int64_t row = ch.r0 + tid;
+  const bool ok = row < ch.r1;
+  const double* __restrict__ mrow = Mt + (size_t)(ok ? row : ch.r0) * J;
   const double* __restrict__ Q2 = Q2all + (size_t)ch.t * J * L2;
-  for (int64_t rb = r0; rb < r1; rb += 64) {
-    const int nr = (int)((r1 - rb) < 64 ? (r1 - rb) : 64);
-    double acc[8];
-    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-    for (int jc = 0; jc < J; jc += 64) {
-      __syncthreads();
-      {
-        double mv[16], qv[8];
+  double acc[L2];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          const int e = tid + 256 * u, rr = e / 64, jj = e % 64;
-          const bool ok = rr < nr && jc + jj < J;
-          const double x = Mt[ok ? (size_t)(rb + rr) * J + jc + jj : 0];
-          mv[u] = ok ? x : 0.0;
-        }
+  for (int l = 0; l < L2; ++l) acc[l] = 0.0;
+  int j = 0;
+  for (; j + 8 <= J; j += 8) {
+    double m[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int e = tid + 256 * u, jj = e / 32, ll = e % 32;
-          const bool ok = jc + jj < J && ll < L2;
-          const double x = Q2[ok ? (size_t)(jc + jj) * L2 + ll : 0];
-          qv[u] = ok ? x : 0.0;
-        }
+    for (int u = 0; u < 8; ++u) m[u] = mrow[j + u];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          const int e = tid + 256 * u;
-          sM[(e / 64) * 65 + e % 64] = mv[u];
-        }
+    for (int u = 0; u < 8; ++u) {
+      const double* __restrict__ q = Q2 + (size_t)(j + u) * L2;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) sQ[tid + 256 * u] = qv[u];
-      }
-      __syncthreads();
-      for (int jj = 0; jj < 64; ++jj) {
-        const double m = sM[rl * 65 + jj];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) acc[q] += m * sQ[jj * 32 + lg + 4 * q];
-      }
-    }
-    __syncthreads();
-    for (int q = 0; q < 8; ++q) {
-      const int l = lg + 4 * q;
-      if (l < L2) {
-        sB[rl * 33 + l] = (rl < nr) ? acc[q] : 0.0;
-        if (rl < nr) B2t[(size_t)(rb + rl) * L2 + l] = acc[q];
-      }
-    }
-    __syncthreads();
-    for (int q = 0; q < 3; ++q) {
-      const int pi = tid + 256 * q;
-      if (pi < npairs) {
-        int a = 0, rem = pi;
-        while (rem >= L2 - a) { rem -= L2 - a; ++a; }
-        const int b = a + rem;
-        double s = 0.0;
-        for (int rr = 0; rr < nr; ++rr) s += sB[rr * 33 + a] * sB[rr * 33 + b];
-        sacc[q] += s;
-      }
+      for (int l = 0; l < L2; ++l) acc[l] = fma(m[u], q[l], acc[l]);
     }
   }
-  for (int q = 0; q < 3; ++q) {
+  for (; j < J; ++j) {
+    const double m = mrow[j];
+    const double* __restrict__ q = Q2 + (size_t)j * L2;
+#pragma unroll
+    for (int l = 0; l < L2; ++l) acc[l] = fma(m, q[l], acc[l]);
+  }
+  if (ok) {
+#pragma unroll
+    for (int l = 0; l < L2; ++l) B2t[(size_t)row * L2 + l] = acc[l];
+  }
+  // pair indices of this thread
+  int pa[NQ], pb[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    int pi = tid + 256 * q, a = 0;
+    if (pi >= NPAIR) pi = 0;
+    while (pi >= L2 - a) {
+      pi -= L2 - a;
+      ++a;
+    }
+    pa[q] = a;
+    pb[q] = a + pi;
+  }
+  double sacc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) sacc[q] = 0.0;
+  for (int w = 0; w < 4; ++w) {
+    __syncthreads();
+    if ((tid >> 6) == w) {
+#pragma unroll
+      for (int l = 0; l < L2; ++l) sB[(tid & 63) * LP + l] = ok ? acc[l] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      double s = 0.0;
+      for (int rr = 0; rr < 64; ++rr) s = fma(sB[rr * LP + pa[q]], sB[rr * LP + pb[q]], s);
+      sacc[q] += s;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
     const int pi = tid + 256 * q;
-    if (pi < npairs) S2p[(size_t)c * npairs + pi] = sacc[q];
+    if (pi < NPAIR) S2p[(size_t)blockIdx.x * NPAIR + pi] = sacc[q];
+  }
+}
+
+// launches of k_s2_y and k_s2_b for the group's L2
+static hipError_t s2_stream_launch(int which, int L2, int J, int64_t nchunks, const Chunk* chunks,
+                                   const double* Mt, const double* aux, double* out1, double* out2, hipStream_t s) {
+  switch (L2) {
+#define DPAR2_S2(N_)                                                                                          \
+  case N_:                                                                                                    \
+    if (which == 0)                                                                                           \
+      hipLaunchKernelGGL(k_s2_y<N_>, dim3((unsigned)nchunks, (unsigned)((J + 63) / 64)), dim3(64), 0, s,    \
+                         J, chunks, Mt, aux, out1);                                                           \
+    else                                                                                                      \
+      hipLaunchKernelGGL(k_s2_b<N_>, dim3((unsigned)nchunks), dim3(256), 0, s, J, chunks, Mt, aux, out1,    \
+                         out2);                                                                               \
+    return hipGetLastError();
+    DPAR2_S2(1) DPAR2_S2(2) DPAR2_S2(3) DPAR2_S2(4) DPAR2_S2(5) DPAR2_S2(6) DPAR2_S2(7) DPAR2_S2(8)
+    DPAR2_S2(9) DPAR2_S2(10) DPAR2_S2(11) DPAR2_S2(12) DPAR2_S2(13) DPAR2_S2(14) DPAR2_S2(15) DPAR2_S2(16)
+    DPAR2_S2(17) DPAR2_S2(18) DPAR2_S2(19) DPAR2_S2(20) DPAR2_S2(21) DPAR2_S2(22) DPAR2_S2(23) DPAR2_S2(24)
+    DPAR2_S2(25) DPAR2_S2(26) DPAR2_S2(27) DPAR2_S2(28) DPAR2_S2(29) DPAR2_S2(30) DPAR2_S2(31) DPAR2_S2(32)
+#undef DPAR2_S2
+    default:
+      return hipErrorInvalidValue;
   }
 }
 
@@ -254,6 +295,9 @@ hipError_t launch_stage2(const Layout& lay, char* ws, hipStream_t s) {
   Ctl* ctl = reinterpret_cast<Ctl*>(ws + lay.ctl);
   const TDesc* td = reinterpret_cast<const TDesc*>(ws + lay.tdesc);
   const Chunk* chunks = reinterpret_cast<const Chunk*>(ws + lay.chunks);
+  const Chunk* ychunks = reinterpret_cast<const Chunk*>(ws + lay.ychunks);
+  const int64_t* seg_ychunk = reinterpret_cast<const int64_t*>(ws + lay.seg_ychunk);
+  const int32_t* slice_t = reinterpret_cast<const int32_t*>(ws + lay.slice_t);
   const int64_t* seg_chunk = reinterpret_cast<const int64_t*>(ws + lay.seg_chunk);
   const int64_t* seg_slice = reinterpret_cast<const int64_t*>(ws + lay.seg_slice);
   double* Mt = reinterpret_cast<double*>(ws + lay.Mt);
@@ -272,13 +316,23 @@ hipError_t launch_stage2(const Layout& lay, char* ws, hipStream_t s) {
   const int RR = R * R, npairs = L2 * (L2 + 1) / 2;
   const int64_t cstride = sizeof(Ctl) / sizeof(double);
   hipError_t e;
-  hipLaunchKernelGGL(k_s2_y, dim3((unsigned)lay.n2, (unsigned)((J + 63) / 64)), dim3(256), 0, s, J, L2, R,
-                     td, chunks, Mt, Y2p);
-  if ((e = launch_segsum(nt, seg_chunk, lay.n2, (int64_t)J * L2, (int64_t)J * L2, Y2p, Y2, (int64_t)J * L2, s)) !=
-      hipSuccess)
-    return e;
+  // Omega_2 in FP64 (in the B2t buffer until the projection), Y2 = M Omega_2
+  // per chunk, summed per tensor
+  const int64_t KR = lay.K * R;
+  hipLaunchKernelGGL(k_om2d, dim3((unsigned)((KR * L2 + 255) / 256)), dim3(256), 0, s, L2, R, KR, td, slice_t, B2t);
+  if ((e = s2_stream_launch(0, L2, J, lay.n2y, ychunks, Mt, B2t, Y2p, nullptr, s)) != hipSuccess) return e;
+  {
+    // wide Y2: one thread per entry over the partials; narrow: one block per
+    // entry, its threads over the partials
+    const int64_t width = (int64_t)J * L2;
+    if (width >= 8192)
+      hipLaunchKernelGGL(k_colsum, dim3((unsigned)((width + 255) / 256), (unsigned)nt), dim3(256), 0, s, seg_ychunk,
+                         nt == 1 ? lay.n2y : (int64_t)-1, width, width, Y2p, Y2, width);
+    else if ((e = launch_segsum(nt, seg_ychunk, lay.n2y, width, width, Y2p, Y2, width, s)) != hipSuccess)
+      return e;
+  }
   if ((e = s2_small(nt, L2, 0, J, R, Y2, nullptr, D, E, U2s, small, ctl, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_s2_b, dim3((unsigned)lay.n2), dim3(256), 0, s, J, L2, chunks, Mt, Y2, B2t, S2p);
+  if ((e = s2_stream_launch(1, L2, J, lay.n2, chunks, Mt, Y2, B2t, S2p, s)) != hipSuccess) return e;
   if ((e = launch_segsum(nt, seg_chunk, lay.n2, npairs, npairs, S2p, S2, npairs, s)) != hipSuccess) return e;
   // sum_k ||X_k||^2 of each tensor into its control block
   if ((e = launch_segsum(nt, seg_slice, lay.K, 1, 1, xnorm2, &ctl->xnorm2, cstride, s)) != hipSuccess) return e;
