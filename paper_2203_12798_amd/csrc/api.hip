@@ -275,6 +275,7 @@ Layout make_layout(const Group& g) {
   y.S2p = take(sizeof(double) * (size_t)(y.n2 * L2 * (L2 + 1) / 2));
   y.S2 = take(sizeof(double) * (size_t)(nt * L2 * (L2 + 1) / 2));
   y.U2 = take(sizeof(double) * (size_t)(nt * L2 * R));
+  y.s2s = take(sizeof(double) * (size_t)s2_scratch_doubles(nt, J, L2, R));
   y.D = take(sizeof(double) * (size_t)(nt * J * R));
   y.E = take(sizeof(double) * (size_t)(nt * R));
   y.F = take(sizeof(double) * (size_t)(KR * R));
@@ -307,7 +308,7 @@ std::vector<int64_t> layout_key(const Layout& y) {
           (int64_t)y.seg_blk0, (int64_t)y.seg_chunk, (int64_t)y.seg_ychunk, (int64_t)y.seg_slice, (int64_t)y.slice_t, (int64_t)y.ctl,
           (int64_t)y.items, (int64_t)y.slice_ptr, (int64_t)y.slice_list, (int64_t)y.partG, (int64_t)y.partP,
           (int64_t)y.partS, (int64_t)y.xnorm2, (int64_t)y.Mt, (int64_t)y.Phi, (int64_t)y.sig1, (int64_t)y.msgn, (int64_t)y.Y2p,
-          (int64_t)y.Y2, (int64_t)y.B2t, (int64_t)y.S2p, (int64_t)y.S2, (int64_t)y.U2, (int64_t)y.D,
+          (int64_t)y.Y2, (int64_t)y.B2t, (int64_t)y.S2p, (int64_t)y.S2, (int64_t)y.U2, (int64_t)y.s2s, (int64_t)y.D,
           (int64_t)y.E, (int64_t)y.F, (int64_t)y.FtFp, (int64_t)y.Psi, (int64_t)y.Pw, (int64_t)y.Mk,
           (int64_t)y.small, (int64_t)y.partA, (int64_t)y.partB, (int64_t)y.partC, (int64_t)y.partBegin,
           (int64_t)y.red, (int64_t)y.fitp, (int64_t)y.trace, (int64_t)y.om1, (int64_t)y.omq, (int64_t)y.ybuf,

@@ -23,6 +23,16 @@ struct Item {
 constexpr int SKETCH_TM = 64;          // rows per tile of the slab pass
 constexpr int MAX_CHUNK_ROWS = 16384;  // longest item (rows)
 constexpr int STAGE2_CHUNK = 256;      // rows of M^T per second-stage block (one per thread)
+// J from which the second stage's J-long steps (Gram and whitening of Y2,
+// D = Q2 U2_R, D^T D) run on one wave per 64 rows instead of one per tensor
+constexpr int S2_WIDE_J = 512;
+// doubles of second-stage scratch for that form (nt tensors, sketch width
+// L2, rank R): the 64-row partials, the summed Gram and Wh / U2_R
+inline int64_t s2_scratch_doubles(int64_t nt, int64_t J, int64_t L2, int64_t R) {
+  if (J < S2_WIDE_J) return 0;
+  const int64_t M = L2 > R ? L2 : R;
+  return nt * (((J + 63) / 64) * M * M + 2 * L2 * L2);
+}
 // rows of M^T per block of the second-stage sketch Y2 = M Omega_2 (one wave
 // per 64 columns): about 8192 waves over the group's K R rows, 64 to 2048
 // rows each, a multiple of 64
@@ -77,7 +87,7 @@ struct Layout {
   size_t partG, partP, partS;
   size_t xnorm2, Mt, Phi, sig1, msgn;
   // second stage (per chunk / per tensor)
-  size_t Y2p, Y2, B2t, S2p, S2, U2;
+  size_t Y2p, Y2, B2t, S2p, S2, U2, s2s;   // s2s: scratch of the long-J second stage
   size_t D, E, F, FtFp;
   // iteration
   size_t Psi, Pw, Mk, small, partA, partB, partC, partBegin, red, fitp, trace, om1, omq;

@@ -30,24 +30,25 @@ hipError_t slice_dispatch_1(int L, int64_t K, int J, int R, const int32_t* slice
 }
 
 hipError_t s2_small_dispatch_1(int nt, int L2, int which, int J, int R, double* Y2, const double* S2,
-                                 double* D, double* E, double* U2s, double* small, Ctl* ctl, hipStream_t s) {
+                                 double* D, double* E, double* U2s, double* small, Ctl* ctl, double* scratch,
+                                 hipStream_t s) {
   switch (L2) {
-    case 1: return s2_small_launch<1>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
-    case 2: return s2_small_launch<2>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
-    case 3: return s2_small_launch<3>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
-    case 4: return s2_small_launch<4>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
-    case 5: return s2_small_launch<5>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
-    case 6: return s2_small_launch<6>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
-    case 7: return s2_small_launch<7>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
-    case 8: return s2_small_launch<8>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
-    case 9: return s2_small_launch<9>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
-    case 10: return s2_small_launch<10>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
-    case 11: return s2_small_launch<11>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
-    case 12: return s2_small_launch<12>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
-    case 13: return s2_small_launch<13>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
-    case 14: return s2_small_launch<14>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
-    case 15: return s2_small_launch<15>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
-    case 16: return s2_small_launch<16>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
+    case 1: return s2_small_launch<1>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+    case 2: return s2_small_launch<2>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+    case 3: return s2_small_launch<3>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+    case 4: return s2_small_launch<4>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+    case 5: return s2_small_launch<5>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+    case 6: return s2_small_launch<6>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+    case 7: return s2_small_launch<7>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+    case 8: return s2_small_launch<8>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+    case 9: return s2_small_launch<9>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+    case 10: return s2_small_launch<10>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+    case 11: return s2_small_launch<11>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+    case 12: return s2_small_launch<12>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+    case 13: return s2_small_launch<13>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+    case 14: return s2_small_launch<14>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+    case 15: return s2_small_launch<15>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+    case 16: return s2_small_launch<16>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
     default: return hipErrorInvalidValue;
   }
 }

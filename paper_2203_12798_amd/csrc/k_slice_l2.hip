@@ -30,24 +30,25 @@ hipError_t slice_dispatch_2(int L, int64_t K, int J, int R, const int32_t* slice
 }
 
 hipError_t s2_small_dispatch_2(int nt, int L2, int which, int J, int R, double* Y2, const double* S2,
-                                 double* D, double* E, double* U2s, double* small, Ctl* ctl, hipStream_t s) {
+                                 double* D, double* E, double* U2s, double* small, Ctl* ctl, double* scratch,
+                                 hipStream_t s) {
   switch (L2) {
-    case 17: return s2_small_launch<17>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
-    case 18: return s2_small_launch<18>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
-    case 19: return s2_small_launch<19>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
-    case 20: return s2_small_launch<20>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
-    case 21: return s2_small_launch<21>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
-    case 22: return s2_small_launch<22>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
-    case 23: return s2_small_launch<23>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
-    case 24: return s2_small_launch<24>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
-    case 25: return s2_small_launch<25>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
-    case 26: return s2_small_launch<26>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
-    case 27: return s2_small_launch<27>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
-    case 28: return s2_small_launch<28>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
-    case 29: return s2_small_launch<29>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
-    case 30: return s2_small_launch<30>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
-    case 31: return s2_small_launch<31>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
-    case 32: return s2_small_launch<32>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
+    case 17: return s2_small_launch<17>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+    case 18: return s2_small_launch<18>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+    case 19: return s2_small_launch<19>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+    case 20: return s2_small_launch<20>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+    case 21: return s2_small_launch<21>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+    case 22: return s2_small_launch<22>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+    case 23: return s2_small_launch<23>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+    case 24: return s2_small_launch<24>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+    case 25: return s2_small_launch<25>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+    case 26: return s2_small_launch<26>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+    case 27: return s2_small_launch<27>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+    case 28: return s2_small_launch<28>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+    case 29: return s2_small_launch<29>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+    case 30: return s2_small_launch<30>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+    case 31: return s2_small_launch<31>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+    case 32: return s2_small_launch<32>(nt, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -220,16 +220,18 @@ hipError_t launch_segsum(int nt, const int64_t* seg, int64_t n1, int64_t stride,
 }
 
 hipError_t s2_small_dispatch_1(int nt, int L2, int which, int J, int R, double* Y2, const double* S2,
-                               double* D, double* E, double* U2s, double* small, Ctl* ctl, hipStream_t s);
+                               double* D, double* E, double* U2s, double* small, Ctl* ctl, double* scratch,
+                               hipStream_t s);
 hipError_t s2_small_dispatch_2(int nt, int L2, int which, int J, int R, double* Y2, const double* S2,
-                               double* D, double* E, double* U2s, double* small, Ctl* ctl, hipStream_t s);
+                               double* D, double* E, double* U2s, double* small, Ctl* ctl, double* scratch,
+                               hipStream_t s);
 
 // orthonormalisation of Y2 (which = 0) or the small SVD and D, E (which = 1),
 // one block per tensor
 static hipError_t s2_small(int nt, int L2, int which, int J, int R, double* Y2, const double* S2, double* D,
-                           double* E, double* U2s, double* small, Ctl* ctl, hipStream_t s) {
-  if (L2 <= 16) return s2_small_dispatch_1(nt, L2, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
-  return s2_small_dispatch_2(nt, L2, which, J, R, Y2, S2, D, E, U2s, small, ctl, s);
+                           double* E, double* U2s, double* small, Ctl* ctl, double* scratch, hipStream_t s) {
+  if (L2 <= 16) return s2_small_dispatch_1(nt, L2, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+  return s2_small_dispatch_2(nt, L2, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
 }
 
 // F = B2^T (U2_R E^{-1}) over one chunk (U2 of the chunk's tensor) and the
@@ -307,6 +309,7 @@ hipError_t launch_stage2(const Layout& lay, char* ws, hipStream_t s) {
   double* S2p = reinterpret_cast<double*>(ws + lay.S2p);
   double* S2 = reinterpret_cast<double*>(ws + lay.S2);
   double* U2s = reinterpret_cast<double*>(ws + lay.U2);
+  double* s2s = reinterpret_cast<double*>(ws + lay.s2s);
   double* D = reinterpret_cast<double*>(ws + lay.D);
   double* E = reinterpret_cast<double*>(ws + lay.E);
   double* F = reinterpret_cast<double*>(ws + lay.F);
@@ -331,12 +334,12 @@ hipError_t launch_stage2(const Layout& lay, char* ws, hipStream_t s) {
     else if ((e = launch_segsum(nt, seg_ychunk, lay.n2y, width, width, Y2p, Y2, width, s)) != hipSuccess)
       return e;
   }
-  if ((e = s2_small(nt, L2, 0, J, R, Y2, nullptr, D, E, U2s, small, ctl, s)) != hipSuccess) return e;
+  if ((e = s2_small(nt, L2, 0, J, R, Y2, nullptr, D, E, U2s, small, ctl, s2s, s)) != hipSuccess) return e;
   if ((e = s2_stream_launch(1, L2, J, lay.n2, chunks, Mt, Y2, B2t, S2p, s)) != hipSuccess) return e;
   if ((e = launch_segsum(nt, seg_chunk, lay.n2, npairs, npairs, S2p, S2, npairs, s)) != hipSuccess) return e;
   // sum_k ||X_k||^2 of each tensor into its control block
   if ((e = launch_segsum(nt, seg_slice, lay.K, 1, 1, xnorm2, &ctl->xnorm2, cstride, s)) != hipSuccess) return e;
-  if ((e = s2_small(nt, L2, 1, J, R, Y2, S2, D, E, U2s, small, ctl, s)) != hipSuccess) return e;
+  if ((e = s2_small(nt, L2, 1, J, R, Y2, S2, D, E, U2s, small, ctl, s2s, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_s2_f, dim3((unsigned)lay.n2), dim3(256), 0, s, L2, R, chunks, B2t, U2s, F, FtFp);
   if ((e = launch_segsum(nt, seg_chunk, lay.n2, RR, RR, FtFp, small + SM_FTF * RR, (int64_t)SM_COUNT * RR, s)) !=
       hipSuccess)

@@ -154,6 +154,14 @@ def c4_rank20(seed=41):
     return synth.parafac2(rows, 128, 20, seed, noise_abs=0.05)
 
 
+def rank20_long_j(seed=520):
+    """Rank 20 at J = 520 (the second stage's J-long steps on one wave per
+    64 rows, the wide slab pass at L = 30): K=12, I_k in [60, 200],
+    N(0, 0.02^2) noise, R=20, L=30."""
+    rows = synth.uniform_rows(12, 60, 200, seed)
+    return synth.parafac2(rows, 520, 20, seed, noise_abs=0.02)
+
+
 def rank_r(R):
     """Rank-R data for the rank instantiations R = 12 and 28: K=20, J=48,
     I_k in [40, 160], N(0, 0.02^2) noise."""
@@ -169,6 +177,7 @@ CASES = {
     "stock_like_K120": (lambda: synth.stock_like(K=120), 10, 20, 32),
     "outlier_tile": (outlier_tile, 5, 15, 40),
     "rank20_J128": (c4_rank20, 20, 30, 30),
+    "rank20_J520": (rank20_long_j, 20, 30, 30),
     "rank12_J48": (rank_r(12), 12, 22, 20),
     "rank28_J48": (rank_r(28), 28, 32, 20),
 }

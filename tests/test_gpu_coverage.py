@@ -14,7 +14,8 @@ case), and per-row checks next to the Frobenius ones:
     rows);
   * rank 20 with L = 30 on a J = 128 tensor (the batching form's largest rank
     and widest J bucket; k_als_A<20>, k_slice_fin<30>, the second stage at
-    L2 = 30);
+    L2 = 30), and on a J = 520 tensor (the wide slab pass at L = 30 and the
+    second stage's J-long steps spread over 64-row waves);
   * float32 slabs with 128 < J <= 256 (the FP64 matrix-core Gram and
     projection), with 4-element and scalar loads;
   * the rank instantiations R = 12 (L = 22) and R = 28 (L = 32, four

@@ -70,3 +70,26 @@ def test_wide_low_precision_matches_oracle_on_decoded(kind, J, q):
     _check_factors(g, ref)
     assert abs(g["rep"]["fit_true"] - ref.fit) < 1e-7
     assert rel(g["U"], np.concatenate(ref.U, axis=0)) < 1e-5
+
+
+def test_long_j_second_stage_rank_deficient_matches_oracle():
+    """The second stage's J-long steps on one wave per 64 rows (J >= 512) on
+    a noise-free rank-3 tensor at J = 600, whose M has rank 3 < L2 = 8 up to
+    the float32 rounding of the slab (both whitening passes of Y2 take the
+    eigen form, as do the slices' own sketches): compression, error trace,
+    factors and fitness against the oracle at the usual bounds.  (The seed
+    gives an error trace about as sensitive to the compression as the other
+    parity cases: a 1e-7 relative change of D and F moves it by at most 4e-7
+    over 30 iterations in the oracle; some draws of this shape amplify it a
+    hundredfold, beyond what a 1e-6 bound can test.)  Rank 20 with L = 30 at
+    J = 520 is a bounded case of test_gpu_coverage."""
+    X, R, L = _case(30, 600, 3, 40, 160, seed=601, noise=0.0), 3, 8
+    iters = 30
+    om1, om2 = synth.omegas(X.J, L, X.K * R)
+    H0, V0, W0 = synth.init_factors(X.J, X.K, R)
+    ref = O.dpar2(X.slab, X.offsets, R, om1, om2, H0, V0, W0, iters)
+    g = _run_gpu(X, R, L, L, iters, om1, om2, H0, V0, W0)
+    _check_compression(X, R, g, ref)
+    _check_errors(g, ref)
+    _check_factors(g, ref)
+    assert abs(g["rep"]["fit_true"] - ref.fit) < 1e-7
