@@ -870,9 +870,11 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if (tr is None or wide) else tr["bytes_per_launch"],
-                "kernel": ("k_wide_y + k_wide_p (slab pass in 128-column chunks: FP32 MFMA sketch, exact int8 "
-                           "MFMA Gram and projection; the slab is read twice)") if wide else
-                          "k_sketch_q (slab pass: sketch from three-piece bf16 MFMA products, exact int8 MFMA Gram and projection)",
+                "kernel": ("k_wide_y + k_wide_p (slab pass in 128-column chunks: FP32 MFMA sketch, Gram and "
+                           "projection of the 22-bit per-tile fixed point as exact int8 MFMA digit products; the slab "
+                           "is read twice)") if wide else
+                          ("k_sketch_q (slab pass: sketch from three-piece bf16 MFMA products, Gram and projection of "
+                           "the 22-bit per-tile fixed point as exact int8 MFMA digit products)"),
                 "kernel_ms": round(sk_ms, 4), "algorithmic_bytes": int(alg_bytes),
                 "timed_launches": launches}
     sketch_tf = alg_flops / (sk_ms / 1e3) / 1e12
@@ -906,7 +908,7 @@ def main():
                         "int8_mfma_frac_of_peak": round(int8_ops / (sk_ms / 1e3) / 1e12 / INT8_MFMA_PEAK_TOPS, 4),
                         "note": "useful flops 4NJL+2NL^2 of the float32 method against the FP32 matrix-core peak; the "
                                 "pass issues them as bf16 products (sketch: three-piece splits of X and Omega) and "
-                                "int8 digit products (exact Gram and projection), each against the dense peak of "
+                                "int8 digit products (Gram and projection, exact for the 22-bit per-tile fixed point), each against the dense peak of "
                                 "its own type"},
         "fitness": {"gpu": rep["fit_true"], "iters": rep["iters"], "warn_bits": rep["warn_bits"]},
     }

@@ -42,6 +42,8 @@ struct AlsArgs {
   double *partA, *partB, *partC, *partBegin;   // one partial per block
   double* red;                     // nt x (6 R R + 2): partial sums per tensor
   Ctl* ctl;                        // nt
+  const double* Mt;                // fitness: M^T (K R x J), rows C_k B_k
+  double* fitp;                    // fitness: 2 partials per slice
 };
 
 // per-slice kernels: the block's tensor, its control block and small state.
@@ -963,9 +965,97 @@ __global__ __launch_bounds__(EPI_THREADS) void k_als_begin_epi(AlsArgs a, int re
   }
 }
 
+// ---------------------------------------------------------------------------
+// Fitness partials (Sec. IV-A) per slice k: tr(V S_k H^T Psi_k^T (C_k B_k)^T)
+// and W(k,:)(H^T H * V^T V)W(k,:)^T.  One lane per row r of C_k B_k (a row of
+// M^T, read once): Q(r, :) = sum_j M^T(kR + r, j) V(j, :), j in order, the
+// rows of V through scalar loads; then lane (k, r) forms its terms from
+// column r of Q_k and the slice sums its R lanes in order.
+// ---------------------------------------------------------------------------
+template <int R>
+__global__ __launch_bounds__(RC<R>::TPB) void k_fit_rows(AlsArgs a) {
+  ALS_BLOCK_PROLOGUE(R)
+  constexpr int GPB = RC<R>::GPB, TPB = RC<R>::TPB, RR = R * R;
+  __shared__ double sQ[GPB * RR], sP[GPB * RR], sH[RR], sHV[RR], sW[GPB * R], sT[2 * TPB];
+  (void)ctl;
+  const int tid = threadIdx.x, g = tid / R, r = tid % R;
+  const int J = a.J;
+  const int64_t k = bk.s0 + g;
+  const bool live = g < GPB && k < bk.s1;
+  const double* __restrict__ mrow = a.Mt + (size_t)((live ? k : (int64_t)bk.s0) * R + (live ? r : 0)) * J;
+  const double* __restrict__ V = td.V;
+  double acc[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) acc[c] = 0.0;
+  int j = 0;
+  for (; j + 8 <= J; j += 8) {
+    double m[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) m[u] = mrow[j + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double* __restrict__ vr = V + (size_t)(j + u) * R;
+#pragma unroll
+      for (int c = 0; c < R; ++c) acc[c] = fma(m[u], vr[c], acc[c]);
+    }
+  }
+  for (; j < J; ++j) {
+    const double m = mrow[j];
+    const double* __restrict__ vr = V + (size_t)j * R;
+#pragma unroll
+    for (int c = 0; c < R; ++c) acc[c] = fma(m, vr[c], acc[c]);
+  }
+  for (int e = tid; e < RR; e += TPB) {
+    sH[e] = td.H[e];
+    sHV[e] = small[SM_HV * RR + e];
+  }
+  for (int e = tid; e < GPB * RR; e += TPB) {
+    const int64_t kk = bk.s0 + e / RR;
+    sP[e] = kk < bk.s1 ? a.Psi[(size_t)kk * RR + e % RR] : 0.0;
+  }
+  for (int e = tid; e < GPB * R; e += TPB) {
+    const int64_t kk = bk.s0 + e / R;
+    sW[e] = kk < bk.s1 ? td.W[(size_t)(kk - td.k0) * R + e % R] : 0.0;
+  }
+  if (live) {
+#pragma unroll
+    for (int c = 0; c < R; ++c) sQ[g * RR + r * R + c] = acc[c];
+  }
+  __syncthreads();
+  double tr = 0.0, qd = 0.0;
+  if (live) {
+    const double* Q = sQ + g * RR;
+    const double* P = sP + g * RR;
+    double x = 0.0;
+    for (int aa = 0; aa < R; ++aa) {
+      double y = 0.0;
+      for (int b = 0; b < R; ++b) y += P[b * R + aa] * Q[b * R + r];
+      x += sH[aa * R + r] * y;
+    }
+    const double wr = sW[g * R + r];
+    tr = wr * x;
+    double q = 0.0;
+    for (int s2 = 0; s2 < R; ++s2) q += sHV[r * R + s2] * sW[g * R + s2];
+    qd = wr * q;
+  }
+  sT[2 * tid] = tr;
+  sT[2 * tid + 1] = qd;
+  __syncthreads();
+  if (tid < GPB && bk.s0 + tid < bk.s1) {
+    double t1 = 0.0, t2 = 0.0;
+    for (int rr = 0; rr < R; ++rr) {
+      t1 += sT[2 * (tid * R + rr)];
+      t2 += sT[2 * (tid * R + rr) + 1];
+    }
+    a.fitp[2 * (bk.s0 + tid)] = t1;
+    a.fitp[2 * (bk.s0 + tid) + 1] = t2;
+  }
+}
+
 // Launches of one rank's kernels: phase 0 = begin (+epi) of a call, 1 = one
 // iteration, 2 = the begin step that closes an iteration in the resumable
-// mode (W^T W, V^T V, E D^T V from the factors, as at the start of a call).
+// mode (W^T W, V^T V, E D^T V from the factors, as at the start of a call),
+// 3 = the fitness partials.
 // nb, nb0: blocks of the iteration / begin per-slice kernels; seg, seg0: their
 // per-tensor block offsets (device, nt + 1).
 template <int R>
@@ -977,7 +1067,9 @@ hipError_t als_launch(int phase, const AlsArgs& a, int nb, int nb0, const int64_
   // each per-slice kernel writes one partial per block; the segmented column
   // sum reduces them per tensor (one load per thread) before the epilogues
   hipError_t e;
-  if (phase == 0 || phase == 2) {
+  if (phase == 3) {
+    hipLaunchKernelGGL(k_fit_rows<R>, dim3(nb), dim3(TPB), 0, s, a);
+  } else if (phase == 0 || phase == 2) {
     hipLaunchKernelGGL(k_als_begin<R>, dim3(nb0), dim3(TPB), 0, s, a);
     if ((e = launch_segsum(nt, seg0, nb0, 3 * RR, 3 * RR, a.partBegin, a.red + 3 * RR + 2, RW, s)) != hipSuccess)
       return e;

@@ -39,92 +39,6 @@ __global__ void k_als_vmat(int J, int R, const TDesc* __restrict__ td, const dou
   td[t].V[e] = s;
 }
 
-// Fitness partials, one slice per block: tr(V S_k H^T Psi_k^T (C_k B_k)^T)
-// and W(k,:)(H^T H * V^T V)W(k,:)^T.  LDS sized for the rank
-// (fit_part_lds_bytes), so that several blocks share a compute unit.
-__host__ __device__ inline size_t fit_part_lds_doubles(int R) {
-  return (size_t)3 * R * 33 + (size_t)R * 65 + (size_t)64 * (R + 1) + 16;
-}
-
-__global__ __launch_bounds__(256) void k_fit_part(int J, int R, const TDesc* __restrict__ td,
-                                                  const int32_t* __restrict__ slice_t,
-                                                  const double* __restrict__ Mt, const double* __restrict__ Psi,
-                                                  const double* __restrict__ small, double* __restrict__ fitp) {
-  extern __shared__ double fit_lds[];
-  double* Q = fit_lds;                 // R x 33
-  double* sPsi = Q + R * 33;           // R x 33
-  double* sH = sPsi + R * 33;          // R x 33
-  double* sM = sH + R * 33;            // R x 65
-  double* sV = sM + R * 65;            // 64 x (R + 1)
-  double* red = sV + 64 * (R + 1);     // 16
-  const int SV = R + 1;
-  const int tid = threadIdx.x, RR = R * R;
-  const int64_t k = blockIdx.x;
-  const int t = slice_t[k];
-  const TDesc& d = td[t];
-  const double* V = d.V;
-  const double* W = d.W + (size_t)(k - d.k0) * R;
-  const double* HV = small + (size_t)t * SM_COUNT * RR + SM_HV * RR;
-  const double* Mk = Mt + (size_t)k * R * J;
-  for (int e = tid; e < RR; e += 256) {
-    const int r = e / R, s = e % R;
-    sH[r * 33 + s] = d.H[e];
-    sPsi[r * 33 + s] = Psi[(size_t)k * RR + e];
-  }
-  // Q = (C_k B_k)^T V (R x R) over J in 64-column tiles staged in LDS
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int j0 = 0; j0 < J; j0 += 64) {
-    const int nj = (J - j0 < 64) ? J - j0 : 64;
-    __syncthreads();
-    for (int e = tid; e < R * 64; e += 256) {
-      const int r = e / 64, jj = e % 64;
-      sM[r * 65 + jj] = jj < nj ? Mk[(size_t)r * J + j0 + jj] : 0.0;
-    }
-    for (int e = tid; e < 64 * R; e += 256) {
-      const int jj = e / R, c = e % R;
-      sV[jj * SV + c] = jj < nj ? V[(size_t)(j0 + jj) * R + c] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + 256 * q;
-      if (e < RR) {
-        const int r = e / R, c = e % R;
-        double a = acc[q];
-        for (int jj = 0; jj < nj; ++jj) a = fma(sM[r * 65 + jj], sV[jj * SV + c], a);
-        acc[q] = a;
-      }
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int e = tid + 256 * q;
-    if (e < RR) Q[(e / R) * 33 + e % R] = acc[q];
-  }
-  __syncthreads();
-  double tr = 0.0, qd = 0.0;
-  if (tid < R) {
-    const int r = tid;
-    const double wr = W[r];
-    double x = 0.0;
-    for (int a = 0; a < R; ++a) {
-      double y = 0.0;
-      for (int b = 0; b < R; ++b) y += sPsi[b * 33 + a] * Q[b * 33 + r];
-      x += sH[a * 33 + r] * y;
-    }
-    tr = wr * x;
-    double q = 0.0;
-    for (int s = 0; s < R; ++s) q += HV[r * R + s] * W[s];
-    qd = wr * q;
-  }
-  tr = block_sum(tr, red);
-  qd = block_sum(qd, red);
-  if (tid == 0) {
-    fitp[2 * k] = tr;
-    fitp[2 * k + 1] = qd;
-  }
-}
-
 // fitness of each tensor from its summed partials (fits: nt x 2)
 __global__ void k_fit_final(int nt, const double* __restrict__ fits, double* __restrict__ fit, Ctl* ctl) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -186,6 +100,8 @@ static AlsArgs make_args(const Layout& lay, char* ws) {
   a.partBegin = reinterpret_cast<double*>(ws + lay.partBegin);
   a.red = reinterpret_cast<double*>(ws + lay.red);
   a.ctl = reinterpret_cast<Ctl*>(ws + lay.ctl);
+  a.Mt = reinterpret_cast<const double*>(ws + lay.Mt);
+  a.fitp = reinterpret_cast<double*>(ws + lay.fitp);
   return a;
 }
 
@@ -228,14 +144,9 @@ hipError_t launch_als_end(const Layout& lay, char* ws, hipStream_t s) {
 hipError_t launch_fitness(const Layout& lay, char* ws, double* fit, hipStream_t s) {
   double* fitp = reinterpret_cast<double*>(ws + lay.fitp);
   double* fits = fitp + 2 * lay.K;   // nt x 2 sums after the K per-slice partials
-  hipLaunchKernelGGL(k_fit_part, dim3((unsigned)lay.K), dim3(256), sizeof(double) * fit_part_lds_doubles(lay.R), s,
-                     (int)lay.J, lay.R,
-                     reinterpret_cast<const TDesc*>(ws + lay.tdesc),
-                     reinterpret_cast<const int32_t*>(ws + lay.slice_t), reinterpret_cast<const double*>(ws + lay.Mt),
-                     reinterpret_cast<const double*>(ws + lay.Psi), reinterpret_cast<const double*>(ws + lay.small),
-                     fitp);
-  hipError_t e = launch_segsum(lay.nt, reinterpret_cast<const int64_t*>(ws + lay.seg_slice), lay.K, 2, 2, fitp, fits, 2,
-                               s);
+  hipError_t e = als_dispatch(lay, ws, 3, s);
+  if (e != hipSuccess) return e;
+  e = launch_segsum(lay.nt, reinterpret_cast<const int64_t*>(ws + lay.seg_slice), lay.K, 2, 2, fitp, fits, 2, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_fit_final, dim3((unsigned)((lay.nt + 63) / 64)), dim3(64), 0, s, lay.nt, fits, fit,
                      reinterpret_cast<Ctl*>(ws + lay.ctl));
