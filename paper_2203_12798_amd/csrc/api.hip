@@ -186,7 +186,6 @@ void build_schedule(const Group& g, Schedule* s) {
   s->seg_blk0.assign(1, 0);
   s->seg_chunk.assign(1, 0);
   s->seg_ychunk.assign(1, 0);
-  const int64_t ych = stage2_ychunk(K * R, J);
   s->seg_slice.assign(g.k0.begin(), g.k0.end());
   s->slice_t.assign((size_t)K, 0);
   for (int t = 0; t < nt; ++t) {
@@ -198,6 +197,9 @@ void build_schedule(const Group& g, Schedule* s) {
       s->blk0.push_back(Blk{t, (int32_t)b, (int32_t)std::min<int64_t>(rows, b + gpb), 0});
     for (int64_t r = k0 * R; r < (k0 + Kt) * R; r += STAGE2_CHUNK)
       s->chunks.push_back(Chunk{r, std::min<int64_t>((k0 + Kt) * R, r + STAGE2_CHUNK), t, 0});
+    // the tensor's own chunk length, so that its partial sums are blocked as
+    // in a decomposition of that tensor alone
+    const int64_t ych = stage2_ychunk(Kt * R, J);
     for (int64_t r = k0 * R; r < (k0 + Kt) * R; r += ych)
       s->ychunks.push_back(Chunk{r, std::min<int64_t>((k0 + Kt) * R, r + ych), t, 0});
     s->seg_blk.push_back((int64_t)s->blk.size());
@@ -227,13 +229,13 @@ Layout make_layout(const Group& g) {
   y.nblk = 0;
   y.nblk0 = 0;
   const int gpb = als_slices_per_block(y.R);
-  const int64_t ych = stage2_ychunk(g.k0[(size_t)g.nt] * y.R, y.J);
   for (int t = 0; t < g.nt; ++t) {
     const int64_t* off = g.X[t].row_offsets_host;
     const int64_t Kt = g.X[t].K;
     y.N += off[Kt];
     for (int64_t k = 0; k < Kt; ++k) y.n_items += items_of(off[k + 1] - off[k], item_cap(g));
     y.n2 += (Kt * y.R + STAGE2_CHUNK - 1) / STAGE2_CHUNK;
+    const int64_t ych = stage2_ychunk(Kt * y.R, y.J);
     y.n2y += (Kt * y.R + ych - 1) / ych;
     y.nblk += (int)((Kt + gpb - 1) / gpb);
     y.nblk0 += (int)((std::max<int64_t>(Kt, y.J) + gpb - 1) / gpb);

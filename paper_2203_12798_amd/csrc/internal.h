@@ -34,8 +34,9 @@ inline int64_t s2_scratch_doubles(int64_t nt, int64_t J, int64_t L2, int64_t R) 
   return nt * (((J + 63) / 64) * M * M + 2 * L2 * L2);
 }
 // rows of M^T per block of the second-stage sketch Y2 = M Omega_2 (one wave
-// per 64 columns): about 8192 waves over the group's K R rows, 64 to 2048
-// rows each, a multiple of 64
+// per 64 columns): about 8192 waves over a tensor's K R rows, 64 to 2048
+// rows each, a multiple of 64 (per tensor, so that a tensor in a batch is
+// blocked as when decomposed alone)
 inline int64_t stage2_ychunk(int64_t KR, int64_t J) {
   int64_t r = (KR * ((J + 63) / 64) + 8191) / 8192;
   r = (r + 63) / 64 * 64;
