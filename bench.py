@@ -52,8 +52,12 @@ def parse():
                     help="skip the precision form at J = 2049 (K = 8000, spectrogram-like, R = 10 and 20)")
     ap.add_argument("--wide-k", type=int, default=8000)
     ap.add_argument("--scalability", action="store_true",
-                    help="run only the tenrand scalability workloads (five sizes at R = 10, R = 10..30 at "
+                    help="run only the tenrand scalability workloads (five sizes at R = 10, R = 10..50 at "
                          "2000 x 2000 x 4000); one JSON line")
+    ap.add_argument("--scale-ranks", default="10,20,30,40,50",
+                    help="with --scalability: ranks of the rank sweep at 2000 x 2000 x 4000")
+    ap.add_argument("--scale-no-sizes", action="store_true",
+                    help="with --scalability: leave out the size sweep at R = 10")
     ap.add_argument("--scalability-plain", action="store_true",
                     help="with --scalability: also time PARAFAC2-ALS (Alg. 2) at every point")
     ap.add_argument("--wide-only", action="store_true",
@@ -416,14 +420,13 @@ def gen_wide(K, d, torch, np, seed=3, chunk=256):
 
 
 SCALE_SIZES = [(1000, 1000, 1000), (1000, 1000, 2000), (2000, 1000, 2000), (2000, 2000, 2000), (2000, 2000, 4000)]
-SCALE_RANKS = [10, 20, 30]
 
 
 def bench_scalability(args, d, torch, np, binding):
     """The paper's synthetic scalability workloads (Sec. IV-C): tenrand-style
     tensors of K slices of I x J entries uniform in [0, 1) (torch's generator
     on the GPU, seed 5), float32; the five sizes I x J x K at R = 10, and
-    R = 10, 20, 30 at 2000 x 2000 x 4000 (64 GB).  As in those experiments the
+    R = 10, 20, 30, 40, 50 at 2000 x 2000 x 4000 (64 GB).  As in those experiments the
     randomized SVD runs at the target rank (L = L2 = R) and 32 iterations.
     Per point: ms per decomposition (mean of the timed runs), the slab-pass
     time, the fitness, and PARAFAC2-ALS on the GPU (Alg. 2, same factors and
@@ -431,7 +434,9 @@ def bench_scalability(args, d, torch, np, binding):
     out = {"workload": "tenrand I x J x K uniform [0, 1) float32; L = R; 32 iterations", "points": []}
     g = torch.Generator(device="cuda").manual_seed(5)
     runs = max(1, args.steps // 2)
-    cases = [(I, J, K, 10) for I, J, K in SCALE_SIZES] + [(2000, 2000, 4000, R) for R in SCALE_RANKS if R != 10]
+    ranks = [int(r) for r in args.scale_ranks.split(",")]
+    cases = [] if args.scale_no_sizes else [(I, J, K, 10) for I, J, K in SCALE_SIZES]
+    cases += [(2000, 2000, 4000, R) for R in ranks if R != 10 or args.scale_no_sizes]
     cur = None
     for I, J, K, R in cases:
         if cur is None or cur[0] != (I, J, K):

@@ -74,7 +74,7 @@ typedef enum {
   DPAR2_FP8_E4M3 = 2     /* slab of OCP fp8 e4m3fn bytes; value = decode(byte) *
                             slice_scale[k] in float32 (powers of two keep it exact)  */
   /* every dtype: J <= 16384; the whole-row slab pass covers J <= 256 (float32)
-     or J <= 128 (bf16, fp8), the 128-column-chunk pass the rest */
+     or J <= 128 (bf16, fp8) at L <= 32, the 128-column-chunk pass the rest */
 } dpar2_dtype;
 
 /* Warning bits reported in dpar2_report.warn_bits (device-side, never fatal). */
@@ -88,9 +88,10 @@ typedef enum {
 /* dpar2_opts.flags: the first stage's slab pass (Sec. III-B, Eq. 4) in
  * 128-column chunks (a sketch kernel that writes Y, then a projection kernel
  * per chunk) for any J <= 16384, not only above the whole-row limit (J > 256
- * for float32, > 128 for bf16 / fp8).  Reads the slab twice and needs
- * about 1.6 (L <= 16) or 3.1 (L > 16) KiB per 64 rows of workspace for the
- * digit planes of Y (dpar2_workspace_bytes accounts for it).  Results agree with the whole-row pass to rounding;
+ * for float32, > 128 for bf16 / fp8) or above L = 32.  Reads the slab twice
+ * and needs about 1.6 (L <= 16), 3.1 (L <= 32) or 6.1 (L > 32) KiB per 64
+ * rows of workspace for the digit planes of Y (dpar2_workspace_bytes accounts
+ * for it).  Results agree with the whole-row pass to rounding;
  * dpar2_autotune_slab chooses between the two. */
 #define DPAR2_FLAG_WIDE_SLAB    0x2u
 
@@ -121,11 +122,15 @@ typedef struct {
 
 /* Parameters of Alg. 1 / Alg. 3. */
 typedef struct {
-  int32_t rank;        /* R: target rank of both stages and of PARAFAC2            */
-  int32_t sketch;      /* L = R + s: columns of Omega_1 (first stage), R <= L <= 32,
-                          L <= J and L <= every I_k                                 */
-  int32_t sketch2;     /* L2: columns of Omega_2 (second stage), R <= L2 <= 32,
-                          L2 <= J and L2 <= K R                                     */
+  int32_t rank;        /* R: target rank of both stages and of PARAFAC2: 1..32, 40
+                          or 50 (the rank sweep of Sec. IV-C goes to 50); the
+                          warm start and the post-processing take R <= 32      */
+  int32_t sketch;      /* L = R + s: columns of Omega_1 (first stage), R <= L, L in
+                          1..32 or one of 40, 50, 60 (above 32 the slab pass is
+                          always the 128-column-chunk pass), L <= J and L <=
+                          every I_k                                                 */
+  int32_t sketch2;     /* L2: columns of Omega_2 (second stage), R <= L2, L2 in
+                          1..32 or one of 40, 50, 60, L2 <= J and L2 <= K R          */
   int32_t max_iter;    /* iterations of the repeat loop of Alg. 3, >= 0             */
   double tol;          /* stop when e_{t-1} - e_t < tol * e_{t-1}; tol < 0: never   */
   uint32_t flags;      /* DPAR2_FLAG_* bits, others must be 0                        */

@@ -86,9 +86,14 @@ template <int R>
 struct RC {
   static constexpr int N = R + (R & 1);                           // Jacobi players
   static constexpr int RM = pow2ceil(N) < 2 ? 2 : pow2ceil(N);    // lanes per slice
-  static constexpr int TPB = (R > 16) ? 128 : 256;                // per-slice block
+  // per-slice block (one slice per 64-lane block above R = 32: the per-slice
+  // R x R matrices in LDS then take up to 100 KB)
+  static constexpr int TPB = (R > 32) ? 64 : (R > 16) ? 128 : 256;
   static constexpr int GPB = TPB / RM;                            // slices per block
   static constexpr int RR = R * R;
+  // R x R matrices of the epilogues in LDS: leading dimension and rows
+  static constexpr int LD = (R > 32) ? R + 1 : 33;
+  static constexpr int MR = (R > 32) ? R : 32;
 };
 
 // One-sided Jacobi (Hestenes) on the R columns held by a group of RM lanes:
@@ -146,55 +151,91 @@ __device__ inline int group_jacobi(double (&t)[R], double (&v)[R], int j, int gb
 }
 
 // Inverse of a symmetric positive definite R x R matrix G (LDS, leading
-// dimension 33) by Gauss-Jordan elimination without pivoting on [G | I], one
-// lane per column (2R <= 64 lanes of wave 0).  Returns false (wave-uniform)
+// dimension RC<R>::LD) by Gauss-Jordan elimination without pivoting on
+// [G | I], one lane per column (2R <= 64 lanes of wave 0; above R = 32 lane c
+// holds both column c of G and column c of I).  Returns false (wave-uniform)
 // when a pivot falls below 1e-13 max_i G_ii, i.e. when G is singular to
 // working accuracy; the caller then takes the eigen-based pseudoinverse.
 template <int R>
 __device__ inline bool wave_spd_inverse(const double* G, double* Ginv) {
+  constexpr int LD = RC<R>::LD;
   const int c = threadIdx.x;   // lane of wave 0
-  double col[R];
-#pragma unroll
-  for (int i = 0; i < R; ++i)
-    col[i] = (c < R) ? G[i * 33 + c] : ((c - R == i) ? 1.0 : 0.0);
   double dmax = 0.0;
 #pragma unroll
-  for (int i = 0; i < R; ++i) dmax = fmax(dmax, G[i * 33 + i]);
+  for (int i = 0; i < R; ++i) dmax = fmax(dmax, G[i * LD + i]);
   bool ok = dmax > 0.0;
-#pragma unroll
-  for (int p = 0; p < R; ++p) {
-    double colp[R];
-#pragma unroll
-    for (int i = 0; i < R; ++i) colp[i] = __shfl(col[i], p, 64);
-    const double piv = colp[p];
-    ok = ok && (piv > 1e-13 * dmax);
-    // a pivot that fails the test leaves garbage, discarded with ok = false
-    const double f = col[p] * nr_rcp(piv);
+  if constexpr (2 * R <= 64) {
+    double col[R];
 #pragma unroll
     for (int i = 0; i < R; ++i)
-      if (i != p) col[i] = fma(-colp[i], f, col[i]);
-    col[p] = f;
-  }
-  if (c >= R && c < 2 * R)
+      col[i] = (c < R) ? G[i * LD + c] : ((c - R == i) ? 1.0 : 0.0);
 #pragma unroll
-    for (int i = 0; i < R; ++i) Ginv[i * 33 + (c - R)] = col[i];
+    for (int p = 0; p < R; ++p) {
+      double colp[R];
+#pragma unroll
+      for (int i = 0; i < R; ++i) colp[i] = __shfl(col[i], p, 64);
+      const double piv = colp[p];
+      ok = ok && (piv > 1e-13 * dmax);
+      // a pivot that fails the test leaves garbage, discarded with ok = false
+      const double f = col[p] * nr_rcp(piv);
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+        if (i != p) col[i] = fma(-colp[i], f, col[i]);
+      col[p] = f;
+    }
+    if (c >= R && c < 2 * R)
+#pragma unroll
+      for (int i = 0; i < R; ++i) Ginv[i * LD + (c - R)] = col[i];
+  } else {
+    double col[R], idc[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      col[i] = (c < R) ? G[i * LD + c] : 0.0;
+      idc[i] = (c == i) ? 1.0 : 0.0;
+    }
+    for (int p = 0; p < R; ++p) {
+      double colp[R];
+#pragma unroll
+      for (int i = 0; i < R; ++i) colp[i] = __shfl(col[i], p, 64);
+      double piv = 0.0, cp = 0.0, ip = 0.0;
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+        if (i == p) {
+          piv = colp[i];
+          cp = col[i];
+          ip = idc[i];
+        }
+      ok = ok && (piv > 1e-13 * dmax);
+      const double rp = nr_rcp(piv);
+      const double f = cp * rp, g = ip * rp;
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        col[i] = (i == p) ? f : fma(-colp[i], f, col[i]);
+        idc[i] = (i == p) ? g : fma(-colp[i], g, idc[i]);
+      }
+    }
+    if (c < R)
+#pragma unroll
+      for (int i = 0; i < R; ++i) Ginv[i * LD + c] = idc[i];
+  }
   return ok;
 }
 
 // Moore-Penrose pseudoinverse of a symmetric positive semidefinite R x R
-// matrix G (LDS, ld 33): one-sided Jacobi G P = T (columns t_j = lambda_j
-// p_j), G^dagger = sum_j p_j t_j^T / lambda_j^2 over lambda_j > R eps
-// lambda_max.  Wave 0 runs the Jacobi; sT, sV: LDS 32 x 33; sg: 32 doubles.
+// matrix G (LDS, ld RC<R>::LD): one-sided Jacobi G P = T (columns t_j =
+// lambda_j p_j), G^dagger = sum_j p_j t_j^T / lambda_j^2 over lambda_j > R eps
+// lambda_max.  Wave 0 runs the Jacobi; sT, sV: LDS RC<R>::MR x RC<R>::LD; sg:
+// RC<R>::MR doubles.
 template <int R>
 __device__ inline int jacobi_pinv(const double* G, double* Ginv, double* sT, double* sV, double* sg) {
-  constexpr int RM = RC<R>::RM;
+  constexpr int RM = RC<R>::RM, LD = RC<R>::LD;
   int capped = 0;
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x, j = lane % RM, gbase = lane & ~(RM - 1);
     double t[R], v[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-      t[i] = (j < R) ? G[i * 33 + j] : 0.0;
+      t[i] = (j < R) ? G[i * LD + j] : 0.0;
       v[i] = (i == j) ? 1.0 : 0.0;
     }
     capped = group_jacobi<R>(t, v, j, gbase) == JACOBI_SWEEPS;
@@ -204,8 +245,8 @@ __device__ inline int jacobi_pinv(const double* G, double* Ginv, double* sT, dou
     if (lane < RM && j < R) {
 #pragma unroll
       for (int i = 0; i < R; ++i) {
-        sT[i * 33 + j] = t[i];
-        sV[i * 33 + j] = v[i];
+        sT[i * LD + j] = t[i];
+        sV[i * LD + j] = v[i];
       }
       sg[j] = sqrt(s2);
     }
@@ -219,9 +260,9 @@ __device__ inline int jacobi_pinv(const double* G, double* Ginv, double* sT, dou
     double s = 0.0;
     for (int i = 0; i < R; ++i) {
       const double l = sg[i];
-      if (l > cut) s += sV[a * 33 + i] * sT[b * 33 + i] / (l * l);
+      if (l > cut) s += sV[a * LD + i] * sT[b * LD + i] / (l * l);
     }
-    Ginv[a * 33 + b] = s;
+    Ginv[a * LD + b] = s;
   }
   __syncthreads();
   return capped;
@@ -554,8 +595,8 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_A(AlsArgs a) {
 template <int R>
 __global__ __launch_bounds__(EPI_THREADS) void k_als_A_epi(AlsArgs a, int nblk) {
   ALS_EPI_PROLOGUE(R)
-  constexpr int LD = 33, RR = R * R;
-  __shared__ double G1[32 * LD], Gm[32 * LD], Gi[32 * LD], sT[32 * LD], sV[32 * LD], sg[32];
+  constexpr int LD = RC<R>::LD, MR = RC<R>::MR, RR = R * R;
+  __shared__ double G1[MR * LD], Gm[MR * LD], Gi[MR * LD], sT[MR * LD], sV[MR * LD], sg[MR];
   __shared__ int sflag;
   const int tid = threadIdx.x;
   (void)nblk;
@@ -672,8 +713,8 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_B(AlsArgs a) {
 template <int R>
 __global__ __launch_bounds__(EPI_THREADS) void k_als_B_epi(AlsArgs a, int nblk) {
   ALS_EPI_PROLOGUE(R)
-  constexpr int LD = 33, RR = R * R;
-  __shared__ double N[32 * LD], Gm[32 * LD], Gi[32 * LD], sT[32 * LD], sV[32 * LD], sg[32];
+  constexpr int LD = RC<R>::LD, MR = RC<R>::MR, RR = R * R;
+  __shared__ double N[MR * LD], Gm[MR * LD], Gi[MR * LD], sT[MR * LD], sV[MR * LD], sg[MR];
   __shared__ double DtD[RR], Et[R];
   __shared__ int sflag;
   const int tid = threadIdx.x;

@@ -70,9 +70,11 @@ dpar2_status validate(const dpar2_tensor* X, const dpar2_opts* o) {
     return fail(DPAR2_EINVAL, "opts.item_rows must be 0 or in 64..65536");
   if (o->power_iters < 0 || o->power_iters > 4) return fail(DPAR2_EINVAL, "power_iters must be in [0, 4]");
   const int R = o->rank, L = o->sketch, L2 = o->sketch2;
-  if (R < 1 || R > 32) return fail(DPAR2_ESHAPE, "rank must be in [1, 32]");
-  if (L < R || L > 32) return fail(DPAR2_ESHAPE, "sketch width L must satisfy R <= L <= 32");
-  if (L2 < R || L2 > 32) return fail(DPAR2_ESHAPE, "sketch width L2 must satisfy R <= L2 <= 32");
+  if (!rank_supported(R)) return fail(DPAR2_ESHAPE, "rank must be in [1, 32] or one of 40, 50");
+  if (L < R || !width_supported(L))
+    return fail(DPAR2_ESHAPE, "sketch width L must satisfy R <= L and be in [1, 32] or one of 40, 50, 60");
+  if (L2 < R || !width_supported(L2))
+    return fail(DPAR2_ESHAPE, "sketch width L2 must satisfy R <= L2 and be in [1, 32] or one of 40, 50, 60");
   if (o->max_iter < 0) return fail(DPAR2_EINVAL, "max_iter must be >= 0");
   const int64_t K = X->K, J = X->J;
   if (L > J) return fail(DPAR2_ESHAPE, "sketch width L exceeds J");
@@ -296,7 +298,7 @@ Layout make_layout(const Group& g) {
   y.om1 = take(sizeof(float) * (size_t)(nt * J * L));      // copy of each Omega_1 for the U pass
   y.omq = take(y.q > 0 ? sizeof(float) * (size_t)(K * J * L) : 0);   // power-step sketches
   // the wide slab pass keeps Y (16 LT floats per row) between its two kernels
-  y.wide = J > narrow_j_limit(g.X[0].dtype) || (o->flags & DPAR2_FLAG_WIDE_SLAB) != 0;
+  y.wide = J > narrow_j_limit(g.X[0].dtype) || y.L > 32 || (o->flags & DPAR2_FLAG_WIDE_SLAB) != 0;
   y.ybuf = take(y.wide ? wide_tile_bytes(y.L) * (size_t)((y.N + SKETCH_TM - 1) / SKETCH_TM + y.n_items) : 0);
   y.det = (o->flags & DPAR2_FLAG_DETERMINISTIC) != 0;
   y.total = p;
@@ -1458,6 +1460,7 @@ int64_t dpar2_warm_param_count(int32_t rank) {
 dpar2_status dpar2_warm_features(const dpar2_tensor* X, const dpar2_opts* o, const void* ws, size_t ws_bytes,
                                  float* tok, dpar2_stream_t stream) {
   Comp c;
+  if (o && o->rank > 32) return fail(DPAR2_EINVAL, "the warm start takes ranks up to 32");
   dpar2_status st = comp_of(X, o, ws, ws_bytes, &c);
   if (st != DPAR2_OK) return st;
   if (!tok) return fail(DPAR2_EINVAL, "tok is NULL");
@@ -1472,6 +1475,7 @@ dpar2_status dpar2_warm_features(const dpar2_tensor* X, const dpar2_opts* o, con
 dpar2_status dpar2_warm_targets(const dpar2_tensor* X, const dpar2_opts* o, const void* ws, size_t ws_bytes,
                                 const dpar2_factors* f, float* tH, float* tV, float* tW, dpar2_stream_t stream) {
   Comp c;
+  if (o && o->rank > 32) return fail(DPAR2_EINVAL, "the warm start takes ranks up to 32");
   dpar2_status st = comp_of(X, o, ws, ws_bytes, &c);
   if (st != DPAR2_OK) return st;
   if (!f || !f->H || !f->V || !f->W || !tH || !tV || !tW) return fail(DPAR2_EINVAL, "NULL factor or target");
@@ -1486,6 +1490,7 @@ dpar2_status dpar2_warm_apply(const dpar2_tensor* X, const dpar2_opts* o, const 
                               const float* pH, const float* pV, const float* pW, dpar2_factors* f,
                               dpar2_stream_t stream) {
   Comp c;
+  if (o && o->rank > 32) return fail(DPAR2_EINVAL, "the warm start takes ranks up to 32");
   dpar2_status st = comp_of(X, o, ws, ws_bytes, &c);
   if (st != DPAR2_OK) return st;
   if (!f || !f->H || !f->V || !f->W || !pH || !pV || !pW) return fail(DPAR2_EINVAL, "NULL factor or prediction");

@@ -21,6 +21,12 @@ struct Item {
 };
 
 constexpr int SKETCH_TM = 64;          // rows per tile of the slab pass
+// Ranks and sketch widths: every value up to 32, and above 32 the ranks 40 and
+// 50 and the sketch widths 40, 50 and 60 (the per-slice R x R and L x L
+// factorisations give each column one lane of a 64-lane wave)
+constexpr int MAX_RANK = 64;
+inline bool rank_supported(int R) { return (R >= 1 && R <= 32) || R == 40 || R == 50; }
+inline bool width_supported(int L) { return (L >= 1 && L <= 32) || L == 40 || L == 50 || L == 60; }
 constexpr int MAX_CHUNK_ROWS = 16384;  // longest item (rows)
 constexpr int STAGE2_CHUNK = 256;      // rows of M^T per second-stage block (one per thread)
 // J from which the second stage's J-long steps (Gram and whitening of Y2,
@@ -135,7 +141,9 @@ struct SlabArgs {
 inline int narrow_j_limit(int dtype) { return dtype == 0 ? 256 : 128; }
 // bytes per 64-row tile of the wide pass's Y-digit buffer: three digit planes
 // of 16 LT columns x 64 row bytes, then the 16 LT column exponents
-__host__ __device__ inline size_t wide_tile_bytes(int L) { return L <= 16 ? 3 * 16 * 64 + 16 * 4 : 3 * 32 * 64 + 32 * 4; }
+// (16 LT columns: LT = 1, 2 or 4 for L up to 16, 32 or 64)
+__host__ __device__ inline int wide_lt(int L) { return L <= 16 ? 1 : L <= 32 ? 2 : 4; }
+__host__ __device__ inline size_t wide_tile_bytes(int L) { return (size_t)wide_lt(L) * (3 * 16 * 64 + 16 * 4); }
 constexpr int MAX_J = 16384;
 // Slab pass over all work items: per-item partials of Y^T Y, Y^T X and
 // ||X||^2, or (uout) U = Y Theta_k.  dtype: dpar2_dtype; vec: every slab is

@@ -15,13 +15,15 @@ hipError_t als_dispatch_3(int R, int phase, const AlsArgs& a, int nb, int nb0, c
                           const int64_t* seg0, hipStream_t s);
 hipError_t als_dispatch_4(int R, int phase, const AlsArgs& a, int nb, int nb0, const int64_t* seg,
                           const int64_t* seg0, hipStream_t s);
+hipError_t als_dispatch_5(int R, int phase, const AlsArgs& a, int nb, int nb0, const int64_t* seg,
+                          const int64_t* seg0, hipStream_t s);
 
 int als_slices_per_block(int R) {
   const int n = R + (R & 1);
   int rm = 1;
   while (rm < n) rm *= 2;
   if (rm < 2) rm = 2;
-  return (R > 16 ? 128 : 256) / rm;   // RC<R>::GPB
+  return (R > 32 ? 64 : R > 16 ? 128 : 256) / rm;   // RC<R>::GPB
 }
 
 // V = D VC for each tensor whose V was updated during the call.
@@ -53,20 +55,21 @@ __global__ void k_fit_final(int nt, const double* __restrict__ fits, double* __r
 __global__ __launch_bounds__(256) void k_theta(int K, int L, int R, const double* __restrict__ Phi,
                                                const double* __restrict__ Psi, const double* __restrict__ H,
                                                double* __restrict__ theta) {
-  __shared__ double sT[32 * 33];
+  constexpr int LD = MAX_RANK + 1;
+  __shared__ double sT[MAX_RANK * LD];
   const int k = blockIdx.x, tid = threadIdx.x, RR = R * R;
   // T = Psi_k H
   for (int e = tid; e < RR; e += 256) {
     const int a = e / R, b = e % R;
     double s = 0.0;
     for (int i = 0; i < R; ++i) s += Psi[(size_t)k * RR + a * R + i] * H[i * R + b];
-    sT[a * 33 + b] = s;
+    sT[a * LD + b] = s;
   }
   __syncthreads();
   for (int e = tid; e < L * R; e += 256) {
     const int l = e / R, b = e % R;
     double s = 0.0;
-    for (int i = 0; i < R; ++i) s += Phi[(size_t)k * L * R + l * R + i] * sT[i * 33 + b];
+    for (int i = 0; i < R; ++i) s += Phi[(size_t)k * L * R + l * R + i] * sT[i * LD + b];
     theta[(size_t)k * L * R + e] = s;
   }
 }
@@ -113,7 +116,8 @@ static hipError_t als_dispatch(const Layout& lay, char* ws, int phase, hipStream
   if (R <= 8) return als_dispatch_1(R, phase, a, lay.nblk, lay.nblk0, seg, seg0, s);
   if (R <= 16) return als_dispatch_2(R, phase, a, lay.nblk, lay.nblk0, seg, seg0, s);
   if (R <= 24) return als_dispatch_3(R, phase, a, lay.nblk, lay.nblk0, seg, seg0, s);
-  return als_dispatch_4(R, phase, a, lay.nblk, lay.nblk0, seg, seg0, s);
+  if (R <= 32) return als_dispatch_4(R, phase, a, lay.nblk, lay.nblk0, seg, seg0, s);
+  return als_dispatch_5(R, phase, a, lay.nblk, lay.nblk0, seg, seg0, s);
 }
 
 hipError_t launch_pw_identity(const Layout& lay, char* ws, hipStream_t s) {

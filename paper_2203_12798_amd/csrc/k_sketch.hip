@@ -217,7 +217,7 @@ __global__ __launch_bounds__(256) void k_sketch(SlabArgs a) {
 
 bool sketch_supported(int J, int L, int dtype) {
   (void)dtype;
-  return L >= 1 && L <= 32 && J >= 1 && J <= MAX_J;
+  return width_supported(L) && J >= 1 && J <= MAX_J;
 }
 
 static int jt_bucket(int J) {
@@ -254,7 +254,7 @@ hipError_t slab_launch_fp8(const SlabArgs& a, int64_t n_items, bool vec, bool uo
 hipError_t launch_slab(const SlabArgs& a, int dtype, int64_t n_items, bool vec, bool uout, bool wide,
                        hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  if (wide || a.J > narrow_j_limit(dtype)) return launch_slab_wide(a, dtype, n_items, vec, uout, s);
+  if (wide || a.J > narrow_j_limit(dtype) || a.L > 32) return launch_slab_wide(a, dtype, n_items, vec, uout, s);
   if (a.J > 128) return uout ? dispatch_wide<true>(a, n_items, vec, s) : dispatch_wide<false>(a, n_items, vec, s);
   if (dtype == DPAR2_F32) return slab_launch_f32(a, n_items, vec, uout, s);
   if (dtype == DPAR2_BF16) return slab_launch_bf16(a, n_items, vec, uout, s);

@@ -66,6 +66,19 @@ __device__ __forceinline__ float4 buf_load<float4>(rsrc_t r, uint32_t voff, uint
   return make_float4(__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]), __uint_as_float(v[3]));
 }
 
+// Tile g of the upper triangle of the Gram, column by column: (0,0), (0,1),
+// (1,1), (0,2), (1,2), (2,2), ...; gram_a is its row tile, gram_b its column
+// tile.
+__device__ __forceinline__ int gram_b(int g) {
+  int b = 0;
+  while (g > b) {
+    g -= b + 1;
+    ++b;
+  }
+  return b;
+}
+__device__ __forceinline__ int gram_a(int g) { return g - gram_b(g) * (gram_b(g) + 1) / 2; }
+
 template <int LT, bool VEC, int TIN, bool UOUT>
 __global__ __launch_bounds__(256, 2) void k_wide_y(SlabArgs a) {
   typedef typename In<TIN>::E E;
@@ -85,15 +98,20 @@ __global__ __launch_bounds__(256, 2) void k_wide_y(SlabArgs a) {
   static_assert(KS * TM * LP * 2 <= TM * WXS, "partial sums of Y must fit over the X chunk");
   __shared__ __align__(16) float sX[TM * WXS];
   __shared__ float sYf[UOUT ? TM * YS : 1];
-  __shared__ double sTh[UOUT ? 32 * 32 : 1];
+  __shared__ double sTh[UOUT ? (LT > 2 ? 64 * 64 : 32 * 32) : 1];
   __shared__ double sred[8];
   constexpr int QW = 20;                       // dwords per digit-plane row (64 bytes + pad)
   __shared__ __align__(16) uint32_t sYq[UOUT ? 4 : 3 * LP * QW];
   __shared__ float sYm[UOUT ? 1 : 4 * LP];
   __shared__ int sYe[UOUT ? 1 : LP];
-  constexpr int NG = (LT == 1) ? 1 : 3;        // Gram tiles (upper triangle), waves 0 .. NG-1
+  // Gram tiles (upper triangle, column by column: tile g = (ga, gb), ga <= gb),
+  // tile g on wave g % 4
+  constexpr int NG = LT * (LT + 1) / 2;
+  constexpr int NGW = (NG + 3) / 4;            // tiles per wave
   const size_t TB = wide_tile_bytes(L);
-  v4d gacc = v4d{0.0, 0.0, 0.0, 0.0};
+  v4d gacc[NGW];
+#pragma unroll
+  for (int gi = 0; gi < NGW; ++gi) gacc[gi] = v4d{0.0, 0.0, 0.0, 0.0};
   double* sYp = reinterpret_cast<double*>(sX);
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -284,15 +302,19 @@ __global__ __launch_bounds__(256, 2) void k_wide_y(SlabArgs a) {
       }
       __syncthreads();
       // exact Gram of the represented Y: nine digit products per 16 x 16 tile
-      if (w < NG) {
-        const int ca = (w == 2) ? 16 : 0, cb = (w == 0) ? 0 : 16;
-        v4i A[3], B[3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          A[d] = *reinterpret_cast<const v4i*>(&sYq[(d * LP + ca + lr) * QW + 4 * lk]);
-          B[d] = *reinterpret_cast<const v4i*>(&sYq[(d * LP + cb + lr) * QW + 4 * lk]);
+      for (int gi = 0; gi < NGW; ++gi) {
+        const int g = w + 4 * gi;
+        if (g < NG) {
+          const int ca = 16 * gram_a(g), cb = 16 * gram_b(g);
+          v4i A[3], B[3];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            A[d] = *reinterpret_cast<const v4i*>(&sYq[(d * LP + ca + lr) * QW + 4 * lk]);
+            B[d] = *reinterpret_cast<const v4i*>(&sYq[(d * LP + cb + lr) * QW + 4 * lk]);
+          }
+          gacc[gi] = digit_tile_fma(A, B, sYe[cb + lr], sYe, ca, lane, gacc[gi]);
         }
-        gacc = digit_tile_fma(A, B, sYe[cb + lr], sYe, ca, lane, gacc);
       }
     } else {
 #pragma unroll
@@ -309,15 +331,19 @@ __global__ __launch_bounds__(256, 2) void k_wide_y(SlabArgs a) {
     }
   }
   if constexpr (!UOUT) {
-    if (w < NG) {
-      double* Gp = a.partG + (size_t)blockIdx.x * L * L;
-      const int ga = (w == 2) ? 1 : 0, gb = (w == 0) ? 0 : 1;
+    double* Gp = a.partG + (size_t)blockIdx.x * L * L;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = ga * 16 + f32_row(lane, v), j = gb * 16 + lr;
-        if (i < L && j < L) {
-          Gp[i * L + j] = gacc[v];
-          if (ga != gb) Gp[j * L + i] = gacc[v];
+    for (int gi = 0; gi < NGW; ++gi) {
+      const int g = w + 4 * gi;
+      if (g < NG) {
+        const int ga = gram_a(g), gb = gram_b(g);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = ga * 16 + f32_row(lane, v), j = gb * 16 + lr;
+          if (i < L && j < L) {
+            Gp[i * L + j] = gacc[gi][v];
+            if (ga != gb) Gp[j * L + i] = gacc[gi][v];
+          }
         }
       }
     }
@@ -499,14 +525,16 @@ static hipError_t wide_launch(const SlabArgs& a, int64_t n_items, bool vec, bool
 
 hipError_t launch_slab_wide(const SlabArgs& a, int dtype, int64_t n_items, bool vec, bool uout, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  if (a.L > 32 || a.J > MAX_J || (!uout && !a.ybuf)) return hipErrorInvalidValue;
-  const bool l1 = a.L <= 16;
-  if (dtype == DPAR2_F32) return l1 ? wide_launch<1, DPAR2_F32>(a, n_items, vec, uout, s)
-                                    : wide_launch<2, DPAR2_F32>(a, n_items, vec, uout, s);
-  if (dtype == DPAR2_BF16) return l1 ? wide_launch<1, DPAR2_BF16>(a, n_items, vec, uout, s)
-                                     : wide_launch<2, DPAR2_BF16>(a, n_items, vec, uout, s);
-  return l1 ? wide_launch<1, DPAR2_FP8_E4M3>(a, n_items, vec, uout, s)
-            : wide_launch<2, DPAR2_FP8_E4M3>(a, n_items, vec, uout, s);
+  if (a.L > 64 || a.J > MAX_J || (!uout && !a.ybuf)) return hipErrorInvalidValue;
+  const int lt = wide_lt(a.L);
+#define DPAR2_WL(TIN_)                                                     \
+  return lt == 1 ? wide_launch<1, TIN_>(a, n_items, vec, uout, s)          \
+       : lt == 2 ? wide_launch<2, TIN_>(a, n_items, vec, uout, s)          \
+                 : wide_launch<4, TIN_>(a, n_items, vec, uout, s);
+  if (dtype == DPAR2_F32) { DPAR2_WL(DPAR2_F32) }
+  if (dtype == DPAR2_BF16) { DPAR2_WL(DPAR2_BF16) }
+  DPAR2_WL(DPAR2_FP8_E4M3)
+#undef DPAR2_WL
 }
 
 }  // namespace dpar2

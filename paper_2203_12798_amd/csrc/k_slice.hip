@@ -29,6 +29,10 @@ hipError_t slice_dispatch_2(int L, int64_t K, int J, int R, const int32_t* slice
                             const int32_t* slice_list, const double* partG, const double* partP,
                             const double* partS, double* xnorm2, double* Mt, double* Phi, double* sig1,
                             float* omega_next, float* msgn, Ctl* ctl, const int32_t* slice_t, hipStream_t s);
+hipError_t slice_dispatch_3(int L, int64_t K, int J, int R, const int32_t* slice_ptr,
+                            const int32_t* slice_list, const double* partG, const double* partP,
+                            const double* partS, double* xnorm2, double* Mt, double* Phi, double* sig1,
+                            float* omega_next, float* msgn, Ctl* ctl, const int32_t* slice_t, hipStream_t s);
 
 // Rows kR + r of M^T whose column of C_k B_k takes a negative sign: one block
 // per row, the rows with a positive sign return at once.
@@ -46,10 +50,12 @@ hipError_t launch_slice_finish(int64_t K, int J, int L, int R, const int32_t* sl
                                const int32_t* slice_t, hipStream_t s) {
   if (K <= 0) return hipSuccess;
   const hipError_t e =
-      L <= 16 ? slice_dispatch_1(L, K, J, R, slice_ptr, slice_list, partG, partP, partS, xnorm2, Mt, Phi, sig1,
-                                 omega_next, msgn, ctl, slice_t, s)
-              : slice_dispatch_2(L, K, J, R, slice_ptr, slice_list, partG, partP, partS, xnorm2, Mt, Phi, sig1,
-                                 omega_next, msgn, ctl, slice_t, s);
+      L <= 16   ? slice_dispatch_1(L, K, J, R, slice_ptr, slice_list, partG, partP, partS, xnorm2, Mt, Phi, sig1,
+                                   omega_next, msgn, ctl, slice_t, s)
+      : L <= 32 ? slice_dispatch_2(L, K, J, R, slice_ptr, slice_list, partG, partP, partS, xnorm2, Mt, Phi, sig1,
+                                   omega_next, msgn, ctl, slice_t, s)
+                : slice_dispatch_3(L, K, J, R, slice_ptr, slice_list, partG, partP, partS, xnorm2, Mt, Phi, sig1,
+                                   omega_next, msgn, ctl, slice_t, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_msign, dim3((unsigned)(K * R)), dim3(256), 0, s, J, msgn, Mt);
   return hipGetLastError();

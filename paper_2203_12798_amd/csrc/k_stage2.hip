@@ -204,6 +204,7 @@ static hipError_t s2_stream_launch(int which, int L2, int J, int64_t nchunks, co
     DPAR2_S2(9) DPAR2_S2(10) DPAR2_S2(11) DPAR2_S2(12) DPAR2_S2(13) DPAR2_S2(14) DPAR2_S2(15) DPAR2_S2(16)
     DPAR2_S2(17) DPAR2_S2(18) DPAR2_S2(19) DPAR2_S2(20) DPAR2_S2(21) DPAR2_S2(22) DPAR2_S2(23) DPAR2_S2(24)
     DPAR2_S2(25) DPAR2_S2(26) DPAR2_S2(27) DPAR2_S2(28) DPAR2_S2(29) DPAR2_S2(30) DPAR2_S2(31) DPAR2_S2(32)
+    DPAR2_S2(40) DPAR2_S2(50) DPAR2_S2(60)
 #undef DPAR2_S2
     default:
       return hipErrorInvalidValue;
@@ -225,22 +226,29 @@ hipError_t s2_small_dispatch_1(int nt, int L2, int which, int J, int R, double* 
 hipError_t s2_small_dispatch_2(int nt, int L2, int which, int J, int R, double* Y2, const double* S2,
                                double* D, double* E, double* U2s, double* small, Ctl* ctl, double* scratch,
                                hipStream_t s);
+hipError_t s2_small_dispatch_3(int nt, int L2, int which, int J, int R, double* Y2, const double* S2,
+                               double* D, double* E, double* U2s, double* small, Ctl* ctl, double* scratch,
+                               hipStream_t s);
 
 // orthonormalisation of Y2 (which = 0) or the small SVD and D, E (which = 1),
 // one block per tensor
 static hipError_t s2_small(int nt, int L2, int which, int J, int R, double* Y2, const double* S2, double* D,
                            double* E, double* U2s, double* small, Ctl* ctl, double* scratch, hipStream_t s) {
   if (L2 <= 16) return s2_small_dispatch_1(nt, L2, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
-  return s2_small_dispatch_2(nt, L2, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+  if (L2 <= 32) return s2_small_dispatch_2(nt, L2, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
+  return s2_small_dispatch_3(nt, L2, which, J, R, Y2, S2, D, E, U2s, small, ctl, scratch, s);
 }
 
 // F = B2^T (U2_R E^{-1}) over one chunk (U2 of the chunk's tensor) and the
-// chunk's partial of F^T F.
+// chunk's partial of F^T F.  BIG: L2 up to 60 and R up to 50, else both up to
+// 32.
+template <bool BIG>
 __global__ __launch_bounds__(256) void k_s2_f(int L2, int R, const Chunk* __restrict__ chunks,
                                               const double* __restrict__ B2t, const double* __restrict__ U2all,
                                               double* __restrict__ F, double* __restrict__ FtFp) {
-  __shared__ double sU[32 * 32];
-  __shared__ double sF[256 * 33];
+  constexpr int LDF = BIG ? 51 : 33;
+  __shared__ double sU[BIG ? 60 * 50 : 32 * 32];
+  __shared__ double sF[256 * LDF];
   const int tid = threadIdx.x;
   const Chunk ch = chunks[blockIdx.x];
   const double* U2s = U2all + (size_t)ch.t * L2 * R;
@@ -252,14 +260,14 @@ __global__ __launch_bounds__(256) void k_s2_f(int L2, int R, const Chunk* __rest
     double s = 0.0;
     if (ok)
       for (int l = 0; l < L2; ++l) s += B2t[(size_t)row * L2 + l] * sU[l * R + r];
-    sF[tid * 33 + r] = s;
+    sF[tid * LDF + r] = s;
     if (ok) F[(size_t)row * R + r] = s;
   }
   __syncthreads();
   for (int e = tid; e < R * R; e += 256) {
     const int a = e / R, b = e % R;
     double s = 0.0;
-    for (int i = 0; i < 256; ++i) s += sF[i * 33 + a] * sF[i * 33 + b];
+    for (int i = 0; i < 256; ++i) s += sF[i * LDF + a] * sF[i * LDF + b];
     FtFp[(size_t)blockIdx.x * R * R + e] = s;
   }
 }
@@ -340,7 +348,10 @@ hipError_t launch_stage2(const Layout& lay, char* ws, hipStream_t s) {
   // sum_k ||X_k||^2 of each tensor into its control block
   if ((e = launch_segsum(nt, seg_slice, lay.K, 1, 1, xnorm2, &ctl->xnorm2, cstride, s)) != hipSuccess) return e;
   if ((e = s2_small(nt, L2, 1, J, R, Y2, S2, D, E, U2s, small, ctl, s2s, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_s2_f, dim3((unsigned)lay.n2), dim3(256), 0, s, L2, R, chunks, B2t, U2s, F, FtFp);
+  if (L2 > 32)
+    hipLaunchKernelGGL(k_s2_f<true>, dim3((unsigned)lay.n2), dim3(256), 0, s, L2, R, chunks, B2t, U2s, F, FtFp);
+  else
+    hipLaunchKernelGGL(k_s2_f<false>, dim3((unsigned)lay.n2), dim3(256), 0, s, L2, R, chunks, B2t, U2s, F, FtFp);
   if ((e = launch_segsum(nt, seg_chunk, lay.n2, RR, RR, FtFp, small + SM_FTF * RR, (int64_t)SM_COUNT * RR, s)) !=
       hipSuccess)
     return e;

@@ -67,7 +67,7 @@ __global__ __launch_bounds__(256) void k_pl_begin(PlainArgs a) {
 
 // Start of an iteration: the slab pass reads the float32 V the previous
 // iteration produced (om_cur keeps the one of the last pass that ran, for U).
-__global__ __launch_bounds__(256) void k_pl_commit(PlainArgs a, int n) {
+static __global__ __launch_bounds__(256) void k_pl_commit(PlainArgs a, int n) {
   if (a.ctl->done) return;
   for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) a.om_cur[e] = a.om_next[e];
 }
@@ -210,8 +210,8 @@ __global__ __launch_bounds__(64) void k_pl_slice(PlainArgs a) {
 // the first R R entries of red, sum_k ||X_k||^2 after the 6 R R + 1st.
 template <int R>
 __global__ __launch_bounds__(EPI_THREADS) void k_pl_h(PlainArgs a) {
-  constexpr int LD = 33, RR = R * R;
-  __shared__ double G1[32 * LD], Gm[32 * LD], Gi[32 * LD], sT[32 * LD], sV[32 * LD], sg[32];
+  constexpr int LD = RC<R>::LD, MR = RC<R>::MR, RR = R * R;
+  __shared__ double G1[MR * LD], Gm[MR * LD], Gi[MR * LD], sT[MR * LD], sV[MR * LD], sg[MR];
   __shared__ int sflag;
   const int tid = threadIdx.x;
   if (a.ctl->done) return;
@@ -292,8 +292,8 @@ __global__ __launch_bounds__(256) void k_pl_v(PlainArgs a) {
 // pass; H^T H * V^T V and (V^T V * H^T H)^dagger.  One block.
 template <int R>
 __global__ __launch_bounds__(EPI_THREADS) void k_pl_vupd(PlainArgs a) {
-  constexpr int LD = 33, RR = R * R;
-  __shared__ double Gm[32 * LD], Gi[32 * LD], sT[32 * LD], sV[32 * LD], sg[32], nrm[32], red[16];
+  constexpr int LD = RC<R>::LD, MR = RC<R>::MR, RR = R * R;
+  __shared__ double Gm[MR * LD], Gi[MR * LD], sT[MR * LD], sV[MR * LD], sg[MR], nrm[MR], red[16];
   __shared__ int sflag;
   const int tid = threadIdx.x, J = a.J;
   if (a.ctl->done) return;
@@ -488,6 +488,40 @@ __global__ __launch_bounds__(64) void k_pl_theta(PlainArgs a) {
     for (int i = 0; i < R; ++i) s = fma(th[p * R + i], sH[i * R + q], s);
     T[e] = s;
   }
+}
+
+// the launch sequence of one phase (0 begin, 1 iteration, 2 U output)
+template <int R>
+inline hipError_t plain_launch(int phase, const PlainArgs& a, const PlainLaunch& pl, hipStream_t s) {
+  constexpr int RR = R * R;
+  const int64_t K = a.K;
+  const int J = a.J;
+  hipError_t e;
+  if (phase == 0) {   // begin
+    hipLaunchKernelGGL(k_pl_begin<R>, dim3(1), dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
+  if (phase == 2) {   // U output: Theta_k H
+    hipLaunchKernelGGL(k_pl_theta<R>, dim3((unsigned)K), dim3(64), 0, s, a);
+    return hipGetLastError();
+  }
+  const int n = J * R;
+  hipLaunchKernelGGL(k_pl_commit, dim3((unsigned)std::min(64, (n + 255) / 256)), dim3(256), 0, s, a, n);
+  if ((e = launch_slab(pl.slab, pl.dtype, pl.n_items, pl.vec, false, pl.wide, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pl_slice<R>, dim3((unsigned)K), dim3(64), 0, s, a);
+  if ((e = launch_segsum(1, nullptr, K, RR, RR, a.g1p, a.red, RR, s)) != hipSuccess) return e;
+  if ((e = launch_segsum(1, nullptr, K, 1, 1, a.xnorm2, a.red + RED_WIDTH * RR + 1, 1, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pl_h<R>, dim3(1), dim3(EPI_THREADS), 0, s, a);
+  const unsigned nvb = (unsigned)((K + PL_VSLICES - 1) / PL_VSLICES);
+  hipLaunchKernelGGL(k_pl_v<R>, dim3(nvb, (unsigned)((J + 255) / 256)), dim3(256), 0, s, a);
+  if ((e = launch_segsum(1, nullptr, nvb, (int64_t)J * R, (int64_t)J * R, a.g2p, a.g2, (int64_t)J * R, s)) !=
+      hipSuccess)
+    return e;
+  hipLaunchKernelGGL(k_pl_vupd<R>, dim3(1), dim3(EPI_THREADS), 0, s, a);
+  hipLaunchKernelGGL(k_pl_w<R>, dim3((unsigned)K), dim3(64), 0, s, a);
+  if ((e = launch_segsum(1, nullptr, K, RR + 2, RR + 2, a.wp, a.red + 2 * RR, RR + 2, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pl_err<R>, dim3(1), dim3(64), 0, s, a);
+  return hipGetLastError();
 }
 
 }  // namespace dpar2

@@ -27,23 +27,27 @@ namespace dpar2 {
 // chunk of 32 columns, A from the L x LD matrix `a` (column r of a = row r of
 // the product), B from the chunk `b` (row stride CP); acc[tr][tj] is the
 // 16 x 16 tile (rows 16 tr, columns 16 tj), lane l holding rows
-// f64_row(l, v) and column l % 16.  All 64 lanes take part.
-template <int L, int LD, int CP>
-__device__ __forceinline__ void chunk_atb(const double* a, const double* b, int nrow, v4d (&acc)[2][2],
+// f64_row(l, v) and column l % 16; nrow <= 16 TRN.  All 64 lanes take part.
+template <int L>
+constexpr int row_tiles() { return L > 32 ? 4 : 2; }
+
+template <int L, int LD, int CP, int TRN>
+__device__ __forceinline__ void chunk_atb(const double* a, const double* b, int nrow, v4d (&acc)[TRN][2],
                                           int lane) {
   const int i16 = lane & 15, k4 = lane >> 4;
 #pragma unroll
   for (int kk = 0; kk < (L + 3) / 4; ++kk) {
     const int k = 4 * kk + k4;
-    double av[2], bv[2];
+    double av[TRN], bv[2];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < TRN; ++t) {
       const int r = 16 * t + i16;
       av[t] = (k < L && r < nrow) ? a[k * LD + r] : 0.0;
-      bv[t] = (k < L) ? b[k * CP + 16 * t + i16] : 0.0;
     }
 #pragma unroll
-    for (int tr = 0; tr < 2; ++tr) {
+    for (int t = 0; t < 2; ++t) bv[t] = (k < L) ? b[k * CP + 16 * t + i16] : 0.0;
+#pragma unroll
+    for (int tr = 0; tr < TRN; ++tr) {
       if (16 * tr >= nrow) continue;   // wave-uniform
 #pragma unroll
       for (int tj = 0; tj < 2; ++tj) acc[tr][tj] = mfma_f64(av[tr], bv[tj], acc[tr][tj]);
@@ -62,6 +66,7 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
                                                   float* __restrict__ msgn, Ctl* ctl,
                                                   const int32_t* __restrict__ slice_t) {
   constexpr int RM = SC<L>::RM, LH = SC<L>::LH, LD = SC<L>::LD, CW = SC<L>::CW, LL = L * L;
+  constexpr int TRN = row_tiles<L>();   // 16-row tiles of the L- and R-row products
   constexpr int CP = CW + 1;        // padded chunk row (conflict-free column reads)
   constexpr int NPX = (L * CP > L * LD) ? L * CP : L * LD;
   // G and its Cholesky factors are not needed while P is streamed: the chunks
@@ -198,11 +203,11 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
   // B_c = Wh^T P_c, and then S += B_c B_c^T.  (Forming P P^T before the
   // whitening would square the condition of Y as well as that of B: a slice
   // with one dominant row then loses its small singular values.)
-  v4d sacc[2][2];
+  v4d sacc[TRN][TRN];
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < TRN; ++x)
 #pragma unroll
-    for (int y2 = 0; y2 < 2; ++y2) sacc[x][y2] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int y2 = 0; y2 < TRN; ++y2) sacc[x][y2] = v4d{0.0, 0.0, 0.0, 0.0};
   {
     const int i16 = lane & 15, k4 = lane >> 4;
     fetch(0);
@@ -210,14 +215,14 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
       stash();
       if (jc + CW < J) fetch(jc + CW);
       __syncthreads();
-      v4d bacc[2][2];
+      v4d bacc[TRN][2];
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
+      for (int x = 0; x < TRN; ++x)
 #pragma unroll
         for (int y2 = 0; y2 < 2; ++y2) bacc[x][y2] = v4d{0.0, 0.0, 0.0, 0.0};
-      chunk_atb<L, LD, CP>(Ws, Pc, L, bacc, lane);
+      chunk_atb<L, LD, CP, TRN>(Ws, Pc, L, bacc, lane);
 #pragma unroll
-      for (int tr = 0; tr < 2; ++tr)
+      for (int tr = 0; tr < TRN; ++tr)
 #pragma unroll
         for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
@@ -229,21 +234,22 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
 #pragma unroll
       for (int kk = 0; kk < CW / 4; ++kk) {
         const int j = 4 * kk + k4;
-        double bv2[2];
+        double bv2[TRN];
 #pragma unroll
-        for (int t = 0; t < 2; ++t) bv2[t] = (16 * t + i16 < L) ? Mc[(16 * t + i16) * CP + j] : 0.0;
-        sacc[0][0] = mfma_f64(bv2[0], bv2[0], sacc[0][0]);
-        if (L > 16) {
-          sacc[0][1] = mfma_f64(bv2[0], bv2[1], sacc[0][1]);
-          sacc[1][1] = mfma_f64(bv2[1], bv2[1], sacc[1][1]);
-        }
+        for (int t = 0; t < TRN; ++t) bv2[t] = (16 * t + i16 < L) ? Mc[(16 * t + i16) * CP + j] : 0.0;
+        // the upper triangle of tiles that L covers
+#pragma unroll
+        for (int tr = 0; tr < TRN; ++tr)
+#pragma unroll
+          for (int tj = tr; tj < TRN; ++tj)
+            if (16 * tj < L) sacc[tr][tj] = mfma_f64(bv2[tr], bv2[tj], sacc[tr][tj]);
       }
       __syncthreads();
     }
 #pragma unroll
-    for (int tr = 0; tr < 2; ++tr)
+    for (int tr = 0; tr < TRN; ++tr)
 #pragma unroll
-      for (int tj = tr; tj < 2; ++tj)
+      for (int tj = tr; tj < TRN; ++tj)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int a = 16 * tr + f64_row(lane, v), b = 16 * tj + i16;
@@ -331,14 +337,14 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
       stash();
       if (jc + CW < J) fetch(jc + CW);
       __syncthreads();
-      v4d oacc[2][2];
+      v4d oacc[TRN][2];
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
+      for (int x = 0; x < TRN; ++x)
 #pragma unroll
         for (int y2 = 0; y2 < 2; ++y2) oacc[x][y2] = v4d{0.0, 0.0, 0.0, 0.0};
-      chunk_atb<L, LD, CP>(Ss, Pc, L, oacc, lane);
+      chunk_atb<L, LD, CP, TRN>(Ss, Pc, L, oacc, lane);
 #pragma unroll
-      for (int tr = 0; tr < 2; ++tr)
+      for (int tr = 0; tr < TRN; ++tr)
 #pragma unroll
         for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
@@ -360,14 +366,14 @@ __global__ __launch_bounds__(64) void k_slice_fin(int K, int J, int R, const int
     stash();
     if (jc + CW < J) fetch(jc + CW);
     __syncthreads();
-    v4d macc[2][2];
+    v4d macc[TRN][2];
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < TRN; ++x)
 #pragma unroll
       for (int y2 = 0; y2 < 2; ++y2) macc[x][y2] = v4d{0.0, 0.0, 0.0, 0.0};
-    chunk_atb<L, LD, CP>(Ss, Pc, R, macc, lane);
+    chunk_atb<L, LD, CP, TRN>(Ss, Pc, R, macc, lane);
 #pragma unroll
-    for (int tr = 0; tr < 2; ++tr)
+    for (int tr = 0; tr < TRN; ++tr)
 #pragma unroll
       for (int tj = 0; tj < 2; ++tj)
 #pragma unroll

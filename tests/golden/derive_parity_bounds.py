@@ -171,6 +171,17 @@ def rank_r(R):
     return make
 
 
+def large_rank(K, lo, hi, J, R, seed):
+    """Ranks above 32 (one slice per 64-lane group in the iteration, the
+    slab pass's four 16-column tiles of Y, the 64-lane factorisations of the
+    L x L and L2 x L2 matrices): K slices with I_k in [lo, hi], rank-R
+    PARAFAC2 + N(0, 0.02^2)."""
+    def make():
+        rows = synth.uniform_rows(K, lo, hi, seed)
+        return synth.parafac2(rows, J, R, seed, noise_abs=0.02)
+    return make
+
+
 # name -> (tensor factory, R, L, iterations); the GPU tests use the same cases
 CASES = {
     "small_parity": (lambda: synth.small_parity(), 5, 15, 100),
@@ -180,6 +191,9 @@ CASES = {
     "rank20_J520": (rank20_long_j, 20, 30, 30),
     "rank12_J48": (rank_r(12), 12, 22, 20),
     "rank28_J48": (rank_r(28), 28, 32, 20),
+    "rank40_J600": (large_rank(30, 60, 200, 600, 40, 4040), 40, 50, 10),
+    "rank40_J96": (large_rank(40, 40, 150, 96, 40, 4041), 40, 40, 10),
+    "rank50_L60_J300": (large_rank(24, 70, 250, 300, 50, 5060), 50, 60, 10),
 }
 
 
@@ -267,6 +281,7 @@ PLAIN_CASES = {
     "plain_stock_K60": (lambda: synth.stock_like(K=60), 10, 60, 1e-2),
     "plain_ragged_J300": (plain_ragged(300), 4, 20, -1.0),
     "plain_ragged_J40": (plain_ragged(40), 4, 20, -1.0),
+    "plain_rank40_J300": (large_rank(20, 50, 200, 300, 40, 4042), 40, 10, -1.0),
 }
 
 

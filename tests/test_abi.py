@@ -68,6 +68,23 @@ def test_invalid_arguments_are_rejected_on_host(offsets, opts, status):
     assert lib.dpar2_workspace_size(ctypes.byref(t), ctypes.byref(o)) == 0
 
 
+def test_rank_and_sketch_width_sets():
+    """Ranks 1..32 and, above, 40 and 50; sketch widths 1..32 and 40, 50, 60
+    (every other value is a shape error before anything is enqueued)."""
+    binding, lib = _lib()
+    off = np.array([0, 80, 160], dtype=np.int64)
+    hp = off.ctypes.data_as(ctypes.c_void_p).value
+    t = binding.c_tensor(2, 600, 0x1000, hp, 0x2000, binding.DPAR2_F32, None)
+    for R, L, L2, ok in [(40, 50, 50, True), (50, 60, 60, True), (40, 40, 40, True), (32, 60, 40, True),
+                         (33, 40, 40, False), (48, 50, 50, False), (40, 45, 50, False), (40, 50, 64, False),
+                         (64, 64, 64, False), (50, 60, 70, False)]:
+        o = binding.c_opts(R, L, L2, 5, -1.0, 0)
+        need = lib.dpar2_workspace_size(ctypes.byref(t), ctypes.byref(o))
+        assert (need > 0) == ok, (R, L, L2)
+        if not ok:
+            assert _status(lib, binding, t, o) == -2, (R, L, L2)
+
+
 def test_workspace_checks():
     binding, lib = _lib()
     t, _keep = _tensor(binding, [0, 10, 25, 40])
