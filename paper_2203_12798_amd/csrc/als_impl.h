@@ -406,14 +406,22 @@ template <int R>
 __global__ __launch_bounds__(RC<R>::TPB) void k_als_A(AlsArgs a) {
   ALS_BLOCK_PROLOGUE(R)
   constexpr int RM = RC<R>::RM, GPB = RC<R>::GPB, TPB = RC<R>::TPB, RR = R * R;
-  __shared__ double sH[RR], sB[RR];
-  __shared__ double sF[GPB * RR], sZ[GPB * RR], sP[GPB * RR], sT[GPB * RR], sW[GPB * R];
+  // above R = 32 (one slice per 64-lane block) H, Bm and F^(k) are read from
+  // global memory where they are used and Z_k takes the place of T_k once
+  // T_k has been read for the last time (one wave: its LDS accesses stay in
+  // order), so that four blocks share a compute unit's LDS
+  constexpr bool GO = R > 32;
+  __shared__ double sH[GO ? 1 : RR], sB[GO ? 1 : RR];
+  __shared__ double sF[GO ? 1 : GPB * RR], sZ[GO ? 1 : GPB * RR], sP[GPB * RR], sT[GPB * RR], sW[GPB * R];
   const int64_t K = bk.s1;   // slices bk.s0 .. bk.s1 - 1 (at most GPB)
   const int tid = threadIdx.x, g = tid / RM, j = tid % RM;
   const int lane = tid & 63, gbase = lane & ~(RM - 1);
   const double* Bm = small + SM_BM * RR;
-  double* F_ = sF + g * RR;
-  double* Z_ = sZ + g * RR;
+  const double* Hs = GO ? td.H : sH;
+  const double* Bs = GO ? Bm : sB;
+  double* Fl = sF + g * RR;
+  const double* F_ = GO ? a.F + (size_t)bk.s0 * RR : Fl;
+  double* Z_ = (GO ? sT : sZ) + g * RR;
   double* P_ = sP + g * RR;
   double* T_ = sT + g * RR;
   double acc[R];
@@ -426,13 +434,15 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_A(AlsArgs a) {
     const bool live = (k < K) && (j < R);
     // every global read of the slice set-up is issued before the stop flag
     // is tested (one round of loads)
-    constexpr int NS = (RR + TPB - 1) / TPB;
+    constexpr int NS = GO ? 1 : (RR + TPB - 1) / TPB;
     double hv[NS], bv[NS];
+    if constexpr (!GO) {
 #pragma unroll
-    for (int u = 0; u < NS; ++u) {
-      const int e = tid + TPB * u;
-      hv[u] = (e < RR) ? td.H[e] : 0.0;
-      bv[u] = (e < RR) ? Bm[e] : 0.0;
+      for (int u = 0; u < NS; ++u) {
+        const int e = tid + TPB * u;
+        hv[u] = (e < RR) ? td.H[e] : 0.0;
+        bv[u] = (e < RR) ? Bm[e] : 0.0;
+      }
     }
     constexpr int NF = (RR + RM - 1) / RM;   // loads issued together (clamped index)
     // F^(k) and the previous P_k (row-major, as flat arrays) and W(k, j):
@@ -442,25 +452,29 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_A(AlsArgs a) {
     for (int u = 0; u < NF; ++u) {
       const int e = j + RM * u;
       const bool ok = k < K && e < RR;
-      const double x = a.F[ok ? (size_t)k * RR + e : 0];
       const double y = a.Pw[ok ? (size_t)k * RR + e : 0];
-      fv[u] = ok ? x : 0.0;
       pv[u] = ok ? y : 0.0;
+      if constexpr (!GO) {
+        const double x = a.F[ok ? (size_t)k * RR + e : 0];
+        fv[u] = ok ? x : 0.0;
+      }
     }
     const double wkj = live ? td.W[(size_t)(k - td.k0) * R + j] : 0.0;
     if (ctl->done) return;
+    if constexpr (!GO) {
 #pragma unroll
-    for (int u = 0; u < NS; ++u) {
-      const int e = tid + TPB * u;
-      if (e < RR) {
-        sH[e] = hv[u];
-        sB[e] = bv[u];
+      for (int u = 0; u < NS; ++u) {
+        const int e = tid + TPB * u;
+        if (e < RR) {
+          sH[e] = hv[u];
+          sB[e] = bv[u];
+        }
       }
     }
 #pragma unroll
     for (int u = 0; u < NF; ++u)
       if (j + RM * u < RR) {
-        F_[j + RM * u] = fv[u];
+        if constexpr (!GO) Fl[j + RM * u] = fv[u];
         P_[j + RM * u] = pv[u];
       }
     if (live) sW[g * R + j] = wkj;
@@ -474,9 +488,9 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_A(AlsArgs a) {
       for (int i = 0; i < R; ++i) x[i] = 0.0;
 #pragma unroll
       for (int i = 0; i < R; ++i) {
-        const double y = sW[g * R + i] * sH[(live ? j : 0) * R + i];
+        const double y = sW[g * R + i] * Hs[(live ? j : 0) * R + i];
 #pragma unroll
-        for (int q = 0; q < R; ++q) x[q] = fma(sB[q * R + i], y, x[q]);
+        for (int q = 0; q < R; ++q) x[q] = fma(Bs[q * R + i], y, x[q]);
       }
       if (live) {
 #pragma unroll
@@ -581,14 +595,14 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_A(AlsArgs a) {
 #pragma unroll
       for (int i = 0; i < R; ++i)
 #pragma unroll
-        for (int q = 0; q < R; ++q) sq[q] = fma(Z_[q * R + i], sB[i * R + j], sq[q]);
+        for (int q = 0; q < R; ++q) sq[q] = fma(Z_[q * R + i], Bs[i * R + j], sq[q]);
 #pragma unroll
       for (int q = 0; q < R; ++q) acc[q] = fma(wj, sq[q], acc[q]);
     }
   }
   for (int o = 1; o < 64; o <<= 1) warn |= __shfl_xor((int)warn, o, 64);
   if (lane == 0 && warn) atomicOr(&ctl->warn, warn);
-  block_partial_out<R>(acc, sZ, a.partA + (size_t)blockIdx.x * RR);
+  block_partial_out<R>(acc, GO ? sT : sZ, a.partA + (size_t)blockIdx.x * RR);
 }
 
 // H = G1 (W^T W * V^T V)^dagger, unit columns; H^T H.
@@ -801,7 +815,10 @@ template <int R>
 __global__ __launch_bounds__(RC<R>::TPB) void k_als_C(AlsArgs a) {
   ALS_BLOCK_PROLOGUE(R)
   constexpr int RM = RC<R>::RM, GPB = RC<R>::GPB, TPB = RC<R>::TPB, RR = R * R;
-  __shared__ double sH[RR], sB[RR], sGi[RR], sHV[RR];
+  // above R = 32 (one slice per block) the small state is read from global
+  // memory where it is used, so that several blocks share a compute unit's LDS
+  constexpr bool GO = R > 32;
+  __shared__ double sH[GO ? 1 : RR], sB[GO ? 1 : RR], sGi[GO ? 1 : RR], sHV[GO ? 1 : RR];
   __shared__ double sM[GPB * RR];
   __shared__ double sRed[TPB * 2];
   const int64_t K = bk.s1;
@@ -817,16 +834,18 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_C(AlsArgs a) {
     const int64_t k = base + g;
     const bool live = (k < K) && (j < R);
     // the small state and M_k read before the stop flag is tested
-    constexpr int NS = (RR + TPB - 1) / TPB, NM = (RR + RM - 1) / RM;
+    constexpr int NS = GO ? 1 : (RR + TPB - 1) / TPB, NM = (RR + RM - 1) / RM;
     double hv[NS], bv[NS], gv[NS], qv[NS], mv[NM];
+    if constexpr (!GO) {
 #pragma unroll
-    for (int u = 0; u < NS; ++u) {
-      const int e = tid + TPB * u;
-      const bool ok = e < RR;
-      hv[u] = ok ? td.H[e] : 0.0;
-      bv[u] = ok ? small[SM_BM * RR + e] : 0.0;
-      gv[u] = ok ? small[SM_G3INV * RR + e] : 0.0;
-      qv[u] = ok ? small[SM_HV * RR + e] : 0.0;
+      for (int u = 0; u < NS; ++u) {
+        const int e = tid + TPB * u;
+        const bool ok = e < RR;
+        hv[u] = ok ? td.H[e] : 0.0;
+        bv[u] = ok ? small[SM_BM * RR + e] : 0.0;
+        gv[u] = ok ? small[SM_G3INV * RR + e] : 0.0;
+        qv[u] = ok ? small[SM_HV * RR + e] : 0.0;
+      }
     }
 #pragma unroll
     for (int u = 0; u < NM; ++u) {
@@ -834,16 +853,22 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_C(AlsArgs a) {
       mv[u] = (k < K && e < RR) ? a.Mk[(size_t)k * RR + e] : 0.0;
     }
     if (ctl->done) return;
+    if constexpr (!GO) {
 #pragma unroll
-    for (int u = 0; u < NS; ++u) {
-      const int e = tid + TPB * u;
-      if (e < RR) {
-        sH[e] = hv[u];
-        sB[e] = bv[u];
-        sGi[e] = gv[u];
-        sHV[e] = qv[u];
+      for (int u = 0; u < NS; ++u) {
+        const int e = tid + TPB * u;
+        if (e < RR) {
+          sH[e] = hv[u];
+          sB[e] = bv[u];
+          sGi[e] = gv[u];
+          sHV[e] = qv[u];
+        }
       }
     }
+    const double* Hs = GO ? td.H : sH;
+    const double* Bs = GO ? small + SM_BM * RR : sB;
+    const double* Gis = GO ? small + SM_G3INV * RR : sGi;
+    const double* HVs = GO ? small + SM_HV * RR : sHV;
 #pragma unroll
     for (int u = 0; u < NM; ++u) {
       const int e = j + RM * u;
@@ -858,9 +883,9 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_C(AlsArgs a) {
 #pragma unroll
       for (int i = 0; i < R; ++i)
 #pragma unroll
-        for (int q = 0; q < R; ++q) sq[q] = fma(M_[q * R + i], sB[i * R + j], sq[q]);
+        for (int q = 0; q < R; ++q) sq[q] = fma(M_[q * R + i], Bs[i * R + j], sq[q]);
 #pragma unroll
-      for (int q = 0; q < R; ++q) g3 = fma(sH[q * R + j], sq[q], g3);
+      for (int q = 0; q < R; ++q) g3 = fma(Hs[q * R + j], sq[q], g3);
     }
     double gs[R];
 #pragma unroll
@@ -868,7 +893,7 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_C(AlsArgs a) {
     double wnew = 0.0;
     if (live) {
 #pragma unroll
-      for (int s = 0; s < R; ++s) wnew = fma(gs[s], sGi[s * R + j], wnew);
+      for (int s = 0; s < R; ++s) wnew = fma(gs[s], Gis[s * R + j], wnew);
       td.W[(size_t)(k - td.k0) * R + j] = wnew;
       ewg = fma(wnew, g3, ewg);
     }
@@ -879,7 +904,7 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_als_C(AlsArgs a) {
       double q2 = 0.0;
 #pragma unroll
       for (int s = 0; s < R; ++s) {
-        q2 = fma(sHV[j * R + s], ws[s], q2);
+        q2 = fma(HVs[j * R + s], ws[s], q2);
         wtw[s] = fma(ws[s], wnew, wtw[s]);
       }
       equad = fma(wnew, q2, equad);
@@ -1017,7 +1042,12 @@ template <int R>
 __global__ __launch_bounds__(RC<R>::TPB) void k_fit_rows(AlsArgs a) {
   ALS_BLOCK_PROLOGUE(R)
   constexpr int GPB = RC<R>::GPB, TPB = RC<R>::TPB, RR = R * R;
-  __shared__ double sQ[GPB * RR], sP[GPB * RR], sH[RR], sHV[RR], sW[GPB * R], sT[2 * TPB];
+  // above R = 32 (one slice per block) H, H^T H * V^T V and Psi_k are read
+  // from global memory where they are used, so that several blocks share a
+  // compute unit's LDS
+  constexpr bool GO = R > 32;
+  __shared__ double sQ[GPB * RR], sP[GO ? 1 : GPB * RR], sH[GO ? 1 : RR], sHV[GO ? 1 : RR], sW[GPB * R];
+  __shared__ double sT[2 * TPB];
   (void)ctl;
   const int tid = threadIdx.x, g = tid / R, r = tid % R;
   const int J = a.J;
@@ -1046,14 +1076,18 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_fit_rows(AlsArgs a) {
 #pragma unroll
     for (int c = 0; c < R; ++c) acc[c] = fma(m, vr[c], acc[c]);
   }
-  for (int e = tid; e < RR; e += TPB) {
-    sH[e] = td.H[e];
-    sHV[e] = small[SM_HV * RR + e];
+  if constexpr (!GO) {
+    for (int e = tid; e < RR; e += TPB) {
+      sH[e] = td.H[e];
+      sHV[e] = small[SM_HV * RR + e];
+    }
+    for (int e = tid; e < GPB * RR; e += TPB) {
+      const int64_t kk = bk.s0 + e / RR;
+      sP[e] = kk < bk.s1 ? a.Psi[(size_t)kk * RR + e % RR] : 0.0;
+    }
   }
-  for (int e = tid; e < GPB * RR; e += TPB) {
-    const int64_t kk = bk.s0 + e / RR;
-    sP[e] = kk < bk.s1 ? a.Psi[(size_t)kk * RR + e % RR] : 0.0;
-  }
+  const double* Hs = GO ? td.H : sH;
+  const double* HVs = GO ? small + SM_HV * RR : sHV;
   for (int e = tid; e < GPB * R; e += TPB) {
     const int64_t kk = bk.s0 + e / R;
     sW[e] = kk < bk.s1 ? td.W[(size_t)(kk - td.k0) * R + e % R] : 0.0;
@@ -1066,17 +1100,17 @@ __global__ __launch_bounds__(RC<R>::TPB) void k_fit_rows(AlsArgs a) {
   double tr = 0.0, qd = 0.0;
   if (live) {
     const double* Q = sQ + g * RR;
-    const double* P = sP + g * RR;
+    const double* P = GO ? a.Psi + (size_t)k * RR : sP + g * RR;
     double x = 0.0;
     for (int aa = 0; aa < R; ++aa) {
       double y = 0.0;
       for (int b = 0; b < R; ++b) y += P[b * R + aa] * Q[b * R + r];
-      x += sH[aa * R + r] * y;
+      x += Hs[aa * R + r] * y;
     }
     const double wr = sW[g * R + r];
     tr = wr * x;
     double q = 0.0;
-    for (int s2 = 0; s2 < R; ++s2) q += sHV[r * R + s2] * sW[g * R + s2];
+    for (int s2 = 0; s2 < R; ++s2) q += HVs[r * R + s2] * sW[g * R + s2];
     qd = wr * q;
   }
   sT[2 * tid] = tr;
