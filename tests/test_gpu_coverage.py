@@ -19,7 +19,12 @@ case), and per-row checks next to the Frobenius ones:
   * float32 slabs with 128 < J <= 256 (the FP64 matrix-core Gram and
     projection), with 4-element and scalar loads;
   * the rank instantiations R = 12 (L = 22) and R = 28 (L = 32, four
-    oversampled columns only)."""
+    oversampled columns only);
+  * the ranks above 32: R = 40 with L = 50 at J = 600 (the second stage's
+    J-long steps), R = L = 40 at J = 96 (the chunked slab pass below the
+    whole-row limit, taken for every J above L = 32) and R = 50 with L = 60
+    at J = 300 (one slice per 64-lane block in the iteration, four
+    16-column tiles of Y in the slab pass)."""
 import json
 import os
 
