@@ -64,18 +64,28 @@ def item_ranges(n: int):
     return [(n * c // nc, n * (c + 1) // nc) for c in range(nc)]
 
 
-def emulated_stage1(Xk: np.ndarray, omega: np.ndarray, R: int):
+def emulated_stage1(Xk: np.ndarray, omega: np.ndarray, R: int, q: int = 0):
     """(A_k, sigma, C_k) as the slab pass and the per-slice FP64 completion
-    compute them: exact randomized SVD of the rounded (Y, X) pair."""
+    compute them: exact randomized SVD of the rounded (Y, X) pair.  With q
+    power steps, each step's sketch matrix is the slice's right singular
+    basis of B (all L columns; those of a singular value below 64 eps of the
+    largest set to zero) rounded to float32, as the completion writes it for
+    the next slab pass."""
     X = np.asarray(Xk, dtype=np.float64)
-    Y = (X @ np.asarray(omega, dtype=np.float64)).astype(np.float32).astype(np.float64)
     starts = item_ranges(X.shape[0])
-    Yq, Xq = tile_round(Y, starts), tile_round(X, starts)
-    G = Yq.T @ Yq
-    P = Yq.T @ Xq
-    Rc = np.linalg.cholesky(G).T            # G = Rc^T Rc
-    B = np.linalg.solve(Rc.T, P)            # Q^T X with Q = Yq Rc^-1
-    Ut, s, Vt = np.linalg.svd(B, full_matrices=False)
+    Xq = tile_round(X, starts)
+    om = np.asarray(omega, dtype=np.float64)
+    for step in range(q + 1):
+        Y = (X @ om).astype(np.float32).astype(np.float64)
+        Yq = tile_round(Y, starts)
+        G = Yq.T @ Yq
+        P = Yq.T @ Xq
+        Rc = np.linalg.cholesky(G).T            # G = Rc^T Rc
+        B = np.linalg.solve(Rc.T, P)            # Q^T X with Q = Yq Rc^-1
+        Ut, s, Vt = np.linalg.svd(B, full_matrices=False)
+        if step < q:
+            keep = s > 64.0 * np.finfo(np.float64).eps * s[0]
+            om = (Vt.T * keep[None, :]).astype(np.float32).astype(np.float64)
     V = Vt[:R].T
     sg = np.sign(V[np.argmax(np.abs(V), axis=0), np.arange(R)])
     sg[sg == 0] = 1.0
@@ -83,13 +93,13 @@ def emulated_stage1(Xk: np.ndarray, omega: np.ndarray, R: int):
     return A, s[:R], V * sg[None, :]
 
 
-def emulated_dpar2(X, R, om1, om2, H0, V0, W0, iters):
+def emulated_dpar2(X, R, om1, om2, H0, V0, W0, iters, q=0):
     K, J = X.K, X.J
     A, C, Bd = [], [], np.zeros((K, R))
     xn = np.zeros(K)
     for k in range(K):
         Xk = X.slice(k)
-        a, s, c = emulated_stage1(Xk, om1, R)
+        a, s, c = emulated_stage1(Xk, om1, R, q)
         A.append(a)
         C.append(c)
         Bd[k] = s
@@ -195,6 +205,59 @@ CASES = {
     "rank40_J96": (large_rank(40, 40, 150, 96, 40, 4041), 40, 40, 10),
     "rank50_L60_J300": (large_rank(24, 70, 250, 300, 50, 5060), 50, 60, 10),
 }
+
+
+def wide_case(K, J, R, lo, hi, seed, kind="f32"):
+    """The chunked slab pass's parity tensors: K slices with I_k in [lo, hi],
+    rank-R PARAFAC2 + N(0, 0.02^2); kind "bf16" / "fp8": the slab as the
+    library reads it after encoding (the oracle runs on the decoded values)."""
+    def make():
+        X = synth.parafac2(synth.uniform_rows(K, lo, hi, seed), J, R, seed, noise_abs=0.02)
+        if kind == "bf16":
+            return synth.IrregularTensor(slab=synth.decode_bf16(synth.encode_bf16(X.slab)), offsets=X.offsets)
+        if kind == "fp8":
+            codes, scale = synth.encode_fp8(X.slab, X.offsets)
+            return synth.IrregularTensor(slab=synth.decode_fp8(codes, X.offsets, scale), offsets=X.offsets)
+        return X
+    return make
+
+
+# one power step (q = 1): name -> (tensor factory, R, L, iterations, Omega_1
+# rounded to bf16); tests/test_gpu_wide.py uses the same cases.  From a random
+# start the early iterations of ALS amplify the difference between the FP32
+# sketch matrices of the power step and the oracle's FP64 ones, so the error
+# trace gets a bound of its own here.
+POWER_CASES = {
+    "wide_q1_J517": (wide_case(9, 517, 4, 40, 300, 517), 4, 12, 30, False),
+    "wide_q1_J2049_fp8": (wide_case(8, 2049, 5, 40, 200, 2057, "fp8"), 5, 12, 30, True),
+    "wide_q1_J2049_bf16": (wide_case(8, 2049, 5, 40, 200, 2057, "bf16"), 5, 12, 30, True),
+}
+
+
+def measure_power(name):
+    make, R, L, iters, om_bf16 = POWER_CASES[name]
+    X = make()
+    om1, om2 = synth.omegas(X.J, L, X.K * R)
+    if om_bf16:
+        om1 = synth.round_bf16(om1)
+    H0, V0, W0 = synth.init_factors(X.J, X.K, R)
+    ref = O.dpar2(X.slab, X.offsets, R, om1, om2, H0, V0, W0, iters, q=1)
+    comp, st, U, fit = emulated_dpar2(X, R, om1, om2, H0, V0, W0, iters, q=1)
+    c = ref.comp
+    Hg, Vg, Wg = canonical(st.H, st.V, st.W)
+    Hr, Vr, Wr = canonical(ref.state.H, ref.state.V, ref.state.W)
+    model = lambda H, V, W: np.einsum("ir,kr,jr->kij", H, W, V)
+    e, er = np.asarray(st.errors), np.asarray(ref.state.errors)
+    return {
+        "sigma": float(np.max(np.abs(comp.Bdiag - c.Bdiag) / c.Bdiag)),
+        "M": rel(comp.M, c.M),
+        "errors": float(np.max(np.abs(e - er) / er)),
+        "V": rel(Vg, Vr),
+        "W": rel(Wg, Wr),
+        "model": rel(model(st.H, st.V, st.W), model(ref.state.H, ref.state.V, ref.state.W)),
+        "U": rel(np.concatenate(U), np.concatenate(ref.U)),
+        "fit": abs(fit - ref.fit),
+    }
 
 
 def measure(name):
@@ -313,6 +376,10 @@ def main():
     out = {"safety": SAFETY, "cases": {}, "bounds": {}}
     for name in CASES:
         m = measure(name)
+        out["cases"][name] = m
+        print(name, {k: f"{v:.2e}" for k, v in m.items()}, flush=True)
+    for name in POWER_CASES:
+        m = measure_power(name)
         out["cases"][name] = m
         print(name, {k: f"{v:.2e}" for k, v in m.items()}, flush=True)
     for name in PLAIN_CASES:

@@ -5,6 +5,9 @@ the FP64 oracle.  Same tolerances as the narrow path; ragged tiles (rows not a
 multiple of 64), J not a multiple of 4 (scalar loads) and of 128 (partial last
 chunk), both sketch widths (L <= 16 and L > 16), the U output, a power step
 and the low-precision inputs."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -15,6 +18,23 @@ from tests.test_gpu_forms import _lp_tensor
 from tests.test_gpu_parity import _check_compression, _check_errors, _check_factors, _run_gpu
 
 pytestmark = pytest.mark.gpu
+
+# error-trace bounds of the power-step cases, from the CPU emulation of the
+# slab pass (tests/golden/derive_parity_bounds.py, POWER_CASES)
+BOUNDS = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                     "parity_bounds.json")))["bounds"]
+
+
+def _check_errors_power(g, ref, case):
+    """Per-iteration error with one power step: the GPU keeps each slice's
+    next sketch matrix in FP32 (the oracle in FP64), and the early iterations
+    of ALS from a random start amplify that difference; the relative bound is
+    the emulation's deviation of the trace times 4 (at least 1e-6)."""
+    e_ref = np.asarray(ref.state.errors)
+    e0 = float(np.sum(ref.comp.E ** 2))
+    dev = float(np.max(np.abs(g["err"] - e_ref) / e_ref))
+    print(f"[wide] {case}: error trace {dev:.2e} (bound {BOUNDS[case]['errors']:.1e})", flush=True)
+    np.testing.assert_allclose(g["err"], e_ref, rtol=BOUNDS[case]["errors"], atol=1e-12 * e0)
 
 
 def _case(K, J, R, lo, hi, seed, noise=0.02):
@@ -35,12 +55,9 @@ def test_wide_float32_matches_oracle(J, R, L, q):
     g = _run_gpu(X, R, L, L, iters, om1, om2, H0, V0, W0, want_U=True, power_iters=q)
     _check_compression(X, R, g, ref)
     if q == 0:
-        # with a power step the GPU keeps each slice's next sketch matrix in
-        # FP32 (the oracle in FP64); the slow early phase of ALS from a random
-        # start amplifies that difference in the error trace beyond 1e-6,
-        # while the compression above, the factors and the fitness below stay
-        # within their bounds
         _check_errors(g, ref)
+    else:
+        _check_errors_power(g, ref, f"wide_q1_J{J}")
     _check_factors(g, ref)
     assert abs(g["rep"]["fit_true"] - ref.fit) < 1e-7
     assert rel(g["U"], np.concatenate(ref.U, axis=0)) < 1e-5
@@ -66,7 +83,9 @@ def test_wide_low_precision_matches_oracle_on_decoded(kind, J, q):
     g = _run_gpu(Xd, R, L, L, iters, om1, om2, H0, V0, W0, want_U=True, T=T, power_iters=q)
     _check_compression(Xd, R, g, ref)
     if q == 0:
-        _check_errors(g, ref)   # (with a power step: see test_wide_float32_matches_oracle)
+        _check_errors(g, ref)
+    else:
+        _check_errors_power(g, ref, f"wide_q1_J{J}_{kind}")
     _check_factors(g, ref)
     assert abs(g["rep"]["fit_true"] - ref.fit) < 1e-7
     assert rel(g["U"], np.concatenate(ref.U, axis=0)) < 1e-5
