@@ -15,7 +15,9 @@ the GPU's compressed data are, to FP64 rounding, the exact randomized SVD of
 the rounded pair (Yq, Xq).  This script computes exactly that with NumPy
 (Yq, Xq as described; Y rounded to float32 after an FP64 product), runs the
 oracle's second stage and iteration on it, and compares with the plain
-oracle on the same inputs.  The deviations it reports are what the GPU's
+oracle on the same inputs.  With a power step (q = 1) the next sketch matrix
+of each slice is its right singular basis of B rounded to float32, as the
+library writes it for the second slab pass.  The deviations it reports are what the GPU's
 arithmetic is expected to produce; the tests allow a factor SAFETY above the
 largest deviation seen over the cases of one check (and never less than the
 floor given per check).
