@@ -156,18 +156,24 @@ def test_graph_replays_match_eager():
         assert repe["iters"] == iters
 
 
-@pytest.mark.parametrize("shape", ["J600_three", "J4096_R32_pair"])
+@pytest.mark.parametrize("shape", ["J600_three", "J4096_R32_pair", "J600_R40_pair"])
 def test_long_j_batch_equals_single_runs(shape):
     """Batches at long J (the second stage's J-long steps on one wave per 64
     rows, the wide Y2 partials summed one thread per entry, per tensor):
-    three tensors at J = 600 (R = 5, L = 15), and two rank-32 tensors at
+    three tensors at J = 600 (R = 5, L = 15), two rank-32 tensors at
     J = 4096 whose K R together would call for longer row chunks of the
     second-stage sketch than each alone (the chunk length is the tensor's
-    own); bit for bit the single runs."""
+    own), and two rank-40 tensors at J = 600 (L = 50: one slice per block
+    in the iteration, the block table across both tensors); bit for bit the
+    single runs."""
     if shape == "J600_three":
         Xs = [synth.parafac2(synth.uniform_rows(K, 40, 120, 60 + i), 600, 5, 60 + i, noise_abs=0.02)
               for i, K in enumerate([30, 45, 20])]
         _case(Xs, 5, 15, 12, [-1.0] * 3)
+    elif shape == "J600_R40_pair":
+        Xs = [synth.parafac2(synth.uniform_rows(K, 60, 160, 80 + i), 600, 40, 80 + i, noise_abs=0.02)
+              for i, K in enumerate([24, 17])]
+        _case(Xs, 40, 50, 6, [-1.0] * 2)
     else:
         Xs = [synth.parafac2(synth.uniform_rows(140, 33, 40, 70 + i), 4096, 32, 70 + i, noise_abs=0.02)
               for i in range(2)]
