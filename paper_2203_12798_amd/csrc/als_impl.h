@@ -110,6 +110,67 @@ __device__ inline int group_jacobi(double (&t)[R], double (&v)[R], int j, int gb
     for (int r = 0; r < N - 1; ++r) {
       const int pc = (j < N) ? rr_partner(j, r, N) : j;
       const int src = gbase + pc;
+      if constexpr (4 * R > 192) {
+        // (t and the partner's whole column would take more than 192 of the
+        // 256 vector registers) the partner's column in two halves, fetched
+        // once for the sums and again for the rotation (both halves are
+        // fetched before this lane changes them); the same sums in the same
+        // order as below
+        constexpr int HF = (R + 1) / 2;
+        double aa = 0.0, bb = 0.0, ab = 0.0;
+#pragma unroll
+        for (int hf = 0; hf < 2; ++hf) {
+          double tp[HF];
+#pragma unroll
+          for (int i = 0; i < HF; ++i)
+            if (hf * HF + i < R) tp[i] = __shfl(t[hf * HF + i], src, 64);
+#pragma unroll
+          for (int i = 0; i < HF; ++i)
+            if (hf * HF + i < R) {
+              aa = fma(t[hf * HF + i], t[hf * HF + i], aa);
+              bb = fma(tp[i], tp[i], bb);
+              ab = fma(t[hf * HF + i], tp[i], ab);
+            }
+        }
+        const bool low = j < pc;
+        const double alpha = low ? aa : bb, beta = low ? bb : aa;
+        const double ab2 = ab * ab, ref = alpha * beta;
+        const bool rot = j < N && pc != j && ab != 0.0 && ab2 > (JACOBI_TOL * JACOBI_TOL) * ref;
+        double c = 1.0, sn = 0.0;
+        if (rot) {
+          big |= (ab2 > 1e-14 * ref) ? 1 : 0;
+          jacobi_cs(alpha, beta, ab, &c, &sn);
+          rotated = 1;
+        }
+        const double sa = low ? -sn : sn;
+#pragma unroll
+        for (int hf = 0; hf < 2; ++hf) {
+          double tp[HF];
+#pragma unroll
+          for (int i = 0; i < HF; ++i)
+            if (hf * HF + i < R) tp[i] = __shfl(t[hf * HF + i], src, 64);
+          if (rot) {
+#pragma unroll
+            for (int i = 0; i < HF; ++i)
+              if (hf * HF + i < R) t[hf * HF + i] = fma(c, t[hf * HF + i], sa * tp[i]);
+          }
+        }
+        if constexpr (WITHV) {
+#pragma unroll
+          for (int hf = 0; hf < 2; ++hf) {
+            double vp[HF];
+#pragma unroll
+            for (int i = 0; i < HF; ++i)
+              if (hf * HF + i < R) vp[i] = __shfl(v[hf * HF + i], src, 64);
+            if (rot) {
+#pragma unroll
+              for (int i = 0; i < HF; ++i)
+                if (hf * HF + i < R) v[hf * HF + i] = fma(c, v[hf * HF + i], sa * vp[i]);
+            }
+          }
+        }
+        continue;
+      }
       double tp[R], vp[R];
 #pragma unroll
       for (int i = 0; i < R; ++i) tp[i] = __shfl(t[i], src, 64);
