@@ -27,7 +27,10 @@ struct SC {
   static constexpr int RM = pow2ceil(N) < 2 ? 2 : pow2ceil(N);   // column groups
   static constexpr int H = 64 / RM;                              // lanes per column
   static constexpr int LH = (L + H - 1) / H;                     // rows per lane
-  static constexpr int LD = L + 1;                               // LDS leading dimension
+  // LDS leading dimension: padded up to L = 32; above, unpadded, so that the
+  // per-slice completion's four L x L matrices at L = 50 leave room for two
+  // blocks per compute unit
+  static constexpr int LD = (L > 32) ? L : L + 1;
   static constexpr int CW = 32;                                  // P columns per chunk
 };
 
