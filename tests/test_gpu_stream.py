@@ -112,15 +112,22 @@ def test_append_equals_decompose_and_matches_oracle():
     assert g["rep"]["warn_bits"] == 0
 
 
-@pytest.mark.parametrize("kind", ["q1_cut_items", "wide_J300", "long_J600", "fp8"])
+@pytest.mark.parametrize("kind", ["q1_cut_items", "wide_J300", "long_J600", "fp8", "rank40_J300"])
 def test_two_appends_equal_decompose(kind):
     """Two appends in a row (20 -> 21 -> 48 slices, the first of a single
     slice): with q = 1 and 64-row work items (every slice cut into several
     items), with the wide slab pass at J = 300, at J = 600 (the second
-    stage's J-long steps spread over 64-row waves), and with an fp8 slab (the
-    per-slice scales of the new slices); bit for bit the single call."""
+    stage's J-long steps spread over 64-row waves), with an fp8 slab (the
+    per-slice scales of the new slices), and at rank 40 (L = 50); bit for bit
+    the single call."""
     _torch()
     import paper_2203_12798_amd as d
+    if kind == "rank40_J300":
+        X = synth.parafac2(synth.uniform_rows(48, 60, 200, 9), 300, 40, 9, noise_abs=0.02)
+        T = d.Tensor.from_numpy(X.slab, X.offsets)
+        g, full, _ = _stream_vs_full(X, T, 40, 50, 6, [20, 21])
+        _same(g, full)
+        return
     J = {"wide_J300": 300, "long_J600": 600}.get(kind, 24)
     X = synth.parafac2(synth.uniform_rows(48, 40, 260, 7), J, 4, 7, noise_abs=0.02)
     om1 = None
