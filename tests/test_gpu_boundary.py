@@ -217,7 +217,7 @@ def test_released_and_reused_workspace():
     d.release(ws)
 
 
-@pytest.mark.parametrize("R,L", [(5, 15), (10, 15), (20, 24)])
+@pytest.mark.parametrize("R,L", [(5, 15), (10, 15), (20, 24), (40, 40), (50, 50)])
 def test_rank_deficient_q_step_keeps_psi_orthogonal(R, L):
     """A starting W with a zero column makes every T_k of the first Q-step
     (Eq. 8) singular: the polar factor is then not unique, and the Q-step
@@ -225,9 +225,9 @@ def test_rank_deficient_q_step_keeps_psi_orthogonal(R, L):
     U_k = A_k Psi_k H: U_k^T U_k = H^T H for every slice (A_k has orthonormal
     columns), with the rank-deficiency warning raised and finite factors;
     R = 5, 10 and 20 (groups of 8, 16 and 32 lanes per slice, one lane per
-    column)."""
+    column), and R = 40, 50 (one slice per 64-lane block, J = 64)."""
     torch = _torch()
-    X = synth.small_parity(seed=2, K=40)
+    X = synth.small_parity(seed=2, K=40) if R <= 32 else synth.small_parity(seed=2, K=40, J=64)
     d, T, o, o1, o2, (H0, V0, W0) = _setup(X, R, L, 1)
     W0 = W0.copy()
     W0[:, 2] = 0.0
