@@ -124,7 +124,7 @@ typedef struct {
 typedef struct {
   int32_t rank;        /* R: target rank of both stages and of PARAFAC2: 1..32, 40
                           or 50 (the rank sweep of Sec. IV-C goes to 50); the
-                          warm start and the post-processing take R <= 32      */
+                          warm start takes R <= 32                              */
   int32_t sketch;      /* L = R + s: columns of Omega_1 (first stage), R <= L, L in
                           1..32 or one of 40, 50, 60 (above 32 the slab pass is
                           always the 128-column-chunk pass), L <= J and L <=
@@ -322,14 +322,16 @@ dpar2_status dpar2_als_plain(const dpar2_tensor* X, const dpar2_opts* o, dpar2_f
 /* ---- Post-processing of the factors (Sec. IV-E, discovery) ----------------
  * Feature similarity: C (device, J x J float64) = the Pearson correlation
  * coefficients between the rows V(i,:) (device, J x R float64, row-major,
- * e.g. the V of a decomposition); a row of zero variance has no defined
- * correlation and gets 0 in its row and column. */
+ * e.g. the V of a decomposition; R in 1..32, 40 or 50, else DPAR2_EINVAL); a
+ * row of zero variance has no defined correlation and gets 0 in its row and
+ * column. */
 dpar2_status dpar2_feature_pcc(int64_t J, int32_t R, const double* V, double* C, dpar2_stream_t stream);
 
 /* Slice similarity of Eq. 9: S (device, n x n float64) with
  * S[i][j] = exp(-gamma ||U_{idx[i]} - U_{idx[j]}||_F^2), U the N x R float64
  * output of dpar2_output_U (rows row_offsets[k] .. of slice k; X supplies
- * the offsets, device and host).  idx: device int32 n slice indices and its
+ * the offsets, device and host; R in 1..32, 40 or 50).  idx: device int32 n
+ * slice indices and its
  * host copy; every listed slice must have the same number of rows (else
  * DPAR2_ESHAPE, checked on the host). */
 dpar2_status dpar2_slice_similarity(const dpar2_tensor* X, int32_t R, const double* U, int32_t n,

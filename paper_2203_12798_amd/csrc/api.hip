@@ -1399,7 +1399,7 @@ dpar2_status dpar2_als_plain(const dpar2_tensor* X, const dpar2_opts* o, dpar2_f
 
 dpar2_status dpar2_feature_pcc(int64_t J, int32_t R, const double* V, double* C, dpar2_stream_t stream) {
   if (J < 1 || J > ((int64_t)1 << 20)) return fail(DPAR2_EINVAL, "J must be in 1..2^20");
-  if (R < 1 || R > 32) return fail(DPAR2_EINVAL, "R must be in 1..32");
+  if (!rank_supported(R)) return fail(DPAR2_EINVAL, "R must be in 1..32 or one of 40, 50");
   if (!V || !C) return fail(DPAR2_EINVAL, "V and C must be non-NULL");
   const hipError_t e = launch_pcc(J, R, V, C, reinterpret_cast<hipStream_t>(stream));
   return e == hipSuccess ? DPAR2_OK : hip_fail(e, "feature pcc");
@@ -1408,7 +1408,7 @@ dpar2_status dpar2_feature_pcc(int64_t J, int32_t R, const double* V, double* C,
 dpar2_status dpar2_slice_similarity(const dpar2_tensor* X, int32_t R, const double* U, int32_t n, const int32_t* idx,
                                     const int32_t* idx_host, double gamma, double* S, dpar2_stream_t stream) {
   if (!X || !X->row_offsets || !X->row_offsets_host) return fail(DPAR2_EINVAL, "tensor and row offsets must be non-NULL");
-  if (R < 1 || R > 32) return fail(DPAR2_EINVAL, "R must be in 1..32");
+  if (!rank_supported(R)) return fail(DPAR2_EINVAL, "R must be in 1..32 or one of 40, 50");
   if (n < 1 || n > (1 << 20)) return fail(DPAR2_EINVAL, "n must be in 1..2^20");
   if (!U || !idx || !idx_host || !S) return fail(DPAR2_EINVAL, "U, idx and S must be non-NULL");
   if (!(gamma >= 0.0)) return fail(DPAR2_EINVAL, "gamma must be >= 0");

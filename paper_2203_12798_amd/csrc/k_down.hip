@@ -8,17 +8,18 @@ namespace dpar2 {
 constexpr int DT = 32;   // output tile (rows and columns) of the pairwise kernels
 
 // C[a][b] = sum_r da[r] db[r] / sqrt(ssa ssb), d the centred rows of V; rows
-// of zero variance give 0.  Block = a 32 x 32 tile of C.
+// of zero variance give 0.  Block = a 32 x 32 tile of C; R <= MAX_RANK.
 __global__ __launch_bounds__(256) void k_pcc(int64_t J, int R, const double* __restrict__ V,
                                              double* __restrict__ C) {
-  __shared__ double A[DT][33], B[DT][33], ssA[DT], ssB[DT];
+  constexpr int RP = MAX_RANK + 1;
+  __shared__ double A[DT][RP], B[DT][RP], ssA[DT], ssB[DT];
   const int tid = threadIdx.x;
   const int64_t a0 = (int64_t)blockIdx.y * DT, b0 = (int64_t)blockIdx.x * DT;
   // thread t < 64 centres row t % 32 of side t / 32
   if (tid < 2 * DT) {
     const int side = tid / DT, i = tid % DT;
     const int64_t row = (side ? b0 : a0) + i;
-    double (*M)[33] = side ? B : A;
+    double (*M)[RP] = side ? B : A;
     double* ss = side ? ssB : ssA;
     if (row < J) {
       double m = 0.0;

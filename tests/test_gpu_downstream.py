@@ -45,6 +45,10 @@ def test_feature_pcc_matches_oracle():
     assert abs(C[0, 6] - 1.0) < 1e-14 and abs(C[0, 7] + 1.0) < 1e-14
     assert np.all(C[5] == 0.0) and np.all(C[:, 5] == 0.0)
     assert np.all(_pcc(rng.standard_normal((33, 1))) == 0.0)
+    for R in (40, 50):   # the ranks above 32
+        W = rng.standard_normal((45, R))
+        W[3] = 1.5
+        np.testing.assert_allclose(_pcc(W), D.feature_pcc(W), rtol=1e-13, atol=1e-14)
 
 
 def _tensor_U(K, I, R, seed):
