@@ -1,8 +1,9 @@
 // Small dense FP64 linear algebra done by one 64-lane wave on an n x n
-// matrix (n <= 32), in a "split" layout: column c is held by H = 64 / RM
+// matrix (n <= 64), in a "split" layout: column c is held by H = 64 / RM
 // lanes (lane = h RM + c, RM = the power of two >= n rounded up to even),
 // lane h holding rows h LH .. h LH + LH - 1.  A Jacobi round then exchanges
-// LH rows per lane instead of n, and every lane of the wave has work.
+// LH rows per lane instead of n, and every lane of the wave has work (above
+// n = 32 one lane per column: H = 1).
 #pragma once
 
 #include "internal.h"
