@@ -98,7 +98,8 @@ __global__ __launch_bounds__(256, 2) void k_wide_y(SlabArgs a) {
   static_assert(KS * TM * LP * 2 <= TM * WXS, "partial sums of Y must fit over the X chunk");
   __shared__ __align__(16) float sX[TM * WXS];
   __shared__ float sYf[UOUT ? TM * YS : 1];
-  __shared__ double sTh[UOUT ? (LT > 2 ? 64 * 64 : 32 * 32) : 1];
+  // Theta_k (L x R): above L = 32 at most 60 x 50 (the supported ranks and widths)
+  __shared__ double sTh[UOUT ? (LT > 2 ? 60 * 50 : 32 * 32) : 1];
   __shared__ double sred[8];
   constexpr int QW = 20;                       // dwords per digit-plane row (64 bytes + pad)
   __shared__ __align__(16) uint32_t sYq[UOUT ? 4 : 3 * LP * QW];
