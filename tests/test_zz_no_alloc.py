@@ -83,3 +83,12 @@ def test_noalloc_rejects_a_decomposition_beyond_the_scratch():
     assert ei.value.status == -6 and "static scratch" in str(ei.value)
     H, V, W = f.numpy()
     assert np.array_equal(H, H0) and np.array_equal(V, V0) and np.array_equal(W, W0)
+
+
+def test_noalloc_equals_workspace_entry_point_at_rank_40():
+    """Rank 40 with L = 50 (one slice per block in the iteration, the chunked
+    slab pass with four tiles of Y): 20 slices of 60..160 rows at J = 300,
+    8 iterations; bit for bit the workspace entry point."""
+    X = synth.parafac2(synth.uniform_rows(20, 60, 160, 40), 300, 40, 40, noise_abs=0.02)
+    a, b = _both(X, 40, 50, 8)
+    _same(a, b)
