@@ -73,6 +73,8 @@ def parse():
                     help="warm-start training compares components in the targets' own order (no matching)")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip PARAFAC2-ALS on the uncompressed slices (Alg. 2) on the same workload")
+    ap.add_argument("--no-down", action="store_true",
+                    help="skip the post-processing leg (Sec. IV-E: PCC, Eq. 9 similarity, top-k, RWR)")
     ap.add_argument("--no-stream", action="store_true",
                     help="skip the streaming leg (the last 10%% of the slices appended to a decomposition of the rest)")
     ap.add_argument("--cpu-runs", type=int, default=3, help="timed runs of the CPU oracle (mean and median)")
@@ -493,6 +495,80 @@ def bench_scalability(args, d, torch, np, binding):
             del wsp
         print(f"[bench] scalability {I}x{J}x{K} R={R}: {ms:.2f} ms", file=sys.stderr, flush=True)
         out["points"].append(pt)
+    return out
+
+
+def bench_downstream(args, d, torch, np):
+    """Post-processing of Sec. IV-E on a decomposition computed here: a
+    stock-shaped tensor of K = 2000 slices of equal length (I = 250 rows,
+    J = 88 features, rank-10 PARAFAC2 with feature scales 10^U(-2, 3) and 5%
+    noise, drawn on the GPU with torch's generator, seed 9), DPar2 at R = 10
+    (L = 20, 32 iterations) with U_k; then the feature PCC over the rows of V
+    (J x J), the Eq. 9 similarity of all K slices (K x K, gamma = 1 / mean
+    ||U_k||^2), the top 10 of slice 0 and the random walk with restart from
+    slice 0 (c = 0.15, 100 iterations), each timed with HIP events (mean of
+    the timed runs).  The similarity kernel's rate is given against the FP64
+    vector peak: K^2 I R (subtract + fused multiply-add) = 3 K^2 I R flops."""
+    K, I, J, R, L = 2000, 250, 88, 10, 20
+    g = torch.Generator(device="cuda").manual_seed(9)
+    G = torch.randn(K, I, R, device="cuda", generator=g)
+    Q = torch.linalg.qr(G).Q
+    H = torch.randn(R, R, device="cuda", generator=g)
+    V = torch.randn(J, R, device="cuda", generator=g)
+    W = 0.5 + torch.rand(K, R, device="cuda", generator=g)
+    X = torch.bmm(Q.contiguous(), ((H[None] * W[:, None, :]) @ V.t()).contiguous())
+    X = X * (10.0 ** (-2.0 + 5.0 * torch.rand(J, device="cuda", generator=g)))[None, None, :]
+    rms = X.pow(2).mean(dim=(0, 1)).sqrt()
+    X = X + 0.05 * rms[None, None, :] * torch.randn(X.shape, device="cuda", generator=g)
+    slab = X.reshape(K * I, J).contiguous().float()
+    del G, Q, X
+    offs = np.arange(K + 1, dtype=np.int64) * I
+    T = d.Tensor(slab, torch.from_numpy(offs).cuda(), offs)
+    o = d.Options(rank=R, sketch=L, sketch2=L, max_iter=32)
+    om1 = torch.randn(J, L, device="cuda", generator=g)
+    om2 = torch.randn(K * R, L, device="cuda", generator=g)
+    f = d.Factors(torch.eye(R, dtype=torch.float64, device="cuda"),
+                  torch.randn(J, R, dtype=torch.float64, device="cuda", generator=g),
+                  torch.ones(K, R, dtype=torch.float64, device="cuda"))
+    ws = d.alloc_workspace(T, o)
+    U = torch.zeros((K * I, R), dtype=torch.float64, device="cuda")
+    rep = d.decompose(T, o, om1, om2, f, ws, U=U, report=True)
+    gamma = 1.0 / float(U.pow(2).sum() / K)
+    C = torch.empty((J, J), dtype=torch.float64, device="cuda")
+    S = torch.empty((K, K), dtype=torch.float64, device="cuda")
+    top = torch.empty(10, dtype=torch.int32, device="cuda")
+    r = torch.empty(K, dtype=torch.float64, device="cuda")
+    work = torch.empty(3 * K, dtype=torch.float64, device="cuda")   # 3 n doubles of scratch
+    runs = max(3, args.steps)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(runs):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / runs
+
+    ms_pcc = timed(lambda: d.feature_pcc(f.V, C))
+    ms_sim = timed(lambda: d.slice_similarity(T, U, range(K), gamma, S))
+    ms_top = timed(lambda: d.top_k(S[0], 0, 10, top))
+    ms_rwr = timed(lambda: d.rwr(S, 0, r, work, c=0.15, iters=100))
+    sim_flops = 3.0 * K * K * I * R
+    out = {"workload": f"K={K} slices of I={I} rows, J={J}, rank-10 PARAFAC2 (feature scales 10^U(-2,3), 5% noise); "
+                       f"DPar2 R={R} L={L}, 32 iterations, U_k",
+           "fitness": rep["fit_true"],
+           "pcc_ms": round(ms_pcc, 4), "similarity_ms": round(ms_sim, 3), "top10_ms": round(ms_top, 4),
+           "rwr_100_iterations_ms": round(ms_rwr, 3),
+           "similarity_fp64_tflops": round(sim_flops / (ms_sim / 1e3) / 1e12, 2),
+           "similarity_frac_of_fp64_vector_peak": round(sim_flops / (ms_sim / 1e3) / 1e12 / 78.6, 4),
+           "rwr_hbm_gbs": round(100 * K * K * 8 / (ms_rwr / 1e3) / 1e9, 1),
+           "top10_of_slice_0": [int(x) for x in top.cpu().numpy()]}
+    print(f"[bench] post-processing: pcc {ms_pcc:.3f} ms, similarity {ms_sim:.2f} ms, top-10 {ms_top:.3f} ms, "
+          f"rwr {ms_rwr:.2f} ms", file=sys.stderr, flush=True)
+    d.release(ws)
     return out
 
 
@@ -922,6 +998,11 @@ def main():
         out["plain_als"] = plain
     if stream is not None:
         out["stream"] = stream
+    if not args.no_down:
+        try:
+            out["post_processing"] = bench_downstream(args, d, torch, np)
+        except Exception as exc:   # reported, not fatal
+            out["post_processing"] = {"error": str(exc)[:300]}
     if forms is not None:
         out["forms"] = forms
     if not args.no_batch:

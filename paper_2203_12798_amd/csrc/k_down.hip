@@ -177,20 +177,31 @@ __global__ __launch_bounds__(256) void k_rwr_w(const double* __restrict__ r, con
   if (i < n) w[i] = d[i] > 0.0 ? r[i] / d[i] : 0.0;
 }
 
-// r_new[j] = (1 - c) sum_{i != j} S[i][j] w[i] + c q[j]; thread per column
-// (consecutive threads read consecutive entries of a row).
-__global__ __launch_bounds__(256) void k_rwr_step(const double* __restrict__ S, const double* __restrict__ w, int n,
-                                                  int target, double c, double* __restrict__ rn) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= n) return;
+// r_new[j] = (1 - c) sum_{i != j} S[i][j] w[i] + c q[j]: one block per 16
+// columns; thread t takes column 16 b + t % 16 and every 64th row from row
+// t / 16 (a wave reads 16 consecutive entries of 4 rows), and the 64 row-group
+// sums of a column are added in a fixed order.
+__global__ __launch_bounds__(1024) void k_rwr_step(const double* __restrict__ S, const double* __restrict__ w, int n,
+                                                   int target, double c, double* __restrict__ rn) {
+  __shared__ double part[64][17];
+  const int tid = threadIdx.x, cl = tid & 15, g = tid >> 4;
+  const int j = blockIdx.x * 16 + cl;
   double s0 = 0.0, s1 = 0.0;
-  int i = 0;
-  for (; i + 1 < n; i += 2) {
-    s0 += (i == j) ? 0.0 : S[(size_t)i * n + j] * w[i];
-    s1 += (i + 1 == j) ? 0.0 : S[(size_t)(i + 1) * n + j] * w[i + 1];
+  if (j < n) {
+    int i = g;
+    for (; i + 64 < n; i += 128) {
+      s0 += (i == j) ? 0.0 : S[(size_t)i * n + j] * w[i];
+      s1 += (i + 64 == j) ? 0.0 : S[(size_t)(i + 64) * n + j] * w[i + 64];
+    }
+    if (i < n) s0 += (i == j) ? 0.0 : S[(size_t)i * n + j] * w[i];
   }
-  if (i < n) s0 += (i == j) ? 0.0 : S[(size_t)i * n + j] * w[i];
-  rn[j] = (1.0 - c) * (s0 + s1) + ((j == target) ? c : 0.0);
+  part[g][cl] = s0 + s1;
+  __syncthreads();
+  if (g == 0 && j < n) {
+    double s = 0.0;
+    for (int q = 0; q < 64; ++q) s += part[q][cl];
+    rn[j] = (1.0 - c) * s + ((j == target) ? c : 0.0);
+  }
 }
 
 hipError_t launch_pcc(int64_t J, int R, const double* V, double* C, hipStream_t s) {
@@ -223,7 +234,7 @@ hipError_t launch_rwr(const double* S, int n, int target, double c, int iters, d
   const unsigned nb = (unsigned)((n + 255) / 256);
   for (int it = 0; it < iters; ++it) {
     hipLaunchKernelGGL(k_rwr_w, dim3(nb), dim3(256), 0, s, cur, d, n, w);
-    hipLaunchKernelGGL(k_rwr_step, dim3(nb), dim3(256), 0, s, S, w, n, target, c, nxt);
+    hipLaunchKernelGGL(k_rwr_step, dim3((unsigned)((n + 15) / 16)), dim3(1024), 0, s, S, w, n, target, c, nxt);
     double* t = cur;
     cur = nxt;
     nxt = t;
