@@ -53,48 +53,63 @@ __global__ __launch_bounds__(256) void k_pcc(int64_t J, int R, const double* __r
 }
 
 // S[i][j] = exp(-gamma sum (u_i - u_j)^2) over the M = I R entries of the
-// slices idx[i], idx[j] (rows off[idx] .. of U), streamed in chunks of 64.
-constexpr int SCH = 64;
+// slices idx[i], idx[j] (rows off[idx] .. of U), streamed in chunks of SCH
+// entries through LDS.  Block = a 64 x 64 tile of S; thread (ti, tj) = (t /
+// 16, t % 16) holds the 4 x 4 entries (ti + 16 a, tj + 16 b), each summed over
+// the entries in order.
+constexpr int ST = 64;    // output tile (rows and columns) of the similarity
+constexpr int SCH = 32;   // entries per chunk
 __global__ __launch_bounds__(256) void k_sim(int n, int64_t M, int R, const int64_t* __restrict__ off,
                                              const int32_t* __restrict__ idx, const double* __restrict__ U,
                                              double gamma, double* __restrict__ S) {
-  __shared__ double A[DT][SCH + 1], B[DT][SCH + 1];
-  __shared__ const double* pa[DT];
-  __shared__ const double* pb[DT];
-  const int tid = threadIdx.x;
-  const int i0 = blockIdx.y * DT, j0 = blockIdx.x * DT;
-  if (tid < 2 * DT) {
-    const int side = tid / DT, t = tid % DT, s = (side ? j0 : i0) + t;
+  __shared__ double A[ST][SCH + 1], B[ST][SCH + 1];
+  __shared__ const double* pa[ST];
+  __shared__ const double* pb[ST];
+  const int tid = threadIdx.x, ti = tid >> 4, tj = tid & 15;
+  const int i0 = blockIdx.y * ST, j0 = blockIdx.x * ST;
+  if (tid < 2 * ST) {
+    const int side = tid / ST, t = tid % ST, s = (side ? j0 : i0) + t;
     const double* p = (s < n) ? U + off[idx[s]] * R : nullptr;
     if (side) pb[t] = p;
     else pa[t] = p;
   }
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
   for (int64_t m0 = 0; m0 < M; m0 += SCH) {
     const int nm = (M - m0 < SCH) ? (int)(M - m0) : SCH;
     __syncthreads();
-    for (int e = tid; e < DT * SCH; e += 256) {
+    for (int e = tid; e < ST * SCH; e += 256) {
       const int t = e / SCH, c = e % SCH;
       A[t][c] = (pa[t] && c < nm) ? pa[t][m0 + c] : 0.0;
       B[t][c] = (pb[t] && c < nm) ? pb[t][m0 + c] : 0.0;
     }
     __syncthreads();
+    for (int c = 0; c < nm; ++c) {
+      double x[4], y[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + 256 * q, i = e / DT, j = e % DT;
-      double s = acc[q];
-      for (int c = 0; c < nm; ++c) {
-        const double d = A[i][c] - B[j][c];
-        s = fma(d, d, s);
+      for (int a = 0; a < 4; ++a) {
+        x[a] = A[ti + 16 * a][c];
+        y[a] = B[tj + 16 * a][c];
       }
-      acc[q] = s;
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const double d = x[a] - y[b];
+          acc[a][b] = fma(d, d, acc[a][b]);
+        }
     }
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int e = tid + 256 * q, i = i0 + e / DT, j = j0 + e % DT;
-    if (i < n && j < n) S[(size_t)i * n + j] = exp(-gamma * acc[q]);
-  }
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = i0 + ti + 16 * a, j = j0 + tj + 16 * b;
+      if (i < n && j < n) S[(size_t)i * n + j] = exp(-gamma * acc[a][b]);
+    }
 }
 
 // Order of the ranking: larger value first, then lower index; NaN ranks
@@ -212,7 +227,7 @@ hipError_t launch_pcc(int64_t J, int R, const double* V, double* C, hipStream_t 
 
 hipError_t launch_similarity(int n, int64_t M, int R, const int64_t* off, const int32_t* idx, const double* U,
                              double gamma, double* S, hipStream_t s) {
-  const unsigned t = (unsigned)((n + DT - 1) / DT);
+  const unsigned t = (unsigned)((n + ST - 1) / ST);
   hipLaunchKernelGGL(k_sim, dim3(t, t), dim3(256), 0, s, n, M, R, off, idx, U, gamma, S);
   return hipGetLastError();
 }
